@@ -1,0 +1,263 @@
+"""FP64 CPU oracle for one relational layer.  TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  The HIP library never calls it and
+shares no code with it; the two meet only at the seeded inputs of ``relgen``.
+
+What it computes, and where the paper defines it:
+
+* join (Section 2.2, "Join"): natural join of the link relation with each
+  body atom on the atom's key; the embedding of a joined tuple is the
+  concatenation of the contributing embeddings in body-atom order;
+* transformation (Section 2.2, "Transformation"): tau applied independently
+  to every joined tuple, here tau = act_pre(Linear(Concat(...)));
+* projected union with k = 1 (Section 2.2, "Projected union"): the output
+  content is the *set* of distinct head keys; each output tuple aggregates
+  the *multiset* B_t of joined tuples that project onto it, with
+  alpha in {sum, mean, max}, applied once;
+* the join rule (Section 3.1) composes these as union(T(join(...))); an
+  activation after the aggregate follows the union-rule form, where T comes
+  after the union (Section 3.1);
+* training (Section 2.3) needs gradients with respect to both the
+  per-tuple embeddings and the transform weights: ``layer_bwd``.
+
+Readings where the paper is silent (each is listed with its reason in the
+design notes of the repository): bag semantics for link rows; absent output
+for empty groups; canonical tuple order (group key, FK values of the atoms
+in body order, link row); MAX ties go to the earliest canonical tuple and
+its gradient goes only there; ReLU'(0) = 0; W is [K, h] with y = x W + b.
+
+Parity is pinned by tests/test_oracle_pins.py: brute-force enumeration,
+dense closed forms, a hand-worked golden example, permutation invariance,
+finite differences and a torch-CPU FP64 composition of the paper's physical
+plan (Section 4.2).  The two-hop path cap and the neighbourhood sampler are
+readings of ours with no counterpart in the paper: "parity unpinned" by the
+paper, pinned only by brute force and by their own invariants.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+
+class NotUnique(ValueError):
+    """A keyed atom has a duplicate primary key (FK -> PK join required)."""
+
+
+# ---------------------------------------------------------------------------
+# join
+# ---------------------------------------------------------------------------
+def lookup_rows(n_rows: int, keys: Optional[np.ndarray], values: np.ndarray) -> np.ndarray:
+    """Row of the relation whose key equals each value; -1 if none (a
+    dangling foreign key, which drops the joined tuple: inner join)."""
+    values = np.asarray(values, dtype=np.int64)
+    if keys is None:
+        ok = (values >= 0) & (values < n_rows)
+        return np.where(ok, values, -1)
+    pos = {}
+    for r, k in enumerate(np.asarray(keys).tolist()):
+        if k in pos:
+            raise NotUnique(f"duplicate key {k}")
+        pos[k] = r
+    return np.array([pos.get(v, -1) for v in values.tolist()], dtype=np.int64)
+
+
+def two_hop_paths(cols: Sequence[np.ndarray], mid: int, cap: int):
+    """Self-join of the link relation on column ``mid`` (Buys |x| Buys^T).
+
+    For every mid key m (ascending) the link rows with that key are ordered
+    by their other columns, then by link row: B_m = [b_0 .. b_{n-1}].  Path
+    number p (0 <= p < min(cap, n*n)) pairs b_i with b_j where
+    i = p mod n and j = (i + 1 + p div n) mod n, which walks all n*n ordered
+    pairs, starting with each row's successor.  Returns the two link-row
+    arrays, in path order."""
+    n_link = len(cols[0])
+    others = [np.asarray(c, np.int64) for q, c in enumerate(cols) if q != mid]
+    order = np.lexsort([np.arange(n_link)] + others[::-1] + [np.asarray(cols[mid], np.int64)])
+    midv = np.asarray(cols[mid], np.int64)[order]
+    la, lb = [], []
+    start = 0
+    while start < n_link:
+        end = start
+        while end < n_link and midv[end] == midv[start]:
+            end += 1
+        n = end - start
+        for p in range(min(cap, n * n)):
+            i = p % n
+            j = (i + 1 + p // n) % n
+            la.append(order[start + i])
+            lb.append(order[start + j])
+        start = end
+    return np.array(la, np.int64), np.array(lb, np.int64)
+
+
+@dataclass
+class Index:
+    """Join result in canonical order plus the group structure."""
+    link_row: np.ndarray      # [E] link row (or path number) of each tuple
+    rows: List[np.ndarray]    # k x [E] row of atom j joined to each tuple
+    gkey: np.ndarray          # [E] head key of each tuple
+    group_keys: np.ndarray    # [G] distinct head keys, ascending
+    offsets: np.ndarray       # [G+1] segment bounds in the tuple list
+    tuple_group: np.ndarray   # [E] segment number of each tuple
+
+    @property
+    def E(self) -> int:
+        return int(self.link_row.shape[0])
+
+    @property
+    def G(self) -> int:
+        return int(self.group_keys.shape[0])
+
+
+def build_index(rule) -> Index:
+    """Join the link relation with the body atoms and group by the head key."""
+    cols = [np.asarray(c, np.int64) for c in rule.cols]
+    if rule.two_hop_mid >= 0:
+        la, lb = two_hop_paths(rule.cols, rule.two_hop_mid, rule.two_hop_cap)
+        cols = [c[la] for c in cols] + [c[lb] for c in cols]
+    n_link = len(cols[0])
+    valid = np.ones(n_link, dtype=bool)
+    for ch in rule.chains:                       # derived columns, in order
+        r = lookup_rows(ch.n_rows, ch.keys, cols[ch.src_col])
+        valid &= r >= 0
+        cols.append(np.where(r >= 0, np.asarray(ch.vals, np.int64)[np.maximum(r, 0)], 0))
+    rows = []
+    for a in rule.atoms:
+        r = lookup_rows(a.n_rows, a.keys, cols[a.col])
+        valid &= r >= 0
+        rows.append(r)
+    ell = np.nonzero(valid)[0]
+    g = cols[rule.group_col][ell]
+    fk = [cols[a.col][ell] for a in rule.atoms]
+    # canonical order: head key, then FK values of the atoms, then link row
+    order = np.lexsort([ell] + fk[::-1] + [g])
+    ell, g = ell[order], g[order]
+    rows = [r[ell] for r in rows]
+    head = np.ones(len(ell), dtype=bool)
+    head[1:] = g[1:] != g[:-1]
+    starts = np.nonzero(head)[0]
+    offsets = np.append(starts, len(ell)).astype(np.int64)
+    tuple_group = np.cumsum(head) - 1
+    return Index(link_row=ell, rows=rows, gkey=g, group_keys=g[starts],
+                 offsets=offsets, tuple_group=tuple_group)
+
+
+# ---------------------------------------------------------------------------
+# transform + aggregate
+# ---------------------------------------------------------------------------
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """float32 -> bfloat16 (round to nearest, ties to even), returned as the
+    float32 value it represents.  NaN is not expected in these inputs."""
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (b >> 16) & 1
+    b = (b + 0x7FFF + lsb) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def _act(name: str, v: np.ndarray) -> np.ndarray:
+    if name == "none":
+        return v
+    if name == "relu":
+        return np.maximum(v, 0.0)
+    raise ValueError(name)
+
+
+def _act_grad(name: str, v: np.ndarray) -> np.ndarray:
+    if name == "none":
+        return np.ones_like(v)
+    if name == "relu":
+        return (v > 0).astype(np.float64)          # ReLU'(0) = 0
+    raise ValueError(name)
+
+
+def gather_concat(idx: Index, embs: Sequence[np.ndarray], sel=slice(None)) -> np.ndarray:
+    """x_tau = z_1[r_1] (+) ... (+) z_k[r_k] in body-atom order, FP64."""
+    parts = [np.asarray(e, np.float64)[r[sel]] for e, r in zip(embs, idx.rows)]
+    return np.concatenate(parts, axis=1)
+
+
+def transform(x: np.ndarray, W: np.ndarray, b: np.ndarray, act_pre: str) -> np.ndarray:
+    return _act(act_pre, x @ np.asarray(W, np.float64) + np.asarray(b, np.float64))
+
+
+def _groups(idx: Index, groups):
+    return np.arange(idx.G) if groups is None else np.asarray(groups, np.int64)
+
+
+def layer_fwd(idx: Index, embs, W, b, agg="sum", act_pre="none", act_post="none",
+              groups=None):
+    """Evaluate the layer for all groups (or the listed group numbers).
+
+    Returns (out, pre, argmax): out = act_post(pre); pre = alpha over the
+    group's tuples of act_pre(x W + b); argmax [G', h] is the canonical
+    tuple position of the first maximiser (MAX only, else None)."""
+    gsel = _groups(idx, groups)
+    h = W.shape[1]
+    pre = np.zeros((len(gsel), h), np.float64)
+    amax = np.full((len(gsel), h), -1, np.int64) if agg == "max" else None
+    for q, g in enumerate(gsel):
+        s, e = int(idx.offsets[g]), int(idx.offsets[g + 1])
+        y = transform(gather_concat(idx, embs, slice(s, e)), W, b, act_pre)
+        if agg == "sum":
+            pre[q] = y.sum(axis=0)
+        elif agg == "mean":
+            pre[q] = y.sum(axis=0) / (e - s)
+        elif agg == "max":
+            j = np.argmax(y, axis=0)                 # first maximiser
+            pre[q] = y[j, np.arange(h)]
+            amax[q] = s + j
+        else:
+            raise ValueError(agg)
+    return _act(act_post, pre), pre, amax
+
+
+def layer_bwd(idx: Index, embs, W, b, pre, argmax, dout, agg="sum",
+              act_pre="none", act_post="none"):
+    """Gradients of sum(out * dout) with respect to every atom's embedding,
+    W and b (chain rule through the layer of ``layer_fwd``).
+
+    Returns (demb, dW, db); demb[j] has the shape of embs[j].  Atoms that
+    share one embedding relation (self-joins) get separate entries, which the
+    caller adds."""
+    W64 = np.asarray(W, np.float64)
+    dA = np.asarray(dout, np.float64) * _act_grad(act_post, np.asarray(pre, np.float64))
+    x = gather_concat(idx, embs)
+    g = idx.tuple_group
+    cnt = np.diff(idx.offsets).astype(np.float64)
+    if agg == "sum":
+        dY = dA[g]
+    elif agg == "mean":
+        dY = dA[g] / cnt[g][:, None]
+    elif agg == "max":
+        pos = np.arange(idx.E)[:, None]
+        dY = np.where(np.asarray(argmax)[g] == pos, dA[g], 0.0)
+    else:
+        raise ValueError(agg)
+    if act_pre != "none":
+        dY = dY * _act_grad(act_pre, x @ W64 + np.asarray(b, np.float64))
+    dW = x.T @ dY
+    db = dY.sum(axis=0)
+    dX = dY @ W64.T
+    demb, off = [], 0
+    for e, r in zip(embs, idx.rows):
+        d = e.shape[1]
+        acc = np.zeros(e.shape, np.float64)
+        np.add.at(acc, r, dX[:, off:off + d])
+        demb.append(acc)
+        off += d
+    return demb, dW, db
+
+
+# ---------------------------------------------------------------------------
+# error measures (the relative bound of the precision forms)
+# ---------------------------------------------------------------------------
+def row_rel_err(z: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Per output row ||z - ref||_2 / max(||ref||_2, 1e-30)."""
+    z = np.asarray(z, np.float64)
+    ref = np.asarray(ref, np.float64)
+    num = np.linalg.norm(z - ref, axis=-1)
+    den = np.maximum(np.linalg.norm(ref, axis=-1), 1e-30)
+    return num / den

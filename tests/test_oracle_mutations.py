@@ -1,0 +1,128 @@
+"""Planted mistakes in the oracle must be caught by its pins (CPU only).
+
+Each case monkeypatches one plausible slip into ``oracle.relnn_oracle`` (a
+dropped term, a wrong sign or index, a transposed operand, a swapped order)
+and runs the pins; at least one of them must fail.
+"""
+import numpy as np
+import pytest
+
+from oracle import relnn_oracle as orc
+from tests import test_oracle_pins as pins
+
+PIN_SET = [
+    pins.test_golden_index,
+    lambda: pins.test_golden_forward("sum", "sum_pre"),
+    lambda: pins.test_golden_forward("mean", "mean_pre"),
+    lambda: pins.test_golden_forward("max", "max_pre"),
+    pins.test_golden_relu_and_grad,
+    pins.test_sum_closed_form,
+    pins.test_mean_closed_form,
+    pins.test_max_properties,
+    lambda: pins.test_layer_matches_brute("sum", pins.CASES[0], ("none", "relu")),
+    lambda: pins.test_layer_matches_brute("max", pins.CASES[3], ("relu", "none")),
+    lambda: pins.test_grad_finite_differences("mean", "none"),
+    lambda: pins.test_grad_finite_differences("max", "relu"),
+    pins.test_grad_closed_form_sum,
+    lambda: pins.test_join_matches_nested_loop(pins.CASES[7]),
+]
+
+
+def caught(mp):
+    for pin in PIN_SET:
+        try:
+            pin()
+        except (AssertionError, ValueError, IndexError):
+            return True
+    return False
+
+
+orig_gather = orc.gather_concat
+orig_transform = orc.transform
+orig_fwd = orc.layer_fwd
+orig_bwd = orc.layer_bwd
+orig_lookup = orc.lookup_rows
+
+
+def m_concat_reversed(idx, embs, sel=slice(None)):
+    parts = [np.asarray(e, np.float64)[r[sel]] for e, r in zip(embs, idx.rows)]
+    return np.concatenate(parts[::-1], axis=1)
+
+
+def m_bias_dropped(x, W, b, act_pre):
+    return orig_transform(x, W, np.zeros_like(b), act_pre)
+
+
+def m_bias_sign(x, W, b, act_pre):
+    return orig_transform(x, W, -np.asarray(b), act_pre)
+
+
+def m_mean_off_by_one(idx, embs, W, b, agg="sum", act_pre="none", act_post="none", groups=None):
+    out, pre, am = orig_fwd(idx, embs, W, b, agg, act_pre, act_post, groups)
+    if agg == "mean":
+        cnt = np.diff(idx.offsets)[orc._groups(idx, groups)].astype(np.float64)
+        pre = pre * cnt[:, None] / (cnt[:, None] + 1)
+        out = orc._act(act_post, pre)
+    return out, pre, am
+
+
+def m_argmax_last(idx, embs, W, b, agg="sum", act_pre="none", act_post="none", groups=None):
+    out, pre, am = orig_fwd(idx, embs, W, b, agg, act_pre, act_post, groups)
+    if agg == "max":
+        for q, g in enumerate(orc._groups(idx, groups)):
+            s, e = int(idx.offsets[g]), int(idx.offsets[g + 1])
+            y = orc.transform(orc.gather_concat(idx, embs, slice(s, e)), W, b, act_pre)
+            am[q] = s + (e - s - 1) - np.argmax(y[::-1], axis=0)
+    return out, pre, am
+
+
+def m_bwd_mean_no_scale(idx, embs, W, b, pre, argmax, dout, agg="sum", act_pre="none", act_post="none"):
+    if agg == "mean":
+        agg = "sum"
+    return orig_bwd(idx, embs, W, b, pre, argmax, dout, agg, act_pre, act_post)
+
+
+def m_bwd_relu_grad_at_zero(idx, embs, W, b, pre, argmax, dout, agg="sum", act_pre="none", act_post="none"):
+    pre = np.where(np.asarray(pre) == 0, 1.0, pre)
+    return orig_bwd(idx, embs, W, b, pre, argmax, dout, agg, act_pre, act_post)
+
+
+def m_bwd_transposed_roles(idx, embs, W, b, pre, argmax, dout, agg="sum", act_pre="none", act_post="none"):
+    demb, dW, db = orig_bwd(idx, embs, W, b, pre, argmax, dout, agg, act_pre, act_post)
+    if len(demb) == 2 and demb[0].shape == demb[1].shape:
+        demb = [demb[1], demb[0]]
+    return demb, dW, db
+
+
+def m_lookup_off_by_one(n_rows, keys, values):
+    r = orig_lookup(n_rows, keys, values)
+    if keys is None:
+        values = np.asarray(values, np.int64)
+        r = np.where((values >= 0) & (values <= n_rows) & (values < n_rows + 1), values, -1)
+        r = np.where(r == n_rows, -1, r)
+        r = np.where(r >= 1, r - 1, r)
+    return r
+
+
+MUTANTS = {
+    "concat_reversed": ("gather_concat", m_concat_reversed),
+    "bias_dropped": ("transform", m_bias_dropped),
+    "bias_sign": ("transform", m_bias_sign),
+    "mean_off_by_one": ("layer_fwd", m_mean_off_by_one),
+    "argmax_last": ("layer_fwd", m_argmax_last),
+    "bwd_mean_no_scale": ("layer_bwd", m_bwd_mean_no_scale),
+    "bwd_relu_grad_at_zero": ("layer_bwd", m_bwd_relu_grad_at_zero),
+    "bwd_transposed_roles": ("layer_bwd", m_bwd_transposed_roles),
+    "lookup_off_by_one": ("lookup_rows", m_lookup_off_by_one),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, monkeypatch):
+    attr, fn = MUTANTS[name]
+    monkeypatch.setattr(orc, attr, fn)
+    assert caught(monkeypatch), f"no pin caught the planted mistake {name}"
+
+
+def test_unmutated_oracle_passes_every_pin(monkeypatch):
+    assert not caught(monkeypatch)
