@@ -1,0 +1,203 @@
+/*
+ * relnn.h -- C ABI of librelnn, an MI355X (gfx950) library for one
+ * relational layer of Neuro-Relational Algebra:
+ *
+ *     Out(g; act_post(alpha(act_pre(Linear(z_1 (+) ... (+) z_k)))))
+ *         :- Link(...), R_1(c_1; z_1), ..., R_k(c_k; z_k)
+ *
+ * i.e. the join rule of Section 3.1 compiled to projected-union(T(join)):
+ *   - join (Section 2.2): natural join of a link relation with body atoms on
+ *     foreign-key -> primary-key equality; a joined tuple's embedding is the
+ *     concatenation of the atoms' embeddings in body order;
+ *   - transformation (Section 2.2): tau = act_pre(x W + b) per joined tuple;
+ *   - projected union, k = 1 (Section 2.2): group the joined tuples by the
+ *     head key (a set of keys) and aggregate each multiset with SUM, MEAN or
+ *     MAX exactly once; act_post follows the union-rule form (Section 3.1),
+ *     where the transform comes after the union.
+ * Parameters include both the embeddings and the weights (Section 2.3), so
+ * the backward returns gradients for both.
+ *
+ * Conventions for every entry point:
+ *   - Return a relnn_status; nothing throws across the ABI.  On an error
+ *     relnn_last_error() holds a message (thread-local).
+ *   - Arguments are validated before any launch; on a validation error
+ *     nothing is written.
+ *   - "device" pointers are HIP device memory of the current device;
+ *     "host" pointers are ordinary host memory.  Arrays of device pointers
+ *     (emb, demb, cols) are themselves host arrays.
+ *   - The caller owns every embedding, weight, output and workspace buffer
+ *     and keeps them alive until the stream work completes.  The library
+ *     owns relnn_index and relnn_server and all memory inside them.
+ *   - Layer calls are asynchronous on the given stream.  relnn_build_index
+ *     synchronises the stream (the sizes E and G become known there).
+ *   - Ids and keys are int32; a tuple count must stay below 2^31.
+ */
+#ifndef RELNN_H
+#define RELNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Same type as hipStream_t; NULL is the default stream. */
+typedef struct ihipStream_t* relnn_stream_t;
+
+typedef enum {
+  RELNN_OK = 0,
+  RELNN_E_INVALID = 1,      /* bad argument or descriptor */
+  RELNN_E_RANGE = 2,        /* a size or count out of the supported range */
+  RELNN_E_NOT_UNIQUE = 3,   /* duplicate primary key in a keyed relation */
+  RELNN_E_OOM = 4,          /* device allocation failed / budget exceeded */
+  RELNN_E_HIP = 5,          /* a HIP runtime call failed */
+  RELNN_E_BUSY = 6,         /* server: no slot or budget free right now */
+  RELNN_E_NOT_READY = 7,    /* server: request not finished yet */
+  RELNN_E_UNSUPPORTED = 8   /* valid, but a shape this build does not run */
+} relnn_status;
+
+typedef enum { RELNN_F32 = 0, RELNN_BF16 = 1 } relnn_dtype;
+typedef enum { RELNN_SUM = 0, RELNN_MEAN = 1, RELNN_MAX = 2 } relnn_agg;
+typedef enum { RELNN_ACT_NONE = 0, RELNN_ACT_RELU = 1 } relnn_act;
+
+/* ---------------------------------------------------------------- index */
+
+/* A body atom R_j(key; z_j) (Section 2.1: content plus embedding).  Its
+ * rows are matched to the link tuples whose column `col` equals the key. */
+typedef struct {
+  int64_t n_rows;          /* |R_j| */
+  const int32_t* keys;     /* device [n_rows] primary key; NULL => dense ids
+                              0..n_rows-1 (row = key) */
+  int32_t col;             /* link column (0..n_cols-1) or derived column
+                              (n_cols + chain number) holding the FK */
+} relnn_atom;
+
+/* A derived column: for every link tuple, the value vals[r] of the row r of
+ * a lookup relation whose key equals column src_col (an FK chain such as
+ * Buys.item -> BelongsTo.cat).  A missing key drops the tuple. */
+typedef struct {
+  int32_t src_col;         /* link column or an earlier derived column */
+  int64_t n_rows;
+  const int32_t* keys;     /* device [n_rows]; NULL => dense */
+  const int32_t* vals;     /* device [n_rows] */
+} relnn_chain;
+
+#define RELNN_IDX_BWD 1u   /* also build per-atom transpose CSRs (backward) */
+
+/* The join of one rule: the link relation (bag semantics: every stored row
+ * is a tuple), its FK chains, its body atoms in Concat order, and the head
+ * key (the projection attribute of the projected union). */
+typedef struct {
+  int64_t n_link;                 /* rows of the link relation */
+  int32_t n_cols;                 /* its columns */
+  const int32_t* const* cols;     /* host [n_cols] of device [n_link] */
+  int32_t n_chains;
+  const relnn_chain* chains;      /* host [n_chains] */
+  int32_t n_atoms;                /* k, 1..RELNN_MAX_ATOMS */
+  const relnn_atom* atoms;        /* host [k] */
+  int32_t group_col;              /* column holding the head key */
+  int32_t two_hop_mid;            /* -1, or the column on which the link
+                                     relation is self-joined first */
+  int32_t two_hop_cap;            /* paths kept per mid key (two-hop only) */
+  uint32_t flags;                 /* RELNN_IDX_BWD */
+} relnn_join_desc;
+
+#define RELNN_MAX_ATOMS 4
+
+typedef struct relnn_index relnn_index;   /* opaque, device-resident */
+
+/* Builds the join result in canonical order -- tuples sorted by (head key,
+ * FK values of the atoms in body order, link row) -- and its group CSR:
+ * group_keys[G] ascending, offsets[G+1], and per tuple the joined row of
+ * every atom.  Dangling foreign keys drop the tuple (inner join); groups
+ * with no tuple are absent (the output content is the set of head keys that
+ * occur).  A duplicate key in a keyed atom or chain: RELNN_E_NOT_UNIQUE.
+ *
+ * Two-hop (two_hop_mid >= 0): the link relation is first self-joined on
+ * column two_hop_mid.  For each mid key, its link rows are ordered by their
+ * other columns then by link row (b_0..b_{n-1}), and path p < min(cap, n*n)
+ * pairs b_i with b_j, i = p mod n, j = (i + 1 + p div n) mod n.  The path
+ * relation has 2*n_cols columns: 0..n_cols-1 from b_i, n_cols.. from b_j;
+ * atoms, chains and group_col refer to those.  "link row" then means the
+ * path number (mid keys ascending, then p).
+ *
+ * Synchronises `stream`.  *out is owned by the caller through
+ * relnn_index_free. */
+relnn_status relnn_build_index(const relnn_join_desc* desc, relnn_stream_t stream,
+                               relnn_index** out);
+
+/* Sizes: joined tuples E, groups G, device bytes held by the index. */
+relnn_status relnn_index_query(const relnn_index* idx, int64_t* n_tuples,
+                               int64_t* n_groups, int64_t* dev_bytes);
+
+/* Copies the canonical index into caller device buffers (any may be NULL):
+ * group_keys[G], offsets[G+1], link_rows[E], tuple_rows[k*E] (atom-major:
+ * tuple_rows[j*E + e] is the row of atom j joined to tuple e).  Async. */
+relnn_status relnn_index_export(const relnn_index* idx, int32_t* group_keys,
+                                int32_t* offsets, int32_t* link_rows,
+                                int32_t* tuple_rows, relnn_stream_t stream);
+
+relnn_status relnn_index_free(relnn_index* idx);
+
+/* ---------------------------------------------------------------- layer */
+
+#define RELNN_FUSED    0u  /* default: gather -> MFMA -> segmented reduce in
+                              one pass, nothing [E, .] in HBM */
+#define RELNN_PLAIN    1u  /* unfused pipeline: materialise X = [E, K], then
+                              Y = [E, h], then reduce (comparison path) */
+#define RELNN_DW_ACCUM 2u  /* backward adds into dW / db instead of writing */
+
+typedef struct {
+  int32_t k;               /* body atoms, equal to the index's */
+  const int32_t* d;        /* host [k] embedding widths, Concat order */
+  int32_t h;               /* output width */
+  int32_t dtype;           /* relnn_dtype of embeddings and W; accumulation,
+                              bias, outputs and gradients are FP32 */
+  int32_t agg;             /* relnn_agg */
+  int32_t act_pre;         /* relnn_act inside tau, per joined tuple */
+  int32_t act_post;        /* relnn_act after the aggregate */
+  uint32_t flags;          /* RELNN_FUSED | RELNN_PLAIN, RELNN_DW_ACCUM */
+} relnn_layer_desc;
+
+/* Workspace bytes relnn_layer_fwd (bwd = 0) or relnn_layer_bwd (bwd = 1)
+ * needs for this index and layer. */
+relnn_status relnn_workspace_size(const relnn_index* idx, const relnn_layer_desc* L,
+                                  int bwd, size_t* bytes);
+
+/* Forward.  emb: host [k] of device [n_j, d_j] row-major (dtype), 16-byte
+ * aligned rows.  W: device [K, h] row-major (dtype), y = x W + b, K = sum
+ * d_j (the transpose of nn.Linear.weight).  b: device [h] FP32 or NULL.
+ * out: device [G, h] FP32, row q is group group_keys[q].  pre: device
+ * [G, h] FP32 aggregate before act_post, or NULL (needed by the backward
+ * when act_post != NONE).  argmax: device [G, h] int32 canonical tuple
+ * position of the first maximiser, MAX only, or NULL.  ws: device
+ * workspace of relnn_workspace_size(.., 0) bytes. */
+relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_layer_desc* L,
+                             const void* const* emb, const void* W, const float* b,
+                             float* out, float* pre, int32_t* argmax,
+                             void* ws, size_t ws_bytes, relnn_stream_t stream);
+
+/* Backward of sum(out * dout) through the forward above.  Needs an index
+ * built with RELNN_IDX_BWD.  pre: the forward's pre (required when
+ * act_post != NONE); argmax: the forward's argmax (required for MAX).
+ * demb: host [k] of device [n_j, d_j] FP32, ACCUMULATED (+=); entries may
+ * alias (a self-join adds both roles).  dW: device [K, h] FP32, written
+ * (or added with RELNN_DW_ACCUM).  db: device [h] FP32 or NULL, same rule.
+ * The joined tuples are re-gathered, not stored. */
+relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_layer_desc* L,
+                             const void* const* emb, const void* W, const float* b,
+                             const float* pre, const int32_t* argmax, const float* dout,
+                             float* const* demb, float* dW, float* db,
+                             void* ws, size_t ws_bytes, relnn_stream_t stream);
+
+/* ---------------------------------------------------------------- serve */
+
+typedef struct relnn_server relnn_server;
+
+const char* relnn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RELNN_H */

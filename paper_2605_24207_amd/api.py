@@ -1,0 +1,247 @@
+"""Python binding of librelnn with the C ABI's names.
+
+Argument marshalling only: every step of the layer runs in the library's
+HIP kernels.  Torch supplies device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+from ._lib import check, lib
+
+_DTYPES = {"f32": (L.F32, torch.float32), "bf16": (L.BF16, torch.bfloat16)}
+_AGGS = {"sum": L.SUM, "mean": L.MEAN, "max": L.MAX}
+_ACTS = {"none": L.ACT_NONE, "relu": L.ACT_RELU}
+
+
+def _vp(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _i32(t: torch.Tensor, what: str) -> torch.Tensor:
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous int32 CUDA tensor")
+    return t
+
+
+class Index:
+    """relnn_build_index: the join of one rule in canonical order plus its
+    group CSR (device-resident, library-owned).
+
+    cols: link columns, int32 [n_link] each.  atoms: (n_rows, col, keys)
+    per body atom in Concat order (keys None = dense ids).  chains:
+    (src_col, vals, keys) derived columns.  two_hop: (mid_col, cap) or None.
+    """
+
+    def __init__(self, cols: Sequence[torch.Tensor], atoms, group_col: int, chains=(),
+                 two_hop=None, bwd: bool = False, stream=None):
+        lib()
+        self._handle = None
+        cols = [_i32(c, "link column") for c in cols]
+        n_link = int(cols[0].numel())
+        col_arr = (C.c_void_p * len(cols))(*[c.data_ptr() for c in cols])
+        at = (L.Atom * len(atoms))()
+        keep = list(cols)
+        for j, (n_rows, col, keys) in enumerate(atoms):
+            at[j].n_rows = int(n_rows)
+            at[j].col = int(col)
+            at[j].keys = None if keys is None else _i32(keys, "atom keys").data_ptr()
+            keep.append(keys)
+        ch = (L.Chain * max(1, len(chains)))()
+        for i, (src, vals, keys) in enumerate(chains):
+            ch[i].src_col = int(src)
+            ch[i].n_rows = int(vals.numel())
+            ch[i].vals = _i32(vals, "chain values").data_ptr()
+            ch[i].keys = None if keys is None else _i32(keys, "chain keys").data_ptr()
+            keep += [vals, keys]
+        d = L.JoinDesc()
+        d.n_link = n_link
+        d.n_cols = len(cols)
+        d.cols = col_arr
+        d.n_chains = len(chains)
+        d.chains = ch
+        d.n_atoms = len(atoms)
+        d.atoms = at
+        d.group_col = int(group_col)
+        d.two_hop_mid, d.two_hop_cap = (-1, 0) if two_hop is None else (int(two_hop[0]), int(two_hop[1]))
+        d.flags = L.IDX_BWD if bwd else 0
+        h = C.c_void_p()
+        check(lib().relnn_build_index(C.byref(d), _stream(stream), C.byref(h)))
+        self._handle = h
+        self.k = len(atoms)
+        self.n_rows = [int(a[0]) for a in atoms]
+        self.bwd = bwd
+        E, G, B = C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib().relnn_index_query(h, C.byref(E), C.byref(G), C.byref(B)))
+        self.E, self.G, self.dev_bytes = E.value, G.value, B.value
+        self.device = cols[0].device
+
+    @property
+    def handle(self):
+        return self._handle
+
+    def export(self, stream=None):
+        """group_keys [G], offsets [G+1], link_rows [E], tuple_rows [k, E]."""
+        dev = self.device
+        gk = torch.empty(self.G, dtype=torch.int32, device=dev)
+        off = torch.empty(self.G + 1, dtype=torch.int32, device=dev)
+        lr = torch.empty(self.E, dtype=torch.int32, device=dev)
+        tr = torch.empty(self.k, self.E, dtype=torch.int32, device=dev)
+        check(lib().relnn_index_export(self._handle, _vp(gk), _vp(off), _vp(lr), _vp(tr), _stream(stream)))
+        return {"group_keys": gk, "offsets": off, "link_rows": lr, "tuple_rows": tr}
+
+    def free(self):
+        if self._handle is not None and _lib_alive():
+            check(lib().relnn_index_free(self._handle))
+        self._handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _lib_alive():
+    return L._lib is not None
+
+
+class Layer:
+    """relnn_layer_desc: widths, output width, dtype, aggregate, activations."""
+
+    def __init__(self, dims: Sequence[int], h: int, dtype: str = "f32", agg: str = "sum",
+                 act_pre: str = "none", act_post: str = "none", plain: bool = False):
+        self.dims = [int(x) for x in dims]
+        self.h = int(h)
+        self.dtype = dtype
+        self.agg = agg
+        self.act_pre = act_pre
+        self.act_post = act_post
+        self.plain = plain
+        self._d = (C.c_int32 * len(self.dims))(*self.dims)
+
+    @property
+    def K(self):
+        return sum(self.dims)
+
+    @property
+    def torch_dtype(self):
+        return _DTYPES[self.dtype][1]
+
+    def desc(self, dw_accum=False) -> L.LayerDesc:
+        d = L.LayerDesc()
+        d.k = len(self.dims)
+        d.d = self._d
+        d.h = self.h
+        d.dtype = _DTYPES[self.dtype][0]
+        d.agg = _AGGS[self.agg]
+        d.act_pre = _ACTS[self.act_pre]
+        d.act_post = _ACTS[self.act_post]
+        d.flags = (L.PLAIN if self.plain else L.FUSED) | (L.DW_ACCUM if dw_accum else 0)
+        return d
+
+
+def workspace_size(index: Index, layer: Layer, bwd: bool = False) -> int:
+    n = C.c_size_t()
+    d = layer.desc()
+    check(lib().relnn_workspace_size(index.handle, C.byref(d), int(bwd), C.byref(n)))
+    return int(n.value)
+
+
+def workspace(index: Index, layer: Layer, bwd: bool = False) -> torch.Tensor:
+    return torch.empty(max(1, workspace_size(index, layer, bwd)), dtype=torch.uint8, device=index.device)
+
+
+def _check_embs(layer: Layer, embs: Sequence[torch.Tensor]):
+    if len(embs) != len(layer.dims):
+        raise ValueError("one embedding per atom is required")
+    for j, e in enumerate(embs):
+        if e.dtype != layer.torch_dtype or not e.is_cuda or not e.is_contiguous():
+            raise TypeError(f"embedding {j} must be a contiguous {layer.torch_dtype} CUDA tensor")
+        if e.dim() != 2 or e.shape[1] != layer.dims[j]:
+            raise ValueError(f"embedding {j} must be [n, {layer.dims[j]}]")
+
+
+def layer_fwd(index: Index, layer: Layer, embs: Sequence[torch.Tensor], W: torch.Tensor,
+              b: Optional[torch.Tensor] = None, want_pre: bool = True, want_argmax: bool = True,
+              ws: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None, stream=None):
+    """relnn_layer_fwd.  Returns (out [G,h], pre [G,h] or None, argmax [G,h] or None)."""
+    _check_embs(layer, embs)
+    if W.dtype != layer.torch_dtype or W.shape != (layer.K, layer.h) or not W.is_contiguous():
+        raise TypeError(f"W must be a contiguous {layer.torch_dtype} [{layer.K}, {layer.h}] tensor")
+    if b is not None and (b.dtype != torch.float32 or b.numel() != layer.h):
+        raise TypeError("b must be float32 [h]")
+    dev = index.device
+    G, h = index.G, layer.h
+    if out is None:
+        out = torch.empty(G, h, dtype=torch.float32, device=dev)
+    pre = torch.empty(G, h, dtype=torch.float32, device=dev) if want_pre else None
+    am = torch.empty(G, h, dtype=torch.int32, device=dev) if (want_argmax and layer.agg == "max") else None
+    if ws is None:
+        ws = workspace(index, layer, False)
+    emb_arr = (C.c_void_p * len(embs))(*[e.data_ptr() for e in embs])
+    d = layer.desc()
+    check(lib().relnn_layer_fwd(index.handle, C.byref(d), emb_arr, _vp(W), _vp(b), _vp(out), _vp(pre),
+                                _vp(am), _vp(ws), ws.numel(), _stream(stream)))
+    return out, pre, am
+
+
+def layer_bwd(index: Index, layer: Layer, embs: Sequence[torch.Tensor], W: torch.Tensor,
+              b: Optional[torch.Tensor], pre: Optional[torch.Tensor], argmax: Optional[torch.Tensor],
+              dout: torch.Tensor, demb: Sequence[torch.Tensor], dW: torch.Tensor,
+              db: Optional[torch.Tensor] = None, dw_accum: bool = False,
+              ws: Optional[torch.Tensor] = None, stream=None):
+    """relnn_layer_bwd.  demb entries are accumulated (+=) and may alias."""
+    _check_embs(layer, embs)
+    if ws is None:
+        ws = workspace(index, layer, True)
+    emb_arr = (C.c_void_p * len(embs))(*[e.data_ptr() for e in embs])
+    demb_arr = (C.c_void_p * len(demb))(*[g.data_ptr() for g in demb])
+    d = layer.desc(dw_accum=dw_accum)
+    check(lib().relnn_layer_bwd(index.handle, C.byref(d), emb_arr, _vp(W), _vp(b), _vp(pre), _vp(argmax),
+                                _vp(dout.contiguous()), demb_arr, _vp(dW), _vp(db), _vp(ws), ws.numel(),
+                                _stream(stream)))
+
+
+class RelLayerFn(torch.autograd.Function):
+    """out = layer(embs; W, b) with the hand-written backward of librelnn.
+
+    Usage: RelLayerFn.apply(index, layer, W, b, *embs).  Gradients flow to
+    W, b and every embedding (FP32 master gradients; autograd casts them to
+    the parameter dtype).  Atoms that share one tensor get one buffer."""
+
+    @staticmethod
+    def forward(ctx, index: Index, layer: Layer, W, b, *embs):
+        out, pre, am = layer_fwd(index, layer, embs, W, b, want_pre=layer.act_post != "none",
+                                 want_argmax=True)
+        ctx.index, ctx.layer = index, layer
+        ctx.save_for_backward(W, b, pre, am, *embs)
+        return out
+
+    @staticmethod
+    def backward(ctx, dout):
+        W, b, pre, am, *embs = ctx.saved_tensors
+        index, layer = ctx.index, ctx.layer
+        dev = dout.device
+        bufs, grads = {}, []
+        for e in embs:
+            key = e.data_ptr()
+            if key not in bufs:
+                bufs[key] = torch.zeros(e.shape, dtype=torch.float32, device=dev)
+                grads.append(bufs[key])
+            else:
+                grads.append(None)
+        demb = [bufs[e.data_ptr()] for e in embs]
+        dW = torch.empty(layer.K, layer.h, dtype=torch.float32, device=dev)
+        db = torch.empty(layer.h, dtype=torch.float32, device=dev) if b is not None else None
+        layer_bwd(index, layer, embs, W, b, pre, am, dout, demb, dW, db)
+        return (None, None, dW, db) + tuple(grads)

@@ -1,0 +1,108 @@
+// Shared host/device helpers of librelnn (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <string>
+#include <utility>
+
+#include "../../include/relnn.h"
+
+namespace relnn {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+
+struct Fail {
+  relnn_status st;
+};
+
+#define RELNN_REQUIRE(cond, code, ...)          \
+  do {                                          \
+    if (!(cond)) {                              \
+      ::relnn::set_error(__VA_ARGS__);          \
+      throw ::relnn::Fail{code};                \
+    }                                           \
+  } while (0)
+
+#define RELNN_HIP(call)                                                           \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ::relnn::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),   \
+                         __FILE__, __LINE__);                                     \
+      throw ::relnn::Fail{e_ == hipErrorOutOfMemory ? RELNN_E_OOM : RELNN_E_HIP}; \
+    }                                                                             \
+  } while (0)
+
+#define RELNN_LAUNCHED() RELNN_HIP(hipGetLastError())
+
+// Runs `body` and maps a Fail (or any C++ exception) to a status.
+template <class F>
+relnn_status guard(F&& body) {
+  try {
+    body();
+    return RELNN_OK;
+  } catch (const Fail& f) {
+    return f.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return RELNN_E_OOM;
+  } catch (...) {
+    set_error("unexpected C++ exception");
+    return RELNN_E_HIP;
+  }
+}
+
+// Device buffer owned by host code, freed on scope exit.
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t bytes) { alloc(bytes); }
+  void alloc(size_t bytes) {
+    release();
+    n = bytes;
+    if (bytes) RELNN_HIP(hipMalloc(&p, bytes));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+// ------------------------------------------------------------------ device
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// wave64 inclusive prefix sum of an int.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o, 64);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace relnn

@@ -1,0 +1,458 @@
+// Forward of one relational layer: join -> transformation -> projected union.
+//
+//   y_tau = act_pre(x_tau W + b),  x_tau = z_1[r_1] (+) ... (+) z_k[r_k]
+//   pre_g = alpha over the tuples of group g of y_tau,  out_g = act_post(pre_g)
+//
+// (join and its concatenated embedding, transformation applied per tuple,
+// projected union with SUM / MEAN / MAX applied once: Section 2.2; their
+// composition by a join rule: Section 3.1.)
+//
+// Fused path: one kernel per tile of TM tuples gathers the joined rows
+// into LDS with 16-byte coalesced loads, multiplies them on the matrix cores
+// (bf16 16x16x32 or f32 16x16x4, FP32 accumulation), keeps the FP32 result
+// tile in LDS and reduces it per group; nothing of size [E, .] reaches HBM.
+// Plain path: the same steps as three kernels that materialise X = [E, K]
+// and Y = [E, h] in HBM, the shape of a library pipeline
+// (index_select + cat -> Linear -> scatter).
+#include "layer_common.hpp"
+#include "layer_fwd.hpp"
+
+namespace relnn {
+
+__global__ void k_swizzle_bf16(const __bf16* __restrict__ W, int K, int Kp, int h, __bf16* __restrict__ Wsw) {
+  const int ncb = h / 16;
+  const int64_t total = (int64_t)Kp * h;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    // i enumerates (ks, cb, lane, e) in Wsw order
+    const int e = (int)(i & 7);
+    const int64_t f = i >> 3;
+    const int lane = (int)(f & 63);
+    const int64_t kc = f >> 6;
+    const int cb = (int)(kc % ncb);
+    const int ks = (int)(kc / ncb);
+    const int k = ks * 32 + (lane >> 4) * 8 + e;
+    const int n = cb * 16 + (lane & 15);
+    Wsw[i] = k < K ? W[(int64_t)k * h + n] : (__bf16)0.0f;
+  }
+}
+
+__global__ void k_swizzle_f32(const float* __restrict__ W, int K, int Kp, int h, float* __restrict__ Wsw) {
+  const int ncb = h / 16;
+  const int64_t total = (int64_t)Kp * h;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = (int)(i & 63);
+    const int64_t kc = i >> 6;
+    const int cb = (int)(kc % ncb);
+    const int ks = (int)(kc / ncb);
+    const int k = ks * 4 + (lane >> 4);
+    const int n = cb * 16 + (lane & 15);
+    Wsw[i] = k < K ? W[(int64_t)k * h + n] : 0.0f;
+  }
+}
+
+// Copies the joined rows of tuples e0..e0+nv-1 into Xs [TM][XS] (T), in
+// Concat order, zero-filling the K..Kp pad and rows past nv.
+template <class T>
+__device__ __forceinline__ void gather_rows(const Atoms& at, const int32_t* __restrict__ rows, int64_t E,
+                                            int64_t e0, int nv, int TM, int K, int Kp, T* Xs, int XS,
+                                            const int32_t* rowidx) {
+  constexpr int EPC = Mfma<T>::EPC;
+  const int cpr = Kp / EPC;
+  for (int i = threadIdx.x; i < TM * cpr; i += blockDim.x) {
+    const int r = i / cpr;
+    const int c = i - r * cpr;
+    const int el = c * EPC;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (r < nv && el < K) {
+      int j = 0;
+#pragma unroll
+      for (int q = 1; q < kMaxAtoms; ++q)
+        if (q < at.k && el >= at.koff[q]) j = q;
+      const int64_t row = rowidx[j * TM + r];
+      const T* src = static_cast<const T*>(at.emb[j]) + row * at.d[j] + (el - at.koff[j]);
+      v = *reinterpret_cast<const uint4*>(src);
+    }
+    *reinterpret_cast<uint4*>(Xs + r * XS + el) = v;
+  }
+}
+
+// Combines the carry partials of segments that cross tile edges.  Block b
+// (b >= 1) handles the segment containing position b*TM if that segment
+// starts in tile b-1.  Partials are summed in tile order: contiguous runs
+// per strand (blocks of 64, then the block sums), strands in order.
+__global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int TM, int h, Sink sink,
+                                                    const float* carry, const int32_t* carry_arg) {
+  const int64_t b = (int64_t)blockIdx.x + 1;
+  const int64_t e = b * TM;
+  if (e >= sg.n) return;
+  const int64_t s = sg.seg_of[e];
+  if (sg.seg_of[e - 1] != s) return;
+  const int64_t g0 = sg.offsets[s], g1 = sg.offsets[s + 1];
+  const int64_t t0 = g0 / TM;
+  if (t0 != b - 1) return;
+  const int64_t t1 = (g1 - 1) / TM;
+  const int64_t P = t1 - t0 + 1;
+  const int first_slot = (sg.seg_of[t0 * TM] == s) ? 0 : 1;
+  const int CG = min(h, kThreads);
+  const int S = kThreads / CG;
+  const int strand = threadIdx.x / CG;
+  __shared__ float red_v[kThreads];
+  __shared__ int32_t red_a[kThreads];
+  for (int cbase = 0; cbase < h; cbase += CG) {
+    const int c = cbase + (threadIdx.x % CG);
+    const bool active = strand < S && c < h;
+    float v = 0.0f;
+    int32_t am = -1;
+    if (active) {
+      const int64_t lo = (P * strand) / S, hi = (P * (strand + 1)) / S;
+      if (sink.agg == RELNN_MAX) {
+        v = -INFINITY;
+        for (int64_t i = lo; i < hi; ++i) {
+          const int64_t t = t0 + i;
+          const int slot = (i == 0) ? first_slot : 0;
+          const float x = carry[(t * 2 + slot) * h + c];
+          const int32_t xa = carry_arg[(t * 2 + slot) * h + c];
+          if (x > v || (x == v && (am < 0 || xa < am))) {
+            v = x;
+            am = xa;
+          }
+        }
+      } else {
+        for (int64_t i0 = lo; i0 < hi; i0 += 64) {
+          float inner = 0.0f;
+          const int64_t i1 = min(hi, i0 + 64);
+          for (int64_t i = i0; i < i1; ++i) {
+            const int64_t t = t0 + i;
+            const int slot = (i == 0) ? first_slot : 0;
+            inner += carry[(t * 2 + slot) * h + c];
+          }
+          v += inner;
+        }
+      }
+    }
+    red_v[threadIdx.x] = v;
+    red_a[threadIdx.x] = am;
+    __syncthreads();
+    if (strand == 0 && c < h) {
+      float acc = red_v[threadIdx.x];
+      int32_t aa = red_a[threadIdx.x];
+      for (int q = 1; q < S; ++q) {
+        const float x = red_v[q * CG + threadIdx.x];
+        const int32_t xa = red_a[q * CG + threadIdx.x];
+        if (sink.agg == RELNN_MAX) {
+          if (xa >= 0 && (x > acc || (x == acc && (aa < 0 || xa < aa)))) {
+            acc = x;
+            aa = xa;
+          }
+        } else {
+          acc += x;
+        }
+      }
+      sink_write(sink, s, c, h, acc, aa, (int32_t)(g1 - g0));
+    }
+    __syncthreads();
+  }
+}
+
+
+enum { MODE_FUSED = 0, MODE_GEMM = 1, MODE_REDUCE = 2 };
+
+// One tile of TM tuples per block.
+template <class T, int MODE>
+__global__ void __launch_bounds__(kThreads) k_layer_fwd(FwdArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int TM = a.TM;
+  const int64_t tile = blockIdx.x;
+  const int64_t e0 = tile * TM;
+  const int nv = (int)min<int64_t>(TM, a.E - e0);
+  const int XS = a.Kp + Mfma<T>::XPAD;
+  const int YS = a.h + 4;
+  int32_t* rowidx = reinterpret_cast<int32_t*>(smem);
+  T* Xs = reinterpret_cast<T*>(smem + a.off_x);
+  float* Ys = reinterpret_cast<float*>(smem + a.off_y);
+  const int ncb = a.h / 16;
+  const int nblk = (TM / 16) * ncb;
+
+  if constexpr (MODE == MODE_FUSED) {
+    for (int i = threadIdx.x; i < a.at.k * TM; i += blockDim.x) {
+      const int j = i / TM, r = i - (i / TM) * TM;
+      rowidx[i] = r < nv ? a.rows[(int64_t)j * a.E + e0 + r] : 0;
+    }
+    __syncthreads();
+    gather_rows<T>(a.at, a.rows, a.E, e0, nv, TM, a.K, a.Kp, Xs, XS, rowidx);
+  }
+  if constexpr (MODE == MODE_GEMM) {
+    constexpr int EPC = Mfma<T>::EPC;
+    const int cpr = a.Kp / EPC;
+    const T* X = static_cast<const T*>(a.X);
+    for (int i = threadIdx.x; i < TM * cpr; i += blockDim.x) {
+      const int r = i / cpr, c = i - (i / cpr) * cpr;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (r < nv) v = *reinterpret_cast<const uint4*>(X + (e0 + r) * a.Kp + c * EPC);
+      *reinterpret_cast<uint4*>(Xs + r * XS + c * EPC) = v;
+    }
+  }
+  if constexpr (MODE != MODE_REDUCE) {
+    __syncthreads();
+    f32x4 acc[kMaxQ];
+    mfma_tile<T>(Xs, XS, a.Kp, nblk, ncb, static_cast<const T*>(a.Wsw), acc);
+    if constexpr (MODE == MODE_GEMM) {
+      const int lane = __lane_id();
+      const int w = threadIdx.x / 64;
+#pragma unroll
+      for (int qi = 0; qi < kMaxQ; ++qi) {
+        const int q = w + 4 * qi;
+        if (q < nblk) {
+          const int rb = q / ncb, cb = q - (q / ncb) * ncb;
+          const int col = cb * 16 + (lane & 15);
+          const float bv = a.b ? a.b[col] : 0.0f;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = rb * 16 + (lane >> 4) * 4 + i;
+            if (row < nv) a.Y[(e0 + row) * a.h + col] = act_apply(a.act_pre, acc[qi][i] + bv);
+          }
+        }
+      }
+      return;
+    } else {
+      store_acc(acc, nblk, ncb, a.b, a.act_pre, Ys, YS);
+    }
+  } else {
+    for (int i = threadIdx.x; i < nv * a.h; i += blockDim.x) {
+      const int r = i / a.h, c = i - (i / a.h) * a.h;
+      Ys[r * YS + c] = a.Y[(e0 + r) * a.h + c];
+    }
+  }
+  __syncthreads();
+  reduce_tile(Ys, YS, a.h, e0, nv, tile, a.sg, a.sink, a.carry, a.carry_arg);
+}
+
+// Plain gather: X[e] = concat of the joined rows, Kp columns (pad zero).
+template <class T>
+__global__ void k_gather_plain(Atoms at, const int32_t* __restrict__ rows, int64_t E, int K, int Kp,
+                               T* __restrict__ X) {
+  constexpr int EPC = Mfma<T>::EPC;
+  const int cpr = Kp / EPC;
+  const int64_t total = E * cpr;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i / cpr;
+    const int c = (int)(i - e * cpr);
+    const int el = c * EPC;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (el < K) {
+      int j = 0;
+#pragma unroll
+      for (int q = 1; q < kMaxAtoms; ++q)
+        if (q < at.k && el >= at.koff[q]) j = q;
+      const int64_t row = rows[(int64_t)j * E + e];
+      v = *reinterpret_cast<const uint4*>(static_cast<const T*>(at.emb[j]) + row * at.d[j] + (el - at.koff[j]));
+    }
+    *reinterpret_cast<uint4*>(X + e * Kp + el) = v;
+  }
+}
+
+// ---------------------------------------------------------------- host
+namespace {
+
+unsigned grid_for(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 1 << 20));
+}
+
+template <class KernelT>
+void allow_lds(KernelT k, size_t bytes) {
+  RELNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+template <class T>
+void launch_fwd_t(const FwdPlan& P, FwdArgs a, bool plain, hipStream_t s) {
+  const int64_t ntiles = P.ntiles;
+  if (plain) {
+    k_gather_plain<T><<<grid_for(a.E * (a.Kp / Mfma<T>::EPC)), 256, 0, s>>>(
+        a.at, a.rows, a.E, a.K, a.Kp, static_cast<T*>(const_cast<void*>(a.X)));
+    RELNN_LAUNCHED();
+    allow_lds(k_layer_fwd<T, MODE_GEMM>, P.lds);
+    k_layer_fwd<T, MODE_GEMM><<<(unsigned)ntiles, kThreads, P.lds, s>>>(a);
+    RELNN_LAUNCHED();
+    allow_lds(k_layer_fwd<T, MODE_REDUCE>, P.lds);
+    k_layer_fwd<T, MODE_REDUCE><<<(unsigned)ntiles, kThreads, P.lds, s>>>(a);
+    RELNN_LAUNCHED();
+  } else {
+    allow_lds(k_layer_fwd<T, MODE_FUSED>, P.lds);
+    k_layer_fwd<T, MODE_FUSED><<<(unsigned)ntiles, kThreads, P.lds, s>>>(a);
+    RELNN_LAUNCHED();
+  }
+  launch_fixup(a.sg, a.TM, a.h, ntiles, a.sink, a.carry, a.carry_arg, s);
+}
+
+}  // namespace
+
+void launch_fixup(const Seg& sg, int TM, int h, int64_t ntiles, const Sink& sink, const float* carry,
+                  const int32_t* carry_arg, hipStream_t s) {
+  if (ntiles <= 1) return;
+  k_fixup<<<(unsigned)(ntiles - 1), kThreads, 0, s>>>(sg, TM, h, sink, carry, carry_arg);
+  RELNN_LAUNCHED();
+}
+
+FwdPlan plan_fwd(const relnn_index* idx, const relnn_layer_desc* L) {
+  FwdPlan P;
+  const bool bf = L->dtype == RELNN_BF16;
+  const int esz = bf ? 2 : 4;
+  const int KS = bf ? 32 : 4;
+  const int XPAD = bf ? 8 : 4;
+  int K = 0;
+  for (int j = 0; j < L->k; ++j) K += L->d[j];
+  P.K = K;
+  P.Kp = (int)round_up(K, KS);
+  const int h = L->h;
+  P.TM = 0;
+  for (int TM : {64, 32, 16}) {
+    if ((TM / 16) * (h / 16) > 4 * kMaxQ) continue;
+    const size_t rowidx = (size_t)kMaxAtoms * TM * 4;
+    const size_t xs = (size_t)TM * (P.Kp + XPAD) * esz;
+    const size_t ys = (size_t)TM * (h + 4) * 4;
+    const size_t lds = round_up(rowidx, 16) + round_up(xs, 16) + ys;
+    if (lds <= 160 * 1024) {
+      P.TM = TM;
+      P.off_x = round_up(rowidx, 16);
+      P.off_y = P.off_x + round_up(xs, 16);
+      P.lds = lds;
+      break;
+    }
+  }
+  const int64_t E = idx->E;
+  P.ntiles = P.TM ? cdiv(E, P.TM) : 0;
+  size_t off = 0;
+  P.ws_wsw = off;
+  off += round_up((int64_t)P.Kp * h * esz, 256);
+  P.ws_carry = off;
+  off += round_up(std::max<int64_t>(P.ntiles, 1) * 2 * h * 4, 256);
+  P.ws_carry_arg = off;
+  if (L->agg == RELNN_MAX) off += round_up(std::max<int64_t>(P.ntiles, 1) * 2 * h * 4, 256);
+  P.ws_fused = off;
+  P.ws_x = off;
+  off += round_up(std::max<int64_t>(E, 1) * P.Kp * esz, 256);
+  P.ws_y = off;
+  off += round_up(std::max<int64_t>(E, 1) * h * 4, 256);
+  P.ws_plain = off;
+  return P;
+}
+
+void check_layer(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P) {
+  RELNN_REQUIRE(idx != nullptr && L != nullptr, RELNN_E_INVALID, "index or layer descriptor is NULL");
+  RELNN_REQUIRE(L->k == idx->k, RELNN_E_INVALID, "layer has %d atoms, index has %d", L->k, idx->k);
+  RELNN_REQUIRE(L->d != nullptr, RELNN_E_INVALID, "layer widths are NULL");
+  RELNN_REQUIRE(L->dtype == RELNN_F32 || L->dtype == RELNN_BF16, RELNN_E_INVALID, "unknown dtype");
+  RELNN_REQUIRE(L->agg >= RELNN_SUM && L->agg <= RELNN_MAX, RELNN_E_INVALID, "unknown aggregate");
+  RELNN_REQUIRE((L->act_pre == RELNN_ACT_NONE || L->act_pre == RELNN_ACT_RELU) &&
+                    (L->act_post == RELNN_ACT_NONE || L->act_post == RELNN_ACT_RELU),
+                RELNN_E_INVALID, "unknown activation");
+  RELNN_REQUIRE((L->flags & ~(RELNN_PLAIN | RELNN_DW_ACCUM)) == 0, RELNN_E_INVALID, "unknown layer flags");
+  RELNN_REQUIRE(L->h > 0, RELNN_E_INVALID, "h must be positive");
+  const int epc = L->dtype == RELNN_BF16 ? 8 : 4;
+  for (int j = 0; j < L->k; ++j) {
+    RELNN_REQUIRE(L->d[j] > 0, RELNN_E_INVALID, "d[%d] must be positive", j);
+    RELNN_REQUIRE(L->d[j] % epc == 0, RELNN_E_UNSUPPORTED,
+                  "d[%d] = %d: rows must be a multiple of 16 bytes", j, L->d[j]);
+  }
+  RELNN_REQUIRE(L->h % 16 == 0, RELNN_E_UNSUPPORTED, "h = %d must be a multiple of 16", L->h);
+  RELNN_REQUIRE(P.TM > 0, RELNN_E_UNSUPPORTED, "K = %d, h = %d does not fit the LDS tile", P.K, L->h);
+}
+
+Atoms make_atoms(const relnn_layer_desc* L, const void* const* emb) {
+  Atoms at{};
+  at.k = L->k;
+  int off = 0;
+  for (int j = 0; j < L->k; ++j) {
+    at.emb[j] = emb[j];
+    at.d[j] = L->d[j];
+    at.koff[j] = off;
+    off += L->d[j];
+  }
+  return at;
+}
+
+void swizzle_w(const void* W, int dtype, int K, int Kp, int h, void* Wsw, hipStream_t s) {
+  if (dtype == RELNN_BF16)
+    k_swizzle_bf16<<<grid_for((int64_t)Kp * h), 256, 0, s>>>(static_cast<const __bf16*>(W), K, Kp, h,
+                                                              static_cast<__bf16*>(Wsw));
+  else
+    k_swizzle_f32<<<grid_for((int64_t)Kp * h), 256, 0, s>>>(static_cast<const float*>(W), K, Kp, h,
+                                                             static_cast<float*>(Wsw));
+  RELNN_LAUNCHED();
+}
+
+void launch_fwd(const FwdPlan& P, const FwdArgs& a, int dtype, bool plain, hipStream_t s) {
+  if (dtype == RELNN_BF16)
+    launch_fwd_t<__bf16>(P, a, plain, s);
+  else
+    launch_fwd_t<float>(P, a, plain, s);
+}
+
+}  // namespace relnn
+
+using namespace relnn;
+
+extern "C" relnn_status relnn_workspace_size(const relnn_index* idx, const relnn_layer_desc* L, int bwd,
+                                             size_t* bytes) {
+  return guard([&] {
+    RELNN_REQUIRE(bytes != nullptr, RELNN_E_INVALID, "bytes is NULL");
+    FwdPlan P = plan_fwd(idx, L);
+    check_layer(idx, L, P);
+    if (bwd) {
+      *bytes = bwd_workspace(idx, L, P);
+    } else {
+      *bytes = (L->flags & RELNN_PLAIN) ? P.ws_plain : P.ws_fused;
+    }
+  });
+}
+
+extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_layer_desc* L,
+                                        const void* const* emb, const void* W, const float* b, float* out,
+                                        float* pre, int32_t* argmax, void* ws, size_t ws_bytes,
+                                        relnn_stream_t stream) {
+  return guard([&] {
+    RELNN_REQUIRE(idx != nullptr && L != nullptr, RELNN_E_INVALID, "index or layer descriptor is NULL");
+    FwdPlan P = plan_fwd(idx, L);
+    check_layer(idx, L, P);
+    const bool plain = (L->flags & RELNN_PLAIN) != 0;
+    const size_t need = plain ? P.ws_plain : P.ws_fused;
+    RELNN_REQUIRE(emb != nullptr, RELNN_E_INVALID, "emb is NULL");
+    for (int j = 0; j < L->k; ++j) {
+      RELNN_REQUIRE(emb[j] != nullptr || idx->n_rows[j] == 0, RELNN_E_INVALID, "emb[%d] is NULL", j);
+      RELNN_REQUIRE(((uintptr_t)emb[j] & 15) == 0, RELNN_E_UNSUPPORTED, "emb[%d] is not 16-byte aligned", j);
+    }
+    RELNN_REQUIRE(W != nullptr, RELNN_E_INVALID, "W is NULL");
+    RELNN_REQUIRE(out != nullptr || idx->G == 0, RELNN_E_INVALID, "out is NULL");
+    RELNN_REQUIRE(ws != nullptr && ws_bytes >= need, RELNN_E_INVALID,
+                  "workspace of %zu bytes given, %zu needed", ws_bytes, need);
+    RELNN_REQUIRE(((uintptr_t)ws & 255) == 0, RELNN_E_INVALID, "workspace must be 256-byte aligned");
+    if (idx->E == 0) return;
+    hipStream_t s = (hipStream_t)stream;
+    char* w = static_cast<char*>(ws);
+    swizzle_w(W, L->dtype, P.K, P.Kp, L->h, w + P.ws_wsw, s);
+    FwdArgs a{};
+    a.at = make_atoms(L, emb);
+    a.rows = idx->rows;
+    a.E = idx->E;
+    a.K = P.K;
+    a.Kp = P.Kp;
+    a.h = L->h;
+    a.TM = P.TM;
+    a.off_x = (int)P.off_x;
+    a.off_y = (int)P.off_y;
+    a.Wsw = w + P.ws_wsw;
+    a.b = b;
+    a.act_pre = L->act_pre;
+    a.sg = Seg{idx->tuple_group, idx->offsets, idx->E};
+    a.sink = Sink{L->agg, L->act_post, out, pre, argmax, false, nullptr};
+    a.carry = reinterpret_cast<float*>(w + P.ws_carry);
+    a.carry_arg = L->agg == RELNN_MAX ? reinterpret_cast<int32_t*>(w + P.ws_carry_arg) : nullptr;
+    a.X = w + P.ws_x;
+    a.Y = reinterpret_cast<float*>(w + P.ws_y);
+    launch_fwd(P, a, L->dtype, plain, s);
+  });
+}
