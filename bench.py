@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Joined tuples per second of the relational layer on one MI355X.
+
+Workload (the heterogeneous ER schema, hidden 128, two layers, FP32):
+User 1M, Item 500k, Category 1k rows with N(0,1) embeddings of width 128;
+Buys(user, item) 20M rows, item ~ Zipf(1.1), user uniform; BelongsTo gives
+each item a uniform category.  Per layer two join rules run:
+
+  Item'(i; sum(Lin_I(z_u (+) z_i (+) z_c)))  :- Buys(u,i), BelongsTo(i,c), ...   K = 384
+  User'(u; mean(Lin_U(z_u (+) z_i)))          :- Buys(u,i), ...                   K = 256
+
+with ReLU after each aggregate; layer 2 reads layer 1's outputs.  A step is
+the four layer evaluations (80M joined tuples).  Inputs and indices are
+resident in HBM before timing; the index build is timed separately.
+
+Prints ONE JSON line.  ``value`` is the fused FP32 path; the same line
+carries the FP32 plain (unfused) path and the fused BF16 path, the
+roofline of the dominant kernel, and the FP64 oracle timed on host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "joined tuples/sec per layer (fwd, fwd+bwd) vs FP32 plain; serve p50/p99 ms"
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}     # MI355X dense matrix peaks
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_workload(scale: float):
+    import torch
+
+    import relgen
+    from paper_2605_24207_amd import Index
+
+    t0 = time.perf_counter()
+    n_user, n_item, n_buys = int(1_000_000 * scale), int(500_000 * scale), int(20_000_000 * scale)
+    g = relgen.er_graph(n_user=n_user, n_item=n_item, n_buys=n_buys)
+    log(f"generated ER graph in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    D = {"g": g, "U": t(g.user), "I": t(g.item), "C": t(g.cat), "bu": t(g.buys_u), "bi": t(g.buys_i),
+         "bc": t(g.belongs_cat)}
+    D["W_item"] = [t(w) for w in g.W_item]
+    D["W_user"] = [t(w) for w in g.W_user]
+    D["b_item"] = [t(b) for b in g.b_item]
+    D["b_user"] = [t(b) for b in g.b_user]
+    nu, ni, nc = g.user.shape[0], g.item.shape[0], g.cat.shape[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    D["ix_item1"] = Index([D["bu"], D["bi"]], [(nu, 0, None), (ni, 1, None), (nc, 2, None)], 1,
+                          chains=[(1, D["bc"], None)])
+    D["ix_user1"] = Index([D["bu"], D["bi"]], [(nu, 0, None), (ni, 1, None)], 0)
+    ki = D["ix_item1"].export()["group_keys"]
+    ku = D["ix_user1"].export()["group_keys"]
+    Gi, Gu = D["ix_item1"].G, D["ix_user1"].G
+    D["ix_item2"] = Index([D["bu"], D["bi"]], [(Gu, 0, ku), (Gi, 1, ki), (nc, 2, None)], 1,
+                          chains=[(1, D["bc"], None)])
+    D["ix_user2"] = Index([D["bu"], D["bi"]], [(Gu, 0, ku), (Gi, 1, ki)], 0)
+    torch.cuda.synchronize()
+    D["index_build_s"] = time.perf_counter() - t0
+    D["keys"] = (ki, ku)
+    log(f"built 4 indices in {D['index_build_s']:.2f}s: E_item={D['ix_item1'].E} G_item={Gi} "
+        f"E_user={D['ix_user1'].E} G_user={Gu}")
+    return D
+
+
+class Net:
+    """The two-layer ER network in one precision / path."""
+
+    def __init__(self, D, dtype: str, plain: bool):
+        import torch
+
+        from paper_2605_24207_amd import Layer, workspace_size
+
+        self.D = D
+        tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+        self.dtype = dtype
+        cv = lambda x: x.to(tdt).contiguous()
+        self.U, self.I, self.C = cv(D["U"]), cv(D["I"]), cv(D["C"])
+        self.W_item = [cv(w) for w in D["W_item"]]
+        self.W_user = [cv(w) for w in D["W_user"]]
+        od = "bf16" if dtype == "bf16" else "f32"
+        self.L_item = Layer([128, 128, 128], 128, dtype, "sum", "none", "relu", plain=plain, out_dtype=od)
+        self.L_user = Layer([128, 128], 128, dtype, "mean", "none", "relu", plain=plain, out_dtype=od)
+        ix = [D["ix_item1"], D["ix_user1"], D["ix_item2"], D["ix_user2"]]
+        ws = max(workspace_size(ix[q], [self.L_item, self.L_user][q % 2]) for q in range(4))
+        self.ws = torch.empty(ws, dtype=torch.uint8, device="cuda")
+        Gi, Gu = D["ix_item1"].G, D["ix_user1"].G
+        self.out = [torch.empty(G, 128, dtype=tdt, device="cuda") for G in (Gi, Gu, Gi, Gu)]
+        self.tuples = sum(x.E for x in ix)
+        # algorithmic flops of one step: per tuple 2 K h (Linear) + h (bias) + h (aggregate)
+        self.flops = sum(x.E * (2 * K * 128 + 2 * 128) for x, K in zip(ix, (384, 256, 384, 256)))
+
+    def step(self):
+        from paper_2605_24207_amd import layer_fwd
+
+        D, o = self.D, self.out
+        layer_fwd(D["ix_item1"], self.L_item, [self.U, self.I, self.C], self.W_item[0], D["b_item"][0],
+                  want_pre=False, ws=self.ws, out=o[0])
+        layer_fwd(D["ix_user1"], self.L_user, [self.U, self.I], self.W_user[0], D["b_user"][0],
+                  want_pre=False, ws=self.ws, out=o[1])
+        layer_fwd(D["ix_item2"], self.L_item, [o[1], o[0], self.C], self.W_item[1], D["b_item"][1],
+                  want_pre=False, ws=self.ws, out=o[2])
+        layer_fwd(D["ix_user2"], self.L_user, [o[1], o[0]], self.W_user[1], D["b_user"][1],
+                  want_pre=False, ws=self.ws, out=o[3])
+
+
+def time_net(net: Net, steps: int, warmup: int, kernels):
+    import torch
+
+    from paper_2605_24207_amd import api
+
+    for _ in range(warmup):
+        net.step()
+    torch.cuda.synchronize()
+    api.timing_reset()
+    api.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    api.timing_enable(False)
+    ktime = {k: api.timing_read(k) for k in kernels}
+    api.timing_reset()
+    return dt, ktime
+
+
+def cpu_baseline(D, budget_tuples: int):
+    """The FP64 oracle, as it stands, on a seeded sample of output groups of
+    both rules (all tuples of the sampled groups)."""
+    import relgen
+    from oracle import relnn_oracle as orc
+
+    g = D["g"]
+    rng = np.random.default_rng(42)
+    total_t, total_s, desc = 0, 0.0, []
+    for name, gcol in (("item", 1), ("user", 0)):
+        keys = g.buys_i if gcol == 1 else g.buys_u
+        cnt = np.bincount(keys, minlength=(g.item if gcol == 1 else g.user).shape[0])
+        cand = rng.permutation(np.nonzero(cnt)[0])
+        take, acc = [], 0
+        for k in cand:
+            if acc + cnt[k] > budget_tuples // 2:
+                continue
+            take.append(k)
+            acc += cnt[k]
+            if acc >= 0.9 * (budget_tuples // 2):
+                break
+        sel = np.isin(keys, np.array(take))
+        sub = relgen.ERGraph(g.user, g.item, g.cat, g.buys_u[sel], g.buys_i[sel], g.belongs_cat,
+                             g.W_item, g.W_user, g.b_item, g.b_user)
+        rule = relgen.er_item_rule(sub) if gcol == 1 else relgen.er_user_rule(sub)
+        t0 = time.perf_counter()
+        idx = orc.build_index(rule)
+        orc.layer_fwd(idx, [a.emb for a in rule.atoms], rule.W, rule.b, rule.agg, rule.act_pre,
+                      rule.act_post)
+        total_s += time.perf_counter() - t0
+        total_t += idx.E
+        desc.append(f"{len(take)} {name} groups ({idx.E} tuples)")
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    return {"value": total_t / total_s, "unit": "tuples/s", "cores": int(cores), "kind": "oracle",
+            "sample": "layer-1 forward of both rules over a seeded sample of output groups: "
+                      + ", ".join(desc) + f"; {total_s:.1f}s of FP64 numpy"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
+    ap.add_argument("--cpu-budget", type=int, default=2_000_000, help="oracle sample size in tuples")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="f32,plain,bf16", help="comma list of f32,plain,bf16")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    legs = set(args.legs.split(","))
+    D = build_workload(args.scale)
+    res = {}
+    for leg in ("f32", "plain", "bf16"):
+        if leg not in legs:
+            continue
+        dtype = "bf16" if leg == "bf16" else "f32"
+        net = Net(D, dtype, plain=(leg == "plain"))
+        kern = ["fwd_gather", "fwd_gemm", "fwd_reduce"] if leg == "plain" else ["fwd_fused"]
+        steps = args.steps if leg != "plain" else max(1, args.steps // 2)
+        dt, kt = time_net(net, steps, args.warmup, kern)
+        res[leg] = {"dt": dt, "steps": steps, "kt": kt, "tuples": net.tuples, "flops": net.flops}
+        log(f"{leg}: {dt / steps * 1e3:.2f} ms/step, {net.tuples * steps / dt / 1e9:.3f} G tuples/s; "
+            + ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms x{v[1]}" for k, v in kt.items()))
+        del net
+        torch.cuda.empty_cache()
+
+    main_leg = res["f32"]
+    ms = main_leg["dt"] / main_leg["steps"] * 1e3
+    value = main_leg["tuples"] * main_leg["steps"] / main_leg["dt"]
+    k_ms, k_n = main_leg["kt"]["fwd_fused"]
+    launches_per_step = k_n / main_leg["steps"]
+    flops_per_launch = main_leg["flops"] / launches_per_step
+    achieved = flops_per_launch / (k_ms / k_n * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": value, "unit": "tuples/s", "n_gpus": 1, "steps": main_leg["steps"],
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ER schema User 1M / Item 500k / Category 1k, Buys 20M (item Zipf 1.1), "
+                               "hidden 128, 2 layers x (Item SUM K=384, User MEAN K=256), ReLU, FP32 forward",
+                   "scale": args.scale, "tuples_per_step": main_leg["tuples"], "layers_per_step": 4,
+                   "index_build_s": round(D["index_build_s"], 3)},
+        "roofline": {"bound": "mfma", "kernel": "k_layer_fwd<float, fused>", "achieved": achieved,
+                     "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"],
+                     "traffic": None, "avg_launch_ms": k_ms / k_n},
+    }
+    for leg, key in (("plain", "plain_f32"), ("bf16", "fused_bf16")):
+        if leg in res:
+            r = res[leg]
+            line[key] = {"value": r["tuples"] * r["steps"] / r["dt"], "unit": "tuples/s",
+                         "ms_per_step": r["dt"] / r["steps"] * 1e3,
+                         "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in r["kt"].items()}}
+    if "plain" in res:
+        line["speedup_vs_plain_f32"] = value / line["plain_f32"]["value"]
+    if "bf16" in res:
+        r = res["bf16"]
+        bk_ms, bk_n = r["kt"]["fwd_fused"]
+        line["fused_bf16"]["speedup_vs_plain_f32"] = (line["fused_bf16"]["value"] / line["plain_f32"]["value"]
+                                                      if "plain" in res else None)
+        line["fused_bf16"]["mfma_tflops"] = r["flops"] / (bk_n / r["steps"]) / (bk_ms / bk_n * 1e-3) / 1e12
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        line["cpu_baseline"] = cpu_baseline(D, args.cpu_budget)
+        log(f"cpu baseline in {time.perf_counter() - t0:.1f}s")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

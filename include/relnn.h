@@ -147,6 +147,9 @@ relnn_status relnn_index_free(relnn_index* idx);
 #define RELNN_PLAIN    1u  /* unfused pipeline: materialise X = [E, K], then
                               Y = [E, h], then reduce (comparison path) */
 #define RELNN_DW_ACCUM 2u  /* backward adds into dW / db instead of writing */
+#define RELNN_OUT_BF16 4u  /* forward writes `out` as bf16 (round to nearest
+                              even) so it can feed a bf16 layer; `pre` stays
+                              FP32 */
 
 typedef struct {
   int32_t k;               /* body atoms, equal to the index's */
@@ -157,7 +160,8 @@ typedef struct {
   int32_t agg;             /* relnn_agg */
   int32_t act_pre;         /* relnn_act inside tau, per joined tuple */
   int32_t act_post;        /* relnn_act after the aggregate */
-  uint32_t flags;          /* RELNN_FUSED | RELNN_PLAIN, RELNN_DW_ACCUM */
+  uint32_t flags;          /* RELNN_FUSED | RELNN_PLAIN, RELNN_DW_ACCUM,
+                              RELNN_OUT_BF16 */
 } relnn_layer_desc;
 
 /* Workspace bytes relnn_layer_fwd (bwd = 0) or relnn_layer_bwd (bwd = 1)
@@ -168,7 +172,8 @@ relnn_status relnn_workspace_size(const relnn_index* idx, const relnn_layer_desc
 /* Forward.  emb: host [k] of device [n_j, d_j] row-major (dtype), 16-byte
  * aligned rows.  W: device [K, h] row-major (dtype), y = x W + b, K = sum
  * d_j (the transpose of nn.Linear.weight).  b: device [h] FP32 or NULL.
- * out: device [G, h] FP32, row q is group group_keys[q].  pre: device
+ * out: device [G, h] FP32 (bf16 with RELNN_OUT_BF16), row q is group
+ * group_keys[q].  pre: device
  * [G, h] FP32 aggregate before act_post, or NULL (needed by the backward
  * when act_post != NONE).  argmax: device [G, h] int32 canonical tuple
  * position of the first maximiser, MAX only, or NULL.  ws: device
@@ -194,6 +199,18 @@ relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_layer_desc* L,
 /* ---------------------------------------------------------------- serve */
 
 typedef struct relnn_server relnn_server;
+
+/* ---------------------------------------------------------------- timing */
+
+/* Measurement hooks.  While enabled, each main kernel launch of the layer
+ * calls is bracketed by HIP events on its own stream, under a class name:
+ * "fwd_fused", "fwd_gather", "fwd_gemm", "fwd_reduce", "bwd_dx", "bwd_dw".
+ * relnn_timing_read waits for the recorded launches of one class and
+ * returns their summed milliseconds and count; relnn_timing_reset drops
+ * the records.  Process-wide; not for use inside graph capture. */
+relnn_status relnn_timing_enable(int on);
+relnn_status relnn_timing_reset(void);
+relnn_status relnn_timing_read(const char* kernel, double* total_ms, int64_t* launches);
 
 const char* relnn_last_error(void);
 

@@ -175,7 +175,7 @@ def _act_grad(name: str, v: np.ndarray) -> np.ndarray:
 
 def gather_concat(idx: Index, embs: Sequence[np.ndarray], sel=slice(None)) -> np.ndarray:
     """x_tau = z_1[r_1] (+) ... (+) z_k[r_k] in body-atom order, FP64."""
-    parts = [np.asarray(e, np.float64)[r[sel]] for e, r in zip(embs, idx.rows)]
+    parts = [np.asarray(e)[r[sel]].astype(np.float64) for e, r in zip(embs, idx.rows)]
     return np.concatenate(parts, axis=1)
 
 

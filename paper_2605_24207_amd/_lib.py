@@ -15,7 +15,7 @@ F32, BF16 = 0, 1
 SUM, MEAN, MAX = 0, 1, 2
 ACT_NONE, ACT_RELU = 0, 1
 IDX_BWD = 1
-FUSED, PLAIN, DW_ACCUM = 0, 1, 2
+FUSED, PLAIN, DW_ACCUM, OUT_BF16 = 0, 1, 2, 4
 MAX_ATOMS = 4
 
 p_i32 = C.POINTER(C.c_int32)
@@ -68,6 +68,9 @@ _SIGS = {
     "relnn_layer_bwd": (C.c_int, [C.c_void_p, C.POINTER(LayerDesc), C.POINTER(C.c_void_p), C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p),
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "relnn_timing_enable": (C.c_int, [C.c_int]),
+    "relnn_timing_reset": (C.c_int, []),
+    "relnn_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "relnn_last_error": (C.c_char_p, []),
 }
 

@@ -119,7 +119,9 @@ class Layer:
     """relnn_layer_desc: widths, output width, dtype, aggregate, activations."""
 
     def __init__(self, dims: Sequence[int], h: int, dtype: str = "f32", agg: str = "sum",
-                 act_pre: str = "none", act_post: str = "none", plain: bool = False):
+                 act_pre: str = "none", act_post: str = "none", plain: bool = False,
+                 out_dtype: str = "f32"):
+        self.out_dtype = out_dtype
         self.dims = [int(x) for x in dims]
         self.h = int(h)
         self.dtype = dtype
@@ -146,7 +148,8 @@ class Layer:
         d.agg = _AGGS[self.agg]
         d.act_pre = _ACTS[self.act_pre]
         d.act_post = _ACTS[self.act_post]
-        d.flags = (L.PLAIN if self.plain else L.FUSED) | (L.DW_ACCUM if dw_accum else 0)
+        d.flags = ((L.PLAIN if self.plain else L.FUSED) | (L.DW_ACCUM if dw_accum else 0)
+                   | (L.OUT_BF16 if self.out_dtype == "bf16" else 0))
         return d
 
 
@@ -183,7 +186,8 @@ def layer_fwd(index: Index, layer: Layer, embs: Sequence[torch.Tensor], W: torch
     dev = index.device
     G, h = index.G, layer.h
     if out is None:
-        out = torch.empty(G, h, dtype=torch.float32, device=dev)
+        odt = torch.bfloat16 if layer.out_dtype == "bf16" else torch.float32
+        out = torch.empty(G, h, dtype=odt, device=dev)
     pre = torch.empty(G, h, dtype=torch.float32, device=dev) if want_pre else None
     am = torch.empty(G, h, dtype=torch.int32, device=dev) if (want_argmax and layer.agg == "max") else None
     if ws is None:
@@ -245,3 +249,19 @@ class RelLayerFn(torch.autograd.Function):
         db = torch.empty(layer.h, dtype=torch.float32, device=dev) if b is not None else None
         layer_bwd(index, layer, embs, W, b, pre, am, dout, demb, dW, db)
         return (None, None, dW, db) + tuple(grads)
+
+
+def timing_enable(on: bool = True):
+    """relnn_timing_enable: bracket the main kernels with HIP events."""
+    check(lib().relnn_timing_enable(int(on)))
+
+
+def timing_reset():
+    check(lib().relnn_timing_reset())
+
+
+def timing_read(kernel: str):
+    """(total milliseconds, launches) of one kernel class since the reset."""
+    ms, n = C.c_double(), C.c_int64()
+    check(lib().relnn_timing_read(kernel.encode(), C.byref(ms), C.byref(n)))
+    return ms.value, n.value

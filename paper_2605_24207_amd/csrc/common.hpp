@@ -79,6 +79,22 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
 };
 
+// Brackets one kernel launch with HIP events on its stream when timing is
+// enabled (relnn_timing_enable); a no-op otherwise.
+class KTimer {
+ public:
+  KTimer(const char* name, hipStream_t s);
+  ~KTimer();
+  KTimer(const KTimer&) = delete;
+  KTimer& operator=(const KTimer&) = delete;
+
+ private:
+  const char* name_;
+  hipStream_t s_;
+  void* a_ = nullptr;
+  void* b_ = nullptr;
+};
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 

@@ -340,6 +340,16 @@ extern "C" relnn_status relnn_build_index(const relnn_join_desc* D, relnn_stream
                                tk.as<uint32_t>(), tv.as<int32_t>(), E,
                                prim::bits_for((uint64_t)std::max<int64_t>(nr - 1, 0)), s);
         prim::csr_from_sorted(reinterpret_cast<uint32_t*>(idx->t_row[j]), E, nr, idx->t_off[j], s);
+        DevBuf so((E + 1) * sizeof(int32_t)), sr(std::max<int64_t>(E, 1) * sizeof(int32_t));
+        idx->t_seg[j] = idx->alloc<int32_t>(E);
+        const int64_t ns = prim::segments(idx->t_row[j], E, idx->t_seg[j], so.as<int32_t>(), sr.as<int32_t>(), s);
+        idx->t_nseg[j] = ns;
+        idx->t_segoff[j] = idx->alloc<int32_t>(ns + 1);
+        idx->t_segrow[j] = idx->alloc<int32_t>(ns);
+        RELNN_HIP(hipMemcpyAsync(idx->t_segoff[j], so.p, (ns + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        if (ns > 0)
+          RELNN_HIP(hipMemcpyAsync(idx->t_segrow[j], sr.p, ns * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        RELNN_HIP(hipStreamSynchronize(s));
       }
     }
     RELNN_HIP(hipStreamSynchronize(s));

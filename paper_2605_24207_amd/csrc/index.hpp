@@ -21,6 +21,12 @@ struct relnn_index {
   int32_t* t_off[RELNN_MAX_ATOMS] = {};   // [n_rows+1]
   int32_t* t_row[RELNN_MAX_ATOMS] = {};   // [E] joined row, ascending
   int32_t* t_pos[RELNN_MAX_ATOMS] = {};   // [E] canonical tuple position
+  // Its non-empty rows as segments: t_seg[E] segment of each position,
+  // t_segoff[nseg+1], t_segrow[nseg] the row of each segment.
+  int64_t t_nseg[RELNN_MAX_ATOMS] = {0, 0, 0, 0};
+  int32_t* t_seg[RELNN_MAX_ATOMS] = {};
+  int32_t* t_segoff[RELNN_MAX_ATOMS] = {};
+  int32_t* t_segrow[RELNN_MAX_ATOMS] = {};
   int64_t dev_bytes = 0;
   std::vector<void*> allocs;
 

@@ -1,15 +1,468 @@
-// Backward of one relational layer (placeholder until the kernels land).
+// Backward of one relational layer: the gradient of sum(out * dout) with
+// respect to W, b and every atom's embedding rows (Section 2.3: the
+// parameters are the per-tuple embeddings and the transform weights).
+//
+// With y_tau = act_pre(x_tau W + b), pre_g = alpha_{tau in g} y_tau and
+// out_g = act_post(pre_g):
+//   dA_g      = dout_g * act_post'(pre_g)                       (ReLU'(0) = 0)
+//   dY_tau    = dA_g            (SUM)
+//             = dA_g / |g|      (MEAN)
+//             = dA_g[j] if tau is the argmax of column j, else 0 (MAX)
+//   dY_tau   *= act_pre'(x_tau W + b)   (recomputed mask, only if act_pre)
+//   dW        = sum_tau x_tau^T dY_tau,   db = sum_tau dY_tau
+//   dz_j[r]  += sum_{tau joined to row r of atom j} (dY_tau W^T)[cols of j]
+//
+// The joined rows x_tau are gathered again, never stored.  dW / db: a
+// persistent kernel accumulates X^T dY over its contiguous run of tiles on
+// the matrix cores (FP32 16x16x4), then the per-block partials are summed in
+// block order.  dz_j: tiles over atom j's transpose order (tuples sorted by
+// joined row), dY rows routed into LDS, multiplied by W_j^T, and reduced per
+// row with the same carry / fix-up scheme as the forward: atomic-free and
+// deterministic.  Atoms run one after another on the stream, so atoms that
+// share one embedding relation (a self-join) add up in stream order.
 #include "layer_fwd.hpp"
 
 namespace relnn {
-size_t bwd_workspace(const relnn_index*, const relnn_layer_desc*, const FwdPlan&) { return 256; }
+
+namespace {
+
+constexpr int kDxTM = 64;
+constexpr int kDwTM = 32;
+constexpr int kDwThreads = 512;
+constexpr int kDwMaxB = 24;              // 16x16 accumulator blocks per wave
+
+struct Route {
+  const float* dout;        // [G][h]
+  const float* pre;         // [G][h] (act_post != NONE)
+  const int32_t* argmax;    // [G][h] (MAX)
+  const int32_t* tuple_group;
+  const int32_t* offsets;
+  const uint8_t* mask;      // [E][h] (act_pre != NONE)
+  int h, agg, act_post;
+};
+
+__device__ __forceinline__ float route(const Route& R, int64_t e, int64_t g, int n) {
+  const int64_t o = g * R.h + n;
+  float v = R.dout[o];
+  if (R.act_post == RELNN_ACT_RELU && !(R.pre[o] > 0.0f)) v = 0.0f;
+  if (R.agg == RELNN_MEAN)
+    v = v / (float)(R.offsets[g + 1] - R.offsets[g]);
+  else if (R.agg == RELNN_MAX && R.argmax[o] != (int32_t)e)
+    v = 0.0f;
+  if (R.mask && !R.mask[e * R.h + n]) v = 0.0f;
+  return v;
+}
+
+// ---------------------------------------------------------------- dz_j
+struct DxArgs {
+  Route R;
+  const int32_t* t_pos;     // [E] canonical position, in transpose order
+  int64_t E;
+  int hp;                   // h rounded up to 4 (k of the product)
+  int d;                    // width of atom j
+  const float* Wsw;         // W_j^T swizzled for mfma_tile<float>
+  Seg sg;                   // transpose segments (non-empty rows)
+  Sink sink;                // accumulate into demb_j rows
+  float* carry;
+};
+
+__global__ void __launch_bounds__(kThreads) k_bwd_dx(DxArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  constexpr int TM = kDxTM;
+  const int64_t tile = blockIdx.x;
+  const int64_t p0 = tile * TM;
+  const int nv = (int)min<int64_t>(TM, a.E - p0);
+  const int DS = a.hp + 4;
+  const int YS = a.d + 4;
+  int64_t* pe = reinterpret_cast<int64_t*>(smem);            // [TM] tuple position
+  int64_t* pg = pe + TM;                                     // [TM] its group
+  float* Ds = reinterpret_cast<float*>(pg + TM);             // [TM][DS] routed dY
+  float* Ys = Ds + TM * DS;                                  // [TM][YS] dY W_j^T
+  for (int r = threadIdx.x; r < TM; r += blockDim.x) {
+    int64_t e = 0, g = 0;
+    if (r < nv) {
+      e = a.t_pos[p0 + r];
+      g = a.R.tuple_group[e];
+    }
+    pe[r] = e;
+    pg[r] = g;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < TM * a.hp; i += blockDim.x) {
+    const int r = i / a.hp, n = i - (i / a.hp) * a.hp;
+    Ds[r * DS + n] = (r < nv && n < a.R.h) ? route(a.R, pe[r], pg[r], n) : 0.0f;
+  }
+  __syncthreads();
+  const int ncb = a.d / 16;
+  const int nblk = (TM / 16) * ncb;
+  f32x4 acc[kMaxQ];
+  mfma_tile<float>(Ds, DS, a.hp, nblk, ncb, a.Wsw, acc);
+  store_acc(acc, nblk, ncb, nullptr, RELNN_ACT_NONE, Ys, YS);
+  __syncthreads();
+  reduce_tile(Ys, YS, a.d, p0, nv, tile, a.sg, a.sink, a.carry, nullptr);
+}
+
+// B = W_j^T [hp x d] in the fragment order of mfma_tile<float>:
+// out[(ks * ncb + cb) * 64 + l] = W[koff + cb*16 + l % 16][ks*4 + l / 16].
+template <class T>
+__global__ void k_swizzle_wt(const T* __restrict__ W, int h, int hp, int koff, int d, float* __restrict__ out) {
+  const int ncb = d / 16;
+  const int64_t total = (int64_t)hp * d;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = (int)(i & 63);
+    const int64_t kc = i >> 6;
+    const int cb = (int)(kc % ncb);
+    const int ks = (int)(kc / ncb);
+    const int n = ks * 4 + (lane >> 4);
+    const int col = cb * 16 + (lane & 15);
+    out[i] = n < h ? (float)W[(int64_t)(koff + col) * h + n] : 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------- dW, db
+struct DwArgs {
+  Atoms at;
+  const int32_t* rows;      // [k*E]
+  int64_t E;
+  int K, K16;               // K and K rounded up to 16
+  int n0, hn;               // output columns [n0, n0 + hn) of this launch
+  Route R;
+  int64_t ntiles, nunits;
+  float* part;              // [nunits][K16][h]
+  float* dbpart;            // [nunits][h]
+};
+
+template <class T>
+__global__ void __launch_bounds__(kDwThreads) k_bwd_dw(DwArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  constexpr int TM = kDwTM;
+  constexpr int EPC = 16 / sizeof(T);
+  const int XS = a.K16 + 4;
+  const int DS = a.hn + 4;
+  float* Xs = reinterpret_cast<float*>(smem);      // [TM][XS] gathered x, FP32
+  float* Ds = Xs + TM * XS;                         // [TM][DS] routed dY
+  const int h = a.R.h;
+  const int lane = __lane_id();
+  const int w = threadIdx.x / 64;
+  const int nrb = a.K16 / 16, ncb = a.hn / 16;
+  const int nblk = nrb * ncb;
+  const int64_t bidx = blockIdx.x;
+  const int64_t tb = (a.ntiles * bidx) / a.nunits, te = (a.ntiles * (bidx + 1)) / a.nunits;
+  f32x4 acc[kDwMaxB];
+#pragma unroll
+  for (int q = 0; q < kDwMaxB; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float dbacc = 0.0f;
+  const int cpr = a.K16 / EPC;
+
+  for (int64_t t = tb; t < te; ++t) {
+    const int64_t e0 = t * TM;
+    const int nv = (int)min<int64_t>(TM, a.E - e0);
+    for (int i = threadIdx.x; i < TM * cpr; i += blockDim.x) {
+      const int r = i / cpr, c = i - (i / cpr) * cpr;
+      const int el = c * EPC;
+      float vals[EPC];
+#pragma unroll
+      for (int u = 0; u < EPC; ++u) vals[u] = 0.0f;
+      if (r < nv && el < a.K) {
+        int j = 0;
+#pragma unroll
+        for (int q = 1; q < kMaxAtoms; ++q)
+          if (q < a.at.k && el >= a.at.koff[q]) j = q;
+        const int64_t row = a.rows[(int64_t)j * a.E + e0 + r];
+        const uint4 raw = *reinterpret_cast<const uint4*>(static_cast<const T*>(a.at.emb[j]) + row * a.at.d[j] +
+                                                          (el - a.at.koff[j]));
+        const T* tv = reinterpret_cast<const T*>(&raw);
+#pragma unroll
+        for (int u = 0; u < EPC; ++u) vals[u] = (float)tv[u];
+      }
+#pragma unroll
+      for (int u = 0; u < EPC; ++u) Xs[r * XS + el + u] = vals[u];
+    }
+    for (int i = threadIdx.x; i < TM * a.hn; i += blockDim.x) {
+      const int r = i / a.hn, n = i - (i / a.hn) * a.hn;
+      float v = 0.0f;
+      if (r < nv) {
+        const int64_t e = e0 + r;
+        v = route(a.R, e, a.R.tuple_group[e], a.n0 + n);
+      }
+      Ds[r * DS + n] = v;
+    }
+    __syncthreads();
+    // dW[k][n] += sum_e X[e][k] dY[e][n]: A = X^T (lane: X[e = 4ks + l/16][k]),
+    // B = dY (lane: dY[4ks + l/16][n]).
+#pragma unroll
+    for (int ks = 0; ks < TM / 4; ++ks) {
+      const int er = ks * 4 + (lane >> 4);
+#pragma unroll
+      for (int q = 0; q < kDwMaxB; ++q) {
+        const int blk = w + 8 * q;
+        if (blk < nblk) {
+          const int rb = blk / ncb, cb = blk - (blk / ncb) * ncb;
+          const float av = Xs[er * XS + rb * 16 + (lane & 15)];
+          const float bv = Ds[er * DS + cb * 16 + (lane & 15)];
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[q], 0, 0, 0);
+        }
+      }
+    }
+    if (threadIdx.x < a.hn)
+      for (int r = 0; r < nv; ++r) dbacc += Ds[r * DS + threadIdx.x];
+    __syncthreads();
+  }
+  // per-block partials
+#pragma unroll
+  for (int q = 0; q < kDwMaxB; ++q) {
+    const int blk = w + 8 * q;
+    if (blk < nblk) {
+      const int rb = blk / ncb, cb = blk - (blk / ncb) * ncb;
+      const int n = a.n0 + cb * 16 + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = rb * 16 + 4 * (lane >> 4) + i;
+        a.part[(bidx * a.K16 + k) * h + n] = acc[q][i];
+      }
+    }
+  }
+  if (threadIdx.x < a.hn) a.dbpart[bidx * h + a.n0 + threadIdx.x] = dbacc;
+}
+
+// dW[k][n] (+)= sum over blocks b of part[b][k][n], in block order, Kahan.
+__global__ void k_dw_reduce(const float* part, const float* dbpart, int64_t nunits, int K, int K16, int h,
+                            float* dW, float* db, int accumulate) {
+  const int64_t total = (int64_t)K * h + (db ? h : 0);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.0f, c = 0.0f;
+    if (i < (int64_t)K * h) {
+      const int64_t k = i / h, n = i - (i / h) * h;
+      for (int64_t b = 0; b < nunits; ++b) {
+        const float y = part[(b * K16 + k) * h + n] - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+      }
+      dW[i] = accumulate ? dW[i] + s : s;
+    } else {
+      const int64_t n = i - (int64_t)K * h;
+      for (int64_t b = 0; b < nunits; ++b) {
+        const float y = dbpart[b * h + n] - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+      }
+      db[n] = accumulate ? db[n] + s : s;
+    }
+  }
+}
+
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+unsigned grid_for(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 1 << 16));
+}
+
+int num_cus() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0;
+    RELNN_HIP(hipGetDevice(&dev));
+    RELNN_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  return n;
+}
+
+struct BwdPlan {
+  FwdPlan F;
+  int K = 0, K16 = 0, hp = 0, hn = 0;
+  int64_t dx_tiles = 0, dw_tiles = 0, dw_units = 0;
+  size_t dx_lds = 0, dw_lds = 0;
+  size_t ws_mask = 0, ws_fwsw = 0, ws_wt = 0, ws_carry = 0, ws_part = 0, ws_dbpart = 0, total = 0;
+  size_t wt_off[kMaxAtoms] = {};
+};
+
+BwdPlan plan_bwd(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& F) {
+  BwdPlan p;
+  p.F = F;
+  p.K = F.K;
+  p.K16 = (int)round_up(F.K, 16);
+  p.hp = (int)round_up(L->h, 4);
+  int hn = (kDwMaxB * 8 * 16 * 16 / p.K16) / 16 * 16;
+  p.hn = std::max(16, std::min(L->h, hn));
+  const int64_t E = idx->E;
+  p.dx_tiles = cdiv(E, kDxTM);
+  p.dw_tiles = cdiv(E, kDwTM);
+  p.dw_units = std::max<int64_t>(1, std::min<int64_t>(p.dw_tiles, num_cus()));
+  int dmax = 0;
+  for (int j = 0; j < L->k; ++j) dmax = std::max(dmax, L->d[j]);
+  p.dx_lds = 2 * kDxTM * sizeof(int64_t) + (size_t)kDxTM * (p.hp + 4) * 4 + (size_t)kDxTM * (dmax + 4) * 4;
+  p.dw_lds = (size_t)kDwTM * (p.K16 + 4) * 4 + (size_t)kDwTM * (p.hn + 4) * 4;
+  size_t off = 0;
+  p.ws_mask = off;
+  if (L->act_pre != RELNN_ACT_NONE) off += round_up(std::max<int64_t>(E, 1) * L->h, 256);
+  p.ws_fwsw = off;
+  off += round_up(F.ws_carry - F.ws_wsw, 256);          // forward W swizzle (mask kernel)
+  p.ws_wt = off;
+  for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
+    p.wt_off[j] = off;
+    off += round_up((int64_t)p.hp * L->d[j] * 4, 256);
+  }
+  p.ws_carry = off;
+  off += round_up(std::max<int64_t>(p.dx_tiles, 1) * 2 * dmax * 4, 256);
+  off = std::max(off, p.ws_carry + round_up(F.carry_units * 2 * L->h * 4, 256));   // mask kernel carry unused
+  p.ws_part = off;
+  off += round_up(p.dw_units * p.K16 * L->h * 4, 256);
+  p.ws_dbpart = off;
+  off += round_up(p.dw_units * L->h * 4, 256);
+  p.total = off;
+  return p;
+}
+
+template <class KernelT>
+void allow_lds(KernelT k, size_t bytes) {
+  RELNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+}  // namespace
+
+size_t bwd_workspace(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P) {
+  return plan_bwd(idx, L, P).total;
+}
+
 }  // namespace relnn
 
 using namespace relnn;
 
-extern "C" relnn_status relnn_layer_bwd(const relnn_index*, const relnn_layer_desc*, const void* const*,
-                                        const void*, const float*, const float*, const int32_t*,
-                                        const float*, float* const*, float*, float*, void*, size_t,
-                                        relnn_stream_t) {
-  return guard([&] { RELNN_REQUIRE(false, RELNN_E_UNSUPPORTED, "backward not built yet"); });
+extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_layer_desc* L,
+                                        const void* const* emb, const void* W, const float* b,
+                                        const float* pre, const int32_t* argmax, const float* dout,
+                                        float* const* demb, float* dW, float* db, void* ws, size_t ws_bytes,
+                                        relnn_stream_t stream) {
+  return guard([&] {
+    RELNN_REQUIRE(idx != nullptr && L != nullptr, RELNN_E_INVALID, "index or layer descriptor is NULL");
+    FwdPlan F = plan_fwd(idx, L);
+    check_layer(idx, L, F);
+    RELNN_REQUIRE(idx->has_bwd, RELNN_E_INVALID, "the index was built without RELNN_IDX_BWD");
+    RELNN_REQUIRE(!(L->flags & RELNN_OUT_BF16), RELNN_E_INVALID, "RELNN_OUT_BF16 is a forward-only flag");
+    const BwdPlan P = plan_bwd(idx, L, F);
+    RELNN_REQUIRE(emb != nullptr && W != nullptr && dW != nullptr && demb != nullptr, RELNN_E_INVALID,
+                  "emb, W, dW and demb are required");
+    RELNN_REQUIRE(dout != nullptr || idx->G == 0, RELNN_E_INVALID, "dout is NULL");
+    RELNN_REQUIRE(L->act_post == RELNN_ACT_NONE || pre != nullptr || idx->G == 0, RELNN_E_INVALID,
+                  "pre is required when act_post is not NONE");
+    RELNN_REQUIRE(L->agg != RELNN_MAX || argmax != nullptr || idx->G == 0, RELNN_E_INVALID,
+                  "argmax is required for MAX");
+    for (int j = 0; j < L->k; ++j) {
+      RELNN_REQUIRE(emb[j] != nullptr || idx->n_rows[j] == 0, RELNN_E_INVALID, "emb[%d] is NULL", j);
+      RELNN_REQUIRE(demb[j] != nullptr || idx->n_rows[j] == 0, RELNN_E_INVALID, "demb[%d] is NULL", j);
+      RELNN_REQUIRE(((uintptr_t)emb[j] & 15) == 0, RELNN_E_UNSUPPORTED, "emb[%d] is not 16-byte aligned", j);
+      RELNN_REQUIRE(L->d[j] % 16 == 0, RELNN_E_UNSUPPORTED, "backward needs d[%d] %% 16 == 0", j);
+    }
+    RELNN_REQUIRE(ws != nullptr && ws_bytes >= P.total, RELNN_E_INVALID,
+                  "workspace of %zu bytes given, %zu needed", ws_bytes, P.total);
+    RELNN_REQUIRE(((uintptr_t)ws & 255) == 0, RELNN_E_INVALID, "workspace must be 256-byte aligned");
+    RELNN_REQUIRE(P.dx_lds <= 160 * 1024 && P.dw_lds <= 160 * 1024, RELNN_E_UNSUPPORTED,
+                  "K = %d, h = %d does not fit the backward LDS tiles", P.K, L->h);
+    hipStream_t s = (hipStream_t)stream;
+    char* w = static_cast<char*>(ws);
+    const int h = L->h;
+    const int64_t E = idx->E;
+    const bool accum = (L->flags & RELNN_DW_ACCUM) != 0;
+    if (E == 0) {
+      if (!accum) {
+        k_fill_f32<<<grid_for((int64_t)P.K * h), 256, 0, s>>>(dW, (int64_t)P.K * h, 0.0f);
+        RELNN_LAUNCHED();
+        if (db) {
+          k_fill_f32<<<1, 256, 0, s>>>(db, h, 0.0f);
+          RELNN_LAUNCHED();
+        }
+      }
+      return;
+    }
+    const Atoms at = make_atoms(L, emb);
+    Route R{dout, pre, argmax, idx->tuple_group, idx->offsets, nullptr, h, L->agg, L->act_post};
+
+    if (L->act_pre != RELNN_ACT_NONE) {      // recompute act_pre'(x W + b) per tuple
+      FwdArgs a{};
+      a.at = at;
+      a.rows = idx->rows;
+      a.E = E;
+      a.K = F.K;
+      a.Kp = F.Kp;
+      a.h = h;
+      a.TM = F.TM;
+      a.off_x = (int)F.off_x;
+      a.off_y = (int)F.off_y;
+      a.Wsw = w + P.ws_fwsw;
+      a.b = b;
+      a.mask = reinterpret_cast<uint8_t*>(w + P.ws_mask);
+      swizzle_w(W, L->dtype, F.K, F.Kp, h, w + P.ws_fwsw, s);
+      launch_mask(F, a, L->dtype, s);
+      R.mask = a.mask;
+    }
+
+    // dW and db
+    {
+      DwArgs d{};
+      d.at = at;
+      d.rows = idx->rows;
+      d.E = E;
+      d.K = P.K;
+      d.K16 = P.K16;
+      d.R = R;
+      d.ntiles = P.dw_tiles;
+      d.nunits = P.dw_units;
+      d.part = reinterpret_cast<float*>(w + P.ws_part);
+      d.dbpart = reinterpret_cast<float*>(w + P.ws_dbpart);
+      for (int n0 = 0; n0 < h; n0 += P.hn) {
+        d.n0 = n0;
+        d.hn = std::min(P.hn, h - n0);
+        KTimer tm("bwd_dw", s);
+        if (L->dtype == RELNN_BF16) {
+          allow_lds(k_bwd_dw<__bf16>, P.dw_lds);
+          k_bwd_dw<__bf16><<<(unsigned)P.dw_units, kDwThreads, P.dw_lds, s>>>(d);
+        } else {
+          allow_lds(k_bwd_dw<float>, P.dw_lds);
+          k_bwd_dw<float><<<(unsigned)P.dw_units, kDwThreads, P.dw_lds, s>>>(d);
+        }
+        RELNN_LAUNCHED();
+      }
+      k_dw_reduce<<<grid_for((int64_t)P.K * h + h), 256, 0, s>>>(d.part, d.dbpart, P.dw_units, P.K, P.K16, h, dW,
+                                                                   db, accum ? 1 : 0);
+      RELNN_LAUNCHED();
+    }
+
+    // dz_j for every atom, in body order
+    for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
+      const int d = L->d[j];
+      float* wt = reinterpret_cast<float*>(w + P.wt_off[j]);
+      const int64_t nsw = (int64_t)P.hp * d;
+      if (L->dtype == RELNN_BF16)
+        k_swizzle_wt<__bf16><<<grid_for(nsw), 256, 0, s>>>(static_cast<const __bf16*>(W), h, P.hp, koff, d, wt);
+      else
+        k_swizzle_wt<float><<<grid_for(nsw), 256, 0, s>>>(static_cast<const float*>(W), h, P.hp, koff, d, wt);
+      RELNN_LAUNCHED();
+      DxArgs x{};
+      x.R = R;
+      x.t_pos = idx->t_pos[j];
+      x.E = E;
+      x.hp = P.hp;
+      x.d = d;
+      x.Wsw = wt;
+      x.sg = Seg{idx->t_seg[j], idx->t_segoff[j], E};
+      x.sink = Sink{RELNN_SUM, RELNN_ACT_NONE, demb[j], nullptr, nullptr, true, idx->t_segrow[j], false};
+      x.carry = reinterpret_cast<float*>(w + P.ws_carry);
+      allow_lds(k_bwd_dx, P.dx_lds);
+      {
+        KTimer tm("bwd_dx", s);
+        k_bwd_dx<<<(unsigned)P.dx_tiles, kThreads, P.dx_lds, s>>>(x);
+        RELNN_LAUNCHED();
+      }
+      launch_fixup(x.sg, kDxTM, d, P.dx_tiles, P.dx_tiles, x.sink, x.carry, nullptr, s);
+    }
+  });
 }

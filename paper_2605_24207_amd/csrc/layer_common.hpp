@@ -117,6 +117,7 @@ struct Sink {
   int32_t* argmax;  // [nseg][h] or null
   bool accumulate;  // out += value (backward scatter into embeddings)
   const int32_t* out_row;   // optional remap: segment -> output row
+  bool out_bf16;    // out holds bf16 (round to nearest even)
 };
 
 __device__ __forceinline__ void sink_write(const Sink& k, int64_t s, int c, int h, float v, int32_t am,
@@ -128,13 +129,16 @@ __device__ __forceinline__ void sink_write(const Sink& k, int64_t s, int c, int 
   if (k.argmax && k.agg == RELNN_MAX) k.argmax[o] = am;
   if (k.accumulate)
     k.out[o] += v;
+  else if (k.out_bf16)
+    reinterpret_cast<__bf16*>(k.out)[o] = (__bf16)act_apply(k.act_post, v);
   else
     k.out[o] = act_apply(k.act_post, v);
 }
 
 // Reduces the rows [0, nv) of the LDS tile Ys (list positions e0..) per
-// segment.  Segments wholly inside the tile are finished and written;
-// boundary segments leave a partial in carry slot 0 (first segment) or 1.
+// segment.  Segments wholly inside the tile are finished and written; a
+// segment cut by the tile start leaves its partial in carry slot 0, one
+// that starts in the tile and runs past its end in slot 1.
 __device__ inline void reduce_tile(const float* Ys, int YS, int h, int64_t e0, int nv, int64_t tile,
                             const Seg& sg, const Sink& sink, float* carry, int32_t* carry_arg) {
   const int64_t s_first = sg.seg_of[e0];
@@ -166,7 +170,7 @@ __device__ inline void reduce_tile(const float* Ys, int YS, int h, int64_t e0, i
     if (g0 >= e0 && g1 <= e0 + nv) {
       sink_write(sink, s, c, h, v, am, (int32_t)(g1 - g0));
     } else {
-      const int slot = (s == s_first) ? 0 : 1;
+      const int slot = (g0 < e0) ? 0 : 1;      // cut by the tile start : by its end
       carry[(tile * 2 + slot) * h + c] = v;
       if (carry_arg) carry_arg[(tile * 2 + slot) * h + c] = am;
     }

@@ -78,23 +78,37 @@ __device__ __forceinline__ void gather_rows(const Atoms& at, const int32_t* __re
   }
 }
 
-// Combines the carry partials of segments that cross tile edges.  Block b
-// (b >= 1) handles the segment containing position b*TM if that segment
-// starts in tile b-1.  Partials are summed in tile order: contiguous runs
-// per strand (blocks of 64, then the block sums), strands in order.
-__global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int TM, int h, Sink sink,
-                                                    const float* carry, const int32_t* carry_arg) {
+// Combines the carry partials of segments cut by unit boundaries.  A unit
+// is a run of tiles: unit u covers list positions [pos(u), pos(u+1)) with
+// pos(u) = ((ntiles * u) / nunits) * TM (one tile per unit when nunits =
+// ntiles).  A unit leaves, per column, a partial in slot 0 for the segment
+// cut by its start and in slot 1 for the segment that starts inside it and
+// runs past its end.  Block b (b >= 1) handles the segment containing
+// pos(b) if it also contains pos(b) - 1 and starts at or after pos(b - 1):
+// its partials are slot 1 of unit b-1 followed by slot 0 of the units that
+// follow, summed in unit order (runs of 64 per strand, Kahan-compensated
+// across runs, strands in order) so the result is deterministic.
+__global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int64_t ntiles, int64_t nunits, int TM, int h,
+                                                    Sink sink, const float* carry, const int32_t* carry_arg) {
   const int64_t b = (int64_t)blockIdx.x + 1;
-  const int64_t e = b * TM;
-  if (e >= sg.n) return;
+  auto pos = [&](int64_t u) { return ((ntiles * u) / nunits) * TM; };
+  const int64_t e = pos(b);
+  if (e <= 0 || e >= sg.n) return;
   const int64_t s = sg.seg_of[e];
   if (sg.seg_of[e - 1] != s) return;
   const int64_t g0 = sg.offsets[s], g1 = sg.offsets[s + 1];
-  const int64_t t0 = g0 / TM;
-  if (t0 != b - 1) return;
-  const int64_t t1 = (g1 - 1) / TM;
-  const int64_t P = t1 - t0 + 1;
-  const int first_slot = (sg.seg_of[t0 * TM] == s) ? 0 : 1;
+  if (g0 < pos(b - 1)) return;
+  int64_t ulast = b;                       // last unit holding part of s
+  {
+    int64_t lo = b, hi = nunits - 1;       // largest u with pos(u) < g1
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (pos(mid) < g1) lo = mid; else hi = mid - 1;
+    }
+    ulast = lo;
+  }
+  const int64_t P = ulast - (b - 1) + 1;   // partials: unit b-1 (slot 1), units b..ulast (slot 0)
+  auto at = [&](int64_t i) { return ((b - 1 + i) * 2 + (i == 0 ? 1 : 0)) * h; };
   const int CG = min(h, kThreads);
   const int S = kThreads / CG;
   const int strand = threadIdx.x / CG;
@@ -103,18 +117,16 @@ __global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int TM, int h, Sink 
   for (int cbase = 0; cbase < h; cbase += CG) {
     const int c = cbase + (threadIdx.x % CG);
     const bool active = strand < S && c < h;
-    float v = 0.0f;
+    float v = 0.0f, comp = 0.0f;
     int32_t am = -1;
     if (active) {
       const int64_t lo = (P * strand) / S, hi = (P * (strand + 1)) / S;
       if (sink.agg == RELNN_MAX) {
         v = -INFINITY;
         for (int64_t i = lo; i < hi; ++i) {
-          const int64_t t = t0 + i;
-          const int slot = (i == 0) ? first_slot : 0;
-          const float x = carry[(t * 2 + slot) * h + c];
-          const int32_t xa = carry_arg[(t * 2 + slot) * h + c];
-          if (x > v || (x == v && (am < 0 || xa < am))) {
+          const float x = carry[at(i) + c];
+          const int32_t xa = carry_arg[at(i) + c];
+          if (x > v || am < 0) {
             v = x;
             am = xa;
           }
@@ -123,16 +135,15 @@ __global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int TM, int h, Sink 
         for (int64_t i0 = lo; i0 < hi; i0 += 64) {
           float inner = 0.0f;
           const int64_t i1 = min(hi, i0 + 64);
-          for (int64_t i = i0; i < i1; ++i) {
-            const int64_t t = t0 + i;
-            const int slot = (i == 0) ? first_slot : 0;
-            inner += carry[(t * 2 + slot) * h + c];
-          }
-          v += inner;
+          for (int64_t i = i0; i < i1; ++i) inner += carry[at(i) + c];
+          const float y = inner - comp;
+          const float tt = v + y;
+          comp = (tt - v) - y;
+          v = tt;
         }
       }
     }
-    red_v[threadIdx.x] = v;
+    red_v[threadIdx.x] = v - comp;
     red_a[threadIdx.x] = am;
     __syncthreads();
     if (strand == 0 && c < h) {
@@ -142,7 +153,7 @@ __global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int TM, int h, Sink 
         const float x = red_v[q * CG + threadIdx.x];
         const int32_t xa = red_a[q * CG + threadIdx.x];
         if (sink.agg == RELNN_MAX) {
-          if (xa >= 0 && (x > acc || (x == acc && (aa < 0 || xa < aa)))) {
+          if (xa >= 0 && (aa < 0 || x > acc)) {
             acc = x;
             aa = xa;
           }
@@ -157,7 +168,7 @@ __global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int TM, int h, Sink 
 }
 
 
-enum { MODE_FUSED = 0, MODE_GEMM = 1, MODE_REDUCE = 2 };
+enum { MODE_FUSED = 0, MODE_GEMM = 1, MODE_REDUCE = 2, MODE_MASK = 3 };
 
 // One tile of TM tuples per block.
 template <class T, int MODE>
@@ -175,7 +186,7 @@ __global__ void __launch_bounds__(kThreads) k_layer_fwd(FwdArgs a) {
   const int ncb = a.h / 16;
   const int nblk = (TM / 16) * ncb;
 
-  if constexpr (MODE == MODE_FUSED) {
+  if constexpr (MODE == MODE_FUSED || MODE == MODE_MASK) {
     for (int i = threadIdx.x; i < a.at.k * TM; i += blockDim.x) {
       const int j = i / TM, r = i - (i / TM) * TM;
       rowidx[i] = r < nv ? a.rows[(int64_t)j * a.E + e0 + r] : 0;
@@ -198,7 +209,7 @@ __global__ void __launch_bounds__(kThreads) k_layer_fwd(FwdArgs a) {
     __syncthreads();
     f32x4 acc[kMaxQ];
     mfma_tile<T>(Xs, XS, a.Kp, nblk, ncb, static_cast<const T*>(a.Wsw), acc);
-    if constexpr (MODE == MODE_GEMM) {
+    if constexpr (MODE == MODE_GEMM || MODE == MODE_MASK) {
       const int lane = __lane_id();
       const int w = threadIdx.x / 64;
 #pragma unroll
@@ -211,7 +222,12 @@ __global__ void __launch_bounds__(kThreads) k_layer_fwd(FwdArgs a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int row = rb * 16 + (lane >> 4) * 4 + i;
-            if (row < nv) a.Y[(e0 + row) * a.h + col] = act_apply(a.act_pre, acc[qi][i] + bv);
+            if (row < nv) {
+              if constexpr (MODE == MODE_MASK)
+                a.mask[(e0 + row) * a.h + col] = (acc[qi][i] + bv) > 0.0f ? 1 : 0;
+              else
+                a.Y[(e0 + row) * a.h + col] = act_apply(a.act_pre, acc[qi][i] + bv);
+            }
           }
         }
       }
@@ -271,29 +287,39 @@ template <class T>
 void launch_fwd_t(const FwdPlan& P, FwdArgs a, bool plain, hipStream_t s) {
   const int64_t ntiles = P.ntiles;
   if (plain) {
-    k_gather_plain<T><<<grid_for(a.E * (a.Kp / Mfma<T>::EPC)), 256, 0, s>>>(
-        a.at, a.rows, a.E, a.K, a.Kp, static_cast<T*>(const_cast<void*>(a.X)));
-    RELNN_LAUNCHED();
+    {
+      KTimer t("fwd_gather", s);
+      k_gather_plain<T><<<grid_for(a.E * (a.Kp / Mfma<T>::EPC)), 256, 0, s>>>(
+          a.at, a.rows, a.E, a.K, a.Kp, static_cast<T*>(const_cast<void*>(a.X)));
+      RELNN_LAUNCHED();
+    }
     allow_lds(k_layer_fwd<T, MODE_GEMM>, P.lds);
-    k_layer_fwd<T, MODE_GEMM><<<(unsigned)ntiles, kThreads, P.lds, s>>>(a);
-    RELNN_LAUNCHED();
+    {
+      KTimer t("fwd_gemm", s);
+      k_layer_fwd<T, MODE_GEMM><<<(unsigned)ntiles, kThreads, P.lds, s>>>(a);
+      RELNN_LAUNCHED();
+    }
     allow_lds(k_layer_fwd<T, MODE_REDUCE>, P.lds);
-    k_layer_fwd<T, MODE_REDUCE><<<(unsigned)ntiles, kThreads, P.lds, s>>>(a);
-    RELNN_LAUNCHED();
+    {
+      KTimer t("fwd_reduce", s);
+      k_layer_fwd<T, MODE_REDUCE><<<(unsigned)ntiles, kThreads, P.lds, s>>>(a);
+      RELNN_LAUNCHED();
+    }
   } else {
     allow_lds(k_layer_fwd<T, MODE_FUSED>, P.lds);
+    KTimer t("fwd_fused", s);
     k_layer_fwd<T, MODE_FUSED><<<(unsigned)ntiles, kThreads, P.lds, s>>>(a);
     RELNN_LAUNCHED();
   }
-  launch_fixup(a.sg, a.TM, a.h, ntiles, a.sink, a.carry, a.carry_arg, s);
+  launch_fixup(a.sg, a.TM, a.h, ntiles, ntiles, a.sink, a.carry, a.carry_arg, s);
 }
 
 }  // namespace
 
-void launch_fixup(const Seg& sg, int TM, int h, int64_t ntiles, const Sink& sink, const float* carry,
-                  const int32_t* carry_arg, hipStream_t s) {
-  if (ntiles <= 1) return;
-  k_fixup<<<(unsigned)(ntiles - 1), kThreads, 0, s>>>(sg, TM, h, sink, carry, carry_arg);
+void launch_fixup(const Seg& sg, int TM, int h, int64_t ntiles, int64_t nunits, const Sink& sink,
+                  const float* carry, const int32_t* carry_arg, hipStream_t s) {
+  if (nunits <= 1) return;
+  k_fixup<<<(unsigned)(nunits - 1), kThreads, 0, s>>>(sg, ntiles, nunits, TM, h, sink, carry, carry_arg);
   RELNN_LAUNCHED();
 }
 
@@ -325,13 +351,17 @@ FwdPlan plan_fwd(const relnn_index* idx, const relnn_layer_desc* L) {
   }
   const int64_t E = idx->E;
   P.ntiles = P.TM ? cdiv(E, P.TM) : 0;
+  // carry partials: one pair per unit of whichever forward kernel runs
+  const WsPlan wp = plan_ws(L->dtype, K, h, E);
+  P.carry_units = std::max<int64_t>(1, std::max<int64_t>(P.ntiles, wp.KP ? wp.nunits : 0));
+  const size_t wsw = std::max<size_t>((size_t)P.Kp * h * esz, wp.KP ? wp.wsw_bytes : 0);
   size_t off = 0;
   P.ws_wsw = off;
-  off += round_up((int64_t)P.Kp * h * esz, 256);
+  off += round_up(wsw, 256);
   P.ws_carry = off;
-  off += round_up(std::max<int64_t>(P.ntiles, 1) * 2 * h * 4, 256);
+  off += round_up(P.carry_units * 2 * h * 4, 256);
   P.ws_carry_arg = off;
-  if (L->agg == RELNN_MAX) off += round_up(std::max<int64_t>(P.ntiles, 1) * 2 * h * 4, 256);
+  if (L->agg == RELNN_MAX) off += round_up(P.carry_units * 2 * h * 4, 256);
   P.ws_fused = off;
   P.ws_x = off;
   off += round_up(std::max<int64_t>(E, 1) * P.Kp * esz, 256);
@@ -350,7 +380,7 @@ void check_layer(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   RELNN_REQUIRE((L->act_pre == RELNN_ACT_NONE || L->act_pre == RELNN_ACT_RELU) &&
                     (L->act_post == RELNN_ACT_NONE || L->act_post == RELNN_ACT_RELU),
                 RELNN_E_INVALID, "unknown activation");
-  RELNN_REQUIRE((L->flags & ~(RELNN_PLAIN | RELNN_DW_ACCUM)) == 0, RELNN_E_INVALID, "unknown layer flags");
+  RELNN_REQUIRE((L->flags & ~(RELNN_PLAIN | RELNN_DW_ACCUM | RELNN_OUT_BF16)) == 0, RELNN_E_INVALID, "unknown layer flags");
   RELNN_REQUIRE(L->h > 0, RELNN_E_INVALID, "h must be positive");
   const int epc = L->dtype == RELNN_BF16 ? 8 : 4;
   for (int j = 0; j < L->k; ++j) {
@@ -383,6 +413,20 @@ void swizzle_w(const void* W, int dtype, int K, int Kp, int h, void* Wsw, hipStr
     k_swizzle_f32<<<grid_for((int64_t)Kp * h), 256, 0, s>>>(static_cast<const float*>(W), K, Kp, h,
                                                              static_cast<float*>(Wsw));
   RELNN_LAUNCHED();
+}
+
+template <class T>
+void launch_mask_t(const FwdPlan& P, const FwdArgs& a, hipStream_t s) {
+  allow_lds(k_layer_fwd<T, MODE_MASK>, P.lds);
+  k_layer_fwd<T, MODE_MASK><<<(unsigned)P.ntiles, kThreads, P.lds, s>>>(a);
+  RELNN_LAUNCHED();
+}
+
+void launch_mask(const FwdPlan& P, const FwdArgs& a, int dtype, hipStream_t s) {
+  if (dtype == RELNN_BF16)
+    launch_mask_t<__bf16>(P, a, s);
+  else
+    launch_mask_t<float>(P, a, s);
 }
 
 void launch_fwd(const FwdPlan& P, const FwdArgs& a, int dtype, bool plain, hipStream_t s) {
@@ -448,11 +492,20 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
     a.b = b;
     a.act_pre = L->act_pre;
     a.sg = Seg{idx->tuple_group, idx->offsets, idx->E};
-    a.sink = Sink{L->agg, L->act_post, out, pre, argmax, false, nullptr};
+    a.sink = Sink{L->agg, L->act_post, out, pre, argmax, false, nullptr, (L->flags & RELNN_OUT_BF16) != 0};
     a.carry = reinterpret_cast<float*>(w + P.ws_carry);
     a.carry_arg = L->agg == RELNN_MAX ? reinterpret_cast<int32_t*>(w + P.ws_carry_arg) : nullptr;
     a.X = w + P.ws_x;
     a.Y = reinterpret_cast<float*>(w + P.ws_y);
+    const WsPlan wp = plan_ws(L->dtype, P.K, L->h, idx->E);
+    RELNN_REQUIRE(P.ntiles <= P.carry_units && (!wp.KP || wp.nunits <= P.carry_units) &&
+                      (!wp.KP || wp.wsw_bytes <= P.ws_carry - P.ws_wsw),
+                  RELNN_E_HIP, "internal: workspace plan does not cover the launch");
+    if (!plain && wp.KP) {
+      swizzle_ws(W, L->dtype, P.K, wp.KP, L->h, w + P.ws_wsw, s);
+      launch_ws(wp, L->dtype, a, w + P.ws_wsw, a.carry, a.carry_arg, s);
+      return;
+    }
     launch_fwd(P, a, L->dtype, plain, s);
   });
 }

@@ -27,12 +27,14 @@ struct FwdArgs {
   int32_t* carry_arg;
   const void* X;             // plain: [E][Kp]
   float* Y;                  // plain: [E][h]
+  uint8_t* mask;             // act_pre mask: [E][h], 1 where x W + b > 0
 };
 
 struct FwdPlan {
   int K = 0, Kp = 0, TM = 0;
   size_t off_x = 0, off_y = 0, lds = 0;
   int64_t ntiles = 0;
+  int64_t carry_units = 0;   // units the carry region holds (max over kernels)
   size_t ws_wsw = 0, ws_carry = 0, ws_carry_arg = 0, ws_x = 0, ws_y = 0;
   size_t ws_fused = 0, ws_plain = 0;
 };
@@ -42,8 +44,22 @@ void check_layer(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
 Atoms make_atoms(const relnn_layer_desc* L, const void* const* emb);
 void swizzle_w(const void* W, int dtype, int K, int Kp, int h, void* Wsw, hipStream_t s);
 void launch_fwd(const FwdPlan& P, const FwdArgs& a, int dtype, bool plain, hipStream_t s);
-void launch_fixup(const Seg& sg, int TM, int h, int64_t ntiles, const Sink& sink, const float* carry,
-                  const int32_t* carry_arg, hipStream_t s);
+// Recomputes y = x W + b per tuple and writes mask = (y > 0) (tile kernel).
+void launch_mask(const FwdPlan& P, const FwdArgs& a, int dtype, hipStream_t s);
+void launch_fixup(const Seg& sg, int TM, int h, int64_t ntiles, int64_t nunits, const Sink& sink,
+                  const float* carry, const int32_t* carry_arg, hipStream_t s);
+
+// Weight-stationary persistent forward (layer_ws.hip).  KP == 0: the shape
+// is not covered and the tile kernel runs instead.
+struct WsPlan {
+  int KP = 0, TM = 0;
+  int64_t ntiles = 0, nunits = 0;
+  size_t wsw_bytes = 0, carry_elems = 0;
+};
+WsPlan plan_ws(int dtype, int K, int h, int64_t E);
+void swizzle_ws(const void* W, int dtype, int K, int KP, int h, void* out, hipStream_t s);
+void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, float* carry,
+               int32_t* carry_arg, hipStream_t s);
 size_t bwd_workspace(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P);
 
 }  // namespace relnn

@@ -143,11 +143,12 @@ def test_fwd_empty_join():
     assert res["out"].shape == (0, rule.h)
 
 
-def test_plain_and_fused_agree_bitwise():
+def test_plain_and_fused_agree():
+    """Same FP32 arithmetic in a different k order: agreement to rounding."""
     rule = relgen.node_edge(seed=10, n_nodes=400, n_edges=9000, bias_std=0.1)
     a = gpu_fwd(rule, "f32", plain=False)
     b = gpu_fwd(rule, "f32", plain=True)
-    np.testing.assert_array_equal(a["pre"], b["pre"])
+    assert rel_rows(a["pre"], b["pre"]).max() <= 2e-6
 
 
 def test_deterministic_and_permutation_invariant():
@@ -159,3 +160,24 @@ def test_deterministic_and_permutation_invariant():
     rule.cols = [c[p] for c in rule.cols]
     c = gpu_fwd(rule, "f32")
     np.testing.assert_array_equal(a["pre"], c["pre"])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("agg", ["sum", "max"])
+@pytest.mark.parametrize("plain", [False, True])
+def test_workspace_is_not_overrun(dtype, agg, plain):
+    """Kernels stay inside the workspace relnn_workspace_size reports: a
+    sentinel region right after it must survive the call."""
+    import torch
+
+    from paper_2605_24207_amd import layer_fwd, workspace_size
+    from tests.helpers import distinct_embs, gpu_layer, to_dev
+
+    rule = relgen.node_edge(seed=13, n_nodes=700, n_edges=20_000, agg=agg)
+    idx = gpu_index(rule)
+    layer = gpu_layer(rule, dtype, plain)
+    n = workspace_size(idx, layer)
+    buf = torch.full((n + 65536,), 0xAB, dtype=torch.uint8, device="cuda")
+    layer_fwd(idx, layer, distinct_embs(rule, dtype), to_dev(rule.W, dtype), to_dev(rule.b), ws=buf[:n])
+    torch.cuda.synchronize()
+    assert bool((buf[n:] == 0xAB).all())
