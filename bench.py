@@ -139,6 +139,134 @@ def time_net(net: Net, steps: int, warmup: int, kernels):
     return dt, ktime
 
 
+def fwd_bwd_leg(steps: int, warmup: int, scale: float):
+    """Differentiation form: Node [2M, 128], Edge 10M with s ~ Zipf(1.2), t
+    uniform; layer 1 SUM + ReLU, layer 2 MAX, MSE against N(0,1) targets.  A
+    step is forward and backward of both layers through RelLayerFn (20M
+    joined tuples, each through fwd + bwd)."""
+    import torch
+
+    import relgen
+    from paper_2605_24207_amd import Index, Layer, RelLayerFn, api
+
+    p = relgen.power_graph(n_nodes=int(2_000_000 * scale), n_edges=int(10_000_000 * scale))
+    dev = "cuda"
+    s = torch.from_numpy(p.s).to(dev)
+    t = torch.from_numpy(p.t).to(dev)
+    n = p.z.shape[0]
+    ix1 = Index([s, t], [(n, 0, None), (n, 1, None)], 1, bwd=True)
+    k1 = ix1.export()["group_keys"]
+    ix2 = Index([s, t], [(ix1.G, 0, k1), (ix1.G, 1, k1)], 1, bwd=True)
+    L1 = Layer([128, 128], 128, "f32", "sum", "none", "relu")
+    L2 = Layer([128, 128], 128, "f32", "max", "none", "none")
+    z = torch.from_numpy(p.z).to(dev).requires_grad_(True)
+    W1 = torch.from_numpy(p.W[0]).to(dev).requires_grad_(True)
+    W2 = torch.from_numpy(p.W[1]).to(dev).requires_grad_(True)
+    b1 = torch.from_numpy(p.b[0]).to(dev).requires_grad_(True)
+    b2 = torch.from_numpy(p.b[1]).to(dev).requires_grad_(True)
+    target = torch.from_numpy(p.target).to(dev)[ix2.export()["group_keys"].long()].contiguous()
+
+    def step():
+        for x in (z, W1, W2, b1, b2):
+            x.grad = None
+        h1 = RelLayerFn.apply(ix1, L1, W1, b1, z, z)
+        h2 = RelLayerFn.apply(ix2, L2, W2, b2, h1, h1)
+        ((h2 - target) ** 2).mean().backward()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    api.timing_reset()
+    api.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    api.timing_enable(False)
+    kt = {k: api.timing_read(k) for k in ("fwd_fused", "bwd_dw", "bwd_dx")}
+    api.timing_reset()
+    tuples = ix1.E + ix2.E
+    return {"value": tuples * steps / dt, "unit": "tuples/s (fwd+bwd, per layer)", "ms_per_step": dt / steps * 1e3,
+            "workload": "Node 2M x 128, Edge 10M (s ~ Zipf 1.2, t uniform); L1 SUM+ReLU, L2 MAX; MSE; FP32",
+            "tuples_per_step": tuples, "steps": steps,
+            "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in kt.items()}}
+
+
+def serve_leg(D, dtype: str, rates, seconds: float):
+    """Serving form: the resident ER graph, seed-item requests with sizes
+    log-uniform over 1..4096, two hops with fanout 15 then 10, open-loop
+    Poisson arrivals at each rate for ``seconds``; HBM budget 64 GiB.
+    Latency = done - arrival, from the library's steady-clock stamps."""
+    import threading
+
+    import torch
+
+    import relgen
+    from paper_2605_24207_amd import Server
+
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    cv = lambda x: x.to(tdt).contiguous()
+    srv = Server(D["bu"], D["bi"], D["bc"], cv(D["U"]), cv(D["I"]), cv(D["C"]), cv(D["W_user"][0]),
+                 cv(D["W_item"][0]), cv(D["W_item"][1]), dtype=dtype, max_seeds=4096, max_slots=64,
+                 budget_bytes=64 << 30)
+    n_items = D["I"].shape[0]
+    warm = relgen.request_stream(n_items, 8, 1000.0, seed=1)
+    for r in warm:
+        srv.wait(srv.submit(r.seeds, r.req_seed), len(r.seeds))
+    res = []
+    for rate in rates:
+        reqs = relgen.request_stream(n_items, max(1, int(rate * seconds)), rate, seed=int(rate))
+        tickets = [None] * len(reqs)
+        t0 = time.perf_counter()
+
+        def submitter():
+            for q, r in enumerate(reqs):
+                dt = r.t_arrive - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[q] = srv.submit(r.seeds, r.req_seed)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        done, lat, tuples, first, last = set(), [], 0, None, None
+        while len(done) < len(reqs):
+            for q, t in enumerate(tickets):
+                if t is None or q in done:
+                    continue
+                r = srv.poll(t, len(reqs[q].seeds))
+                if r is None:
+                    continue
+                st = r[2]
+                done.add(q)
+                lat.append((st["t_done_ns"] - st["t_arrive_ns"]) * 1e-6)
+                tuples += st["tuples"]
+                first = st["t_arrive_ns"] if first is None else min(first, st["t_arrive_ns"])
+                last = st["t_done_ns"] if last is None else max(last, st["t_done_ns"])
+            time.sleep(0.0002)
+        th.join()
+        lat = np.array(lat)
+        res.append({"rate_req_s": rate, "requests": len(reqs), "p50_ms": float(np.percentile(lat, 50)),
+                    "p99_ms": float(np.percentile(lat, 99)), "tuples_per_s": tuples / ((last - first) * 1e-9),
+                    "mean_seeds": float(np.mean([len(r.seeds) for r in reqs]))})
+        log(f"serve {dtype} {rate} req/s: p50 {res[-1]['p50_ms']:.2f} ms, p99 {res[-1]['p99_ms']:.2f} ms, "
+            f"{res[-1]['tuples_per_s'] / 1e6:.1f} M tuples/s")
+    srv.close()
+    return res
+
+
+def copy_calibration(gib: float):
+    """A plain device copy of known size, for scaling HBM byte counters."""
+    import torch
+
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
+
+
 def cpu_baseline(D, budget_tuples: int):
     """The FP64 oracle, as it stands, on a seeded sample of output groups of
     both rules (all tuples of the sampled groups)."""
@@ -189,8 +317,16 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
     ap.add_argument("--cpu-budget", type=int, default=2_000_000, help="oracle sample size in tuples")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="f32,plain,bf16", help="comma list of f32,plain,bf16")
+    ap.add_argument("--legs", default="f32,plain,bf16,serve,fwdbwd",
+                    help="comma list of f32,plain,bf16,serve,fwdbwd")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per serving rate")
+    ap.add_argument("--serve-rates", default="200,500,1000,2000", help="Poisson arrival rates (req/s)")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only run a plain copy of this many GiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_gib > 0:
+        copy_calibration(args.copy_gib)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
@@ -248,9 +384,23 @@ def main():
         line["fused_bf16"]["speedup_vs_plain_f32"] = (line["fused_bf16"]["value"] / line["plain_f32"]["value"]
                                                       if "plain" in res else None)
         line["fused_bf16"]["mfma_tflops"] = r["flops"] / (bk_n / r["steps"]) / (bk_ms / bk_n * 1e-3) / 1e12
+    if "serve" in legs:
+        rates = [float(x) for x in args.serve_rates.split(",")]
+        line["serve"] = {"workload": "resident ER graph (Buys 20M); requests of log-uniform 1..4096 seed items, "
+                                     "fanout 15 then 10, Poisson arrivals; budget 64 GiB",
+                         "fused_f32": serve_leg(D, "f32", rates, args.serve_seconds),
+                         "fused_bf16": serve_leg(D, "bf16", rates, args.serve_seconds)}
+    g_host = D["g"]
+    if "fwdbwd" in legs:
+        del D
+        torch.cuda.empty_cache()
+        fb = fwd_bwd_leg(max(1, args.steps // 2), args.warmup, args.scale)
+        line["fwd_bwd_f32"] = fb
+        log(f"fwd+bwd: {fb['ms_per_step']:.2f} ms/step, {fb['value'] / 1e9:.3f} G tuples/s; " +
+            ", ".join(f"{k} {v:.3f} ms" for k, v in fb["kernels_ms_per_launch"].items()))
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        line["cpu_baseline"] = cpu_baseline(D, args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline({"g": g_host}, args.cpu_budget)
         log(f"cpu baseline in {time.perf_counter() - t0:.1f}s")
     print(json.dumps(line), flush=True)
 

@@ -198,7 +198,91 @@ relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_layer_desc* L,
 
 /* ---------------------------------------------------------------- serve */
 
+/* Serving of the two-layer ER network on sampled neighbourhoods.  The
+ * paper trains whole graphs; sampling and mini-batches are its stated
+ * future work (Section 6).  A request is a set of seed Items and a seed for
+ * the sampler; its result is one h-wide embedding per seed:
+ *
+ *   hop 1: for each seed item s, up to fanout1 of its buyers (Buys rows
+ *          with item = s, ordered by user then row), without replacement;
+ *   hop 2: for each sampled buyer u, up to fanout2 of u's Buys rows
+ *          (ordered by item then row);
+ *   layer 1: User'(u)  = ReLU(MEAN over u's hop-2 rows of Lin_U(z_u (+) z_i)),
+ *            Item'(s)  = ReLU(SUM over s's hop-1 rows of Lin_I1(z_u (+) z_s (+) z_c(s)));
+ *   layer 2: out(s)    = ReLU(SUM over s's hop-1 rows of
+ *                             Lin_I2(User'(u) (+) Item'(s) (+) z_c(s))).
+ *
+ * Each join above is the layer of relnn_layer_fwd on the sampled link
+ * rows; a User' value is computed for every hop-1 row that samples u (the
+ * sampler is keyed by (request seed, hop, node), so copies agree).
+ * Sampling: k of n positions by Floyd's algorithm; draw number q of the
+ * stream for (req_seed, hop, node) is SplitMix64's output function applied
+ * to base + (q + 1) * 0x9E3779B97F4A7C15, base = mix(req_seed +
+ * (2 * node + hop + 1) * 0x9E3779B97F4A7C15); a draw r in [0, j] is
+ * ((r >> 32) * (j + 1)) >> 32.  The sampled positions are sorted.
+ *
+ * Continuous batching: a scheduler thread runs steps back to back; each
+ * step admits waiting requests in arrival order while their seeds fit the
+ * step's capacity (sized from budget_bytes) and max_slots, runs one
+ * captured hipGraph over all of them, and completes them together.
+ * Requests that arrive during a step join a later step. */
+typedef struct {
+  int64_t n_user, n_item, n_cat, n_buys;
+  const int32_t* buys_user;        /* device [n_buys] Buys.user (dense ids) */
+  const int32_t* buys_item;        /* device [n_buys] Buys.item */
+  const int32_t* item_cat;         /* device [n_item] BelongsTo.cat */
+  const void* user_emb;            /* device [n_user, d] (dtype) */
+  const void* item_emb;            /* device [n_item, d] */
+  const void* cat_emb;             /* device [n_cat, d] */
+  int32_t d, h;                    /* input and hidden width (d == h) */
+  const void* W_user;              /* device [2d, h] layer-1 User rule */
+  const void* W_item1;             /* device [3d, h] layer-1 Item rule */
+  const void* W_item2;             /* device [2h + d, h] layer-2 Item rule */
+  const float* b_user;             /* device [h] or NULL (each bias) */
+  const float* b_item1;
+  const float* b_item2;
+  int32_t fanout1, fanout2;        /* 1..32 each (15 and 10) */
+  int32_t dtype;                   /* relnn_dtype of embeddings and weights */
+  int32_t max_seeds;               /* largest request (seeds) */
+  int32_t max_slots;               /* requests per step */
+  size_t budget_bytes;             /* device bytes for in-flight work */
+} relnn_serve_desc;
+
+typedef struct {
+  int64_t t_arrive_ns;             /* submit (steady clock) */
+  int64_t t_admit_ns;              /* its step started */
+  int64_t t_done_ns;               /* its step's results were on the host */
+  int64_t tuples;                  /* joined tuples evaluated for it */
+  int64_t step;                    /* step number it ran in */
+  int32_t n_seeds;
+} relnn_req_stats;
+
 typedef struct relnn_server relnn_server;
+
+/* Builds the item and user adjacency (CSR) of Buys on the device, swizzles
+ * the weights and allocates the step buffers (library-owned, counted
+ * against budget_bytes), then starts the scheduler thread.  The resident
+ * relations and weights stay caller-owned and must outlive the server.
+ * RELNN_E_OOM if budget_bytes cannot hold one largest request. */
+relnn_status relnn_serve_create(const relnn_serve_desc* desc, relnn_server** out);
+
+/* Queues a request: seeds host [n] distinct item ids (an id outside
+ * 0..n_item-1 has no neighbourhood and no output), 1 <= n <= max_seeds.
+ * Returns a ticket at once.  RELNN_E_RANGE if n is out of range,
+ * RELNN_E_BUSY if the queue is full. */
+relnn_status relnn_serve_submit(relnn_server* srv, const int32_t* seeds, int32_t n, uint64_t req_seed,
+                                uint64_t* ticket);
+
+/* Non-blocking.  RELNN_E_NOT_READY until the request's step is done; then
+ * fills out host [n, h] FP32, present host [n] (0 for a seed with no
+ * buyer: its row is zero) and stats (any may be NULL) and forgets the
+ * ticket.  RELNN_E_INVALID for an unknown ticket. */
+relnn_status relnn_serve_poll(relnn_server* srv, uint64_t ticket, float* out, uint8_t* present,
+                              relnn_req_stats* stats);
+
+/* Stops the scheduler after the step in flight and frees everything the
+ * server owns.  Requests not yet polled are dropped. */
+relnn_status relnn_serve_destroy(relnn_server* srv);
 
 /* ---------------------------------------------------------------- timing */
 

@@ -44,6 +44,22 @@ class LayerDesc(C.Structure):
                 ("flags", C.c_uint32)]
 
 
+class ServeDesc(C.Structure):
+    _fields_ = [("n_user", C.c_int64), ("n_item", C.c_int64), ("n_cat", C.c_int64), ("n_buys", C.c_int64),
+                ("buys_user", C.c_void_p), ("buys_item", C.c_void_p), ("item_cat", C.c_void_p),
+                ("user_emb", C.c_void_p), ("item_emb", C.c_void_p), ("cat_emb", C.c_void_p),
+                ("d", C.c_int32), ("h", C.c_int32),
+                ("W_user", C.c_void_p), ("W_item1", C.c_void_p), ("W_item2", C.c_void_p),
+                ("b_user", C.c_void_p), ("b_item1", C.c_void_p), ("b_item2", C.c_void_p),
+                ("fanout1", C.c_int32), ("fanout2", C.c_int32), ("dtype", C.c_int32),
+                ("max_seeds", C.c_int32), ("max_slots", C.c_int32), ("budget_bytes", C.c_size_t)]
+
+
+class ReqStats(C.Structure):
+    _fields_ = [("t_arrive_ns", C.c_int64), ("t_admit_ns", C.c_int64), ("t_done_ns", C.c_int64),
+                ("tuples", C.c_int64), ("step", C.c_int64), ("n_seeds", C.c_int32)]
+
+
 class RelnnError(RuntimeError):
     def __init__(self, status: int, msg: str):
         name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
@@ -68,6 +84,10 @@ _SIGS = {
     "relnn_layer_bwd": (C.c_int, [C.c_void_p, C.POINTER(LayerDesc), C.POINTER(C.c_void_p), C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p),
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "relnn_serve_create": (C.c_int, [C.POINTER(ServeDesc), C.POINTER(C.c_void_p)]),
+    "relnn_serve_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_uint64, C.POINTER(C.c_uint64)]),
+    "relnn_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.POINTER(ReqStats)]),
+    "relnn_serve_destroy": (C.c_int, [C.c_void_p]),
     "relnn_timing_enable": (C.c_int, [C.c_int]),
     "relnn_timing_reset": (C.c_int, []),
     "relnn_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),

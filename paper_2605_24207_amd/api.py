@@ -265,3 +265,86 @@ def timing_read(kernel: str):
     ms, n = C.c_double(), C.c_int64()
     check(lib().relnn_timing_read(kernel.encode(), C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+class Server:
+    """relnn_serve_*: continuous-batching server of the two-layer ER network
+    on sampled two-hop neighbourhoods (semantics in include/relnn.h).
+
+    The resident tensors (Buys columns, BelongsTo, embeddings, weights) stay
+    owned by the caller; this object keeps references to them."""
+
+    def __init__(self, buys_user, buys_item, item_cat, user, item, cat, W_user, W_item1, W_item2,
+                 b_user=None, b_item1=None, b_item2=None, fanout1=15, fanout2=10, dtype="f32",
+                 max_seeds=4096, max_slots=64, budget_bytes=64 << 30):
+        import numpy as np
+
+        lib()
+        self._np = np
+        self._keep = [buys_user, buys_item, item_cat, user, item, cat, W_user, W_item1, W_item2,
+                      b_user, b_item1, b_item2]
+        d = L.ServeDesc()
+        d.n_user, d.n_item, d.n_cat = user.shape[0], item.shape[0], cat.shape[0]
+        d.n_buys = buys_user.numel()
+        d.buys_user, d.buys_item, d.item_cat = (_i32(buys_user, "buys_user").data_ptr(),
+                                                _i32(buys_item, "buys_item").data_ptr(),
+                                                _i32(item_cat, "item_cat").data_ptr())
+        d.user_emb, d.item_emb, d.cat_emb = user.data_ptr(), item.data_ptr(), cat.data_ptr()
+        d.d, d.h = user.shape[1], W_user.shape[1]
+        d.W_user, d.W_item1, d.W_item2 = W_user.data_ptr(), W_item1.data_ptr(), W_item2.data_ptr()
+        d.b_user = None if b_user is None else b_user.data_ptr()
+        d.b_item1 = None if b_item1 is None else b_item1.data_ptr()
+        d.b_item2 = None if b_item2 is None else b_item2.data_ptr()
+        d.fanout1, d.fanout2 = fanout1, fanout2
+        d.dtype = _DTYPES[dtype][0]
+        d.max_seeds, d.max_slots, d.budget_bytes = max_seeds, max_slots, int(budget_bytes)
+        self.h = d.h
+        self._handle = None
+        h = C.c_void_p()
+        check(lib().relnn_serve_create(C.byref(d), C.byref(h)))
+        self._handle = h
+
+    def submit(self, seeds, req_seed: int) -> int:
+        np = self._np
+        a = np.ascontiguousarray(seeds, dtype=np.int32)
+        t = C.c_uint64()
+        check(lib().relnn_serve_submit(self._handle, a.ctypes.data_as(C.c_void_p), int(a.size),
+                                       C.c_uint64(req_seed & ((1 << 64) - 1)), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, n: int):
+        """None while not ready, else (out [n, h] float32, present [n] bool, stats dict)."""
+        np = self._np
+        out = np.empty((n, self.h), np.float32)
+        pres = np.empty(n, np.uint8)
+        st = L.ReqStats()
+        r = lib().relnn_serve_poll(self._handle, C.c_uint64(ticket), out.ctypes.data_as(C.c_void_p),
+                                   pres.ctypes.data_as(C.c_void_p), C.byref(st))
+        if r == L.E_NOT_READY:
+            return None
+        check(r)
+        stats = {k: getattr(st, k) for k, _ in L.ReqStats._fields_}
+        return out, pres.astype(bool), stats
+
+    def wait(self, ticket: int, n: int, timeout_s: float = 120.0, poll_s: float = 0.0002):
+        import time
+
+        t0 = time.perf_counter()
+        while True:
+            r = self.poll(ticket, n)
+            if r is not None:
+                return r
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"request {ticket} not done after {timeout_s}s")
+            time.sleep(poll_s)
+
+    def close(self):
+        if self._handle is not None and _lib_alive():
+            check(lib().relnn_serve_destroy(self._handle))
+        self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librelnn.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "prims.hip", "index.hip", "layer_fwd.hip", "layer_ws.hip", "layer_bwd.hip"]
+SOURCES = ["api.cpp", "prims.hip", "index.hip", "layer_fwd.hip", "layer_ws.hip", "layer_bwd.hip", "serve.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",

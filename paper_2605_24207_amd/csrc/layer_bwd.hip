@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(kDwThreads) k_bwd_dw(DwArgs a) {
 #pragma unroll
         for (int q = 1; q < kMaxAtoms; ++q)
           if (q < a.at.k && el >= a.at.koff[q]) j = q;
-        const int64_t row = a.rows[(int64_t)j * a.E + e0 + r];
+        const int64_t row = a.at.rows[j][e0 + r];
         const uint4 raw = *reinterpret_cast<const uint4*>(static_cast<const T*>(a.at.emb[j]) + row * a.at.d[j] +
                                                           (el - a.at.koff[j]));
         const T* tv = reinterpret_cast<const T*>(&raw);
@@ -383,7 +383,7 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
       }
       return;
     }
-    const Atoms at = make_atoms(L, emb);
+    const Atoms at = make_atoms(L, emb, idx);
     Route R{dout, pre, argmax, idx->tuple_group, idx->offsets, nullptr, h, L->agg, L->act_post};
 
     if (L->act_pre != RELNN_ACT_NONE) {      // recompute act_pre'(x W + b) per tuple
@@ -453,7 +453,7 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
       x.hp = P.hp;
       x.d = d;
       x.Wsw = wt;
-      x.sg = Seg{idx->t_seg[j], idx->t_segoff[j], E};
+      x.sg = Seg{idx->t_seg[j], idx->t_segoff[j], E, nullptr};
       x.sink = Sink{RELNN_SUM, RELNN_ACT_NONE, demb[j], nullptr, nullptr, true, idx->t_segrow[j], false};
       x.carry = reinterpret_cast<float*>(w + P.ws_carry);
       allow_lds(k_bwd_dx, P.dx_lds);

@@ -43,6 +43,7 @@ struct Seg {                 // segment structure of a sorted tuple list
   const int32_t* seg_of;     // [n] segment number of each list position
   const int32_t* offsets;    // [nseg+1]
   int64_t n;
+  const int64_t* n_dev;      // if set: n is read from device memory at run time
 };
 
 __device__ __forceinline__ float act_apply(int act, float v) {

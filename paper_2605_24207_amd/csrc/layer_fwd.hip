@@ -91,6 +91,10 @@ __device__ __forceinline__ void gather_rows(const Atoms& at, const int32_t* __re
 __global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int64_t ntiles, int64_t nunits, int TM, int h,
                                                     Sink sink, const float* carry, const int32_t* carry_arg) {
   const int64_t b = (int64_t)blockIdx.x + 1;
+  if (sg.n_dev) {
+    sg.n = *sg.n_dev;
+    ntiles = (sg.n + TM - 1) / TM;
+  }
   auto pos = [&](int64_t u) { return ((ntiles * u) / nunits) * TM; };
   const int64_t e = pos(b);
   if (e <= 0 || e >= sg.n) return;
@@ -189,7 +193,7 @@ __global__ void __launch_bounds__(kThreads) k_layer_fwd(FwdArgs a) {
   if constexpr (MODE == MODE_FUSED || MODE == MODE_MASK) {
     for (int i = threadIdx.x; i < a.at.k * TM; i += blockDim.x) {
       const int j = i / TM, r = i - (i / TM) * TM;
-      rowidx[i] = r < nv ? a.rows[(int64_t)j * a.E + e0 + r] : 0;
+      rowidx[i] = r < nv ? a.at.rows[j][e0 + r] : 0;
     }
     __syncthreads();
     gather_rows<T>(a.at, a.rows, a.E, e0, nv, TM, a.K, a.Kp, Xs, XS, rowidx);
@@ -263,7 +267,7 @@ __global__ void k_gather_plain(Atoms at, const int32_t* __restrict__ rows, int64
 #pragma unroll
       for (int q = 1; q < kMaxAtoms; ++q)
         if (q < at.k && el >= at.koff[q]) j = q;
-      const int64_t row = rows[(int64_t)j * E + e];
+      const int64_t row = at.rows[j][e];
       v = *reinterpret_cast<const uint4*>(static_cast<const T*>(at.emb[j]) + row * at.d[j] + (el - at.koff[j]));
     }
     *reinterpret_cast<uint4*>(X + e * Kp + el) = v;
@@ -392,12 +396,13 @@ void check_layer(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   RELNN_REQUIRE(P.TM > 0, RELNN_E_UNSUPPORTED, "K = %d, h = %d does not fit the LDS tile", P.K, L->h);
 }
 
-Atoms make_atoms(const relnn_layer_desc* L, const void* const* emb) {
+Atoms make_atoms(const relnn_layer_desc* L, const void* const* emb, const relnn_index* idx) {
   Atoms at{};
   at.k = L->k;
   int off = 0;
   for (int j = 0; j < L->k; ++j) {
     at.emb[j] = emb[j];
+    at.rows[j] = idx ? idx->rows + (int64_t)j * idx->E : nullptr;
     at.d[j] = L->d[j];
     at.koff[j] = off;
     off += L->d[j];
@@ -479,7 +484,7 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
     char* w = static_cast<char*>(ws);
     swizzle_w(W, L->dtype, P.K, P.Kp, L->h, w + P.ws_wsw, s);
     FwdArgs a{};
-    a.at = make_atoms(L, emb);
+    a.at = make_atoms(L, emb, idx);
     a.rows = idx->rows;
     a.E = idx->E;
     a.K = P.K;
@@ -491,7 +496,7 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
     a.Wsw = w + P.ws_wsw;
     a.b = b;
     a.act_pre = L->act_pre;
-    a.sg = Seg{idx->tuple_group, idx->offsets, idx->E};
+    a.sg = Seg{idx->tuple_group, idx->offsets, idx->E, nullptr};
     a.sink = Sink{L->agg, L->act_post, out, pre, argmax, false, nullptr, (L->flags & RELNN_OUT_BF16) != 0};
     a.carry = reinterpret_cast<float*>(w + P.ws_carry);
     a.carry_arg = L->agg == RELNN_MAX ? reinterpret_cast<int32_t*>(w + P.ws_carry_arg) : nullptr;

@@ -7,6 +7,7 @@ namespace relnn {
 
 struct Atoms {
   const void* emb[kMaxAtoms];
+  const int32_t* rows[kMaxAtoms];   // [E] joined row of atom j per tuple
   int32_t d[kMaxAtoms];
   int32_t koff[kMaxAtoms];   // first Concat column of atom j
   int32_t k;
@@ -16,6 +17,7 @@ struct FwdArgs {
   Atoms at;
   const int32_t* rows;       // [k*E]
   int64_t E;
+  const int64_t* E_dev;      // if set: E read from device memory at run time
   int K, Kp, h, TM;
   int off_x, off_y;          // LDS byte offsets of Xs / Ys
   const void* Wsw;
@@ -41,7 +43,7 @@ struct FwdPlan {
 
 FwdPlan plan_fwd(const relnn_index* idx, const relnn_layer_desc* L);
 void check_layer(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P);
-Atoms make_atoms(const relnn_layer_desc* L, const void* const* emb);
+Atoms make_atoms(const relnn_layer_desc* L, const void* const* emb, const relnn_index* idx);
 void swizzle_w(const void* W, int dtype, int K, int Kp, int h, void* Wsw, hipStream_t s);
 void launch_fwd(const FwdPlan& P, const FwdArgs& a, int dtype, bool plain, hipStream_t s);
 // Recomputes y = x W + b per tuple and writes mask = (y > 0) (tile kernel).

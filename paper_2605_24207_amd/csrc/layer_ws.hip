@@ -30,6 +30,7 @@ struct WsArgs {
   Atoms at;
   const int32_t* rows;
   int64_t E;
+  const int64_t* E_dev;      // if set: E (and the tile count) come from device memory
   int K, h;
   int64_t ntiles, nunits;
   const void* Wsw;
@@ -190,6 +191,11 @@ __device__ __forceinline__ void ws_reduce(const WsArgs& a, int64_t t, const floa
 // float atomics -- two addends commute exactly, so the sum is deterministic.
 template <class T, int KP, int KS>
 __global__ void __launch_bounds__((4 * KS + kGatherWaves) * 64) k_fwd_ws(WsArgs a) {
+  if (a.E_dev) {
+    a.E = *a.E_dev;
+    a.ntiles = (a.E + WsCfg<T>::TM - 1) / WsCfg<T>::TM;
+    a.sg.n = a.E;
+  }
   using C = WsCfg<T>;
   constexpr int TM = C::TM;
   constexpr int XS = KP + C::XPAD;
@@ -253,7 +259,7 @@ __global__ void __launch_bounds__((4 * KS + kGatherWaves) * 64) k_fwd_ws(WsArgs 
 #pragma unroll
           for (int u = 1; u < kMaxAtoms; ++u)
             if (u < a.at.k && el >= a.at.koff[u]) j = u;
-          const int64_t row = a.rows[(int64_t)j * a.E + e0 + r];
+          const int64_t row = a.at.rows[j][e0 + r];
           v[q] = *reinterpret_cast<const uint4*>(static_cast<const T*>(a.at.emb[j]) + row * a.at.d[j] +
                                                   (el - a.at.koff[j]));
         }
@@ -289,7 +295,7 @@ __global__ void __launch_bounds__((4 * KS + kGatherWaves) * 64) k_fwd_ws(WsArgs 
 #pragma unroll
             for (int u = 1; u < kMaxAtoms; ++u)
               if (u < a.at.k && el >= a.at.koff[u]) j = u;
-            const int64_t row = a.rows[(int64_t)j * a.E + e0 + r];
+            const int64_t row = a.at.rows[j][e0 + r];
             v[qq] = *reinterpret_cast<const uint4*>(static_cast<const T*>(a.at.emb[j]) + row * a.at.d[j] +
                                                      (el - a.at.koff[j]));
           }
@@ -403,6 +409,11 @@ __global__ void __launch_bounds__((4 * KS + kGatherWaves) * 64) k_fwd_ws(WsArgs 
 // 16m + 4 (lane / 16) + u.  W is swizzled to match (k_ws_swizzle_f16c).
 template <int KP, int NW>
 __global__ void __launch_bounds__(NW * 64) k_fwd_f32(WsArgs a) {
+  if (a.E_dev) {
+    a.E = *a.E_dev;
+    a.ntiles = (a.E + 31) / 32;
+    a.sg.n = a.E;
+  }
   constexpr int TM = 32;
   constexpr int XS = KP + 4;
   constexpr int CPR = KP / 4;
@@ -445,7 +456,7 @@ __global__ void __launch_bounds__(NW * 64) k_fwd_f32(WsArgs a) {
 #pragma unroll
           for (int u = 1; u < kMaxAtoms; ++u)
             if (u < a.at.k && el >= a.at.koff[u]) j = u;
-          const int64_t row = a.rows[(int64_t)j * a.E + e0 + r];
+          const int64_t row = a.at.rows[j][e0 + r];
           v[q] = *reinterpret_cast<const uint4*>(static_cast<const float*>(a.at.emb[j]) + row * a.at.d[j] +
                                                   (el - a.at.koff[j]));
         }
@@ -598,6 +609,7 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
   a.at = f.at;
   a.rows = f.rows;
   a.E = f.E;
+  a.E_dev = f.E_dev;
   a.K = f.K;
   a.h = f.h;
   a.ntiles = p.ntiles;

@@ -1,0 +1,139 @@
+"""GPU serving: results per request against the FP64 serving oracle, the
+same request alone and inside a concurrent mix, HBM-budget admission and
+error paths (through the C ABI)."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import relgen
+from oracle import relnn_oracle as orc
+from oracle import serve_oracle as so
+
+pytestmark = pytest.mark.gpu
+
+
+def small_graph(seed=11):
+    return relgen.er_graph(seed=seed, n_user=20_000, n_item=4_000, n_cat=50, n_buys=120_000, n_layers=2)
+
+
+def make_server(g, dtype="f32", **kw):
+    import torch
+
+    from paper_2605_24207_amd import Server
+
+    dev = "cuda"
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    f = lambda a: t(a).to(tdt).contiguous()
+    return Server(t(g.buys_u), t(g.buys_i), t(g.belongs_cat), f(g.user), f(g.item), f(g.cat),
+                  f(g.W_user[0]), f(g.W_item[0]), f(g.W_item[1]), None, None, None, dtype=dtype, **kw)
+
+
+def oracle_for(g, dtype):
+    r = orc.bf16_round if dtype == "bf16" else (lambda a: a)
+    adj = so.adjacency(g.buys_u, g.buys_i, g.item.shape[0], g.user.shape[0])
+    emb = (r(g.user), r(g.item), r(g.cat), g.belongs_cat)
+    W = (r(g.W_user[0]), r(g.W_item[0]), r(g.W_item[1]))
+    return lambda seeds, rs: so.evaluate(adj, emb, W, (None, None, None), seeds, rs, 15, 10)
+
+
+def requests(g, n, seed=3, max_seeds=64):
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(n):
+        m = int(rng.integers(1, max_seeds + 1))
+        seeds = rng.choice(g.item.shape[0], size=m, replace=False).astype(np.int32)
+        out.append((seeds, int(rng.integers(0, 2**62))))
+    return out
+
+
+def rows_close(z, ref, tol):
+    z = np.asarray(z, np.float64)
+    ref = np.asarray(ref, np.float64)
+    nr = np.linalg.norm(ref, axis=1)
+    scale = np.maximum(nr, 1e-3 * max(np.median(nr[nr > 0]) if np.any(nr > 0) else 1.0, 1e-30))
+    return (np.linalg.norm(z - ref, axis=1) / scale).max() <= tol
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 2e-2)])
+def test_serve_matches_oracle(dtype, tol):
+    g = small_graph()
+    srv = make_server(g, dtype, max_seeds=64, max_slots=8)
+    ref = oracle_for(g, dtype)
+    reqs = requests(g, 24)
+    reqs.append((np.array([g.item.shape[0] + 5, 0, -1], np.int32), 99))     # ids without neighbourhood
+    tickets = [srv.submit(s, rs) for s, rs in reqs]
+    for (s, rs), t in zip(reqs, tickets):
+        out, present, st = srv.wait(t, len(s))
+        r_out, r_pres, r_tuples = ref(s, rs)
+        assert present.tolist() == r_pres.tolist()
+        assert st["tuples"] == r_tuples
+        assert rows_close(out, r_out, tol)
+    srv.close()
+
+
+def test_serve_same_alone_and_in_the_mix():
+    g = small_graph(seed=12)
+    srv = make_server(g, "f32", max_seeds=256, max_slots=16)
+    probe = (np.random.default_rng(5).choice(g.item.shape[0], 200, replace=False).astype(np.int32), 777)
+    alone, _, _ = srv.wait(srv.submit(*probe), 200)
+    # now the same request among concurrent submitters
+    others = requests(g, 60, seed=9, max_seeds=256)
+    got = {}
+
+    def submitter(chunk):
+        for s, rs in chunk:
+            srv.submit(s, rs)
+            time.sleep(0.0005)
+
+    th = [threading.Thread(target=submitter, args=(others[i::3],)) for i in range(3)]
+    for x in th:
+        x.start()
+    t_probe = srv.submit(*probe)
+    for x in th:
+        x.join()
+    mixed, _, st = srv.wait(t_probe, 200)
+    assert rows_close(mixed, alone, 1e-6)
+    got["bitwise"] = bool(np.array_equal(mixed, alone))
+    srv.close()
+
+
+def test_serve_tiny_budget_queues_requests():
+    """A budget that holds one largest request: every step takes one request
+    (or a few small ones), the rest wait, and all come back correct."""
+    from paper_2605_24207_amd import RelnnError
+
+    g = small_graph(seed=13)
+    with pytest.raises(RelnnError, match="OOM"):
+        make_server(g, "f32", max_seeds=64, max_slots=4, budget_bytes=100_000)
+    per_seed = 16 + 8 + 15 * 28 + 150 * 12 + 15 * 128 * 4 + 128 * 4 + 128 * 4 + 4 * 128
+    budget = 64 * per_seed + 256 * 2 * 128 * 4 + (1 << 20)
+    srv = make_server(g, "f32", max_seeds=64, max_slots=4, budget_bytes=budget)
+    ref = oracle_for(g, "f32")
+    reqs = requests(g, 10, seed=4)
+    tickets = [srv.submit(s, rs) for s, rs in reqs]
+    steps = set()
+    for (s, rs), t in zip(reqs, tickets):
+        out, present, st = srv.wait(t, len(s))
+        steps.add(st["step"])
+        assert rows_close(out, ref(s, rs)[0], 1e-5)
+    assert len(steps) >= 5          # 10 requests of up to 64 seeds through a 64-seed step
+    srv.close()
+
+
+def test_serve_errors():
+    from paper_2605_24207_amd import RelnnError
+
+    g = small_graph(seed=14)
+    srv = make_server(g, "f32", max_seeds=16, max_slots=2)
+    with pytest.raises(RelnnError, match="RANGE"):
+        srv.submit(np.arange(17, dtype=np.int32), 1)
+    with pytest.raises(RelnnError, match="INVALID"):
+        srv.poll(123456789, 1)
+    t = srv.submit(np.arange(3, dtype=np.int32), 1)
+    srv.wait(t, 3)
+    with pytest.raises(RelnnError, match="INVALID"):      # a ticket is consumed by its poll
+        srv.poll(t, 3)
+    srv.close()
