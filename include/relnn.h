@@ -150,6 +150,18 @@ relnn_status relnn_index_free(relnn_index* idx);
 #define RELNN_OUT_BF16 4u  /* forward writes `out` as bf16 (round to nearest
                               even) so it can feed a bf16 layer; `pre` stays
                               FP32 */
+#define RELNN_PUSHDOWN 8u  /* forward with the transform pushed below the join
+                              (the "once per node instead of once per edge"
+                              rewrite named as future work in Section 6):
+                              for act_pre = NONE, Linear(z_1 (+) ... (+) z_k)
+                              = sum_j z_j W_j + b, so P_j = Z_j W_j is formed
+                              once per atom row and each tuple sums P rows;
+                              atoms whose key is a function of the head key,
+                              and b, enter once per group.  Same results up
+                              to rounding; needs act_pre = NONE (else
+                              RELNN_E_INVALID), d_j a multiple of 4 (FP32) or
+                              32 (BF16) and h <= 128 with h % 4 == 0 (else
+                              RELNN_E_UNSUPPORTED); not with RELNN_PLAIN */
 
 typedef struct {
   int32_t k;               /* body atoms, equal to the index's */
@@ -160,8 +172,8 @@ typedef struct {
   int32_t agg;             /* relnn_agg */
   int32_t act_pre;         /* relnn_act inside tau, per joined tuple */
   int32_t act_post;        /* relnn_act after the aggregate */
-  uint32_t flags;          /* RELNN_FUSED | RELNN_PLAIN, RELNN_DW_ACCUM,
-                              RELNN_OUT_BF16 */
+  uint32_t flags;          /* RELNN_FUSED | RELNN_PLAIN | RELNN_PUSHDOWN,
+                              RELNN_DW_ACCUM, RELNN_OUT_BF16 */
 } relnn_layer_desc;
 
 /* Workspace bytes relnn_layer_fwd (bwd = 0) or relnn_layer_bwd (bwd = 1)

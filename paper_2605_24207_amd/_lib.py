@@ -15,7 +15,7 @@ F32, BF16 = 0, 1
 SUM, MEAN, MAX = 0, 1, 2
 ACT_NONE, ACT_RELU = 0, 1
 IDX_BWD = 1
-FUSED, PLAIN, DW_ACCUM, OUT_BF16 = 0, 1, 2, 4
+FUSED, PLAIN, DW_ACCUM, OUT_BF16, PUSHDOWN = 0, 1, 2, 4, 8
 MAX_ATOMS = 4
 
 p_i32 = C.POINTER(C.c_int32)

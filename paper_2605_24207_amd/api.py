@@ -120,8 +120,9 @@ class Layer:
 
     def __init__(self, dims: Sequence[int], h: int, dtype: str = "f32", agg: str = "sum",
                  act_pre: str = "none", act_post: str = "none", plain: bool = False,
-                 out_dtype: str = "f32"):
+                 out_dtype: str = "f32", pushdown: bool = False):
         self.out_dtype = out_dtype
+        self.pushdown = pushdown
         self.dims = [int(x) for x in dims]
         self.h = int(h)
         self.dtype = dtype
@@ -149,7 +150,7 @@ class Layer:
         d.act_pre = _ACTS[self.act_pre]
         d.act_post = _ACTS[self.act_post]
         d.flags = ((L.PLAIN if self.plain else L.FUSED) | (L.DW_ACCUM if dw_accum else 0)
-                   | (L.OUT_BF16 if self.out_dtype == "bf16" else 0))
+                   | (L.OUT_BF16 if self.out_dtype == "bf16" else 0) | (L.PUSHDOWN if self.pushdown else 0))
         return d
 
 

@@ -109,6 +109,16 @@ __device__ __forceinline__ void store_acc(const f32x4 (&acc)[kMaxQ], int nblk, i
   }
 }
 
+// Per-group constant of the pushed-down transform: sum over the atoms
+// whose key is a function of the group of P_j[row of the group] (+ bias).
+struct GroupConst {
+  int n;                          // such atoms (0: none)
+  const float* P[RELNN_MAX_ATOMS];      // [n_rows_j][h] node products
+  const int32_t* rows[RELNN_MAX_ATOMS]; // joined rows of the atom per tuple
+  const int32_t* offsets;         // group offsets (any tuple names the row)
+  const float* bias;              // [h] or null
+};
+
 // How a finished segment value is written.
 struct Sink {
   int agg;          // relnn_agg
@@ -119,11 +129,25 @@ struct Sink {
   bool accumulate;  // out += value (backward scatter into embeddings)
   const int32_t* out_row;   // optional remap: segment -> output row
   bool out_bf16;    // out holds bf16 (round to nearest even)
+  GroupConst gc;    // pushed-down transform: per-group constant term
 };
+
+__device__ __forceinline__ float group_const(const GroupConst& g, int64_t s, int c, int h) {
+  float v = g.bias ? g.bias[c] : 0.0f;
+  if (g.n) {
+    const int64_t e = g.offsets[s];
+    for (int j = 0; j < g.n; ++j) v += g.P[j][(int64_t)g.rows[j][e] * h + c];
+  }
+  return v;
+}
 
 __device__ __forceinline__ void sink_write(const Sink& k, int64_t s, int c, int h, float v, int32_t am,
                                            int32_t cnt) {
   if (k.agg == RELNN_MEAN) v = v / (float)cnt;
+  if (k.gc.n || k.gc.bias) {          // pushed-down transform: add the group's constant term
+    const float g = group_const(k.gc, s, c, h);
+    v = (k.agg == RELNN_SUM) ? v + (float)cnt * g : v + g;
+  }
   const int64_t row = k.out_row ? (int64_t)k.out_row[s] : s;
   const int64_t o = row * h + c;
   if (k.pre) k.pre[o] = v;

@@ -372,7 +372,66 @@ FwdPlan plan_fwd(const relnn_index* idx, const relnn_layer_desc* L) {
   P.ws_y = off;
   off += round_up(std::max<int64_t>(E, 1) * h * 4, 256);
   P.ws_plain = off;
+  if (L->flags & RELNN_PUSHDOWN) {        // node products, W slices, carry of the gather-reduce
+    size_t o = 0;
+    for (int j = 0; j < L->k; ++j) {
+      P.ws_push_p[j] = o;
+      o += round_up(std::max<int64_t>(idx->n_rows[j], 1) * h * 4, 256);
+      P.ws_push_w[j] = o;
+      o += round_up((int64_t)L->d[j] * h * esz, 256);
+    }
+    P.carry_units = std::max<int64_t>(P.carry_units, push_units(E));
+    P.ws_carry = o;
+    o += round_up(P.carry_units * 2 * h * 4, 256);
+    P.ws_carry_arg = o;
+    if (L->agg == RELNN_MAX) o += round_up(P.carry_units * 2 * h * 4, 256);
+    P.ws_push = o;
+  }
   return P;
+}
+
+namespace {
+template <class T>
+void node_gemm_t(const void* X, int64_t n, int K, int h, const void* Wsw, float* Y, hipStream_t s) {
+  constexpr int XPAD = Mfma<T>::XPAD;
+  int TM = 0;
+  size_t lds = 0, off_x = 0, off_y = 0;
+  for (int tm : {64, 32, 16}) {
+    if ((tm / 16) * (h / 16) > 4 * kMaxQ) continue;
+    off_x = round_up((size_t)kMaxAtoms * tm * 4, 16);
+    off_y = off_x + round_up((size_t)tm * (K + XPAD) * sizeof(T), 16);
+    lds = off_y + (size_t)tm * (h + 4) * 4;
+    if (lds <= 160 * 1024) {
+      TM = tm;
+      break;
+    }
+  }
+  RELNN_REQUIRE(TM > 0, RELNN_E_UNSUPPORTED, "node product K = %d, h = %d does not fit the LDS tile", K, h);
+  FwdArgs g{};
+  g.E = n;
+  g.K = K;
+  g.Kp = K;
+  g.h = h;
+  g.TM = TM;
+  g.off_x = (int)off_x;
+  g.off_y = (int)off_y;
+  g.Wsw = Wsw;
+  g.act_pre = RELNN_ACT_NONE;
+  g.X = X;
+  g.Y = Y;
+  allow_lds(k_layer_fwd<T, MODE_GEMM>, lds);
+  k_layer_fwd<T, MODE_GEMM><<<(unsigned)cdiv(n, TM), kThreads, lds, s>>>(g);
+  RELNN_LAUNCHED();
+}
+}  // namespace
+
+void launch_node_gemm(const void* X, int dtype, int64_t n, int K, int h, const void* Wsw, float* Y,
+                      hipStream_t s) {
+  if (n <= 0) return;
+  if (dtype == RELNN_BF16)
+    node_gemm_t<__bf16>(X, n, K, h, Wsw, Y, s);
+  else
+    node_gemm_t<float>(X, n, K, h, Wsw, Y, s);
 }
 
 void check_layer(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P) {
@@ -384,7 +443,7 @@ void check_layer(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   RELNN_REQUIRE((L->act_pre == RELNN_ACT_NONE || L->act_pre == RELNN_ACT_RELU) &&
                     (L->act_post == RELNN_ACT_NONE || L->act_post == RELNN_ACT_RELU),
                 RELNN_E_INVALID, "unknown activation");
-  RELNN_REQUIRE((L->flags & ~(RELNN_PLAIN | RELNN_DW_ACCUM | RELNN_OUT_BF16)) == 0, RELNN_E_INVALID, "unknown layer flags");
+  RELNN_REQUIRE((L->flags & ~(RELNN_PLAIN | RELNN_DW_ACCUM | RELNN_OUT_BF16 | RELNN_PUSHDOWN)) == 0, RELNN_E_INVALID, "unknown layer flags");
   RELNN_REQUIRE(L->h > 0, RELNN_E_INVALID, "h must be positive");
   const int epc = L->dtype == RELNN_BF16 ? 8 : 4;
   for (int j = 0; j < L->k; ++j) {
@@ -454,7 +513,7 @@ extern "C" relnn_status relnn_workspace_size(const relnn_index* idx, const relnn
     if (bwd) {
       *bytes = bwd_workspace(idx, L, P);
     } else {
-      *bytes = (L->flags & RELNN_PLAIN) ? P.ws_plain : P.ws_fused;
+      *bytes = (L->flags & RELNN_PUSHDOWN) ? P.ws_push : (L->flags & RELNN_PLAIN) ? P.ws_plain : P.ws_fused;
     }
   });
 }
@@ -468,7 +527,17 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
     FwdPlan P = plan_fwd(idx, L);
     check_layer(idx, L, P);
     const bool plain = (L->flags & RELNN_PLAIN) != 0;
-    const size_t need = plain ? P.ws_plain : P.ws_fused;
+    const bool push = (L->flags & RELNN_PUSHDOWN) != 0;
+    RELNN_REQUIRE(!(plain && push), RELNN_E_INVALID, "RELNN_PLAIN and RELNN_PUSHDOWN exclude each other");
+    if (push) {
+      RELNN_REQUIRE(L->act_pre == RELNN_ACT_NONE, RELNN_E_INVALID,
+                    "RELNN_PUSHDOWN needs an affine transform (act_pre = NONE)");
+      const int ks = L->dtype == RELNN_BF16 ? 32 : 4;
+      for (int j = 0; j < L->k; ++j)
+        RELNN_REQUIRE(L->d[j] % ks == 0, RELNN_E_UNSUPPORTED, "RELNN_PUSHDOWN needs d[%d] %% %d == 0", j, ks);
+      RELNN_REQUIRE(L->h % 4 == 0 && L->h <= 128, RELNN_E_UNSUPPORTED, "RELNN_PUSHDOWN needs h %% 4 == 0, h <= 128");
+    }
+    const size_t need = push ? P.ws_push : plain ? P.ws_plain : P.ws_fused;
     RELNN_REQUIRE(emb != nullptr, RELNN_E_INVALID, "emb is NULL");
     for (int j = 0; j < L->k; ++j) {
       RELNN_REQUIRE(emb[j] != nullptr || idx->n_rows[j] == 0, RELNN_E_INVALID, "emb[%d] is NULL", j);
@@ -482,7 +551,7 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
     if (idx->E == 0) return;
     hipStream_t s = (hipStream_t)stream;
     char* w = static_cast<char*>(ws);
-    swizzle_w(W, L->dtype, P.K, P.Kp, L->h, w + P.ws_wsw, s);
+    if (!push) swizzle_w(W, L->dtype, P.K, P.Kp, L->h, w + P.ws_wsw, s);
     FwdArgs a{};
     a.at = make_atoms(L, emb, idx);
     a.rows = idx->rows;
@@ -502,6 +571,43 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
     a.carry_arg = L->agg == RELNN_MAX ? reinterpret_cast<int32_t*>(w + P.ws_carry_arg) : nullptr;
     a.X = w + P.ws_x;
     a.Y = reinterpret_cast<float*>(w + P.ws_y);
+    if (push) {
+      // node products P_j = Z_j W_j, once per atom row
+      const int esz = L->dtype == RELNN_BF16 ? 2 : 4;
+      const float* Pj[kMaxAtoms];
+      for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
+        void* wj = w + P.ws_push_w[j];
+        swizzle_w(static_cast<const char*>(W) + (size_t)koff * L->h * esz, L->dtype, L->d[j], L->d[j], L->h, wj, s);
+        Pj[j] = reinterpret_cast<const float*>(w + P.ws_push_p[j]);
+        launch_node_gemm(emb[j], L->dtype, idx->n_rows[j], L->d[j], L->h, wj, const_cast<float*>(Pj[j]), s);
+      }
+      // atoms varying inside a group are gathered per tuple; the others
+      // (and the bias) are one constant per group
+      const float* gp[kMaxAtoms];
+      const int32_t* gr[kMaxAtoms];
+      int n = 0;
+      Sink sk = a.sink;
+      sk.gc = GroupConst{};
+      sk.gc.offsets = idx->offsets;
+      sk.gc.bias = b;
+      for (int j = 0; j < L->k; ++j) {
+        const int32_t* rj = idx->rows + (int64_t)j * idx->E;
+        if (idx->atom_fd[j]) {
+          sk.gc.P[sk.gc.n] = Pj[j];
+          sk.gc.rows[sk.gc.n] = rj;
+          ++sk.gc.n;
+        } else {
+          gp[n] = Pj[j];
+          gr[n] = rj;
+          ++n;
+        }
+      }
+      a.sink = sk;
+      a.carry = reinterpret_cast<float*>(w + P.ws_carry);
+      a.carry_arg = L->agg == RELNN_MAX ? reinterpret_cast<int32_t*>(w + P.ws_carry_arg) : nullptr;
+      launch_push(a, push_units(idx->E), n, gp, gr, a.carry, a.carry_arg, s);
+      return;
+    }
     const WsPlan wp = plan_ws(L->dtype, P.K, L->h, idx->E);
     RELNN_REQUIRE(P.ntiles <= P.carry_units && (!wp.KP || wp.nunits <= P.carry_units) &&
                       (!wp.KP || wp.wsw_bytes <= P.ws_carry - P.ws_wsw),

@@ -37,6 +37,9 @@ struct FwdPlan {
   size_t off_x = 0, off_y = 0, lds = 0;
   int64_t ntiles = 0;
   int64_t carry_units = 0;   // units the carry region holds (max over kernels)
+  size_t ws_push_p[RELNN_MAX_ATOMS] = {};   // pushdown: node products of atom j
+  size_t ws_push_w[RELNN_MAX_ATOMS] = {};   // pushdown: swizzled W_j
+  size_t ws_push = 0;                       // pushdown total
   size_t ws_wsw = 0, ws_carry = 0, ws_carry_arg = 0, ws_x = 0, ws_y = 0;
   size_t ws_fused = 0, ws_plain = 0;
 };
@@ -62,6 +65,17 @@ WsPlan plan_ws(int dtype, int K, int h, int64_t E);
 void swizzle_ws(const void* W, int dtype, int K, int KP, int h, void* out, hipStream_t s);
 void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, float* carry,
                int32_t* carry_arg, hipStream_t s);
+
+// Pushed-down transform: gather-sum of the node products P (n atoms per
+// tuple) and per-group reduce (layer_ws.hip); the sink carries the group
+// constant.  push_units: blocks (and carry units) it uses for E tuples.
+void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P, const int32_t* const* rows,
+                 float* carry, int32_t* carry_arg, hipStream_t s);
+int64_t push_units(int64_t E);
+// Y[r] = X[r] W over rows r < n (X row-major [n, K], K a multiple of the
+// MFMA k step): the node products of the pushed-down transform.
+void launch_node_gemm(const void* X, int dtype, int64_t n, int K, int h, const void* Wsw, float* Y,
+                      hipStream_t s);
 size_t bwd_workspace(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P);
 
 }  // namespace relnn

@@ -19,11 +19,11 @@ def gpu_index(rule, bwd=False, device="cuda"):
     return Index(cols, atoms, rule.group_col, chains=chains, two_hop=two, bwd=bwd)
 
 
-def gpu_layer(rule, dtype="f32", plain=False):
+def gpu_layer(rule, dtype="f32", plain=False, pushdown=False):
     from paper_2605_24207_amd import Layer
 
     return Layer([a.d for a in rule.atoms], rule.h, dtype=dtype, agg=rule.agg, act_pre=rule.act_pre,
-                 act_post=rule.act_post, plain=plain)
+                 act_post=rule.act_post, plain=plain, pushdown=pushdown)
 
 
 def to_dev(a, dtype="f32", device="cuda"):
@@ -46,13 +46,13 @@ def distinct_embs(rule, dtype="f32"):
     return out
 
 
-def gpu_fwd(rule, dtype="f32", plain=False, index=None):
+def gpu_fwd(rule, dtype="f32", plain=False, index=None, pushdown=False):
     import torch
 
     from paper_2605_24207_amd import layer_fwd
 
     idx = gpu_index(rule) if index is None else index
-    layer = gpu_layer(rule, dtype, plain)
+    layer = gpu_layer(rule, dtype, plain, pushdown)
     embs = distinct_embs(rule, dtype)
     W = to_dev(rule.W, dtype)
     b = to_dev(rule.b)

@@ -81,8 +81,8 @@ def test_duplicate_key_is_rejected():
         gpu_index(rule)
 
 
-def check_fwd(rule, dtype, plain=False):
-    res = gpu_fwd(rule, dtype, plain)
+def check_fwd(rule, dtype, plain=False, pushdown=False):
+    res = gpu_fwd(rule, dtype, plain, pushdown=pushdown)
     idx, out, pre, am = oracle_fwd(rule, "f32")
     assert res["out"].shape == out.shape
     e_pre = rel_rows(res["pre"], pre)
@@ -181,3 +181,56 @@ def test_workspace_is_not_overrun(dtype, agg, plain):
     layer_fwd(idx, layer, distinct_embs(rule, dtype), to_dev(rule.W, dtype), to_dev(rule.b), ws=buf[:n])
     torch.cuda.synchronize()
     assert bool((buf[n:] == 0xAB).all())
+
+
+@pytest.mark.parametrize("d,h", [(64, 64), (256, 256)])
+@pytest.mark.parametrize("agg", ["sum", "max"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_two_hop_cobuy(d, h, agg, dtype):
+    """Buys |x| Buys^T on item, at most 50 paths per item, grouped by the
+    first buyer: index bit-exact and layer within the bound."""
+    g = relgen.er_graph(seed=8, n_user=3000, n_item=600, n_cat=10, n_buys=20_000, n_layers=1)
+    rule = relgen.cobuy_rule(g, d=d, h=h, cap=50, agg=agg)
+    gi = gpu_index(rule)
+    ref = orc.build_index(rule)
+    assert (gi.E, gi.G) == (ref.E, ref.G)
+    ex = {k: v.cpu().numpy() for k, v in gi.export().items()}
+    np.testing.assert_array_equal(ex["link_rows"], ref.link_row)
+    np.testing.assert_array_equal(ex["offsets"], ref.offsets)
+    for j in range(2):
+        np.testing.assert_array_equal(ex["tuple_rows"][j], ref.rows[j])
+    check_fwd(rule, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("agg", ["sum", "mean", "max"])
+def test_pushdown_node_edge(dtype, agg):
+    """Transform pushed below the join: same layer, same oracle bound."""
+    check_fwd(relgen.node_edge(agg=agg, bias_std=0.5), dtype, pushdown=True)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("which", ["item", "user"])
+def test_pushdown_er_rules(dtype, which):
+    """The ER rules have atoms keyed by the head key (Item and Category in
+    the Item rule, User in the User rule): their terms enter once per group."""
+    g = er_small()
+    g.b_item[0] = np.random.default_rng(1).standard_normal(128).astype(np.float32)
+    g.b_user[0] = np.random.default_rng(2).standard_normal(128).astype(np.float32)
+    rule = relgen.er_item_rule(g) if which == "item" else relgen.er_user_rule(g)
+    check_fwd(rule, dtype, pushdown=True)
+
+
+@pytest.mark.parametrize("agg", ["sum", "mean", "max"])
+def test_pushdown_hot_segment(agg):
+    rule = relgen.node_edge(seed=9, n_nodes=700, n_edges=40_003, agg=agg, bias_std=0.3)
+    rule.cols[1][:30_000] = 11
+    check_fwd(rule, "f32", pushdown=True)
+
+
+def test_pushdown_rejects_nonaffine_transform():
+    from paper_2605_24207_amd import RelnnError
+
+    rule = relgen.node_edge(act_pre="relu")
+    with pytest.raises(RelnnError, match="INVALID"):
+        gpu_fwd(rule, "f32", pushdown=True)
