@@ -80,7 +80,7 @@ def build_workload(scale: float):
 class Net:
     """The two-layer ER network in one precision / path."""
 
-    def __init__(self, D, dtype: str, plain: bool):
+    def __init__(self, D, dtype: str, plain: bool, pushdown: bool = False):
         import torch
 
         from paper_2605_24207_amd import Layer, workspace_size
@@ -93,8 +93,10 @@ class Net:
         self.W_item = [cv(w) for w in D["W_item"]]
         self.W_user = [cv(w) for w in D["W_user"]]
         od = "bf16" if dtype == "bf16" else "f32"
-        self.L_item = Layer([128, 128, 128], 128, dtype, "sum", "none", "relu", plain=plain, out_dtype=od)
-        self.L_user = Layer([128, 128], 128, dtype, "mean", "none", "relu", plain=plain, out_dtype=od)
+        self.L_item = Layer([128, 128, 128], 128, dtype, "sum", "none", "relu", plain=plain, out_dtype=od,
+                            pushdown=pushdown)
+        self.L_user = Layer([128, 128], 128, dtype, "mean", "none", "relu", plain=plain, out_dtype=od,
+                            pushdown=pushdown)
         ix = [D["ix_item1"], D["ix_user1"], D["ix_item2"], D["ix_user2"]]
         ws = max(workspace_size(ix[q], [self.L_item, self.L_user][q % 2]) for q in range(4))
         self.ws = torch.empty(ws, dtype=torch.uint8, device="cuda")
@@ -317,8 +319,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
     ap.add_argument("--cpu-budget", type=int, default=2_000_000, help="oracle sample size in tuples")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="f32,plain,bf16,serve,fwdbwd",
-                    help="comma list of f32,plain,bf16,serve,fwdbwd")
+    ap.add_argument("--legs", default="f32,plain,bf16,push_f32,push_bf16,serve,fwdbwd",
+                    help="comma list of f32,plain,bf16,push_f32,push_bf16,serve,fwdbwd")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per serving rate")
     ap.add_argument("--serve-rates", default="200,500,1000,2000", help="Poisson arrival rates (req/s)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -337,12 +339,13 @@ def main():
     legs = set(args.legs.split(","))
     D = build_workload(args.scale)
     res = {}
-    for leg in ("f32", "plain", "bf16"):
+    for leg in ("f32", "plain", "bf16", "push_f32", "push_bf16"):
         if leg not in legs:
             continue
-        dtype = "bf16" if leg == "bf16" else "f32"
-        net = Net(D, dtype, plain=(leg == "plain"))
-        kern = ["fwd_gather", "fwd_gemm", "fwd_reduce"] if leg == "plain" else ["fwd_fused"]
+        dtype = "bf16" if leg.endswith("bf16") else "f32"
+        net = Net(D, dtype, plain=(leg == "plain"), pushdown=leg.startswith("push"))
+        kern = (["fwd_gather", "fwd_gemm", "fwd_reduce"] if leg == "plain" else
+                ["fwd_push"] if leg.startswith("push") else ["fwd_fused"])
         steps = args.steps if leg != "plain" else max(1, args.steps // 2)
         dt, kt = time_net(net, steps, args.warmup, kern)
         res[leg] = {"dt": dt, "steps": steps, "kt": kt, "tuples": net.tuples, "flops": net.flops}
@@ -370,7 +373,8 @@ def main():
                      "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"],
                      "traffic": None, "avg_launch_ms": k_ms / k_n},
     }
-    for leg, key in (("plain", "plain_f32"), ("bf16", "fused_bf16")):
+    for leg, key in (("plain", "plain_f32"), ("bf16", "fused_bf16"), ("push_f32", "pushdown_f32"),
+                     ("push_bf16", "pushdown_bf16")):
         if leg in res:
             r = res[leg]
             line[key] = {"value": r["tuples"] * r["steps"] / r["dt"], "unit": "tuples/s",

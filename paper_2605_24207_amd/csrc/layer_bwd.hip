@@ -32,25 +32,36 @@ constexpr int kDwThreads = 512;
 constexpr int kDwMaxB = 24;              // 16x16 accumulator blocks per wave
 
 struct Route {
-  const float* dout;        // [G][h]
-  const float* pre;         // [G][h] (act_post != NONE)
+  const float* dA;          // [G][h] dout * act_post'(pre), / |g| for MEAN
   const int32_t* argmax;    // [G][h] (MAX)
   const int32_t* tuple_group;
-  const int32_t* offsets;
   const uint8_t* mask;      // [E][h] (act_pre != NONE)
-  int h, agg, act_post;
+  int h, agg;
 };
 
+// dY of tuple e (group g), column n.
 __device__ __forceinline__ float route(const Route& R, int64_t e, int64_t g, int n) {
   const int64_t o = g * R.h + n;
-  float v = R.dout[o];
-  if (R.act_post == RELNN_ACT_RELU && !(R.pre[o] > 0.0f)) v = 0.0f;
-  if (R.agg == RELNN_MEAN)
-    v = v / (float)(R.offsets[g + 1] - R.offsets[g]);
-  else if (R.agg == RELNN_MAX && R.argmax[o] != (int32_t)e)
-    v = 0.0f;
+  float v = R.dA[o];
+  if (R.agg == RELNN_MAX && R.argmax[o] != (int32_t)e) v = 0.0f;
   if (R.mask && !R.mask[e * R.h + n]) v = 0.0f;
   return v;
+}
+
+// dA[g][n] = dout[g][n] * act_post'(pre[g][n]) (ReLU'(0) = 0), divided by
+// the group's tuple count for MEAN: the per-group part of the routing.
+__global__ void k_route_prep(const float* dout, const float* pre, const int32_t* offsets, int64_t G, int h, int agg,
+                             int act_post, float* dA) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G * h;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float v = dout[i];
+    if (act_post == RELNN_ACT_RELU && !(pre[i] > 0.0f)) v = 0.0f;
+    if (agg == RELNN_MEAN) {
+      const int64_t g = i / h;
+      v = v / (float)(offsets[g + 1] - offsets[g]);
+    }
+    dA[i] = v;
+  }
 }
 
 // ---------------------------------------------------------------- dz_j
@@ -280,7 +291,7 @@ struct BwdPlan {
   int K = 0, K16 = 0, hp = 0, hn = 0;
   int64_t dx_tiles = 0, dw_tiles = 0, dw_units = 0;
   size_t dx_lds = 0, dw_lds = 0;
-  size_t ws_mask = 0, ws_fwsw = 0, ws_wt = 0, ws_carry = 0, ws_part = 0, ws_dbpart = 0, total = 0;
+  size_t ws_mask = 0, ws_fwsw = 0, ws_wt = 0, ws_carry = 0, ws_part = 0, ws_dbpart = 0, ws_dA = 0, total = 0;
   size_t wt_off[kMaxAtoms] = {};
 };
 
@@ -317,6 +328,8 @@ BwdPlan plan_bwd(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   off += round_up(p.dw_units * p.K16 * L->h * 4, 256);
   p.ws_dbpart = off;
   off += round_up(p.dw_units * L->h * 4, 256);
+  p.ws_dA = off;
+  off += round_up(std::max<int64_t>(idx->G, 1) * L->h * 4, 256);
   p.total = off;
   return p;
 }
@@ -343,9 +356,7 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
                                         float* const* demb, float* dW, float* db, void* ws, size_t ws_bytes,
                                         relnn_stream_t stream) {
   return guard([&] {
-    RELNN_REQUIRE(idx != nullptr && L != nullptr, RELNN_E_INVALID, "index or layer descriptor is NULL");
-    FwdPlan F = plan_fwd(idx, L);
-    check_layer(idx, L, F);
+    FwdPlan F = checked_plan(idx, L);
     RELNN_REQUIRE(idx->has_bwd, RELNN_E_INVALID, "the index was built without RELNN_IDX_BWD");
     RELNN_REQUIRE(!(L->flags & RELNN_OUT_BF16), RELNN_E_INVALID, "RELNN_OUT_BF16 is a forward-only flag");
     const BwdPlan P = plan_bwd(idx, L, F);
@@ -384,7 +395,10 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
       return;
     }
     const Atoms at = make_atoms(L, emb, idx);
-    Route R{dout, pre, argmax, idx->tuple_group, idx->offsets, nullptr, h, L->agg, L->act_post};
+    float* dA = reinterpret_cast<float*>(w + P.ws_dA);
+    k_route_prep<<<grid_for(idx->G * h), 256, 0, s>>>(dout, pre, idx->offsets, idx->G, h, L->agg, L->act_post, dA);
+    RELNN_LAUNCHED();
+    Route R{dA, argmax, idx->tuple_group, nullptr, h, L->agg};
 
     if (L->act_pre != RELNN_ACT_NONE) {      // recompute act_pre'(x W + b) per tuple
       FwdArgs a{};

@@ -434,7 +434,7 @@ void launch_node_gemm(const void* X, int dtype, int64_t n, int K, int h, const v
     node_gemm_t<float>(X, n, K, h, Wsw, Y, s);
 }
 
-void check_layer(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P) {
+void check_layer_args(const relnn_index* idx, const relnn_layer_desc* L) {
   RELNN_REQUIRE(idx != nullptr && L != nullptr, RELNN_E_INVALID, "index or layer descriptor is NULL");
   RELNN_REQUIRE(L->k == idx->k, RELNN_E_INVALID, "layer has %d atoms, index has %d", L->k, idx->k);
   RELNN_REQUIRE(L->d != nullptr, RELNN_E_INVALID, "layer widths are NULL");
@@ -452,7 +452,13 @@ void check_layer(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
                   "d[%d] = %d: rows must be a multiple of 16 bytes", j, L->d[j]);
   }
   RELNN_REQUIRE(L->h % 16 == 0, RELNN_E_UNSUPPORTED, "h = %d must be a multiple of 16", L->h);
+}
+
+FwdPlan checked_plan(const relnn_index* idx, const relnn_layer_desc* L) {
+  check_layer_args(idx, L);
+  FwdPlan P = plan_fwd(idx, L);
   RELNN_REQUIRE(P.TM > 0, RELNN_E_UNSUPPORTED, "K = %d, h = %d does not fit the LDS tile", P.K, L->h);
+  return P;
 }
 
 Atoms make_atoms(const relnn_layer_desc* L, const void* const* emb, const relnn_index* idx) {
@@ -508,8 +514,7 @@ extern "C" relnn_status relnn_workspace_size(const relnn_index* idx, const relnn
                                              size_t* bytes) {
   return guard([&] {
     RELNN_REQUIRE(bytes != nullptr, RELNN_E_INVALID, "bytes is NULL");
-    FwdPlan P = plan_fwd(idx, L);
-    check_layer(idx, L, P);
+    FwdPlan P = checked_plan(idx, L);
     if (bwd) {
       *bytes = bwd_workspace(idx, L, P);
     } else {
@@ -523,9 +528,7 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
                                         float* pre, int32_t* argmax, void* ws, size_t ws_bytes,
                                         relnn_stream_t stream) {
   return guard([&] {
-    RELNN_REQUIRE(idx != nullptr && L != nullptr, RELNN_E_INVALID, "index or layer descriptor is NULL");
-    FwdPlan P = plan_fwd(idx, L);
-    check_layer(idx, L, P);
+    FwdPlan P = checked_plan(idx, L);
     const bool plain = (L->flags & RELNN_PLAIN) != 0;
     const bool push = (L->flags & RELNN_PUSHDOWN) != 0;
     RELNN_REQUIRE(!(plain && push), RELNN_E_INVALID, "RELNN_PLAIN and RELNN_PUSHDOWN exclude each other");

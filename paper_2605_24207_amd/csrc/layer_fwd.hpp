@@ -45,7 +45,8 @@ struct FwdPlan {
 };
 
 FwdPlan plan_fwd(const relnn_index* idx, const relnn_layer_desc* L);
-void check_layer(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P);
+// Validates the index / layer pair, then plans (RELNN_E_* on failure).
+FwdPlan checked_plan(const relnn_index* idx, const relnn_layer_desc* L);
 Atoms make_atoms(const relnn_layer_desc* L, const void* const* emb, const relnn_index* idx);
 void swizzle_w(const void* W, int dtype, int K, int Kp, int h, void* Wsw, hipStream_t s);
 void launch_fwd(const FwdPlan& P, const FwdArgs& a, int dtype, bool plain, hipStream_t s);

@@ -48,3 +48,28 @@ def test_validation_errors_without_gpu():
     d = _lib.JoinDesc()
     d.n_link, d.n_cols, d.n_atoms = 10, 0, 1
     assert L.relnn_build_index(ctypes.byref(d), None, ctypes.byref(out)) == _lib.E_INVALID
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librelnn.so not built")
+def test_more_validation_errors_without_gpu():
+    from paper_2605_24207_amd import _lib
+
+    L = _lib.lib()
+    out = ctypes.c_void_p()
+    # serving: NULL descriptor, then a descriptor with NULL relations
+    assert L.relnn_serve_create(None, ctypes.byref(out)) == _lib.E_INVALID
+    d = _lib.ServeDesc()
+    d.n_user = d.n_item = d.n_cat = 10
+    assert L.relnn_serve_create(ctypes.byref(d), ctypes.byref(out)) == _lib.E_INVALID
+    # layer calls without an index
+    ld = _lib.LayerDesc()
+    assert L.relnn_layer_fwd(None, ctypes.byref(ld), None, None, None, None, None, None, None, 0, None) == \
+        _lib.E_INVALID
+    n = ctypes.c_size_t()
+    assert L.relnn_workspace_size(None, ctypes.byref(ld), 0, ctypes.byref(n)) != _lib.OK
+    assert L.relnn_serve_destroy(None) == _lib.OK
+    # timing hooks are host-only
+    assert L.relnn_timing_enable(0) == _lib.OK
+    ms, cnt = ctypes.c_double(), ctypes.c_int64()
+    assert L.relnn_timing_read(b"fwd_fused", ctypes.byref(ms), ctypes.byref(cnt)) == _lib.OK
+    assert cnt.value == 0
