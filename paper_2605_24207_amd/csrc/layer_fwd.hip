@@ -91,9 +91,11 @@ __device__ __forceinline__ void gather_rows(const Atoms& at, const int32_t* __re
 __global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int64_t ntiles, int64_t nunits, int TM, int h,
                                                     Sink sink, const float* carry, const int32_t* carry_arg) {
   const int64_t b = (int64_t)blockIdx.x + 1;
-  if (sg.n_dev) {
+  if (sg.n_dev) {                  // run-time size: the forward kernels used min(units, tiles) units
     sg.n = *sg.n_dev;
     ntiles = (sg.n + TM - 1) / TM;
+    nunits = max<int64_t>(1, min<int64_t>(nunits, ntiles));
+    if (b >= nunits) return;
   }
   auto pos = [&](int64_t u) { return ((ntiles * u) / nunits) * TM; };
   const int64_t e = pos(b);

@@ -253,10 +253,12 @@ __device__ __forceinline__ uint4 chunk_load(const WsArgs& a, int64_t e0, int nv,
 template <int KP>
 __global__ void __launch_bounds__((4 + kGatherWaves) * 64) k_fwd_ws(WsArgs a) {
   using T = __bf16;
-  if (a.E_dev) {
+  if (a.E_dev) {                   // run-time size: as many units as tiles, at most the grid
     a.E = *a.E_dev;
     a.ntiles = (a.E + kTM - 1) / kTM;
     a.sg.n = a.E;
+    a.nunits = max<int64_t>(1, min<int64_t>(a.nunits, a.ntiles));
+    if ((int64_t)blockIdx.x >= a.nunits) return;
   }
   constexpr int TM = kTM;
   constexpr int XS = KP + 8;
@@ -372,10 +374,12 @@ __global__ void __launch_bounds__((4 + kGatherWaves) * 64) k_fwd_ws(WsArgs a) {
 // and W is swizzled to match (k_ws_swizzle_f16c).
 template <int KP, int NW>
 __global__ void __launch_bounds__(NW * 64) k_fwd_f32(WsArgs a) {
-  if (a.E_dev) {
+  if (a.E_dev) {                   // run-time size: as many units as tiles, at most the grid
     a.E = *a.E_dev;
     a.ntiles = (a.E + kTM - 1) / kTM;
     a.sg.n = a.E;
+    a.nunits = max<int64_t>(1, min<int64_t>(a.nunits, a.ntiles));
+    if ((int64_t)blockIdx.x >= a.nunits) return;
   }
   constexpr int TM = kTM;
   constexpr int XS = KP + 4;
