@@ -136,23 +136,29 @@ __device__ __forceinline__ float group_const(const GroupConst& g, int64_t s, int
   float v = g.bias ? g.bias[c] : 0.0f;
   if (g.n) {
     const int64_t e = g.offsets[s];
-    for (int j = 0; j < g.n; ++j) v += g.P[j][(int64_t)g.rows[j][e] * h + c];
+#pragma unroll
+    for (int j = 0; j < RELNN_MAX_ATOMS; ++j)    // constant trip count: no run-time index into the argument
+      if (j < g.n) v += g.P[j][(int64_t)g.rows[j][e] * h + c];
   }
   return v;
 }
 
+// kStoreOnly: the sink has no group constant, no row remap and no
+// accumulation, so writing issues no global load (a kernel that keeps
+// gathers in flight must not wait on them to write a result).
+template <bool kStoreOnly = false>
 __device__ __forceinline__ void sink_write(const Sink& k, int64_t s, int c, int h, float v, int32_t am,
                                            int32_t cnt) {
   if (k.agg == RELNN_MEAN) v = v / (float)cnt;
-  if (k.gc.n || k.gc.bias) {          // pushed-down transform: add the group's constant term
+  if (!kStoreOnly && (k.gc.n || k.gc.bias)) {   // pushed-down transform: add the group's constant term
     const float g = group_const(k.gc, s, c, h);
     v = (k.agg == RELNN_SUM) ? v + (float)cnt * g : v + g;
   }
-  const int64_t row = k.out_row ? (int64_t)k.out_row[s] : s;
+  const int64_t row = (!kStoreOnly && k.out_row) ? (int64_t)k.out_row[s] : s;
   const int64_t o = row * h + c;
   if (k.pre) k.pre[o] = v;
   if (k.argmax && k.agg == RELNN_MAX) k.argmax[o] = am;
-  if (k.accumulate)
+  if (!kStoreOnly && k.accumulate)
     k.out[o] += v;
   else if (k.out_bf16)
     reinterpret_cast<__bf16*>(k.out)[o] = (__bf16)act_apply(k.act_post, v);

@@ -63,7 +63,14 @@ struct OpenState {
   int32_t arg[2][kHMax];     // argmax (MAX)
   int32_t n[2][kHMax];       // tuples so far
   int32_t cut[2][kHMax];     // the group started before the block's range
+  float bias[kHMax];         // b (zero if none), staged once per block
 };
+
+// Stages b in LDS so that the reduce issues no global load of its own
+// (such a load would wait for every gather load in flight before it).
+__device__ __forceinline__ void stage_bias(OpenState* op, const WsArgs& a, int tid, int nthr) {
+  for (int c = tid; c < a.h; c += nthr) op->bias[c] = a.b ? a.b[c] : 0.0f;
+}
 
 __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
   const float y = x - c;
@@ -122,6 +129,7 @@ __device__ __forceinline__ void seg_stage(TileInfo* ti, const WsArgs& a, int64_t
 // MAX per run; finished groups are written, the open group is carried to
 // the next tile of the block, groups cut by the block's range ends leave a
 // partial (slot 0: cut by the range start, slot 1: runs past the end).
+template <bool kStoreOnly>
 __device__ __forceinline__ void ws_reduce(const WsArgs& a, int64_t t, const float* Y, int YS, const TileInfo* ti,
                                           int64_t tb, int64_t range_hi, OpenState* op, int tid, int nthr) {
   const int h = a.h;
@@ -135,7 +143,7 @@ __device__ __forceinline__ void ws_reduce(const WsArgs& a, int64_t t, const floa
     const int c = p - q * h;
     const int r0 = ti->rstart[q], r1 = ti->rstart[q + 1];
     const int64_t s = ti->rgrp[q];
-    const float bc = a.b ? a.b[c] : 0.0f;
+    const float bc = op->bias[c];
     float S, Cc = 0.0f;
     int32_t am = -1;
     if (maxagg) {
@@ -187,7 +195,7 @@ __device__ __forceinline__ void ws_reduce(const WsArgs& a, int64_t t, const floa
         if (a.carry_arg) a.carry_arg[(bidx * 2 + slot) * h + c] = am;
       }
     } else if (!cut) {                             // complete inside this block
-      sink_write(a.sink, s, c, h, S - Cc, am, cnt);
+      sink_write<kStoreOnly>(a.sink, s, c, h, S - Cc, am, cnt);
     } else {                                       // cut by the range start
       a.carry[(bidx * 2 + 0) * h + c] = S - Cc;
       if (a.carry_arg) a.carry_arg[(bidx * 2 + 0) * h + c] = am;
@@ -229,24 +237,76 @@ __global__ void k_ws_swizzle_f16c(const float* __restrict__ W, int K, int KP, in
   }
 }
 
-// Chunk i (16 bytes) of a tile's row-major copy: loaded (zero outside the
-// tile or past K); dst receives its LDS element offset.
-template <class T, int CPR, int XS>
-__device__ __forceinline__ uint4 chunk_load(const WsArgs& a, int64_t e0, int nv, int i, int& dst) {
+// A tile's row-major copy in LDS is moved in 16-byte chunks; chunk i is row
+// i / CPR, elements (i % CPR) * EPC onwards.  Loading takes two stages so
+// that no data load waits on its own row index: chunk_row reads the joined
+// row of the chunk's atom a tile ahead of chunk_fetch, which reads the 16
+// bytes.
+struct AtomRef {
+  const int32_t* rows;
+  const void* emb;
+  int d, koff;
+};
+
+// The atom that owns Concat column el.  Picked with compile-time indices:
+// indexing the argument's arrays with a run-time value would move the whole
+// argument to scratch memory.
+__device__ __forceinline__ AtomRef atom_of(const Atoms& at, int el) {
+  AtomRef r{at.rows[0], at.emb[0], at.d[0], 0};
+  auto pick = [&](auto U) {
+    constexpr int u = decltype(U)::value;
+    if (u < at.k && el >= at.koff[u]) r = AtomRef{at.rows[u], at.emb[u], at.d[u], at.koff[u]};
+  };
+  static_assert(kMaxAtoms == 4, "one pick per atom after the first");
+  pick(std::integral_constant<int, 1>{});
+  pick(std::integral_constant<int, 2>{});
+  pick(std::integral_constant<int, 3>{});
+  return r;
+}
+
+// Both stages are branch-free: a chunk outside the tile (row >= nv) or in
+// the K..KP pad reads a clamped, valid address and is zeroed when stored,
+// so every thread issues the same straight run of loads.
+template <class T, int CPR>
+__device__ __forceinline__ int32_t chunk_row(const WsArgs& a, int64_t e0, int nv, int i) {
   constexpr int EPC = 16 / sizeof(T);
+  const int r = min(i / CPR, nv - 1);
+  const int el = min((i % CPR) * EPC, a.K - EPC);
+  return atom_of(a.at, el).rows[e0 + r];
+}
+
+template <class T, int CPR>
+__device__ __forceinline__ uint4 chunk_fetch(const WsArgs& a, int i, int32_t row) {
+  constexpr int EPC = 16 / sizeof(T);
+  const int el = min((i % CPR) * EPC, a.K - EPC);
+  const AtomRef A = atom_of(a.at, el);
+  return *reinterpret_cast<const uint4*>(static_cast<const T*>(A.emb) + (int64_t)row * A.d + (el - A.koff));
+}
+
+// Whether chunk i holds data (else it is stored as zeros).  Applied when
+// the chunk is written to LDS, long after its load was issued: a select
+// right after the load lets the compiler turn the load into a branch whose
+// zero path must wait for every load in flight.
+template <class T, int CPR>
+__device__ __forceinline__ bool chunk_valid(const WsArgs& a, int nv, int i) {
+  constexpr int EPC = 16 / sizeof(T);
+  return i / CPR < nv && (i % CPR) * EPC < a.K;
+}
+
+// v, or zeros if !keep (masks on values: a conditional over two uint4
+// lvalues would select between their addresses and keep v in scratch).
+__device__ __forceinline__ uint4 keep_or_zero(bool keep, uint4 v) {
+  const uint32_t m = keep ? 0xffffffffu : 0u;
+  return make_uint4(v.x & m, v.y & m, v.z & m, v.w & m);
+}
+
+// LDS element offset of chunk i (-1 past the tile).
+template <class T, int CPR, int XS>
+__device__ __forceinline__ int chunk_dst(int i) {
+  constexpr int EPC = 16 / sizeof(T);
+  if (i >= kTM * CPR) return -1;
   const int r = i / CPR;
-  const int el = (i - r * CPR) * EPC;
-  dst = r * XS + el;
-  uint4 v = make_uint4(0, 0, 0, 0);
-  if (r < nv && el < a.K) {
-    int j = 0;
-#pragma unroll
-    for (int u = 1; u < kMaxAtoms; ++u)
-      if (u < a.at.k && el >= a.at.koff[u]) j = u;
-    const int64_t row = a.at.rows[j][e0 + r];
-    v = *reinterpret_cast<const uint4*>(static_cast<const T*>(a.at.emb[j]) + row * a.at.d[j] + (el - a.at.koff[j]));
-  }
-  return v;
+  return r * XS + (i - r * CPR) * EPC;
 }
 
 // ---------------------------------------------------------------- BF16
@@ -286,6 +346,7 @@ __global__ void __launch_bounds__((4 + kGatherWaves) * 64) k_fwd_ws(WsArgs a) {
   const int64_t te = (a.ntiles * (bidx + 1)) / a.nunits;
   const int64_t range_hi = min<int64_t>(te * TM, a.E);
   if (tb >= te) return;
+  stage_bias(op, a, threadIdx.x, blockDim.x);
 
   bf16x8 w[NKS];
   if (compute) {
@@ -294,15 +355,28 @@ __global__ void __launch_bounds__((4 + kGatherWaves) * 64) k_fwd_ws(WsArgs a) {
     for (int ks = 0; ks < NKS; ++ks) w[ks] = src[ks * 64 + lane];
   }
 
-  if (!compute) {                            // prologue: tile tb
-    const int64_t e0 = tb * TM;
+  // gather waves: row indices two tiles ahead, data one tile ahead
+  int32_t ridx[CH];
+  auto load_idx = [&](int64_t t) {
+    const int64_t e0 = t * TM;
     const int nv = (int)min<int64_t>(TM, a.E - e0);
-    for (int i = gt; i < TM * CPR; i += 256) {
-      int dst;
-      const uint4 v = chunk_load<T, CPR, XS>(a, e0, nv, i, dst);
-      *reinterpret_cast<uint4*>(Xb + dst) = v;
+#pragma unroll
+    for (int q = 0; q < CH; ++q) ridx[q] = chunk_row<T, CPR>(a, e0, nv, gt + q * 256);
+  };
+  if (!compute) {                            // prologue: tile tb, indices of tb + 1
+    load_idx(tb);
+    uint4 v[CH];
+    const int nv = (int)min<int64_t>(TM, a.E - tb * TM);
+#pragma unroll
+    for (int q = 0; q < CH; ++q) v[q] = chunk_fetch<T, CPR>(a, gt + q * 256, ridx[q]);
+    const SegLoad L = stager ? seg_load(a, tb) : SegLoad{-1, -1, -1};
+    if (tb + 1 < te) load_idx(tb + 1);
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int dst = chunk_dst<T, CPR, XS>(gt + q * 256);
+      if (dst >= 0) *reinterpret_cast<uint4*>(Xb + dst) = keep_or_zero(chunk_valid<T, CPR>(a, nv, gt + q * 256), v[q]);
     }
-    if (stager) seg_stage(&tinfo[0], a, tb, seg_load(a, tb));
+    if (stager) seg_stage(&tinfo[0], a, tb, L);
   }
   __syncthreads();
   for (int64_t t = tb; t <= te; ++t) {
@@ -335,28 +409,28 @@ __global__ void __launch_bounds__((4 + kGatherWaves) * 64) k_fwd_ws(WsArgs a) {
         }
       }
     } else {
-      // load-bound: keep every load of tile t+1 in flight while reducing t-1
+      // load-bound: the data of tile t+1 and the indices of t+2 are in
+      // flight while t-1 is reduced
       const bool more = t + 1 < te;
-      const int64_t e1 = (t + 1) * TM;
-      const int nv1 = more ? (int)min<int64_t>(TM, a.E - e1) : 0;
       uint4 v[CH];
-      int dst[CH];
       SegLoad L{-1, -1, -1};
+      const int nv1 = more ? (int)min<int64_t>(TM, a.E - (t + 1) * TM) : 0;
+      if (more) {
+#pragma unroll
+        for (int q = 0; q < CH; ++q) v[q] = chunk_fetch<T, CPR>(a, gt + q * 256, ridx[q]);
+        if (stager) L = seg_load(a, t + 1);
+      }
+      if (t + 2 < te) load_idx(t + 2);
+      if (t > tb)
+        ws_reduce<true>(a, t - 1, Yb + (buf ^ 1) * TM * YS, YS, &tinfo[(t - 1 - tb) & 3], tb, range_hi, op, gt, 256);
       if (more) {
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
-          const int i = gt + q * 256;
-          dst[q] = -1;
-          if (i < TM * CPR) v[q] = chunk_load<T, CPR, XS>(a, e1, nv1, i, dst[q]);
+          const int dst = chunk_dst<T, CPR, XS>(gt + q * 256);
+          if (dst >= 0)
+            *reinterpret_cast<uint4*>(Xb + (buf ^ 1) * TM * XS + dst) =
+                keep_or_zero(chunk_valid<T, CPR>(a, nv1, gt + q * 256), v[q]);
         }
-        if (stager) L = seg_load(a, t + 1);
-      }
-      if (t > tb)
-        ws_reduce(a, t - 1, Yb + (buf ^ 1) * TM * YS, YS, &tinfo[(t - 1 - tb) & 3], tb, range_hi, op, gt, 256);
-      if (more) {
-#pragma unroll
-        for (int q = 0; q < CH; ++q)
-          if (dst[q] >= 0) *reinterpret_cast<uint4*>(Xb + (buf ^ 1) * TM * XS + dst[q]) = v[q];
         if (stager) seg_stage(&tinfo[(t + 1 - tb) & 3], a, t + 1, L);
       }
     }
@@ -399,6 +473,7 @@ __global__ void __launch_bounds__(NW * 64) k_fwd_f32(WsArgs a) {
   const int64_t te = (a.ntiles * ((int64_t)blockIdx.x + 1)) / a.nunits;
   const int64_t range_hi = min<int64_t>(te * TM, a.E);
   if (tb >= te) return;
+  stage_bias(op, a, threadIdx.x, blockDim.x);
 
   float w[NKS];
   {
@@ -407,28 +482,35 @@ __global__ void __launch_bounds__(NW * 64) k_fwd_f32(WsArgs a) {
     for (int ks = 0; ks < NKS; ++ks) w[ks] = src[ks * 64 + lane];
   }
 
+  // row indices two tiles ahead, data one tile ahead
+  int32_t ridx[CH];
   uint4 v[CH];
-  int dst[CH];
   SegLoad L{-1, -1, -1};
-  auto load = [&](int64_t t) {
+  auto load_idx = [&](int64_t t) {
     const int64_t e0 = t * TM;
     const int nv = (int)min<int64_t>(TM, a.E - e0);
 #pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int i = threadIdx.x + q * nthr;
-      dst[q] = -1;
-      if (i < TM * CPR) v[q] = chunk_load<float, CPR, XS>(a, e0, nv, i, dst[q]);
-    }
+    for (int q = 0; q < CH; ++q) ridx[q] = chunk_row<float, CPR>(a, e0, nv, threadIdx.x + q * nthr);
+  };
+  auto load_data = [&](int64_t t) {
+#pragma unroll
+    for (int q = 0; q < CH; ++q) v[q] = chunk_fetch<float, CPR>(a, threadIdx.x + q * nthr, ridx[q]);
     if (wave == 0) L = seg_load(a, t);
   };
   auto store = [&](float* X, TileInfo* ti, int64_t t) {
+    const int nv = (int)min<int64_t>(TM, a.E - t * TM);
 #pragma unroll
-    for (int q = 0; q < CH; ++q)
-      if (dst[q] >= 0) *reinterpret_cast<uint4*>(X + dst[q]) = v[q];
+    for (int q = 0; q < CH; ++q) {
+      const int dst = chunk_dst<float, CPR, XS>(threadIdx.x + q * nthr);
+      if (dst >= 0)
+        *reinterpret_cast<uint4*>(X + dst) = keep_or_zero(chunk_valid<float, CPR>(a, nv, threadIdx.x + q * nthr), v[q]);
+    }
     if (wave == 0) seg_stage(ti, a, t, L);
   };
 
-  load(tb);
+  load_idx(tb);
+  load_data(tb);
+  if (tb + 1 < te) load_idx(tb + 1);
   store(Xb, &tinfo[0], tb);
   __syncthreads();
   for (int64_t t = tb; t < te; ++t) {
@@ -436,7 +518,8 @@ __global__ void __launch_bounds__(NW * 64) k_fwd_f32(WsArgs a) {
     const float* X = Xb + buf * TM * XS;
     float* Y = Yb + buf * TM * YS;
     const bool more = t + 1 < te;
-    if (more) load(t + 1);
+    if (more) load_data(t + 1);
+    if (t + 2 < te) load_idx(t + 2);
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -458,7 +541,7 @@ __global__ void __launch_bounds__(NW * 64) k_fwd_f32(WsArgs a) {
     }
     if (more) store(Xb + (buf ^ 1) * TM * XS, &tinfo[(t + 1 - tb) & 3], t + 1);
     __syncthreads();
-    ws_reduce(a, t, Y, YS, &tinfo[(t - tb) & 3], tb, range_hi, op, threadIdx.x, nthr);
+    ws_reduce<true>(a, t, Y, YS, &tinfo[(t - tb) & 3], tb, range_hi, op, threadIdx.x, nthr);
   }
 }
 
@@ -492,6 +575,7 @@ __global__ void __launch_bounds__(NW * 64) k_push(WsArgs a, PushArgs pa) {
   const int64_t te = (a.ntiles * ((int64_t)blockIdx.x + 1)) / a.nunits;
   const int64_t range_hi = min<int64_t>(te * TM, a.E);
   if (tb >= te) return;
+  stage_bias(op, a, threadIdx.x, blockDim.x);
 
   f32x4 acc[CH];
   SegLoad L{-1, -1, -1};
@@ -530,7 +614,7 @@ __global__ void __launch_bounds__(NW * 64) k_push(WsArgs a, PushArgs pa) {
     const int buf = (int)((t - tb) & 1);
     const bool more = t + 1 < te;
     if (more) load(t + 1);
-    ws_reduce(a, t, Yb + buf * TM * YS, YS, &tinfo[(t - tb) & 3], tb, range_hi, op, threadIdx.x, nthr);
+    ws_reduce<false>(a, t, Yb + buf * TM * YS, YS, &tinfo[(t - tb) & 3], tb, range_hi, op, threadIdx.x, nthr);
     if (more) store(Yb + (buf ^ 1) * TM * YS, &tinfo[(t + 1 - tb) & 3], t + 1);
     __syncthreads();
   }
@@ -657,6 +741,8 @@ void swizzle_ws(const void* W, int dtype, int K, int KP, int h, void* out, hipSt
 
 void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, float* carry, int32_t* carry_arg,
                hipStream_t s) {
+  RELNN_REQUIRE(!f.sink.accumulate && !f.sink.out_row && !f.sink.gc.n && !f.sink.gc.bias, RELNN_E_UNSUPPORTED,
+                "the fused forward kernels write plain outputs only");
   WsArgs a{};
   a.at = f.at;
   a.rows = f.rows;
