@@ -105,6 +105,7 @@ class Net:
         self.tuples = sum(x.E for x in ix)
         # algorithmic flops of one step: per tuple 2 K h (Linear) + h (bias) + h (aggregate)
         self.flops = sum(x.E * (2 * K * 128 + 2 * 128) for x, K in zip(ix, (384, 256, 384, 256)))
+        self.bytes = step_bytes(ix, (384, 256, 384, 256), (3, 2, 3, 2), 128, 2 if dtype == "bf16" else 4)
 
     def step(self):
         from paper_2605_24207_amd import layer_fwd
@@ -118,6 +119,32 @@ class Net:
                   want_pre=False, ws=self.ws, out=o[2])
         layer_fwd(D["ix_user2"], self.L_user, [o[1], o[0]], self.W_user[1], D["b_user"][1],
                   want_pre=False, ws=self.ws, out=o[3])
+
+
+def step_bytes(ix, Ks, ks, h, esz):
+    """Algorithmic HBM bytes of one step, per kernel kind, summed over the
+    step's layers (E tuples, G groups, K = Concat width, k atoms):
+      fused   every joined row read once (E K esz), the k row numbers and the
+              group number per tuple (4 (k + 1) E), out written (G h esz_out)
+      gather  joined rows read and X written (2 E K esz) + row numbers (4 k E)
+      gemm    X read (E K esz), Y written (4 E h), W (K h esz)
+      reduce  Y and group numbers read (4 E (h + 1)), out written (4 G h),
+              offsets (4 G)"""
+    b = {"fused": 0, "gather": 0, "gemm": 0, "reduce": 0}
+    for x, K, k in zip(ix, Ks, ks):
+        E, G = x.E, x.G
+        b["fused"] += E * K * esz + 4 * (k + 1) * E + G * h * esz
+        b["gather"] += 2 * E * K * esz + 4 * k * E
+        b["gemm"] += E * K * esz + 4 * E * h + K * h * esz
+        b["reduce"] += 4 * E * (h + 1) + 4 * G * h + 4 * G
+    return b
+
+
+def gbs(nbytes_per_step, steps, kt):
+    """Achieved GB/s of a kernel: its algorithmic bytes over its summed
+    launch time (HIP events on the launch stream)."""
+    ms = kt[0]
+    return nbytes_per_step * steps / (ms * 1e-3) / 1e9 if ms > 0 else None
 
 
 def time_net(net: Net, steps: int, warmup: int, kernels):
@@ -317,7 +344,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
-    ap.add_argument("--cpu-budget", type=int, default=2_000_000, help="oracle sample size in tuples")
+    ap.add_argument("--cpu-budget", type=int, default=9_000_000, help="oracle sample size in tuples")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="f32,plain,bf16,push_f32,push_bf16,serve,fwdbwd",
                     help="comma list of f32,plain,bf16,push_f32,push_bf16,serve,fwdbwd")
@@ -348,31 +375,36 @@ def main():
                 ["fwd_push"] if leg.startswith("push") else ["fwd_fused"])
         steps = args.steps if leg != "plain" else max(1, args.steps // 2)
         dt, kt = time_net(net, steps, args.warmup, kern)
-        res[leg] = {"dt": dt, "steps": steps, "kt": kt, "tuples": net.tuples, "flops": net.flops}
+        res[leg] = {"dt": dt, "steps": steps, "kt": kt, "tuples": net.tuples, "flops": net.flops,
+                    "bytes": net.bytes}
         log(f"{leg}: {dt / steps * 1e3:.2f} ms/step, {net.tuples * steps / dt / 1e9:.3f} G tuples/s; "
             + ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms x{v[1]}" for k, v in kt.items()))
         del net
         torch.cuda.empty_cache()
 
-    main_leg = res["f32"]
-    ms = main_leg["dt"] / main_leg["steps"] * 1e3
-    value = main_leg["tuples"] * main_leg["steps"] / main_leg["dt"]
-    k_ms, k_n = main_leg["kt"]["fwd_fused"]
-    launches_per_step = k_n / main_leg["steps"]
-    flops_per_launch = main_leg["flops"] / launches_per_step
-    achieved = flops_per_launch / (k_ms / k_n * 1e-3) / 1e12
-    line = {
-        "metric": METRIC, "value": value, "unit": "tuples/s", "n_gpus": 1, "steps": main_leg["steps"],
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "ER schema User 1M / Item 500k / Category 1k, Buys 20M (item Zipf 1.1), "
-                               "hidden 128, 2 layers x (Item SUM K=384, User MEAN K=256), ReLU, FP32 forward",
-                   "scale": args.scale, "tuples_per_step": main_leg["tuples"], "layers_per_step": 4,
-                   "index_build_s": round(D["index_build_s"], 3)},
-        "roofline": {"bound": "mfma", "kernel": "k_layer_fwd<float, fused>", "achieved": achieved,
-                     "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"],
-                     "traffic": None, "avg_launch_ms": k_ms / k_n},
-    }
+    line = {"metric": METRIC, "value": None, "unit": "tuples/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "ER schema User 1M / Item 500k / Category 1k, Buys 20M (item Zipf 1.1), "
+                                   "hidden 128, 2 layers x (Item SUM K=384, User MEAN K=256), ReLU, FP32 forward",
+                       "scale": args.scale, "layers_per_step": 4, "index_build_s": round(D["index_build_s"], 3)}}
+    value = None
+    if "f32" in res:
+        main_leg = res["f32"]
+        value = main_leg["tuples"] * main_leg["steps"] / main_leg["dt"]
+        k_ms, k_n = main_leg["kt"]["fwd_fused"]
+        launches_per_step = k_n / main_leg["steps"]
+        flops_per_launch = main_leg["flops"] / launches_per_step
+        achieved = flops_per_launch / (k_ms / k_n * 1e-3) / 1e12
+        line.update({"value": value, "steps": main_leg["steps"],
+                     "ms_per_step": main_leg["dt"] / main_leg["steps"] * 1e3})
+        line["config"]["tuples_per_step"] = main_leg["tuples"]
+        line["roofline"] = {"bound": "mfma", "kernel": "k_fwd_f32 (fused FP32 layer)", "achieved": achieved,
+                            "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"],
+                            "traffic": None, "avg_launch_ms": k_ms / k_n,
+                            "flop_per_launch": flops_per_launch,
+                            "hbm_gbs_algorithmic": gbs(main_leg["bytes"]["fused"], main_leg["steps"],
+                                                       main_leg["kt"]["fwd_fused"])}
     for leg, key in (("plain", "plain_f32"), ("bf16", "fused_bf16"), ("push_f32", "pushdown_f32"),
                      ("push_bf16", "pushdown_bf16")):
         if leg in res:
@@ -381,13 +413,21 @@ def main():
                          "ms_per_step": r["dt"] / r["steps"] * 1e3,
                          "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in r["kt"].items()}}
     if "plain" in res:
-        line["speedup_vs_plain_f32"] = value / line["plain_f32"]["value"]
+        r = res["plain"]
+        if value is not None:
+            line["speedup_vs_plain_f32"] = value / line["plain_f32"]["value"]
+        line["plain_f32"]["hbm_gbs"] = {k: gbs(r["bytes"][k], r["steps"], r["kt"]["fwd_" + k])
+                                        for k in ("gather", "reduce")}
+        line["plain_f32"]["gemm_tflops"] = (r["flops"] * r["steps"] / (r["kt"]["fwd_gemm"][0] * 1e-3) / 1e12
+                                            if r["kt"]["fwd_gemm"][0] > 0 else None)
+        line["plain_f32"]["hbm_peak_gbs"] = PEAK_HBM_GBS
     if "bf16" in res:
         r = res["bf16"]
         bk_ms, bk_n = r["kt"]["fwd_fused"]
         line["fused_bf16"]["speedup_vs_plain_f32"] = (line["fused_bf16"]["value"] / line["plain_f32"]["value"]
                                                       if "plain" in res else None)
         line["fused_bf16"]["mfma_tflops"] = r["flops"] / (bk_n / r["steps"]) / (bk_ms / bk_n * 1e-3) / 1e12
+        line["fused_bf16"]["hbm_gbs_algorithmic"] = gbs(r["bytes"]["fused"], r["steps"], r["kt"]["fwd_fused"])
     if "serve" in legs:
         rates = [float(x) for x in args.serve_rates.split(",")]
         line["serve"] = {"workload": "resident ER graph (Buys 20M); requests of log-uniform 1..4096 seed items, "

@@ -16,7 +16,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librelnn.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "prims.hip", "index.hip", "layer_fwd.hip", "layer_ws.hip", "layer_bwd.hip", "serve.hip"]
+SOURCES = ["api.cpp", "prims.hip", "index.hip", "layer_fwd.hip", "layer_ws.hip", "plain.hip", "layer_bwd.hip",
+           "serve.hip"]
+ROCM_LIB = "/opt/rocm/lib"
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -48,7 +50,9 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    # rocBLAS: the plain path's GEMM (a library GEMM by design)
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + [
+        f"-L{ROCM_LIB}", "-lrocblas", f"-Wl,-rpath,{ROCM_LIB}"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -11,9 +11,10 @@
 // into LDS with 16-byte coalesced loads, multiplies them on the matrix cores
 // (bf16 16x16x32 or f32 16x16x4, FP32 accumulation), keeps the FP32 result
 // tile in LDS and reduces it per group; nothing of size [E, .] reaches HBM.
-// Plain path: the same steps as three kernels that materialise X = [E, K]
-// and Y = [E, h] in HBM, the shape of a library pipeline
-// (index_select + cat -> Linear -> scatter).
+// Plain path (plain.hip): the same steps as a gather kernel, a library
+// GEMM and a segmented-reduce kernel that materialise X = [E, K] and
+// Y = [E, h] in HBM, the shape of a library pipeline (index_select + cat
+// -> Linear -> scatter).
 #include "layer_common.hpp"
 #include "layer_fwd.hpp"
 
@@ -174,7 +175,7 @@ __global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int64_t ntiles, int6
 }
 
 
-enum { MODE_FUSED = 0, MODE_GEMM = 1, MODE_REDUCE = 2, MODE_MASK = 3 };
+enum { MODE_FUSED = 0, MODE_MASK = 3 };
 
 // One tile of TM tuples per block.
 template <class T, int MODE>
@@ -200,22 +201,11 @@ __global__ void __launch_bounds__(kThreads) k_layer_fwd(FwdArgs a) {
     __syncthreads();
     gather_rows<T>(a.at, a.rows, a.E, e0, nv, TM, a.K, a.Kp, Xs, XS, rowidx);
   }
-  if constexpr (MODE == MODE_GEMM) {
-    constexpr int EPC = Mfma<T>::EPC;
-    const int cpr = a.Kp / EPC;
-    const T* X = static_cast<const T*>(a.X);
-    for (int i = threadIdx.x; i < TM * cpr; i += blockDim.x) {
-      const int r = i / cpr, c = i - (i / cpr) * cpr;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (r < nv) v = *reinterpret_cast<const uint4*>(X + (e0 + r) * a.Kp + c * EPC);
-      *reinterpret_cast<uint4*>(Xs + r * XS + c * EPC) = v;
-    }
-  }
-  if constexpr (MODE != MODE_REDUCE) {
+  {
     __syncthreads();
     f32x4 acc[kMaxQ];
     mfma_tile<T>(Xs, XS, a.Kp, nblk, ncb, static_cast<const T*>(a.Wsw), acc);
-    if constexpr (MODE == MODE_GEMM || MODE == MODE_MASK) {
+    if constexpr (MODE == MODE_MASK) {
       const int lane = __lane_id();
       const int w = threadIdx.x / 64;
 #pragma unroll
@@ -228,23 +218,13 @@ __global__ void __launch_bounds__(kThreads) k_layer_fwd(FwdArgs a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int row = rb * 16 + (lane >> 4) * 4 + i;
-            if (row < nv) {
-              if constexpr (MODE == MODE_MASK)
-                a.mask[(e0 + row) * a.h + col] = (acc[qi][i] + bv) > 0.0f ? 1 : 0;
-              else
-                a.Y[(e0 + row) * a.h + col] = act_apply(a.act_pre, acc[qi][i] + bv);
-            }
+            if (row < nv) a.mask[(e0 + row) * a.h + col] = (acc[qi][i] + bv) > 0.0f ? 1 : 0;
           }
         }
       }
       return;
     } else {
       store_acc(acc, nblk, ncb, a.b, a.act_pre, Ys, YS);
-    }
-  } else {
-    for (int i = threadIdx.x; i < nv * a.h; i += blockDim.x) {
-      const int r = i / a.h, c = i - (i / a.h) * a.h;
-      Ys[r * YS + c] = a.Y[(e0 + r) * a.h + c];
     }
   }
   __syncthreads();
@@ -299,20 +279,15 @@ void launch_fwd_t(const FwdPlan& P, FwdArgs a, bool plain, hipStream_t s) {
           a.at, a.rows, a.E, a.K, a.Kp, static_cast<T*>(const_cast<void*>(a.X)));
       RELNN_LAUNCHED();
     }
-    allow_lds(k_layer_fwd<T, MODE_GEMM>, P.lds);
     {
       KTimer t("fwd_gemm", s);
-      k_layer_fwd<T, MODE_GEMM><<<(unsigned)ntiles, kThreads, P.lds, s>>>(a);
-      RELNN_LAUNCHED();
+      plain_gemm(std::is_same<T, __bf16>::value ? RELNN_BF16 : RELNN_F32, a.X, a.E, a.K, a.Kp, a.W, a.h, a.Y, s);
     }
-    allow_lds(k_layer_fwd<T, MODE_REDUCE>, P.lds);
-    {
-      KTimer t("fwd_reduce", s);
-      k_layer_fwd<T, MODE_REDUCE><<<(unsigned)ntiles, kThreads, P.lds, s>>>(a);
-      RELNN_LAUNCHED();
-    }
-  } else {
-    allow_lds(k_layer_fwd<T, MODE_FUSED>, P.lds);
+    launch_seg_reduce(a.Y, a.E, a.h, a.sg, a.b, a.act_pre, a.sink, a.carry, a.carry_arg, P.carry_units, s);
+    return;
+  }
+  allow_lds(k_layer_fwd<T, MODE_FUSED>, P.lds);
+  {
     KTimer t("fwd_fused", s);
     k_layer_fwd<T, MODE_FUSED><<<(unsigned)ntiles, kThreads, P.lds, s>>>(a);
     RELNN_LAUNCHED();
@@ -379,8 +354,6 @@ FwdPlan plan_fwd(const relnn_index* idx, const relnn_layer_desc* L) {
     for (int j = 0; j < L->k; ++j) {
       P.ws_push_p[j] = o;
       o += round_up(std::max<int64_t>(idx->n_rows[j], 1) * h * 4, 256);
-      P.ws_push_w[j] = o;
-      o += round_up((int64_t)L->d[j] * h * esz, 256);
     }
     P.carry_units = std::max<int64_t>(P.carry_units, push_units(E));
     P.ws_carry = o;
@@ -390,50 +363,6 @@ FwdPlan plan_fwd(const relnn_index* idx, const relnn_layer_desc* L) {
     P.ws_push = o;
   }
   return P;
-}
-
-namespace {
-template <class T>
-void node_gemm_t(const void* X, int64_t n, int K, int h, const void* Wsw, float* Y, hipStream_t s) {
-  constexpr int XPAD = Mfma<T>::XPAD;
-  int TM = 0;
-  size_t lds = 0, off_x = 0, off_y = 0;
-  for (int tm : {64, 32, 16}) {
-    if ((tm / 16) * (h / 16) > 4 * kMaxQ) continue;
-    off_x = round_up((size_t)kMaxAtoms * tm * 4, 16);
-    off_y = off_x + round_up((size_t)tm * (K + XPAD) * sizeof(T), 16);
-    lds = off_y + (size_t)tm * (h + 4) * 4;
-    if (lds <= 160 * 1024) {
-      TM = tm;
-      break;
-    }
-  }
-  RELNN_REQUIRE(TM > 0, RELNN_E_UNSUPPORTED, "node product K = %d, h = %d does not fit the LDS tile", K, h);
-  FwdArgs g{};
-  g.E = n;
-  g.K = K;
-  g.Kp = K;
-  g.h = h;
-  g.TM = TM;
-  g.off_x = (int)off_x;
-  g.off_y = (int)off_y;
-  g.Wsw = Wsw;
-  g.act_pre = RELNN_ACT_NONE;
-  g.X = X;
-  g.Y = Y;
-  allow_lds(k_layer_fwd<T, MODE_GEMM>, lds);
-  k_layer_fwd<T, MODE_GEMM><<<(unsigned)cdiv(n, TM), kThreads, lds, s>>>(g);
-  RELNN_LAUNCHED();
-}
-}  // namespace
-
-void launch_node_gemm(const void* X, int dtype, int64_t n, int K, int h, const void* Wsw, float* Y,
-                      hipStream_t s) {
-  if (n <= 0) return;
-  if (dtype == RELNN_BF16)
-    node_gemm_t<__bf16>(X, n, K, h, Wsw, Y, s);
-  else
-    node_gemm_t<float>(X, n, K, h, Wsw, Y, s);
 }
 
 void check_layer_args(const relnn_index* idx, const relnn_layer_desc* L) {
@@ -568,6 +497,7 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
     a.off_x = (int)P.off_x;
     a.off_y = (int)P.off_y;
     a.Wsw = w + P.ws_wsw;
+    a.W = W;
     a.b = b;
     a.act_pre = L->act_pre;
     a.sg = Seg{idx->tuple_group, idx->offsets, idx->E, nullptr};
@@ -581,10 +511,10 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
       const int esz = L->dtype == RELNN_BF16 ? 2 : 4;
       const float* Pj[kMaxAtoms];
       for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
-        void* wj = w + P.ws_push_w[j];
-        swizzle_w(static_cast<const char*>(W) + (size_t)koff * L->h * esz, L->dtype, L->d[j], L->d[j], L->h, wj, s);
         Pj[j] = reinterpret_cast<const float*>(w + P.ws_push_p[j]);
-        launch_node_gemm(emb[j], L->dtype, idx->n_rows[j], L->d[j], L->h, wj, const_cast<float*>(Pj[j]), s);
+        KTimer t("node_gemm", s);
+        plain_gemm(L->dtype, emb[j], idx->n_rows[j], L->d[j], L->d[j],
+                   static_cast<const char*>(W) + (size_t)koff * L->h * esz, L->h, const_cast<float*>(Pj[j]), s);
       }
       // atoms varying inside a group are gathered per tuple; the others
       // (and the bias) are one constant per group

@@ -27,6 +27,7 @@ struct FwdArgs {
   Sink sink;
   float* carry;
   int32_t* carry_arg;
+  const void* W;             // plain: W as given, row-major [K][h]
   const void* X;             // plain: [E][Kp]
   float* Y;                  // plain: [E][h]
   uint8_t* mask;             // act_pre mask: [E][h], 1 where x W + b > 0
@@ -38,7 +39,6 @@ struct FwdPlan {
   int64_t ntiles = 0;
   int64_t carry_units = 0;   // units the carry region holds (max over kernels)
   size_t ws_push_p[RELNN_MAX_ATOMS] = {};   // pushdown: node products of atom j
-  size_t ws_push_w[RELNN_MAX_ATOMS] = {};   // pushdown: swizzled W_j
   size_t ws_push = 0;                       // pushdown total
   size_t ws_wsw = 0, ws_carry = 0, ws_carry_arg = 0, ws_x = 0, ws_y = 0;
   size_t ws_fused = 0, ws_plain = 0;
@@ -50,6 +50,17 @@ FwdPlan checked_plan(const relnn_index* idx, const relnn_layer_desc* L);
 Atoms make_atoms(const relnn_layer_desc* L, const void* const* emb, const relnn_index* idx);
 void swizzle_w(const void* W, int dtype, int K, int Kp, int h, void* Wsw, hipStream_t s);
 void launch_fwd(const FwdPlan& P, const FwdArgs& a, int dtype, bool plain, hipStream_t s);
+
+// Plain path (plain.hip).  plain_gemm: row-major Y[n][h] = X[n][K] W[K][h]
+// (X with leading dimension ldx) on rocBLAS, FP32 or BF16 inputs with FP32
+// accumulation.  launch_seg_reduce: out_g = act_post(alpha over the rows of
+// group g of act_pre(Y + b)), then the carry fix-up; seg_reduce_units is
+// the number of carry units it uses for E rows.
+void plain_gemm(int dtype, const void* X, int64_t n, int K, int ldx, const void* W, int h, float* Y,
+                hipStream_t s);
+int64_t seg_reduce_units(int64_t E);
+void launch_seg_reduce(const float* Y, int64_t E, int h, const Seg& sg, const float* b, int act_pre,
+                       const Sink& sink, float* carry, int32_t* carry_arg, int64_t carry_units, hipStream_t s);
 // Recomputes y = x W + b per tuple and writes mask = (y > 0) (tile kernel).
 void launch_mask(const FwdPlan& P, const FwdArgs& a, int dtype, hipStream_t s);
 void launch_fixup(const Seg& sg, int TM, int h, int64_t ntiles, int64_t nunits, const Sink& sink,
@@ -73,10 +84,6 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
 void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P, const int32_t* const* rows,
                  float* carry, int32_t* carry_arg, hipStream_t s);
 int64_t push_units(int64_t E);
-// Y[r] = X[r] W over rows r < n (X row-major [n, K], K a multiple of the
-// MFMA k step): the node products of the pushed-down transform.
-void launch_node_gemm(const void* X, int dtype, int64_t n, int K, int h, const void* Wsw, float* Y,
-                      hipStream_t s);
 size_t bwd_workspace(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P);
 
 }  // namespace relnn

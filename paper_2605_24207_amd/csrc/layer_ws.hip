@@ -1,33 +1,39 @@
 // Forward layer, weight-stationary persistent kernels (the fast path).
 //
 // Same arithmetic as the tile kernel of layer_fwd.hip (gather -> Linear on
-// the matrix cores -> per-group reduce -> act_post), organised for gfx950:
+// the matrix cores -> per-group reduce -> act_post), organised for gfx950.
+// One block per CU runs a contiguous range of 32-tuple tiles; a group that
+// spans tiles is accumulated inside the block (Kahan-compensated sum, or max
+// with the earliest maximiser), so a block leaves at most two partials, for
+// the groups cut by its range ends; k_fixup combines those in block order.
 //
-//  * one block per CU, persistent over a contiguous range of 32-tuple tiles;
-//  * the W slice of a wave stays in VGPRs for the whole kernel (loaded once);
-//  * the joined rows of tile t+1 are loaded with 16-byte gathers while
-//    tile t is on the matrix cores, then land in the other LDS buffer;
-//  * the group structure of each tile (runs of equal group, whether the
-//    first run started earlier and the last continues) is staged in LDS
-//    with the prefetch, so the per-group reduce reads LDS only;
-//  * a group that spans tiles is accumulated inside the block (Kahan
-//    compensated sum, or max with the earliest maximiser), so a block
-//    leaves at most two partials, for the groups cut by its range ends;
-//    k_fixup combines those in block order.
-// One __syncthreads per tile separates the stages.
+// k_fwd_dma (FP32 and BF16) has two kinds of waves:
+//  * h/16 compute waves, 16 output columns each, whose W slice stays in
+//    VGPRs for the whole kernel.  They multiply a tile on the matrix cores
+//    (f32 16x16x4 or bf16 16x16x32, FP32 accumulation) and reduce it per
+//    group straight from the accumulators: a lane holds 8 rows of one
+//    column, a run of equal group is summed per lane and across the 4 lanes
+//    of the column by two butterfly shuffles, and the group left open at
+//    the end of a tile stays in registers for the next one.
+//  * 4 DMA waves that move tiles from HBM into an NB-deep LDS ring with
+//    16-byte global->LDS loads (no registers in between): while tile t is
+//    multiplied, tiles t+1 .. t+NB-2 are in flight and t+NB-1 is issued.
+//    The row numbers for a tile are read one tile ahead into VGPRs, before
+//    the previous tile's loads are issued, so that waiting for them never
+//    waits for tile data (vector memory counts retire in order).
+// LDS tile layout: row-major without padding; 16-byte chunk c of row r is
+// stored at position c ^ (r & SWM) of its row, so the 16 rows read by one
+// MFMA operand load fall into 16 different bank groups.
+// One __syncthreads per tile.
 //
-// FP32 (k_fwd_f32): all waves alike, 16 output columns each, f32 16x16x4.
-// BF16 (k_fwd_ws):  h/32 compute waves (32 columns each, bf16 32x32x16)
-//                   plus 4 gather waves that load, stage and reduce.
+// k_push (pushdown) keeps the LDS-staged reduce (ws_reduce).
 #include "layer_fwd.hpp"
 
 namespace relnn {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-constexpr int kGatherWaves = 4;
+constexpr int kDmaWaves = 4;
 constexpr int kHMax = 128;
-constexpr int kTM = 32;                  // tuples per tile, both kernels
+constexpr int kTM = 32;                  // tuples per tile
 
 struct WsArgs {
   Atoms at;
@@ -203,12 +209,12 @@ __device__ __forceinline__ void ws_reduce(const WsArgs& a, int64_t t, const floa
   }
 }
 
-// W in the per-wave fragment order of the BF16 kernel: fragment ks of
-// column block cw, lane l holds W[16 ks + 8 (l / 32) + i][32 cw + l % 32],
-// i = 0..7.
+// W for the BF16 kernel, 16-column slices: fragment ks of slice cw, lane l
+// holds W[32 ks + 8 (l / 16) + i][16 cw + l % 16], i = 0..7 (one 16x16x32
+// B operand).
 __global__ void k_ws_swizzle_bf16(const __bf16* __restrict__ W, int K, int KP, int h, __bf16* __restrict__ out) {
-  const int nks = KP / 16;
-  const int64_t total = (int64_t)(h / 32) * nks * 64 * 8;
+  const int nks = KP / 32;
+  const int64_t total = (int64_t)(h / 16) * nks * 64 * 8;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int e = (int)(i & 7);
@@ -216,8 +222,8 @@ __global__ void k_ws_swizzle_bf16(const __bf16* __restrict__ W, int K, int KP, i
     const int64_t f = i >> 9;
     const int ks = (int)(f % nks);
     const int cw = (int)(f / nks);
-    const int k = 16 * ks + 8 * (lane / 32) + e;
-    out[i] = k < K ? W[(int64_t)k * h + cw * 32 + lane % 32] : (__bf16)0.0f;
+    const int k = 32 * ks + 8 * (lane / 16) + e;
+    out[i] = k < K ? W[(int64_t)k * h + cw * 16 + lane % 16] : (__bf16)0.0f;
   }
 }
 
@@ -237,25 +243,19 @@ __global__ void k_ws_swizzle_f16c(const float* __restrict__ W, int K, int KP, in
   }
 }
 
-// A tile's row-major copy in LDS is moved in 16-byte chunks; chunk i is row
-// i / CPR, elements (i % CPR) * EPC onwards.  Loading takes two stages so
-// that no data load waits on its own row index: chunk_row reads the joined
-// row of the chunk's atom a tile ahead of chunk_fetch, which reads the 16
-// bytes.
-struct AtomRef {
-  const int32_t* rows;
+// Atom owning Concat column el (j: its index).  Picked with compile-time
+// indices: indexing the argument's arrays with a run-time value would move
+// the whole argument to scratch memory.
+struct AtomSel {
   const void* emb;
-  int d, koff;
+  int d, koff, j;
 };
 
-// The atom that owns Concat column el.  Picked with compile-time indices:
-// indexing the argument's arrays with a run-time value would move the whole
-// argument to scratch memory.
-__device__ __forceinline__ AtomRef atom_of(const Atoms& at, int el) {
-  AtomRef r{at.rows[0], at.emb[0], at.d[0], 0};
+__device__ __forceinline__ AtomSel atom_sel(const Atoms& at, int el) {
+  AtomSel r{at.emb[0], at.d[0], 0, 0};
   auto pick = [&](auto U) {
     constexpr int u = decltype(U)::value;
-    if (u < at.k && el >= at.koff[u]) r = AtomRef{at.rows[u], at.emb[u], at.d[u], at.koff[u]};
+    if (u < at.k && el >= at.koff[u]) r = AtomSel{at.emb[u], at.d[u], at.koff[u], u};
   };
   static_assert(kMaxAtoms == 4, "one pick per atom after the first");
   pick(std::integral_constant<int, 1>{});
@@ -264,55 +264,150 @@ __device__ __forceinline__ AtomRef atom_of(const Atoms& at, int el) {
   return r;
 }
 
-// Both stages are branch-free: a chunk outside the tile (row >= nv) or in
-// the K..KP pad reads a clamped, valid address and is zeroed when stored,
-// so every thread issues the same straight run of loads.
-template <class T, int CPR>
-__device__ __forceinline__ int32_t chunk_row(const WsArgs& a, int64_t e0, int nv, int i) {
-  constexpr int EPC = 16 / sizeof(T);
-  const int r = min(i / CPR, nv - 1);
-  const int el = min((i % CPR) * EPC, a.K - EPC);
-  return atom_of(a.at, el).rows[e0 + r];
+template <class T, int KP, int NB>
+struct DmaGeo {
+  static constexpr int EPC = 16 / (int)sizeof(T);          // elements per 16-byte chunk
+  static constexpr int CPR = KP / EPC;                     // chunks per row
+  static constexpr int NI = kTM * CPR / 64;                // wave-wide loads per tile
+  static constexpr int NIW = NI / kDmaWaves;               // ... per DMA wave
+  static constexpr int SWM = (CPR < 16 ? CPR : 16) - 1;    // chunk swizzle mask
+  static constexpr int TILE = kTM * KP * (int)sizeof(T);   // bytes per LDS tile
+  static constexpr int NIR = 2 * NB - 1;                   // index slots (tiles t .. t+2NB-2)
+  static constexpr int IRB = kDmaWaves * 256;              // bytes per index slot
+  // vector-memory operations a DMA wave issues after the loads of tile t+1
+  // up to the end of iteration t: NB-2 iterations of (1 + NIW)
+  static constexpr int WAIT = (NB - 2) * (1 + NIW);
+  static_assert(NI % kDmaWaves == 0, "whole DMA instructions per wave");
+  static_assert(kDmaWaves == kMaxAtoms, "one DMA wave per atom moves the row numbers");
+  static_assert(WAIT >= 0 && WAIT <= 63, "vmcnt range");
+};
+
+// Index slot of tile u (int32): DMA wave j writes 256 bytes at j*64 ints;
+// lanes 0..31 carry atom j's row number of tuple r, lanes 32..63 of wave 0
+// the tuple's group number and lanes 32, 33 of wave 1 the group numbers of
+// the tuples just before and after the tile.  Atoms past k repeat atom 0
+// and tuples past the tile repeat its last one, so that every wave issues
+// the same operations for every tile.
+constexpr int kSlotSeg = 32;          // ints: group numbers of the tile
+constexpr int kSlotEdge = 64 + 32;    // ints: groups before and after it
+
+__device__ __forceinline__ void dma_index(const WsArgs& a, int64_t u, char* slot, int dw) {
+  const int lane = __lane_id();
+  const int64_t e0 = u * kTM;
+  const int nv = (int)min<int64_t>(kTM, a.E - e0);
+  // compile-time indices only (a chain of selects over the argument's
+  // array is turned into a table in scratch memory)
+  const int32_t* src = a.at.rows[0];
+  auto pick = [&](auto U) {
+    constexpr int q = decltype(U)::value;
+    if (dw == q && q < a.at.k) src = a.at.rows[q];
+  };
+  pick(std::integral_constant<int, 1>{});
+  pick(std::integral_constant<int, 2>{});
+  pick(std::integral_constant<int, 3>{});
+  int64_t e = e0 + min(lane & 31, nv - 1);
+  if (lane >= 32) {
+    src = a.sg.seg_of;
+    if (dw == 1) e = lane == 32 ? max<int64_t>(e0 - 1, 0) : min<int64_t>(e0 + nv, a.E - 1);
+  }
+  const bool on = lane < 32 || dw == 0 || (dw == 1 && lane < 34);
+  if (on) __builtin_amdgcn_global_load_lds(src + e, slot + dw * 256, 4, 0, 0);
 }
 
-template <class T, int CPR>
-__device__ __forceinline__ uint4 chunk_fetch(const WsArgs& a, int i, int32_t row) {
-  constexpr int EPC = 16 / sizeof(T);
-  const int el = min((i % CPR) * EPC, a.K - EPC);
-  const AtomRef A = atom_of(a.at, el);
-  return *reinterpret_cast<const uint4*>(static_cast<const T*>(A.emb) + (int64_t)row * A.d + (el - A.koff));
+// Issues this DMA wave's share of the loads of tile u into the LDS tile X.
+// Chunk slot s (= 64 ins + lane) of the tile is row r = s / CPR, position
+// p = s % CPR, holding logical chunk p ^ (r & SWM).  Chunks in the K..KP
+// pad are not loaded (their LDS slots were zeroed once).  The row numbers
+// come from the tile's LDS slot (an LDS read: no wait on vector memory).
+template <class T, int KP, int NB>
+__device__ __forceinline__ void dma_tile(const WsArgs& a, const int32_t* rows, char* X, int dw) {
+  using G = DmaGeo<T, KP, NB>;
+  const int lane = __lane_id();
+#pragma unroll
+  for (int i = 0; i < G::NIW; ++i) {
+    const int ins = dw * G::NIW + i;
+    const int sl = ins * 64 + lane;
+    const int r = sl / G::CPR;
+    const int pos = sl - r * G::CPR;
+    const int el = (pos ^ (r & G::SWM)) * G::EPC;
+    const int elc = min(el, a.K - G::EPC);
+    const AtomSel A = atom_sel(a.at, elc);
+    const int32_t row = rows[A.j * 64 + r];
+    const T* g = static_cast<const T*>(A.emb) + (int64_t)row * A.d + (elc - A.koff);
+    if (el < a.K) __builtin_amdgcn_global_load_lds(g, X + ins * 1024, 16, 0, 0);
+  }
 }
 
-// Whether chunk i holds data (else it is stored as zeros).  Applied when
-// the chunk is written to LDS, long after its load was issued: a select
-// right after the load lets the compiler turn the load into a branch whose
-// zero path must wait for every load in flight.
-template <class T, int CPR>
-__device__ __forceinline__ bool chunk_valid(const WsArgs& a, int nv, int i) {
-  constexpr int EPC = 16 / sizeof(T);
-  return i / CPR < nv && (i % CPR) * EPC < a.K;
+// Barriers of the DMA ring.  __syncthreads() is a release fence plus
+// s_barrier, and a release fence waits for every vector-memory operation,
+// LDS-direct loads included: that would drain the ring at every tile.  So
+// the waves wait for exactly what the others need and then meet at a bare
+// s_barrier; the asm "memory" clobber keeps the compiler from moving memory
+// accesses across it.
+//   DMA waves:     their loads of tile t+1 have landed in LDS (at most N
+//                  newer operations outstanding; vector memory retires in
+//                  order).
+//   compute waves: their LDS reads of tile t are complete.
+template <int N>
+__device__ __forceinline__ void dma_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void compute_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Combining the 4 lanes of one output column (lanes c, c+16, c+32, c+48)
+// with the gfx950 row swaps (VALU, no LDS): after the 16-lane swap a lane
+// holds the values of its row pair, after the 32-lane swap all four.  The
+// operands are taken in the same order in every lane, so all four lanes end
+// with the same bits.
+__device__ __forceinline__ float col_sum4(float v) {
+  const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  const float s = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
 }
 
-// v, or zeros if !keep (masks on values: a conditional over two uint4
-// lvalues would select between their addresses and keep v in scratch).
-__device__ __forceinline__ uint4 keep_or_zero(bool keep, uint4 v) {
-  const uint32_t m = keep ? 0xffffffffu : 0u;
-  return make_uint4(v.x & m, v.y & m, v.z & m, v.w & m);
+// Max with the earliest maximiser (ties: smaller tuple position).
+__device__ __forceinline__ void max_pick(float& v, int32_t& a, float v1, int32_t a1) {
+  if (v1 > v || (v1 == v && a1 < a)) {
+    v = v1;
+    a = a1;
+  }
 }
 
-// LDS element offset of chunk i (-1 past the tile).
-template <class T, int CPR, int XS>
-__device__ __forceinline__ int chunk_dst(int i) {
-  constexpr int EPC = 16 / sizeof(T);
-  if (i >= kTM * CPR) return -1;
-  const int r = i / CPR;
-  return r * XS + (i - r * CPR) * EPC;
+__device__ __forceinline__ void col_max4(float& v, int32_t& a) {
+  const auto pv = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  const auto pa = __builtin_amdgcn_permlane16_swap((uint32_t)a, (uint32_t)a, false, false);
+  v = __uint_as_float(pv[0]);
+  a = (int32_t)pa[0];
+  max_pick(v, a, __uint_as_float(pv[1]), (int32_t)pa[1]);
+  const auto qv = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  const auto qa = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)a, false, false);
+  v = __uint_as_float(qv[0]);
+  a = (int32_t)qa[0];
+  max_pick(v, a, __uint_as_float(qv[1]), (int32_t)qa[1]);
 }
 
-// ---------------------------------------------------------------- BF16
-template <int KP>
-__global__ void __launch_bounds__((4 + kGatherWaves) * 64) k_fwd_ws(WsArgs a) {
-  using T = __bf16;
+template <class T>
+struct DmaMfma;
+template <>
+struct DmaMfma<float> {                  // f32 16x16x4, one float4 A read per 4 steps
+  typedef float W;
+  template <int KP>
+  static constexpr int nks() { return KP / 4; }
+};
+template <>
+struct DmaMfma<__bf16> {                 // bf16 16x16x32, one 16-byte A read per step
+  typedef bf16x8 W;
+  template <int KP>
+  static constexpr int nks() { return KP / 32; }
+};
+
+template <class T, int KP, int NB>
+__global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArgs a) {
+  using G = DmaGeo<T, KP, NB>;
+  using WT = typename DmaMfma<T>::W;
+  constexpr int NKS = DmaMfma<T>::template nks<KP>();
+  constexpr int TM = kTM;
   if (a.E_dev) {                   // run-time size: as many units as tiles, at most the grid
     a.E = *a.E_dev;
     a.ntiles = (a.E + kTM - 1) / kTM;
@@ -320,228 +415,226 @@ __global__ void __launch_bounds__((4 + kGatherWaves) * 64) k_fwd_ws(WsArgs a) {
     a.nunits = max<int64_t>(1, min<int64_t>(a.nunits, a.ntiles));
     if ((int64_t)blockIdx.x >= a.nunits) return;
   }
-  constexpr int TM = kTM;
-  constexpr int XS = KP + 8;
-  constexpr int CPR = KP / 8;                               // 16-byte chunks per row
-  constexpr int CH = (TM * CPR + 255) / 256;                // chunks per gather thread
-  constexpr int NKS = KP / 16;                              // MFMA k steps
-
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  T* Xb = reinterpret_cast<T*>(smem);                                        // [2][TM][XS]
-  float* Yb = reinterpret_cast<float*>(smem + 2 * TM * XS * sizeof(T));      // [2][TM][YS]
   const int h = a.h;
-  const int YS = h + 4;
-  OpenState* op = reinterpret_cast<OpenState*>(Yb + 2 * TM * YS);
-  TileInfo* tinfo = reinterpret_cast<TileInfo*>(op + 1);                     // [4]
-
-  const int ncw = h / 32;
+  const int ncw = h / 16;
   const int wave = threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
-  const bool compute = wave < ncw;
-  const int gt = threadIdx.x - ncw * 64;     // gather thread id (0..255) if !compute
-  const bool stager = !compute && gt < 64;   // first gather wave stages the group runs
-
   const int64_t bidx = blockIdx.x;
   const int64_t tb = (a.ntiles * bidx) / a.nunits;
   const int64_t te = (a.ntiles * (bidx + 1)) / a.nunits;
   const int64_t range_hi = min<int64_t>(te * TM, a.E);
   if (tb >= te) return;
-  stage_bias(op, a, threadIdx.x, blockDim.x);
 
-  bf16x8 w[NKS];
-  if (compute) {
-    const bf16x8* src = reinterpret_cast<const bf16x8*>(a.Wsw) + (int64_t)wave * NKS * 64;
-#pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) w[ks] = src[ks * 64 + lane];
-  }
-
-  // gather waves: row indices two tiles ahead, data one tile ahead
-  int32_t ridx[CH];
-  auto load_idx = [&](int64_t t) {
-    const int64_t e0 = t * TM;
-    const int nv = (int)min<int64_t>(TM, a.E - e0);
-#pragma unroll
-    for (int q = 0; q < CH; ++q) ridx[q] = chunk_row<T, CPR>(a, e0, nv, gt + q * 256);
-  };
-  if (!compute) {                            // prologue: tile tb, indices of tb + 1
-    load_idx(tb);
-    uint4 v[CH];
-    const int nv = (int)min<int64_t>(TM, a.E - tb * TM);
-#pragma unroll
-    for (int q = 0; q < CH; ++q) v[q] = chunk_fetch<T, CPR>(a, gt + q * 256, ridx[q]);
-    const SegLoad L = stager ? seg_load(a, tb) : SegLoad{-1, -1, -1};
-    if (tb + 1 < te) load_idx(tb + 1);
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int dst = chunk_dst<T, CPR, XS>(gt + q * 256);
-      if (dst >= 0) *reinterpret_cast<uint4*>(Xb + dst) = keep_or_zero(chunk_valid<T, CPR>(a, nv, gt + q * 256), v[q]);
-    }
-    if (stager) seg_stage(&tinfo[0], a, tb, L);
-  }
+  // zero the ring once: pad chunks (K..KP) are never written afterwards
+  for (int i = threadIdx.x; i < NB * G::TILE / 16; i += blockDim.x)
+    reinterpret_cast<uint4*>(smem)[i] = make_uint4(0, 0, 0, 0);
   __syncthreads();
-  for (int64_t t = tb; t <= te; ++t) {
-    const int buf = (int)((t - tb) & 1);
-    if (compute) {
-      if (t < te) {
-        const T* X = Xb + buf * TM * XS;
-        float* Y = Yb + buf * TM * YS;
-        f32x16 acc;
+  auto ring = [&](int64_t u) { return smem + (int)((u - tb) % NB) * G::TILE; };
+  char* irs = smem + NB * G::TILE;                          // row-number slots
+  auto islot = [&](int64_t u) { return irs + (int)((u - tb) % G::NIR) * G::IRB; };
+
+  if (wave >= ncw) {
+    // ------------------------------------------------------------ DMA waves
+    // Every vector-memory operation of these waves is a global->LDS load;
+    // at iteration t a wave issues the index slot of tile t+2NB-2, then its
+    // share of tile t+NB-1, then waits until its share of tile t+1 has
+    // landed.  The index slot of tile v is issued just before tile v-NB+1,
+    // so it has landed (and passed a barrier) before tile v is issued.
+    const int dw = wave - ncw;
+    const int64_t tl = te - 1;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-        const T* xr = X + (lane & 31) * XS + 8 * (lane >> 5);
-        // A operands one step ahead of the MFMAs; the scheduling barrier
-        // keeps the compiler from hoisting every LDS read (and its
-        // registers) to the top of the unrolled loop.
-        bf16x8 cur = *reinterpret_cast<const bf16x8*>(xr);
+    for (int j = 0; j + 1 < NB; ++j) dma_index(a, min(tb + j, tl), islot(tb + j), dw);
+    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");   // index slots of tb .. tb+NB-2
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) {
-          bf16x8 nxt = cur;
-          if (ks + 1 < NKS) nxt = *reinterpret_cast<const bf16x8*>(xr + 16 * (ks + 1));
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur, w[ks], acc, 0, 0, 0);
-          __builtin_amdgcn_sched_barrier(0);
-          cur = nxt;
+    for (int j = 0; j + 1 < NB; ++j) {
+      dma_index(a, min(tb + j + NB - 1, tl), islot(tb + j + NB - 1), dw);
+      dma_tile<T, KP, NB>(a, reinterpret_cast<const int32_t*>(islot(tb + j)), ring(tb + j), dw);
+    }
+    dma_barrier<G::WAIT>();                                   // tile tb has landed
+    for (int64_t t = tb; t < te; ++t) {
+      dma_index(a, min(t + 2 * NB - 2, tl), islot(t + 2 * NB - 2), dw);
+      dma_tile<T, KP, NB>(a, reinterpret_cast<const int32_t*>(islot(t + NB - 1)), ring(t + NB - 1), dw);
+      dma_barrier<G::WAIT>();                                 // tile t+1 has landed
+    }
+    // loads past the range may still be landing: the LDS must not be
+    // released to another block before they have
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    return;
+  }
+
+  // -------------------------------------------------------------- compute waves
+  const int cw = wave;
+  const int col = cw * 16 + (lane & 15);
+  const float bc = a.b ? a.b[col] : 0.0f;
+  const bool maxagg = a.sink.agg == RELNN_MAX;
+  WT w[NKS];
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks) w[ks] = reinterpret_cast<const WT*>(a.Wsw)[(cw * NKS + ks) * 64 + lane];
+  // W has landed before the loop: otherwise the compiler waits for it (and
+  // with it for the group numbers of the next tile) at every tile's MFMAs
+  __builtin_amdgcn_s_waitcnt(0);
+
+  // group numbers of tile t from its index slot: lane r < 32 row r
+  // (clamped), lane 32 the row before the tile, lane 33 the row after it
+  // (clamped; their validity follows from e0 and nv)
+  auto seg_read = [&](int64_t t) {
+    const int32_t* sl = reinterpret_cast<const int32_t*>(islot(t));
+    return sl[lane < 32 ? kSlotSeg + lane : kSlotEdge + min(lane - 32, 1)];
+  };
+
+  // state of the group open at the end of the previous tile (per column)
+  float oS = 0.0f, oC = 0.0f;
+  int32_t oArg = -1, oN = 0;
+  bool oCut = false;
+  const int q4 = 4 * (lane >> 4);
+  const int64_t slot_base = bidx * 2 * h + col;
+
+  compute_barrier();                                         // (index slots staged)
+  compute_barrier();                                         // tile tb is in LDS
+  for (int64_t t = tb; t < te; ++t) {
+    const int32_t gcur = seg_read(t);
+    const char* X = ring(t);
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    const int r0 = lane & 15, r1 = 16 + (lane & 15);
+    // A operand of step m: logical chunk 4m + cq of rows r0 / r1, stored at
+    // position (4m + cq) ^ sw = 4 (m ^ (sw >> 2)) + ((cq ^ sw) & 3): a
+    // per-lane base for m % 4 plus a constant for the rest (four registers
+    // per row instead of one address per step)
+    const int cq = lane >> 4;
+    auto chunk_base = [&](int sw, int j) { return 4 * (j ^ (sw >> 2)) + ((cq ^ sw) & 3); };
+    if constexpr (std::is_same<T, float>::value) {
+      const float* x0 = reinterpret_cast<const float*>(X) + r0 * KP;
+      const float* x1 = reinterpret_cast<const float*>(X) + r1 * KP;
+      int b0[4], b1[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        b0[j] = 4 * chunk_base(r0 & G::SWM, j);
+        b1[j] = 4 * chunk_base(r1 & G::SWM, j);
+      }
+      // no read-ahead (the W slice takes most registers): the other compute
+      // wave of the SIMD fills the LDS latency
+#pragma unroll
+      for (int m = 0; m < KP / 16; ++m) {
+        const f32x4 c0 = *reinterpret_cast<const f32x4*>(x0 + 16 * (m & ~3) + b0[m & 3]);
+        const f32x4 c1 = *reinterpret_cast<const f32x4*>(x1 + 16 * (m & ~3) + b1[m & 3]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(c0[u], w[4 * m + u], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(c1[u], w[4 * m + u], acc1, 0, 0, 0);
         }
-        const int col = wave * 32 + (lane & 31);
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-          Y[row * YS + col] = acc[v];
-        }
+        __builtin_amdgcn_sched_barrier(0);
       }
     } else {
-      // load-bound: the data of tile t+1 and the indices of t+2 are in
-      // flight while t-1 is reduced
-      const bool more = t + 1 < te;
-      uint4 v[CH];
-      SegLoad L{-1, -1, -1};
-      const int nv1 = more ? (int)min<int64_t>(TM, a.E - (t + 1) * TM) : 0;
-      if (more) {
+      const __bf16* x0 = reinterpret_cast<const __bf16*>(X) + r0 * KP;
+      const __bf16* x1 = reinterpret_cast<const __bf16*>(X) + r1 * KP;
+      int b0[4], b1[4];
 #pragma unroll
-        for (int q = 0; q < CH; ++q) v[q] = chunk_fetch<T, CPR>(a, gt + q * 256, ridx[q]);
-        if (stager) L = seg_load(a, t + 1);
+      for (int j = 0; j < 4; ++j) {
+        b0[j] = 8 * chunk_base(r0 & G::SWM, j);
+        b1[j] = 8 * chunk_base(r1 & G::SWM, j);
       }
-      if (t + 2 < te) load_idx(t + 2);
-      if (t > tb)
-        ws_reduce<true>(a, t - 1, Yb + (buf ^ 1) * TM * YS, YS, &tinfo[(t - 1 - tb) & 3], tb, range_hi, op, gt, 256);
-      if (more) {
+      bf16x8 c0 = *reinterpret_cast<const bf16x8*>(x0 + b0[0]);
+      bf16x8 c1 = *reinterpret_cast<const bf16x8*>(x1 + b1[0]);
 #pragma unroll
-        for (int q = 0; q < CH; ++q) {
-          const int dst = chunk_dst<T, CPR, XS>(gt + q * 256);
-          if (dst >= 0)
-            *reinterpret_cast<uint4*>(Xb + (buf ^ 1) * TM * XS + dst) =
-                keep_or_zero(chunk_valid<T, CPR>(a, nv1, gt + q * 256), v[q]);
+      for (int ks = 0; ks < NKS; ++ks) {
+        bf16x8 n0 = c0, n1 = c1;
+        if (ks + 1 < NKS) {
+          const int kn = ks + 1;
+          n0 = *reinterpret_cast<const bf16x8*>(x0 + 32 * (kn & ~3) + b0[kn & 3]);
+          n1 = *reinterpret_cast<const bf16x8*>(x1 + 32 * (kn & ~3) + b1[kn & 3]);
         }
-        if (stager) seg_stage(&tinfo[(t + 1 - tb) & 3], a, t + 1, L);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c0, w[ks], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c1, w[ks], acc1, 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        c0 = n0;
+        c1 = n1;
       }
     }
-    __syncthreads();
-  }
-}
 
-// ---------------------------------------------------------------- FP32
-// Every wave gathers, multiplies and reduces.  A wave owns 16 output
-// columns (its W slice, KP/4 VGPRs) and runs f32 16x16x4 MFMAs over the 32
-// rows of a tile; the loads of tile t+1 are issued before the MFMA loop of
-// tile t and land in the other LDS buffer after it.  A lane holds
-// A[row = lane % 16][k = lane / 16]; with one float4 LDS read per lane
-// group the four k of MFMA step 4m+u map to columns 16m + 4 (lane / 16) + u,
-// and W is swizzled to match (k_ws_swizzle_f16c).
-template <int KP, int NW>
-__global__ void __launch_bounds__(NW * 64) k_fwd_f32(WsArgs a) {
-  if (a.E_dev) {                   // run-time size: as many units as tiles, at most the grid
-    a.E = *a.E_dev;
-    a.ntiles = (a.E + kTM - 1) / kTM;
-    a.sg.n = a.E;
-    a.nunits = max<int64_t>(1, min<int64_t>(a.nunits, a.ntiles));
-    if ((int64_t)blockIdx.x >= a.nunits) return;
-  }
-  constexpr int TM = kTM;
-  constexpr int XS = KP + 4;
-  constexpr int CPR = KP / 4;
-  constexpr int NKS = KP / 4;
-  constexpr int nthr = NW * 64;
-  constexpr int CH = (TM * CPR + nthr - 1) / nthr;     // 16-byte chunks per thread
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  float* Xb = reinterpret_cast<float*>(smem);          // [2][TM][XS]
-  float* Yb = Xb + 2 * TM * XS;                        // [2][TM][YS]
-  const int h = a.h;
-  const int YS = h + 4;
-  OpenState* op = reinterpret_cast<OpenState*>(Yb + 2 * TM * YS);
-  TileInfo* tinfo = reinterpret_cast<TileInfo*>(op + 1);   // [4]
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int64_t tb = (a.ntiles * (int64_t)blockIdx.x) / a.nunits;
-  const int64_t te = (a.ntiles * ((int64_t)blockIdx.x + 1)) / a.nunits;
-  const int64_t range_hi = min<int64_t>(te * TM, a.E);
-  if (tb >= te) return;
-  stage_bias(op, a, threadIdx.x, blockDim.x);
-
-  float w[NKS];
-  {
-    const float* src = static_cast<const float*>(a.Wsw) + (int64_t)wave * NKS * 64;
-#pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) w[ks] = src[ks * 64 + lane];
-  }
-
-  // row indices two tiles ahead, data one tile ahead
-  int32_t ridx[CH];
-  uint4 v[CH];
-  SegLoad L{-1, -1, -1};
-  auto load_idx = [&](int64_t t) {
+    // ---- per-group reduce of the tile (rows of this lane: q4 + i, 16 + q4 + i)
     const int64_t e0 = t * TM;
     const int nv = (int)min<int64_t>(TM, a.E - e0);
 #pragma unroll
-    for (int q = 0; q < CH; ++q) ridx[q] = chunk_row<float, CPR>(a, e0, nv, threadIdx.x + q * nthr);
-  };
-  auto load_data = [&](int64_t t) {
-#pragma unroll
-    for (int q = 0; q < CH; ++q) v[q] = chunk_fetch<float, CPR>(a, threadIdx.x + q * nthr, ridx[q]);
-    if (wave == 0) L = seg_load(a, t);
-  };
-  auto store = [&](float* X, TileInfo* ti, int64_t t) {
-    const int nv = (int)min<int64_t>(TM, a.E - t * TM);
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int dst = chunk_dst<float, CPR, XS>(threadIdx.x + q * nthr);
-      if (dst >= 0)
-        *reinterpret_cast<uint4*>(X + dst) = keep_or_zero(chunk_valid<float, CPR>(a, nv, threadIdx.x + q * nthr), v[q]);
+    for (int i = 0; i < 4; ++i) {                    // tuple values y = act_pre(x W + b), in place
+      acc0[i] = act_apply(a.act_pre, acc0[i] + bc);
+      acc1[i] = act_apply(a.act_pre, acc1[i] + bc);
     }
-    if (wave == 0) seg_stage(ti, a, t, L);
-  };
-
-  load_idx(tb);
-  load_data(tb);
-  if (tb + 1 < te) load_idx(tb + 1);
-  store(Xb, &tinfo[0], tb);
-  __syncthreads();
-  for (int64_t t = tb; t < te; ++t) {
-    const int buf = (int)((t - tb) & 1);
-    const float* X = Xb + buf * TM * XS;
-    float* Y = Yb + buf * TM * YS;
-    const bool more = t + 1 < te;
-    if (more) load_data(t + 1);
-    if (t + 2 < te) load_idx(t + 2);
+    // runs of equal group: lane r starts one if its group differs from
+    // lane r-1's (DPP wave shift right by one lane)
+    const int32_t gup = __builtin_amdgcn_update_dpp(0, gcur, 0x138, 0xf, 0xf, false);
+    const bool start = lane < nv && (lane == 0 || gup != gcur);
+    uint64_t runs = __ballot(start);
+    const int32_t g_first = __builtin_amdgcn_readlane(gcur, 0);
+    const int32_t g_last = __builtin_amdgcn_readlane(gcur, nv - 1);
+    const int32_t g_before = __builtin_amdgcn_readlane(gcur, 32);
+    const int32_t g_after = __builtin_amdgcn_readlane(gcur, 33);
+    const bool prev_same = e0 > 0 && g_before == g_first;
+    const bool next_same = e0 + nv < a.E && g_after == g_last;
+    bool first_run = true;
+    while (runs) {
+      const int rs = __builtin_ctzll(runs);
+      runs &= runs - 1;
+      const int re = runs ? __builtin_ctzll(runs) : nv;
+      const bool last_run = runs == 0;
+      const int32_t g = __builtin_amdgcn_readlane(gcur, rs);
+      // this lane's rows of the run, then the 4 lanes of the column
+      float part = maxagg ? -INFINITY : 0.0f;
+      int32_t parg = INT32_MAX;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      const float* xr = X + (rb * 16 + (lane & 15)) * XS + 4 * (lane >> 4);
-      f32x4 cur = *reinterpret_cast<const f32x4*>(xr);
-#pragma unroll
-      for (int m = 0; m < NKS / 4; ++m) {
-        f32x4 nxt = cur;
-        if (m + 1 < NKS / 4) nxt = *reinterpret_cast<const f32x4*>(xr + 16 * (m + 1));
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u], w[4 * m + u], acc, 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        cur = nxt;
+      for (int i = 0; i < 8; ++i) {
+        const int rw = (i < 4 ? 0 : 16) + q4 + (i & 3);
+        const bool in = rw >= rs && rw < re;
+        const float yi = i < 4 ? acc0[i & 3] : acc1[i & 3];
+        if (maxagg) {
+          if (in && yi > part) {
+            part = yi;
+            parg = (int32_t)(e0 + rw);
+          }
+        } else {
+          part += in ? yi : 0.0f;
+        }
       }
-      const int col = wave * 16 + (lane & 15);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Y[(rb * 16 + 4 * (lane >> 4) + i) * YS + col] = acc[i];
+      if (maxagg)
+        col_max4(part, parg);
+      else
+        part = col_sum4(part);
+      const int32_t cnt = re - rs;
+      if (first_run && prev_same) {
+        if (t > tb) {                                        // the block's open group
+          if (maxagg) {
+            if (part > oS) {
+              oS = part;
+              oArg = parg;
+            }
+          } else {
+            kahan_add(oS, oC, part);
+          }
+          oN += cnt;
+        } else {                                             // began before the range
+          oS = part; oC = 0.0f; oArg = parg; oN = cnt; oCut = true;
+        }
+      } else {
+        oS = part; oC = 0.0f; oArg = parg; oN = cnt; oCut = false;
+      }
+      if (last_run && next_same && e0 + nv < range_hi) {
+        // stays open for the next tile
+      } else if (lane < 16) {
+        const float v = maxagg ? oS : oS - oC;
+        if (last_run && next_same) {                         // runs past the range end
+          const int64_t o = slot_base + (oCut ? 0 : h);
+          a.carry[o] = v;
+          if (a.carry_arg) a.carry_arg[o] = oArg;
+        } else if (!oCut) {
+          sink_write<true>(a.sink, g, col, h, v, oArg, oN);
+        } else {                                             // cut by the range start
+          a.carry[slot_base] = v;
+          if (a.carry_arg) a.carry_arg[slot_base] = oArg;
+        }
+      }
+      first_run = false;
     }
-    if (more) store(Xb + (buf ^ 1) * TM * XS, &tinfo[(t + 1 - tb) & 3], t + 1);
-    __syncthreads();
-    ws_reduce<true>(a, t, Y, YS, &tinfo[(t - tb) & 3], tb, range_hi, op, threadIdx.x, nthr);
+    compute_barrier();
   }
 }
 
@@ -630,34 +723,26 @@ void allow_lds(KernelT k, size_t bytes) {
 
 constexpr size_t kStateBytes = sizeof(OpenState) + 4 * sizeof(TileInfo);
 
-size_t f32_lds(int KP, int h) { return 2 * kTM * (KP + 4) * 4 + 2 * kTM * (h + 4) * 4 + kStateBytes; }
-size_t bf16_lds(int KP, int h) { return 2 * kTM * (KP + 8) * 2 + 2 * kTM * (h + 4) * 4 + kStateBytes; }
-
-template <int KP, int NW>
-void run_f32(const WsArgs& a, hipStream_t s) {
-  const size_t lds = f32_lds(KP, a.h);
-  allow_lds(k_fwd_f32<KP, NW>, lds);
-  KTimer tm("fwd_fused", s);
-  k_fwd_f32<KP, NW><<<(unsigned)a.nunits, NW * 64, lds, s>>>(a);
-  RELNN_LAUNCHED();
+// LDS ring depth NB: as many tiles as fit with their 2 NB - 1 index slots,
+// at most 6 (tiles t+1 .. t+4 in flight while t is multiplied).
+template <class T, int KP>
+constexpr int ring_depth() {
+  constexpr int TILE = DmaGeo<T, KP, 2>::TILE;
+  constexpr int IRB = DmaGeo<T, KP, 2>::IRB;
+  constexpr int fit = (160 * 1024 + IRB) / (TILE + 2 * IRB);
+  return fit < 6 ? fit : 6;
 }
 
-template <int KP>
-void run_f32_h(const WsArgs& a, hipStream_t s) {
-  switch (a.h) {
-    case 32: run_f32<KP, 2>(a, s); break;
-    case 64: run_f32<KP, 4>(a, s); break;
-    case 96: run_f32<KP, 6>(a, s); break;
-    default: run_f32<KP, 8>(a, s); break;
-  }
-}
-
-template <int KP>
-void run_bf16(const WsArgs& a, hipStream_t s) {
-  const size_t lds = bf16_lds(KP, a.h);
-  allow_lds(k_fwd_ws<KP>, lds);
+template <class T, int KP>
+void run_dma(const WsArgs& a, hipStream_t s) {
+  constexpr int NB = ring_depth<T, KP>();
+  using G = DmaGeo<T, KP, NB>;
+  static_assert(NB >= 2, "two LDS tiles at least");
+  const size_t lds = (size_t)NB * G::TILE + (size_t)G::NIR * G::IRB;
+  RELNN_REQUIRE(lds <= 160 * 1024, RELNN_E_HIP, "internal: LDS ring of %zu bytes", lds);
+  allow_lds(k_fwd_dma<T, KP, NB>, lds);
   KTimer tm("fwd_fused", s);
-  k_fwd_ws<KP><<<(unsigned)a.nunits, (a.h / 32 + kGatherWaves) * 64, lds, s>>>(a);
+  k_fwd_dma<T, KP, NB><<<(unsigned)a.nunits, (a.h / 16 + kDmaWaves) * 64, lds, s>>>(a);
   RELNN_LAUNCHED();
 }
 
@@ -716,7 +801,7 @@ WsPlan plan_ws(int dtype, int K, int h, int64_t E) {
   WsPlan p;
   const bool bf = dtype == RELNN_BF16;
   p.KP = pick_kp(K);
-  const bool h_ok = bf ? (h % 32 == 0 && h <= kHMax) : (h == 32 || h == 64 || h == 96 || h == 128);
+  const bool h_ok = h % 16 == 0 && h <= kHMax;
   if (!p.KP || !h_ok) {
     p.KP = 0;
     return p;
@@ -761,17 +846,17 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
   a.carry_arg = carry_arg;
   if (dtype == RELNN_BF16) {
     switch (p.KP) {
-      case 64: run_bf16<64>(a, s); break;
-      case 128: run_bf16<128>(a, s); break;
-      case 256: run_bf16<256>(a, s); break;
-      default: run_bf16<384>(a, s); break;
+      case 64: run_dma<__bf16, 64>(a, s); break;
+      case 128: run_dma<__bf16, 128>(a, s); break;
+      case 256: run_dma<__bf16, 256>(a, s); break;
+      default: run_dma<__bf16, 384>(a, s); break;
     }
   } else {
     switch (p.KP) {
-      case 64: run_f32_h<64>(a, s); break;
-      case 128: run_f32_h<128>(a, s); break;
-      case 256: run_f32_h<256>(a, s); break;
-      default: run_f32_h<384>(a, s); break;
+      case 64: run_dma<float, 64>(a, s); break;
+      case 128: run_dma<float, 128>(a, s); break;
+      case 256: run_dma<float, 256>(a, s); break;
+      default: run_dma<float, 384>(a, s); break;
     }
   }
   launch_fixup(f.sg, p.TM, f.h, p.ntiles, p.nunits, f.sink, carry, carry_arg, s);

@@ -89,17 +89,19 @@ def check_fwd(rule, dtype, plain=False, pushdown=False):
     e_out = rel_rows(res["out"], out, scale_ref=pre)
     assert e_pre.max() <= TOL[dtype], (e_pre.max(), np.percentile(e_pre, 99))
     assert e_out.max() <= TOL[dtype]
+    am_ref = am
     if dtype == "bf16":   # kernel arithmetic alone, on the rounded inputs
-        _, out_b, pre_b, _ = oracle_fwd(rule, "bf16", idx=idx)
+        _, out_b, pre_b, am_b = oracle_fwd(rule, "bf16", idx=idx)
         assert rel_rows(res["pre"], pre_b).max() <= 1e-5 * np.sqrt(rule.K)
+        am_ref = am_b     # the argmax is decided on the values the kernel sees
     if rule.agg == "max":
         embs, W, b = oracle_inputs(rule, dtype)
         am_g = res["argmax"]
-        diff = np.nonzero(am_g != am)
+        diff = np.nonzero(am_g != am_ref)
         for g, c in zip(*diff):
             y = orc.transform(orc.gather_concat(idx, embs, [am_g[g, c]]), W, b, rule.act_pre)[0, c]
             assert abs(y - pre[g, c]) <= 4 * TOL[dtype] * max(1.0, abs(pre[g, c]))
-        assert len(diff[0]) <= 0.01 * am.size + 1
+        assert len(diff[0]) <= 0.01 * am_ref.size + 1
     return res
 
 
@@ -135,6 +137,18 @@ def test_fwd_hot_segment_and_ragged_tail(dtype, agg):
 @pytest.mark.parametrize("agg", ["sum", "max"])
 def test_fwd_random_keyed_chains(agg):
     check_fwd(random_rule(7, agg=agg), "f32")
+
+
+@pytest.mark.parametrize("d,h", [((8, 16, 8), 48),          # K 32 in a 64-wide tile (pad), 3 column waves
+                                 ((24, 40, 64), 80),        # K 128, 5 column waves
+                                 ((64, 72, 64), 112),       # K 200 in a 256-wide tile, 7 column waves
+                                 ((96, 104, 96), 128)])     # K 296 in a 384-wide tile
+@pytest.mark.parametrize("agg", ["sum", "mean", "max"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_fwd_tile_shapes_and_long_ranges(d, h, agg, dtype):
+    """~4k tiles (many per block, so the load ring wraps many times) over
+    widths that leave a zero pad in the LDS tile and odd column-wave counts."""
+    check_fwd(random_rule(21, agg=agg, n_link=150_000, d=d, h=h), dtype)
 
 
 def test_fwd_empty_join():
