@@ -140,6 +140,25 @@ def step_bytes(ix, Ks, ks, h, esz):
     return b
 
 
+def measured_traffic():
+    """HBM bytes per launch of the fused FP32 forward from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+
+    summ = os.path.join(ROOT, "profiles", "fused_fwd_er_counters.md")
+    src = os.path.join(ROOT, "paper_2605_24207_amd", "csrc", "layer_ws.hip")
+    try:
+        text = open(summ).read()
+        have = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        want = re.search(r"source_sha256_prefix:\s*([0-9a-f]+)", text).group(1)
+        val = float(re.search(r"traffic_bytes_per_launch_fused_f32:\s*([0-9.e+]+)", text).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    return val if have == want else None
+
+
 def gbs(nbytes_per_step, steps, kt):
     """Achieved GB/s of a kernel: its algorithmic bytes over its summed
     launch time (HIP events on the launch stream)."""
@@ -399,9 +418,10 @@ def main():
         line.update({"value": value, "steps": main_leg["steps"],
                      "ms_per_step": main_leg["dt"] / main_leg["steps"] * 1e3})
         line["config"]["tuples_per_step"] = main_leg["tuples"]
-        line["roofline"] = {"bound": "mfma", "kernel": "k_fwd_f32 (fused FP32 layer)", "achieved": achieved,
-                            "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"],
-                            "traffic": None, "avg_launch_ms": k_ms / k_n,
+        line["roofline"] = {"bound": "mfma", "kernel": "k_fwd_dma<float> (fused FP32 forward)",
+                            "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                            "frac": achieved / PEAK_TFLOPS["f32"], "traffic": measured_traffic(),
+                            "avg_launch_ms": k_ms / k_n,
                             "flop_per_launch": flops_per_launch,
                             "hbm_gbs_algorithmic": gbs(main_leg["bytes"]["fused"], main_leg["steps"],
                                                        main_leg["kt"]["fwd_fused"])}
