@@ -1,0 +1,389 @@
+// Backward of a relational layer through sums over groups and over joined
+// rows.  With dY_tau the gradient of tuple tau's transformed value
+// (dA_g = dout_g * act_post'(pre_g), divided by |g| for MEAN; routed to the
+// argmax tuple per column for MAX; masked by act_pre' when act_pre is
+// ReLU), the map from x_tau to y_tau is affine, so for every layer
+//
+//   dz_j[r] += (sum_{tau joined to row r} dY_tau) W_j^T  =  DS_j[r] W_j^T
+//
+// and, when dY_tau = dA_g for every tuple of g (SUM or MEAN with an affine
+// transform: the transformation commutes with the union, Section 2.2),
+//
+//   dW = sum_g (sum_{tau in g} x_tau)^T dA_g = XS^T dA,   db = sum_g |g| dA_g.
+//
+// XS [G, K] and DS_j [rows of j, h] are segmented gather-sums over sorted
+// lists (k_seg_gather_sum: atomic-free, deterministic); the products are
+// library GEMMs on them, far smaller than the per-tuple ones.  dW of the
+// other layers is the per-tuple product of layer_bwd.hip.
+#include <rocblas/rocblas.h>
+
+#include "layer_fwd.hpp"
+#include "prims.hpp"
+
+namespace relnn {
+
+namespace {
+
+constexpr int kGsTM = 64;          // unit boundaries on multiples of 64 positions
+constexpr int kGsWaves = 4;        // waves per block
+constexpr int kGsBatch = 8;        // positions loaded together
+
+struct GsArgs {
+  const void* emb[kMaxAtoms];      // [n_j][d_j], FP32 or BF16
+  const int32_t* rows[kMaxAtoms];  // [n] row of atom j at each list position
+  int d[kMaxAtoms];
+  int koff[kMaxAtoms];
+  int k;
+  int K;                           // sum of d_j, a multiple of 4
+  bool bf16;
+  int64_t n;                       // list positions
+  Seg sg;                          // segments of the sorted list
+  float* out;                      // [nseg][ldo]
+  int ldo;                         // row stride of out and carry (>= K)
+  float* carry;                    // [nunits][2][ldo]
+  int64_t ntiles, nunits;
+  // routing of a gathered gradient row (one atom, dA of width h; rows[0] is
+  // the group of the tuple at each position, rows[1] its canonical position)
+  const int32_t* argmax;           // [G][h]: keep column c only where argmax == tuple (MAX)
+  const uint8_t* mask;             // [E][h]: act_pre' of the tuple
+};
+
+__device__ __forceinline__ void kahan_add1(float& s, float& c, float x) {
+  const float y = x - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+__device__ __forceinline__ void kahan4(f32x4& s, f32x4& c, const f32x4& x) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float y = x[i] - c[i];
+    const float t = s[i] + y;
+    c[i] = (t - s[i]) - y;
+    s[i] = t;
+  }
+}
+
+// Four consecutive elements of column block cq of the joined row at list
+// position e, as FP32.  The atom of the block is picked with compile-time
+// indices (a run-time index into the argument's arrays would put it in
+// scratch memory).
+struct GsAtom {
+  const void* emb;
+  int d, koff, j;
+};
+
+__device__ __forceinline__ GsAtom gs_atom(const GsArgs& a, int col) {
+  GsAtom r{a.emb[0], a.d[0], 0, 0};
+  auto pick = [&](auto U) {
+    constexpr int u = decltype(U)::value;
+    if (u < a.k && col >= a.koff[u]) r = GsAtom{a.emb[u], a.d[u], a.koff[u], u};
+  };
+  pick(std::integral_constant<int, 1>{});
+  pick(std::integral_constant<int, 2>{});
+  pick(std::integral_constant<int, 3>{});
+  return r;
+}
+
+__device__ __forceinline__ f32x4 gs_load(const GsArgs& a, const GsAtom& A, int32_t row, int col) {
+  const int64_t o = (int64_t)row * A.d + (col - A.koff);
+  if (a.bf16) {
+    const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const __bf16*>(A.emb) + o);
+    return f32x4{__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u), __uint_as_float(v.y << 16),
+                 __uint_as_float(v.y & 0xffff0000u)};
+  }
+  return *reinterpret_cast<const f32x4*>(static_cast<const float*>(A.emb) + o);
+}
+
+// out[s] = sum over the positions e of segment s of the joined row at e.
+// One wavefront per unit of positions [pos(u), pos(u+1)), pos(u) = (ntiles
+// u / nunits) 64; lane l owns the four columns 4 (64 p + l) .. of pass p.  A
+// segment cut by a unit end leaves its partial in carry slot 0 (cut by the
+// start) or 1 (runs past the end); k_fixup combines them in unit order.
+__global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
+  const int lane = threadIdx.x % 64;
+  const int64_t u = (int64_t)blockIdx.x * kGsWaves + threadIdx.x / 64;
+  if (u >= a.nunits) return;
+  const int64_t r0 = ((a.ntiles * u) / a.nunits) * kGsTM;
+  const int64_t r1 = min<int64_t>(((a.ntiles * (u + 1)) / a.nunits) * kGsTM, a.n);
+  if (r0 >= r1) return;
+  const int K = a.K;
+
+  for (int cb = 0; cb < K; cb += 256) {
+    const int col = cb + 4 * lane;
+    const bool on = col < K;
+    const GsAtom A = gs_atom(a, on ? col : 0);
+    f32x4 s = {0.f, 0.f, 0.f, 0.f}, c = {0.f, 0.f, 0.f, 0.f};
+    int32_t g = a.sg.seg_of[r0];
+    bool first = true;
+    auto flush = [&]() {
+      const int64_t g0 = a.sg.offsets[g], g1 = a.sg.offsets[g + 1];
+      const bool cut_lo = first && g0 < r0;
+      const bool cut_hi = g1 > r1;
+      if (on) {
+        const f32x4 v = s - c;
+        float* dst = (cut_lo || cut_hi) ? a.carry + (u * 2 + (cut_lo ? 0 : 1)) * a.ldo + col
+                                        : a.out + (int64_t)g * a.ldo + col;
+        *reinterpret_cast<f32x4*>(dst) = v;
+      }
+      first = false;
+      s = f32x4{0.f, 0.f, 0.f, 0.f};
+      c = s;
+    };
+    for (int64_t base = r0; base < r1; base += 64) {
+      const int n = (int)min<int64_t>(64, r1 - base);
+      const int64_t e = base + min(lane, n - 1);
+      const int32_t gl = a.sg.seg_of[e];
+      // row numbers of the 64 positions, one vector per atom (absent ones
+      // repeat atom 0)
+      int32_t R[kMaxAtoms];
+#pragma unroll
+      for (int j = 0; j < kMaxAtoms; ++j) R[j] = (a.rows[j] ? a.rows[j] : a.rows[0])[e];
+      for (int bt = 0; bt < n; bt += kGsBatch) {
+        f32x4 v[kGsBatch];
+#pragma unroll
+        for (int i = 0; i < kGsBatch; ++i) {
+          const int q = min(bt + i, n - 1);           // clamped: every load is valid
+          int32_t row = __builtin_amdgcn_readlane(R[0], q);
+#pragma unroll
+          for (int j = 1; j < kMaxAtoms; ++j) {
+            const int32_t rj = __builtin_amdgcn_readlane(R[j], q);
+            row = A.j == j ? rj : row;
+          }
+          v[i] = gs_load(a, A, row, on ? col : 0);
+          if (a.argmax || a.mask) {                     // route the gradient row of this tuple
+            const int32_t tau = __builtin_amdgcn_readlane(R[1], q);
+            if (a.argmax) {
+              const int4 am = *reinterpret_cast<const int4*>(a.argmax + (int64_t)row * a.d[0] + (on ? col : 0));
+              v[i][0] = am.x == tau ? v[i][0] : 0.0f;
+              v[i][1] = am.y == tau ? v[i][1] : 0.0f;
+              v[i][2] = am.z == tau ? v[i][2] : 0.0f;
+              v[i][3] = am.w == tau ? v[i][3] : 0.0f;
+            }
+            if (a.mask) {
+              const uint32_t m = *reinterpret_cast<const uint32_t*>(a.mask + (int64_t)tau * a.d[0] + (on ? col : 0));
+              v[i][0] = (m & 0xffu) ? v[i][0] : 0.0f;
+              v[i][1] = (m & 0xff00u) ? v[i][1] : 0.0f;
+              v[i][2] = (m & 0xff0000u) ? v[i][2] : 0.0f;
+              v[i][3] = (m & 0xff000000u) ? v[i][3] : 0.0f;
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < kGsBatch; ++i) {
+          const int q = bt + i;
+          if (q >= n) break;
+          const int32_t gq = __builtin_amdgcn_readlane(gl, q);
+          if (__builtin_expect(gq != g, 0)) {         // a segment ends
+            flush();
+            g = gq;
+          }
+          kahan4(s, c, v[i]);
+        }
+      }
+    }
+    flush();
+  }
+}
+
+// xs[g][K] = |g|: the extra column turns db into one more row of the dW product.
+__global__ void k_counts_col(const int32_t* offsets, int64_t G, int K, int ldx, float* xs) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x)
+    xs[g * ldx + K] = (float)(offsets[g + 1] - offsets[g]);
+}
+
+// dW[k][c] (+)= sum_b part[b][k][c] for k < K, db[c] (+)= sum_b part[b][K][c]:
+// the split-K partials added in chunk order.
+__global__ void k_sum_parts(const float* part, int nb, int K, int h, float* dW, float* db, int accumulate) {
+  const int64_t total = (int64_t)(K + 1) * h;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    float acc = 0.0f, comp = 0.0f;
+    for (int b = 0; b < nb; ++b) kahan_add1(acc, comp, part[(int64_t)b * total + i]);
+    const float v = acc - comp;
+    // part is column-major h x (K+1): i = k h + c
+    const int64_t k = i / h;
+    const int c = (int)(i - k * h);
+    if (k < K) {
+      float* o = dW + k * h + c;
+      *o = accumulate ? *o + v : v;
+    } else if (db) {
+      db[c] = accumulate ? db[c] + v : v;
+    }
+  }
+}
+
+__global__ void k_bf16_to_f32(const __bf16* x, int64_t n, float* y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+// demb[row[s]][:] += dz[s][:], each row named by at most one segment.
+__global__ void k_scatter_add_rows(const float* dz, const int32_t* row, int64_t nseg, int d, float* demb) {
+  const int64_t total = nseg * d;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = i / d;
+    const int c = (int)(i - s * d);
+    demb[(int64_t)row[s] * d + c] += dz[i];
+  }
+}
+
+unsigned grid_n(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 1 << 16)); }
+
+int64_t gs_units(int64_t n) {
+  const int64_t nt = cdiv(std::max<int64_t>(n, 1), kGsTM);
+  return std::max<int64_t>(1, std::min<int64_t>(nt, 8192));
+}
+
+void seg_gather_sum(GsArgs a, int64_t nseg_units_cap, hipStream_t s) {
+  a.ntiles = cdiv(a.n, kGsTM);
+  a.nunits = gs_units(a.n);
+  RELNN_REQUIRE(a.nunits <= nseg_units_cap, RELNN_E_HIP, "internal: carry region too small");
+  RELNN_REQUIRE(a.K % 4 == 0, RELNN_E_UNSUPPORTED, "row width %d is not a multiple of 4", a.K);
+  k_seg_gather_sum<<<(unsigned)cdiv(a.nunits, kGsWaves), kGsWaves * 64, 0, s>>>(a);
+  RELNN_LAUNCHED();
+  // the fix-up reads carry slots and writes out rows with stride ldo
+  Sink sk{};
+  sk.agg = RELNN_SUM;
+  sk.act_post = RELNN_ACT_NONE;
+  sk.out = a.out;
+  launch_fixup(a.sg, kGsTM, a.ldo, a.ntiles, a.nunits, sk, a.carry, nullptr, s);
+}
+
+}  // namespace
+
+// Workspace of the aggregated backward, after `base` bytes.
+LinBwdPlan plan_lin_bwd(const relnn_index* idx, const relnn_layer_desc* L, size_t base, bool xs_dw) {
+  LinBwdPlan p;
+  int K = 0, dmax = 0;
+  for (int j = 0; j < L->k; ++j) {
+    K += L->d[j];
+    dmax = std::max(dmax, L->d[j]);
+  }
+  int64_t nseg = 1;
+  for (int j = 0; j < L->k; ++j) nseg = std::max<int64_t>(nseg, idx->t_nseg[j]);
+  const int64_t G = std::max<int64_t>(idx->G, 1), E = std::max<int64_t>(idx->E, 1);
+  const int h = L->h;
+  size_t off = base;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += round_up(bytes, 256);
+    return o;
+  };
+  p.units = gs_units(E);
+  p.ldx = (int)round_up(K + 1, 4);
+  p.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, G / 4096));
+  if (xs_dw) {
+    p.ws_xs = take((size_t)G * p.ldx * 4);
+    p.ws_part = take((size_t)p.nchunk * (K + 1) * h * 4);
+  }
+  p.ws_tg = take((size_t)E * 4);
+  p.ws_tp = take((size_t)E * 4);
+  p.ws_ds = take((size_t)nseg * h * 4);
+  p.ws_dz = take((size_t)nseg * dmax * 4);
+  p.ws_w32 = take((size_t)K * h * 4);
+  p.ws_carry = take((size_t)p.units * 2 * std::max(p.ldx, h) * 4);
+  p.total = off;
+  return p;
+}
+
+void lin_bwd_dw(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdPlan& P, const void* const* emb,
+                const float* dA, float* dW, float* db, bool accum, char* w, hipStream_t s) {
+  const int h = L->h;
+  const int64_t G = idx->G, E = idx->E;
+  int K = 0;
+  for (int j = 0; j < L->k; ++j) K += L->d[j];
+  float* xs = reinterpret_cast<float*>(w + P.ws_xs);
+  KTimer tm("bwd_dw", s);
+  // XS: per-group sums of the joined rows (canonical order, groups as
+  // segments), with |g| in column K
+  {
+    GsArgs a{};
+    int koff = 0;
+    for (int j = 0; j < L->k; ++j) {
+      a.emb[j] = emb[j];
+      a.rows[j] = idx->rows + (int64_t)j * E;
+      a.d[j] = L->d[j];
+      a.koff[j] = koff;
+      koff += L->d[j];
+    }
+    a.k = L->k;
+    a.K = K;
+    a.bf16 = L->dtype == RELNN_BF16;
+    a.n = E;
+    a.sg = Seg{idx->tuple_group, idx->offsets, E, nullptr};
+    a.out = xs;
+    a.ldo = P.ldx;
+    a.carry = reinterpret_cast<float*>(w + P.ws_carry);
+    seg_gather_sum(a, P.units, s);
+    k_counts_col<<<grid_n(G), 256, 0, s>>>(idx->offsets, G, K, P.ldx, xs);
+    RELNN_LAUNCHED();
+  }
+  // [dW; db] = [XS, |g|]^T dA, split over nchunk chunks of groups (one
+  // batched product), then the partials summed in chunk order.  Column-major
+  // partial b (h x (K+1)) = dA_b^T' (h x m) XS_b (m x (K+1)).
+  float* part = reinterpret_cast<float*>(w + P.ws_part);
+  const int nb = P.nchunk;
+  const int64_t m = G / nb, rest = G - m * (nb - 1);
+  const int64_t spart = (int64_t)(K + 1) * h;
+  if (nb > 1)
+    blas_sgemm_strided_batched(false, true, h, K + 1, (int)m, dA, h, m * h, xs, P.ldx, m * P.ldx, part, h, spart,
+                               nb - 1, s);
+  blas_sgemm(false, true, h, K + 1, (int)rest, dA + (int64_t)(nb - 1) * m * h, h, xs + (int64_t)(nb - 1) * m * P.ldx,
+             P.ldx, 0.0f, part + (int64_t)(nb - 1) * spart, h, s);
+  k_sum_parts<<<grid_n(spart), 256, 0, s>>>(part, nb, K, h, dW, db, accum ? 1 : 0);
+  RELNN_LAUNCHED();
+}
+
+void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdPlan& P, const void* W,
+                const float* dA, const int32_t* argmax, const uint8_t* mask, float* const* demb, char* w,
+                hipStream_t s) {
+  const int h = L->h;
+  const int64_t E = idx->E;
+  int K = 0;
+  for (int j = 0; j < L->k; ++j) K += L->d[j];
+  // W in FP32 for the products
+  const float* W32 = static_cast<const float*>(W);
+  if (L->dtype == RELNN_BF16) {
+    float* w32 = reinterpret_cast<float*>(w + P.ws_w32);
+    k_bf16_to_f32<<<grid_n((int64_t)K * h), 256, 0, s>>>(static_cast<const __bf16*>(W), (int64_t)K * h, w32);
+    RELNN_LAUNCHED();
+    W32 = w32;
+  }
+  const bool routed = argmax != nullptr || mask != nullptr;
+  // dz_j = DS_j W_j^T, added into the rows of atom j
+  for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
+    const int d = L->d[j];
+    const int64_t nseg = idx->t_nseg[j];
+    if (nseg == 0) continue;
+    int32_t* tg = reinterpret_cast<int32_t*>(w + P.ws_tg);
+    float* ds = reinterpret_cast<float*>(w + P.ws_ds);
+    float* dz = reinterpret_cast<float*>(w + P.ws_dz);
+    KTimer tm("bwd_dx", s);
+    prim::gather_i32(idx->tuple_group, idx->t_pos[j], E, tg, s);     // group of each transposed tuple
+    GsArgs a{};
+    a.emb[0] = dA;
+    a.rows[0] = tg;
+    a.rows[1] = routed ? idx->t_pos[j] : tg;                         // canonical position of each tuple
+    a.d[0] = h;
+    a.koff[0] = 0;
+    a.k = 1;
+    a.K = h;
+    a.bf16 = false;
+    a.n = E;
+    a.sg = Seg{idx->t_seg[j], idx->t_segoff[j], E, nullptr};
+    a.out = ds;
+    a.ldo = h;
+    a.carry = reinterpret_cast<float*>(w + P.ws_carry);
+    a.argmax = argmax;
+    a.mask = mask;
+    seg_gather_sum(a, P.units, s);
+    // DZ [nseg][d] = DS [nseg][h] W_j^T, W_j = rows koff.. of W ([d][h]):
+    // column-major DZ^T (d x nseg) = W_j^T' (d x h) DS^T (h x nseg)
+    blas_sgemm(true, false, d, (int)nseg, h, W32 + (size_t)koff * h, h, ds, h, 0.0f, dz, d, s);
+    k_scatter_add_rows<<<grid_n(nseg * d), 256, 0, s>>>(dz, idx->t_segrow[j], nseg, d, demb[j]);
+    RELNN_LAUNCHED();
+  }
+}
+
+}  // namespace relnn

@@ -12,21 +12,18 @@
 //   dW        = sum_tau x_tau^T dY_tau,   db = sum_tau dY_tau
 //   dz_j[r]  += sum_{tau joined to row r of atom j} (dY_tau W^T)[cols of j]
 //
-// The joined rows x_tau are gathered again, never stored.  dW / db: a
-// persistent kernel accumulates X^T dY over its contiguous run of tiles on
-// the matrix cores (FP32 16x16x4), then the per-block partials are summed in
-// block order.  dz_j: tiles over atom j's transpose order (tuples sorted by
-// joined row), dY rows routed into LDS, multiplied by W_j^T, and reduced per
-// row with the same carry / fix-up scheme as the forward: atomic-free and
-// deterministic.  Atoms run one after another on the stream, so atoms that
-// share one embedding relation (a self-join) add up in stream order.
+// dz_j always goes through the per-row sums of dY (bwd_linear.hip).  dW and
+// db go through the per-group sums of x when dY_tau = dA_g (SUM or MEAN with
+// an affine transform); otherwise this file's per-tuple kernel: the joined
+// rows x_tau are gathered again, never stored, and a persistent kernel
+// accumulates X^T dY over its contiguous run of tiles on the matrix cores
+// (FP32 16x16x4), then the per-block partials are summed in block order.
 #include "layer_fwd.hpp"
 
 namespace relnn {
 
 namespace {
 
-constexpr int kDxTM = 64;
 constexpr int kDwTM = 32;
 constexpr int kDwThreads = 512;
 constexpr int kDwMaxB = 24;              // 16x16 accumulator blocks per wave
@@ -61,73 +58,6 @@ __global__ void k_route_prep(const float* dout, const float* pre, const int32_t*
       v = v / (float)(offsets[g + 1] - offsets[g]);
     }
     dA[i] = v;
-  }
-}
-
-// ---------------------------------------------------------------- dz_j
-struct DxArgs {
-  Route R;
-  const int32_t* t_pos;     // [E] canonical position, in transpose order
-  int64_t E;
-  int hp;                   // h rounded up to 4 (k of the product)
-  int d;                    // width of atom j
-  const float* Wsw;         // W_j^T swizzled for mfma_tile<float>
-  Seg sg;                   // transpose segments (non-empty rows)
-  Sink sink;                // accumulate into demb_j rows
-  float* carry;
-};
-
-__global__ void __launch_bounds__(kThreads) k_bwd_dx(DxArgs a) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  constexpr int TM = kDxTM;
-  const int64_t tile = blockIdx.x;
-  const int64_t p0 = tile * TM;
-  const int nv = (int)min<int64_t>(TM, a.E - p0);
-  const int DS = a.hp + 4;
-  const int YS = a.d + 4;
-  int64_t* pe = reinterpret_cast<int64_t*>(smem);            // [TM] tuple position
-  int64_t* pg = pe + TM;                                     // [TM] its group
-  float* Ds = reinterpret_cast<float*>(pg + TM);             // [TM][DS] routed dY
-  float* Ys = Ds + TM * DS;                                  // [TM][YS] dY W_j^T
-  for (int r = threadIdx.x; r < TM; r += blockDim.x) {
-    int64_t e = 0, g = 0;
-    if (r < nv) {
-      e = a.t_pos[p0 + r];
-      g = a.R.tuple_group[e];
-    }
-    pe[r] = e;
-    pg[r] = g;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < TM * a.hp; i += blockDim.x) {
-    const int r = i / a.hp, n = i - (i / a.hp) * a.hp;
-    Ds[r * DS + n] = (r < nv && n < a.R.h) ? route(a.R, pe[r], pg[r], n) : 0.0f;
-  }
-  __syncthreads();
-  const int ncb = a.d / 16;
-  const int nblk = (TM / 16) * ncb;
-  f32x4 acc[kMaxQ];
-  mfma_tile<float>(Ds, DS, a.hp, nblk, ncb, a.Wsw, acc);
-  store_acc(acc, nblk, ncb, nullptr, RELNN_ACT_NONE, Ys, YS);
-  __syncthreads();
-  reduce_tile(Ys, YS, a.d, p0, nv, tile, a.sg, a.sink, a.carry, nullptr);
-}
-
-// B = W_j^T [hp x d] in the fragment order of mfma_tile<float>:
-// out[(ks * ncb + cb) * 64 + l] = W[koff + cb*16 + l % 16][ks*4 + l / 16].
-template <class T>
-__global__ void k_swizzle_wt(const T* __restrict__ W, int h, int hp, int koff, int d, float* __restrict__ out) {
-  const int ncb = d / 16;
-  const int64_t total = (int64_t)hp * d;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int lane = (int)(i & 63);
-    const int64_t kc = i >> 6;
-    const int cb = (int)(kc % ncb);
-    const int ks = (int)(kc / ncb);
-    const int n = ks * 4 + (lane >> 4);
-    const int col = cb * 16 + (lane & 15);
-    out[i] = n < h ? (float)W[(int64_t)(koff + col) * h + n] : 0.0f;
   }
 }
 
@@ -288,11 +218,12 @@ int num_cus() {
 
 struct BwdPlan {
   FwdPlan F;
-  int K = 0, K16 = 0, hp = 0, hn = 0;
-  int64_t dx_tiles = 0, dw_tiles = 0, dw_units = 0;
-  size_t dx_lds = 0, dw_lds = 0;
-  size_t ws_mask = 0, ws_fwsw = 0, ws_wt = 0, ws_carry = 0, ws_part = 0, ws_dbpart = 0, ws_dA = 0, total = 0;
-  size_t wt_off[kMaxAtoms] = {};
+  int K = 0, K16 = 0, hn = 0;
+  int64_t dw_tiles = 0, dw_units = 0;
+  size_t dw_lds = 0;
+  size_t ws_mask = 0, ws_fwsw = 0, ws_part = 0, ws_dbpart = 0, ws_dA = 0, total = 0;
+  bool xs_dw = false;        // dW through the per-group sums (SUM / MEAN, affine)
+  LinBwdPlan lin;
 };
 
 BwdPlan plan_bwd(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& F) {
@@ -300,37 +231,28 @@ BwdPlan plan_bwd(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   p.F = F;
   p.K = F.K;
   p.K16 = (int)round_up(F.K, 16);
-  p.hp = (int)round_up(L->h, 4);
   int hn = (kDwMaxB * 8 * 16 * 16 / p.K16) / 16 * 16;
   p.hn = std::max(16, std::min(L->h, hn));
   const int64_t E = idx->E;
-  p.dx_tiles = cdiv(E, kDxTM);
+  p.xs_dw = L->act_pre == RELNN_ACT_NONE && L->agg != RELNN_MAX;
   p.dw_tiles = cdiv(E, kDwTM);
   p.dw_units = std::max<int64_t>(1, std::min<int64_t>(p.dw_tiles, num_cus()));
-  int dmax = 0;
-  for (int j = 0; j < L->k; ++j) dmax = std::max(dmax, L->d[j]);
-  p.dx_lds = 2 * kDxTM * sizeof(int64_t) + (size_t)kDxTM * (p.hp + 4) * 4 + (size_t)kDxTM * (dmax + 4) * 4;
   p.dw_lds = (size_t)kDwTM * (p.K16 + 4) * 4 + (size_t)kDwTM * (p.hn + 4) * 4;
   size_t off = 0;
   p.ws_mask = off;
   if (L->act_pre != RELNN_ACT_NONE) off += round_up(std::max<int64_t>(E, 1) * L->h, 256);
   p.ws_fwsw = off;
   off += round_up(F.ws_carry - F.ws_wsw, 256);          // forward W swizzle (mask kernel)
-  p.ws_wt = off;
-  for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
-    p.wt_off[j] = off;
-    off += round_up((int64_t)p.hp * L->d[j] * 4, 256);
-  }
-  p.ws_carry = off;
-  off += round_up(std::max<int64_t>(p.dx_tiles, 1) * 2 * dmax * 4, 256);
-  off = std::max(off, p.ws_carry + round_up(F.carry_units * 2 * L->h * 4, 256));   // mask kernel carry unused
   p.ws_part = off;
-  off += round_up(p.dw_units * p.K16 * L->h * 4, 256);
-  p.ws_dbpart = off;
-  off += round_up(p.dw_units * L->h * 4, 256);
+  if (!p.xs_dw) {
+    off += round_up(p.dw_units * p.K16 * L->h * 4, 256);
+    p.ws_dbpart = off;
+    off += round_up(p.dw_units * L->h * 4, 256);
+  }
   p.ws_dA = off;
   off += round_up(std::max<int64_t>(idx->G, 1) * L->h * 4, 256);
-  p.total = off;
+  p.lin = plan_lin_bwd(idx, L, off, p.xs_dw);
+  p.total = p.lin.total;
   return p;
 }
 
@@ -376,7 +298,7 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
     RELNN_REQUIRE(ws != nullptr && ws_bytes >= P.total, RELNN_E_INVALID,
                   "workspace of %zu bytes given, %zu needed", ws_bytes, P.total);
     RELNN_REQUIRE(((uintptr_t)ws & 255) == 0, RELNN_E_INVALID, "workspace must be 256-byte aligned");
-    RELNN_REQUIRE(P.dx_lds <= 160 * 1024 && P.dw_lds <= 160 * 1024, RELNN_E_UNSUPPORTED,
+    RELNN_REQUIRE(P.xs_dw || P.dw_lds <= 160 * 1024, RELNN_E_UNSUPPORTED,
                   "K = %d, h = %d does not fit the backward LDS tiles", P.K, L->h);
     hipStream_t s = (hipStream_t)stream;
     char* w = static_cast<char*>(ws);
@@ -420,7 +342,9 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
     }
 
     // dW and db
-    {
+    if (P.xs_dw) {
+      lin_bwd_dw(idx, L, P.lin, emb, dA, dW, db, accum, w, s);
+    } else {
       DwArgs d{};
       d.at = at;
       d.rows = idx->rows;
@@ -450,33 +374,7 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
       RELNN_LAUNCHED();
     }
 
-    // dz_j for every atom, in body order
-    for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
-      const int d = L->d[j];
-      float* wt = reinterpret_cast<float*>(w + P.wt_off[j]);
-      const int64_t nsw = (int64_t)P.hp * d;
-      if (L->dtype == RELNN_BF16)
-        k_swizzle_wt<__bf16><<<grid_for(nsw), 256, 0, s>>>(static_cast<const __bf16*>(W), h, P.hp, koff, d, wt);
-      else
-        k_swizzle_wt<float><<<grid_for(nsw), 256, 0, s>>>(static_cast<const float*>(W), h, P.hp, koff, d, wt);
-      RELNN_LAUNCHED();
-      DxArgs x{};
-      x.R = R;
-      x.t_pos = idx->t_pos[j];
-      x.E = E;
-      x.hp = P.hp;
-      x.d = d;
-      x.Wsw = wt;
-      x.sg = Seg{idx->t_seg[j], idx->t_segoff[j], E, nullptr};
-      x.sink = Sink{RELNN_SUM, RELNN_ACT_NONE, demb[j], nullptr, nullptr, true, idx->t_segrow[j], false};
-      x.carry = reinterpret_cast<float*>(w + P.ws_carry);
-      allow_lds(k_bwd_dx, P.dx_lds);
-      {
-        KTimer tm("bwd_dx", s);
-        k_bwd_dx<<<(unsigned)P.dx_tiles, kThreads, P.dx_lds, s>>>(x);
-        RELNN_LAUNCHED();
-      }
-      launch_fixup(x.sg, kDxTM, d, P.dx_tiles, P.dx_tiles, x.sink, x.carry, nullptr, s);
-    }
+    // dz_j for every atom, in body order (through the per-row sums of dY)
+    lin_bwd_dx(idx, L, P.lin, W, dA, L->agg == RELNN_MAX ? argmax : nullptr, R.mask, demb, w, s);
   });
 }
