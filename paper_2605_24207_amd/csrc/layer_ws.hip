@@ -7,24 +7,26 @@
 // with the earliest maximiser), so a block leaves at most two partials, for
 // the groups cut by its range ends; k_fixup combines those in block order.
 //
-// k_fwd_dma (FP32 and BF16) has two kinds of waves:
+// k_fwd_dma (FP32 and BF16; one instance for SUM/MEAN and one for MAX) has
+// two kinds of waves:
 //  * h/16 compute waves, 16 output columns each, whose W slice stays in
 //    VGPRs for the whole kernel.  They multiply a tile on the matrix cores
 //    (f32 16x16x4 or bf16 16x16x32, FP32 accumulation) and reduce it per
 //    group straight from the accumulators: a lane holds 8 rows of one
-//    column, a run of equal group is summed per lane and across the 4 lanes
-//    of the column by two butterfly shuffles, and the group left open at
-//    the end of a tile stays in registers for the next one.
+//    column; for each run of equal group the rows of the run are kept by a
+//    bit mask (no per-row branch), summed per lane and across the 4 lanes of
+//    the column by two row swaps, and the group left open at the end of a
+//    tile stays in registers for the next one.
 //  * 4 DMA waves that move tiles from HBM into an NB-deep LDS ring with
 //    16-byte global->LDS loads (no registers in between): while tile t is
 //    multiplied, tiles t+1 .. t+NB-2 are in flight and t+NB-1 is issued.
-//    The row numbers for a tile are read one tile ahead into VGPRs, before
-//    the previous tile's loads are issued, so that waiting for them never
-//    waits for tile data (vector memory counts retire in order).
+//    Each lane's source rows, strides and row-number slots are worked out
+//    once per kernel; per tile a wave reads its row numbers from LDS, waits
+//    once, and issues its loads.
 // LDS tile layout: row-major without padding; 16-byte chunk c of row r is
 // stored at position c ^ (r & SWM) of its row, so the 16 rows read by one
 // MFMA operand load fall into 16 different bank groups.
-// One __syncthreads per tile.
+// One barrier per tile.
 //
 // k_push (pushdown) keeps the LDS-staged reduce (ws_reduce).
 #include "layer_fwd.hpp"
@@ -34,6 +36,7 @@ namespace relnn {
 constexpr int kDmaWaves = 4;
 constexpr int kHMax = 128;
 constexpr int kTM = 32;                  // tuples per tile
+constexpr int kZeroBytes = 64;           // zero bytes after the re-laid weight
 
 struct WsArgs {
   Atoms at;
@@ -43,6 +46,7 @@ struct WsArgs {
   int K, h;
   int64_t ntiles, nunits;
   const void* Wsw;
+  const void* zeros;         // 64 zero bytes (source of the K..KP pad chunks)
   const float* b;
   int act_pre;
   Seg sg;
@@ -225,6 +229,7 @@ __global__ void k_ws_swizzle_bf16(const __bf16* __restrict__ W, int K, int KP, i
     const int k = 32 * ks + 8 * (lane / 16) + e;
     out[i] = k < K ? W[(int64_t)k * h + cw * 16 + lane % 16] : (__bf16)0.0f;
   }
+  if (blockIdx.x == 0 && threadIdx.x < kZeroBytes / 2) out[total + threadIdx.x] = (__bf16)0.0f;
 }
 
 // W for the FP32 kernel, 16-column slices: fragment ks of slice cw, lane l
@@ -241,6 +246,7 @@ __global__ void k_ws_swizzle_f16c(const float* __restrict__ W, int K, int KP, in
     const int k = 16 * (ks / 4) + 4 * (lane / 16) + ks % 4;
     out[i] = k < K ? W[(int64_t)k * h + cw * 16 + lane % 16] : 0.0f;
   }
+  if (blockIdx.x == 0 && threadIdx.x < kZeroBytes / 4) out[total + threadIdx.x] = 0.0f;
 }
 
 // Atom owning Concat column el (j: its index).  Picked with compile-time
@@ -285,58 +291,86 @@ struct DmaGeo {
 // Index slot of tile u (int32): DMA wave j writes 256 bytes at j*64 ints;
 // lanes 0..31 carry atom j's row number of tuple r, lanes 32..63 of wave 0
 // the tuple's group number and lanes 32, 33 of wave 1 the group numbers of
-// the tuples just before and after the tile.  Atoms past k repeat atom 0
-// and tuples past the tile repeat its last one, so that every wave issues
-// the same operations for every tile.
+// the tuples just before and after the tile.  Every lane of every DMA wave
+// loads (atoms past k repeat atom 0, tuples past the tile repeat its last
+// one, the remaining lanes fill slot words nobody reads), so the load needs
+// no branch.
 constexpr int kSlotSeg = 32;          // ints: group numbers of the tile
 constexpr int kSlotEdge = 64 + 32;    // ints: groups before and after it
 
-__device__ __forceinline__ void dma_index(const WsArgs& a, int64_t u, char* slot, int dw) {
-  const int lane = __lane_id();
-  const int64_t e0 = u * kTM;
-  const int nv = (int)min<int64_t>(kTM, a.E - e0);
-  // compile-time indices only (a chain of selects over the argument's
-  // array is turned into a table in scratch memory)
-  const int32_t* src = a.at.rows[0];
-  auto pick = [&](auto U) {
-    constexpr int q = decltype(U)::value;
-    if (dw == q && q < a.at.k) src = a.at.rows[q];
-  };
-  pick(std::integral_constant<int, 1>{});
-  pick(std::integral_constant<int, 2>{});
-  pick(std::integral_constant<int, 3>{});
-  int64_t e = e0 + min(lane & 31, nv - 1);
-  if (lane >= 32) {
-    src = a.sg.seg_of;
-    if (dw == 1) e = lane == 32 ? max<int64_t>(e0 - 1, 0) : min<int64_t>(e0 + nv, a.E - 1);
-  }
-  const bool on = lane < 32 || dw == 0 || (dw == 1 && lane < 34);
-  if (on) __builtin_amdgcn_global_load_lds(src + e, slot + dw * 256, 4, 0, 0);
-}
-
-// Issues this DMA wave's share of the loads of tile u into the LDS tile X.
+// Per-lane plan of a DMA wave's share of a tile, fixed for the whole kernel:
+// load i of the wave moves 16 bytes from src[i] + row * stride[i] into its
+// LDS chunk slot, with row read from the tile's index slot at byte roff[i].
 // Chunk slot s (= 64 ins + lane) of the tile is row r = s / CPR, position
 // p = s % CPR, holding logical chunk p ^ (r & SWM).  Chunks in the K..KP
-// pad are not loaded (their LDS slots were zeroed once).  The row numbers
-// come from the tile's LDS slot (an LDS read: no wait on vector memory).
+// pad load 16 zero bytes (stride 0), so every lane loads and no load needs
+// a branch.
 template <class T, int KP, int NB>
-__device__ __forceinline__ void dma_tile(const WsArgs& a, const int32_t* rows, char* X, int dw) {
+struct DmaPlan {
   using G = DmaGeo<T, KP, NB>;
-  const int lane = __lane_id();
+  const char* src[G::NIW];
+  uint32_t stride[G::NIW];
+  int roff[G::NIW];
+  const int32_t* isrc;       // index slot source of this lane
+  int ilane;                 // tuple of the tile this lane's index word names
+  bool edge;                 // lanes 32.. of wave 1: the groups around the tile
+
+  __device__ __forceinline__ DmaPlan(const WsArgs& a, int dw) {
+    const int lane = __lane_id();
 #pragma unroll
-  for (int i = 0; i < G::NIW; ++i) {
-    const int ins = dw * G::NIW + i;
-    const int sl = ins * 64 + lane;
-    const int r = sl / G::CPR;
-    const int pos = sl - r * G::CPR;
-    const int el = (pos ^ (r & G::SWM)) * G::EPC;
-    const int elc = min(el, a.K - G::EPC);
-    const AtomSel A = atom_sel(a.at, elc);
-    const int32_t row = rows[A.j * 64 + r];
-    const T* g = static_cast<const T*>(A.emb) + (int64_t)row * A.d + (elc - A.koff);
-    if (el < a.K) __builtin_amdgcn_global_load_lds(g, X + ins * 1024, 16, 0, 0);
+    for (int i = 0; i < G::NIW; ++i) {
+      const int ins = dw * G::NIW + i;
+      const int sl = ins * 64 + lane;
+      const int r = sl / G::CPR;
+      const int pos = sl - r * G::CPR;
+      const int el = (pos ^ (r & G::SWM)) * G::EPC;
+      const bool pad = el >= a.K;
+      const AtomSel A = atom_sel(a.at, pad ? 0 : el);
+      src[i] = pad ? static_cast<const char*>(a.zeros)
+                   : static_cast<const char*>(A.emb) + (int64_t)(el - A.koff) * (int)sizeof(T);
+      stride[i] = pad ? 0u : (uint32_t)A.d * (uint32_t)sizeof(T);
+      roff[i] = (A.j * 64 + r) * 4;
+    }
+    // compile-time indices only (a chain of selects over the argument's
+    // array is turned into a table in scratch memory)
+    const int32_t* rs = a.at.rows[0];
+    auto pick = [&](auto U) {
+      constexpr int q = decltype(U)::value;
+      if (dw == q && q < a.at.k) rs = a.at.rows[q];
+    };
+    pick(std::integral_constant<int, 1>{});
+    pick(std::integral_constant<int, 2>{});
+    pick(std::integral_constant<int, 3>{});
+    isrc = lane < 32 ? rs : a.sg.seg_of;
+    ilane = lane & 31;
+    edge = dw == 1 && lane >= 32;
   }
-}
+
+  // index slot of tile u (u < ntiles) into slot
+  __device__ __forceinline__ void index(const WsArgs& a, int64_t u, char* slot, int dw) const {
+    const int64_t e0 = u * kTM;
+    const int nv = (int)min<int64_t>(kTM, a.E - e0);
+    // offset from e0 in 32 bits (a per-lane choice between 64-bit values
+    // costs a conversion sequence)
+    int off = min(ilane, nv - 1);
+    const int before = e0 > 0 ? -1 : 0;
+    const int after = e0 + nv < a.E ? nv : nv - 1;
+    if (edge) off = __lane_id() == 32 ? before : after;
+    __builtin_amdgcn_global_load_lds(isrc + e0 + off, slot + dw * 256, 4, 0, 0);
+  }
+
+  // this wave's loads of a tile whose row numbers are in slot, into X
+  __device__ __forceinline__ void tile(const char* slot, char* X, int dw) const {
+    int32_t rv[G::NIW];
+#pragma unroll
+    for (int i = 0; i < G::NIW; ++i) rv[i] = *reinterpret_cast<const int32_t*>(slot + roff[i]);
+#pragma unroll
+    for (int i = 0; i < G::NIW; ++i) {
+      const char* g = src[i] + (uint64_t)(uint32_t)rv[i] * stride[i];
+      __builtin_amdgcn_global_load_lds(g, X + (dw * G::NIW + i) * 1024, 16, 0, 0);
+    }
+  }
+};
 
 // Barriers of the DMA ring.  __syncthreads() is a release fence plus
 // s_barrier, and a release fence waits for every vector-memory operation,
@@ -368,10 +402,9 @@ __device__ __forceinline__ float col_sum4(float v) {
 
 // Max with the earliest maximiser (ties: smaller tuple position).
 __device__ __forceinline__ void max_pick(float& v, int32_t& a, float v1, int32_t a1) {
-  if (v1 > v || (v1 == v && a1 < a)) {
-    v = v1;
-    a = a1;
-  }
+  const bool take = v1 > v || (v1 == v && a1 < a);
+  v = take ? v1 : v;
+  a = take ? a1 : a;
 }
 
 __device__ __forceinline__ void col_max4(float& v, int32_t& a) {
@@ -385,6 +418,12 @@ __device__ __forceinline__ void col_max4(float& v, int32_t& a) {
   v = __uint_as_float(qv[0]);
   a = (int32_t)qa[0];
   max_pick(v, a, __uint_as_float(qv[1]), (int32_t)qa[1]);
+}
+
+// y if bit i of m is set, else +0 (a bit mask, not a multiply: exact for
+// every y, infinities included)
+__device__ __forceinline__ float keep_bit(float y, uint32_t m, int i) {
+  return __int_as_float(__float_as_int(y) & ((int32_t)(m << (31 - i)) >> 31));
 }
 
 template <class T>
@@ -402,7 +441,7 @@ struct DmaMfma<__bf16> {                 // bf16 16x16x32, one 16-byte A read pe
   static constexpr int nks() { return KP / 32; }
 };
 
-template <class T, int KP, int NB>
+template <class T, int KP, int NB, bool kMax>
 __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArgs a) {
   using G = DmaGeo<T, KP, NB>;
   using WT = typename DmaMfma<T>::W;
@@ -426,36 +465,44 @@ __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArg
   const int64_t range_hi = min<int64_t>(te * TM, a.E);
   if (tb >= te) return;
 
-  // zero the ring once: pad chunks (K..KP) are never written afterwards
+  // zero the ring once (every chunk is rewritten per tile; this only keeps
+  // uninitialised LDS out of the first products)
   for (int i = threadIdx.x; i < NB * G::TILE / 16; i += blockDim.x)
     reinterpret_cast<uint4*>(smem)[i] = make_uint4(0, 0, 0, 0);
   __syncthreads();
-  auto ring = [&](int64_t u) { return smem + (int)((u - tb) % NB) * G::TILE; };
   char* irs = smem + NB * G::TILE;                          // row-number slots
-  auto islot = [&](int64_t u) { return irs + (int)((u - tb) % G::NIR) * G::IRB; };
+  // ring position of a tile relative to tb: tile (it % NB), index slot
+  // (it % NIR); both kept as wrapping 32-bit counters
+  auto wrap = [](int v, int n) { return v >= n ? v - n : v; };
 
   if (wave >= ncw) {
     // ------------------------------------------------------------ DMA waves
-    // Every vector-memory operation of these waves is a global->LDS load;
-    // at iteration t a wave issues the index slot of tile t+2NB-2, then its
+    // At iteration t a wave issues the index slot of tile t+2NB-2, then its
     // share of tile t+NB-1, then waits until its share of tile t+1 has
     // landed.  The index slot of tile v is issued just before tile v-NB+1,
     // so it has landed (and passed a barrier) before tile v is issued.
     const int dw = wave - ncw;
+    const DmaPlan<T, KP, NB> P(a, dw);
     const int64_t tl = te - 1;
 #pragma unroll
-    for (int j = 0; j + 1 < NB; ++j) dma_index(a, min(tb + j, tl), islot(tb + j), dw);
+    for (int j = 0; j + 1 < NB; ++j) P.index(a, min(tb + j, tl), irs + j * G::IRB, dw);
     asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");   // index slots of tb .. tb+NB-2
 #pragma unroll
     for (int j = 0; j + 1 < NB; ++j) {
-      dma_index(a, min(tb + j + NB - 1, tl), islot(tb + j + NB - 1), dw);
-      dma_tile<T, KP, NB>(a, reinterpret_cast<const int32_t*>(islot(tb + j)), ring(tb + j), dw);
+      P.index(a, min(tb + j + NB - 1, tl), irs + (j + NB - 1) * G::IRB, dw);
+      P.tile(irs + j * G::IRB, smem + j * G::TILE, dw);
     }
     dma_barrier<G::WAIT>();                                   // tile tb has landed
+    int si = (2 * NB - 2) % G::NIR;                           // index slot of tile t + 2NB - 2
+    int sr = NB - 1;                                          // index slot of tile t + NB - 1
+    int rr = NB - 1;                                          // ring tile of tile t + NB - 1
     for (int64_t t = tb; t < te; ++t) {
-      dma_index(a, min(t + 2 * NB - 2, tl), islot(t + 2 * NB - 2), dw);
-      dma_tile<T, KP, NB>(a, reinterpret_cast<const int32_t*>(islot(t + NB - 1)), ring(t + NB - 1), dw);
+      P.index(a, min(t + 2 * NB - 2, tl), irs + si * G::IRB, dw);
+      P.tile(irs + sr * G::IRB, smem + rr * G::TILE, dw);
       dma_barrier<G::WAIT>();                                 // tile t+1 has landed
+      si = wrap(si + 1, G::NIR);
+      sr = wrap(sr + 1, G::NIR);
+      rr = wrap(rr + 1, NB);
     }
     // loads past the range may still be landing: the LDS must not be
     // released to another block before they have
@@ -467,7 +514,6 @@ __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArg
   const int cw = wave;
   const int col = cw * 16 + (lane & 15);
   const float bc = a.b ? a.b[col] : 0.0f;
-  const bool maxagg = a.sink.agg == RELNN_MAX;
   WT w[NKS];
 #pragma unroll
   for (int ks = 0; ks < NKS; ++ks) w[ks] = reinterpret_cast<const WT*>(a.Wsw)[(cw * NKS + ks) * 64 + lane];
@@ -475,43 +521,42 @@ __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArg
   // with it for the group numbers of the next tile) at every tile's MFMAs
   __builtin_amdgcn_s_waitcnt(0);
 
-  // group numbers of tile t from its index slot: lane r < 32 row r
-  // (clamped), lane 32 the row before the tile, lane 33 the row after it
-  // (clamped; their validity follows from e0 and nv)
-  auto seg_read = [&](int64_t t) {
-    const int32_t* sl = reinterpret_cast<const int32_t*>(islot(t));
-    return sl[lane < 32 ? kSlotSeg + lane : kSlotEdge + min(lane - 32, 1)];
-  };
-
-  // state of the group open at the end of the previous tile (per column)
-  float oS = 0.0f, oC = 0.0f;
-  int32_t oArg = -1, oN = 0;
+  // state of the group open at the end of the previous tile: value per
+  // column, count and cut flag per wave
+  float oS = kMax ? -INFINITY : 0.0f, oC = 0.0f;
+  int32_t oArg = -1;
+  int oN = 0;
   bool oCut = false;
   const int q4 = 4 * (lane >> 4);
   const int64_t slot_base = bidx * 2 * h + col;
+  const int r0 = lane & 15, r1 = 16 + (lane & 15);
+  const int cq = lane >> 4;
+  // A operand of step m: logical chunk 4m + cq of rows r0 / r1, stored at
+  // position (4m + cq) ^ sw = 4 (m ^ (sw >> 2)) + ((cq ^ sw) & 3): a per-lane
+  // base for m % 4 plus a constant for the rest (four registers per row
+  // instead of one address per step)
+  auto chunk_base = [&](int sw, int j) { return 4 * (j ^ (sw >> 2)) + ((cq ^ sw) & 3); };
+  int b0[4], b1[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    b0[j] = G::EPC * chunk_base(r0 & G::SWM, j);
+    b1[j] = G::EPC * chunk_base(r1 & G::SWM, j);
+  }
 
   compute_barrier();                                         // (index slots staged)
   compute_barrier();                                         // tile tb is in LDS
+  int rr = 0, ri = 0;                                        // ring tile, index slot of t
   for (int64_t t = tb; t < te; ++t) {
-    const int32_t gcur = seg_read(t);
-    const char* X = ring(t);
+    // group numbers of tile t: lane r < 32 row r (clamped), lane 32 the row
+    // before the tile, lane 33 the row after it (clamped; their validity
+    // follows from e0 and nv)
+    const int32_t* gsl = reinterpret_cast<const int32_t*>(irs + ri * G::IRB);
+    const int32_t gcur = gsl[lane < 32 ? kSlotSeg + lane : kSlotEdge + min(lane - 32, 1)];
+    const char* X = smem + rr * G::TILE;
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-    const int r0 = lane & 15, r1 = 16 + (lane & 15);
-    // A operand of step m: logical chunk 4m + cq of rows r0 / r1, stored at
-    // position (4m + cq) ^ sw = 4 (m ^ (sw >> 2)) + ((cq ^ sw) & 3): a
-    // per-lane base for m % 4 plus a constant for the rest (four registers
-    // per row instead of one address per step)
-    const int cq = lane >> 4;
-    auto chunk_base = [&](int sw, int j) { return 4 * (j ^ (sw >> 2)) + ((cq ^ sw) & 3); };
     if constexpr (std::is_same<T, float>::value) {
       const float* x0 = reinterpret_cast<const float*>(X) + r0 * KP;
       const float* x1 = reinterpret_cast<const float*>(X) + r1 * KP;
-      int b0[4], b1[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        b0[j] = 4 * chunk_base(r0 & G::SWM, j);
-        b1[j] = 4 * chunk_base(r1 & G::SWM, j);
-      }
       // no read-ahead (the W slice takes most registers): the other compute
       // wave of the SIMD fills the LDS latency
 #pragma unroll
@@ -526,114 +571,119 @@ __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArg
         __builtin_amdgcn_sched_barrier(0);
       }
     } else {
+      // operand reads run PD steps ahead of the products
       const __bf16* x0 = reinterpret_cast<const __bf16*>(X) + r0 * KP;
       const __bf16* x1 = reinterpret_cast<const __bf16*>(X) + r1 * KP;
-      int b0[4], b1[4];
+      constexpr int PD = NKS < 4 ? NKS : 4;
+      auto rd = [&](const __bf16* x, const int (&b)[4], int k) {
+        return *reinterpret_cast<const bf16x8*>(x + 32 * (k & ~3) + b[k & 3]);
+      };
+      bf16x8 c0[PD], c1[PD];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        b0[j] = 8 * chunk_base(r0 & G::SWM, j);
-        b1[j] = 8 * chunk_base(r1 & G::SWM, j);
+      for (int p = 0; p < PD; ++p) {
+        c0[p] = rd(x0, b0, p);
+        c1[p] = rd(x1, b1, p);
       }
-      bf16x8 c0 = *reinterpret_cast<const bf16x8*>(x0 + b0[0]);
-      bf16x8 c1 = *reinterpret_cast<const bf16x8*>(x1 + b1[0]);
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) {
-        bf16x8 n0 = c0, n1 = c1;
-        if (ks + 1 < NKS) {
-          const int kn = ks + 1;
-          n0 = *reinterpret_cast<const bf16x8*>(x0 + 32 * (kn & ~3) + b0[kn & 3]);
-          n1 = *reinterpret_cast<const bf16x8*>(x1 + 32 * (kn & ~3) + b1[kn & 3]);
+        const bf16x8 u0 = c0[ks % PD], u1 = c1[ks % PD];
+        if (ks + PD < NKS) {
+          c0[ks % PD] = rd(x0, b0, ks + PD);
+          c1[ks % PD] = rd(x1, b1, ks + PD);
         }
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c0, w[ks], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c1, w[ks], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(u0, w[ks], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(u1, w[ks], acc1, 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
-        c0 = n0;
-        c1 = n1;
       }
     }
 
     // ---- per-group reduce of the tile (rows of this lane: q4 + i, 16 + q4 + i)
     const int64_t e0 = t * TM;
     const int nv = (int)min<int64_t>(TM, a.E - e0);
+    float y[8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {                    // tuple values y = act_pre(x W + b), in place
-      acc0[i] = act_apply(a.act_pre, acc0[i] + bc);
-      acc1[i] = act_apply(a.act_pre, acc1[i] + bc);
+    for (int i = 0; i < 4; ++i) {                    // tuple values y = act_pre(x W + b)
+      y[i] = act_apply(a.act_pre, acc0[i] + bc);
+      y[4 + i] = act_apply(a.act_pre, acc1[i] + bc);
     }
     // runs of equal group: lane r starts one if its group differs from
     // lane r-1's (DPP wave shift right by one lane)
     const int32_t gup = __builtin_amdgcn_update_dpp(0, gcur, 0x138, 0xf, 0xf, false);
     const bool start = lane < nv && (lane == 0 || gup != gcur);
-    uint64_t runs = __ballot(start);
+    uint32_t runs = (uint32_t)__ballot(start);
     const int32_t g_first = __builtin_amdgcn_readlane(gcur, 0);
     const int32_t g_last = __builtin_amdgcn_readlane(gcur, nv - 1);
     const int32_t g_before = __builtin_amdgcn_readlane(gcur, 32);
     const int32_t g_after = __builtin_amdgcn_readlane(gcur, 33);
     const bool prev_same = e0 > 0 && g_before == g_first;
     const bool next_same = e0 + nv < a.E && g_after == g_last;
+    const bool keep_open = next_same && e0 + nv < range_hi;
     bool first_run = true;
     while (runs) {
-      const int rs = __builtin_ctzll(runs);
+      const int rs = __builtin_ctz(runs);
       runs &= runs - 1;
-      const int re = runs ? __builtin_ctzll(runs) : nv;
+      const int re = runs ? __builtin_ctz(runs) : nv;
       const bool last_run = runs == 0;
-      const int32_t g = __builtin_amdgcn_readlane(gcur, rs);
-      // this lane's rows of the run, then the 4 lanes of the column
-      float part = maxagg ? -INFINITY : 0.0f;
+      // rows [rs, re) of the tile as a bit mask, then this lane's 4 + 4 bits
+      const uint32_t M = (re >= 32 ? 0xffffffffu : ((1u << re) - 1u)) & ~((1u << rs) - 1u);
+      const uint32_t m0 = M >> q4, m1 = M >> (16 + q4);
+      float part;
       int32_t parg = INT32_MAX;
+      if constexpr (kMax) {
+        part = -INFINITY;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int rw = (i < 4 ? 0 : 16) + q4 + (i & 3);
-        const bool in = rw >= rs && rw < re;
-        const float yi = i < 4 ? acc0[i & 3] : acc1[i & 3];
-        if (maxagg) {
-          if (in && yi > part) {
-            part = yi;
-            parg = (int32_t)(e0 + rw);
+        for (int i = 0; i < 8; ++i) {
+          const uint32_t mb = i < 4 ? m0 : m1;
+          const bool in = (mb >> (i & 3)) & 1u;
+          const int32_t rw = (int32_t)(e0 + (i < 4 ? 0 : 16) + q4 + (i & 3));
+          const bool take = in && (y[i] > part || parg == INT32_MAX);   // the run's first row always
+          part = take ? y[i] : part;
+          parg = take ? rw : parg;
+        }
+        col_max4(part, parg);
+      } else {
+        const float s0 = keep_bit(y[0], m0, 0) + keep_bit(y[1], m0, 1);
+        const float s1 = keep_bit(y[2], m0, 2) + keep_bit(y[3], m0, 3);
+        const float s2 = keep_bit(y[4], m1, 0) + keep_bit(y[5], m1, 1);
+        const float s3 = keep_bit(y[6], m1, 2) + keep_bit(y[7], m1, 3);
+        part = col_sum4((s0 + s1) + (s2 + s3));
+      }
+      const int cnt = re - rs;
+      if (first_run && prev_same && t > tb) {              // the block's open group
+        if constexpr (kMax) {
+          if (part > oS) {
+            oS = part;
+            oArg = parg;
           }
         } else {
-          part += in ? yi : 0.0f;
+          kahan_add(oS, oC, part);
         }
-      }
-      if (maxagg)
-        col_max4(part, parg);
-      else
-        part = col_sum4(part);
-      const int32_t cnt = re - rs;
-      if (first_run && prev_same) {
-        if (t > tb) {                                        // the block's open group
-          if (maxagg) {
-            if (part > oS) {
-              oS = part;
-              oArg = parg;
-            }
-          } else {
-            kahan_add(oS, oC, part);
-          }
-          oN += cnt;
-        } else {                                             // began before the range
-          oS = part; oC = 0.0f; oArg = parg; oN = cnt; oCut = true;
-        }
-      } else {
-        oS = part; oC = 0.0f; oArg = parg; oN = cnt; oCut = false;
-      }
-      if (last_run && next_same && e0 + nv < range_hi) {
-        // stays open for the next tile
-      } else if (lane < 16) {
-        const float v = maxagg ? oS : oS - oC;
-        if (last_run && next_same) {                         // runs past the range end
-          const int64_t o = slot_base + (oCut ? 0 : h);
-          a.carry[o] = v;
-          if (a.carry_arg) a.carry_arg[o] = oArg;
-        } else if (!oCut) {
-          sink_write<true>(a.sink, g, col, h, v, oArg, oN);
-        } else {                                             // cut by the range start
-          a.carry[slot_base] = v;
-          if (a.carry_arg) a.carry_arg[slot_base] = oArg;
-        }
+        oN += cnt;
+      } else {                                             // a new group (cut if it began before the range)
+        oS = part;
+        oC = 0.0f;
+        oArg = parg;
+        oN = cnt;
+        oCut = first_run && prev_same;
       }
       first_run = false;
+      if (last_run && keep_open) break;                    // stays open for the next tile
+      if (lane < 16) {
+        const float v = kMax ? oS : oS - oC;
+        if (last_run && next_same) {                       // runs past the range end
+          const int64_t o = slot_base + (oCut ? 0 : h);
+          a.carry[o] = v;
+          if (kMax && a.carry_arg) a.carry_arg[o] = oArg;
+        } else if (!oCut) {
+          sink_write<true>(a.sink, __builtin_amdgcn_readlane(gcur, rs), col, h, v, oArg, oN);
+        } else {                                           // cut by the range start
+          a.carry[slot_base] = v;
+          if (kMax && a.carry_arg) a.carry_arg[slot_base] = oArg;
+        }
+      }
     }
+    rr = wrap(rr + 1, NB);
+    ri = wrap(ri + 1, G::NIR);
     compute_barrier();
   }
 }
@@ -733,6 +783,14 @@ constexpr int ring_depth() {
   return fit < 6 ? fit : 6;
 }
 
+template <class T, int KP, int NB, bool kMax>
+void launch_dma(const WsArgs& a, size_t lds, hipStream_t s) {
+  allow_lds(k_fwd_dma<T, KP, NB, kMax>, lds);
+  KTimer tm("fwd_fused", s);
+  k_fwd_dma<T, KP, NB, kMax><<<(unsigned)a.nunits, (a.h / 16 + kDmaWaves) * 64, lds, s>>>(a);
+  RELNN_LAUNCHED();
+}
+
 template <class T, int KP>
 void run_dma(const WsArgs& a, hipStream_t s) {
   constexpr int NB = ring_depth<T, KP>();
@@ -740,10 +798,10 @@ void run_dma(const WsArgs& a, hipStream_t s) {
   static_assert(NB >= 2, "two LDS tiles at least");
   const size_t lds = (size_t)NB * G::TILE + (size_t)G::NIR * G::IRB;
   RELNN_REQUIRE(lds <= 160 * 1024, RELNN_E_HIP, "internal: LDS ring of %zu bytes", lds);
-  allow_lds(k_fwd_dma<T, KP, NB>, lds);
-  KTimer tm("fwd_fused", s);
-  k_fwd_dma<T, KP, NB><<<(unsigned)a.nunits, (a.h / 16 + kDmaWaves) * 64, lds, s>>>(a);
-  RELNN_LAUNCHED();
+  if (a.sink.agg == RELNN_MAX)
+    launch_dma<T, KP, NB, true>(a, lds, s);
+  else
+    launch_dma<T, KP, NB, false>(a, lds, s);
 }
 
 int num_cus() {
@@ -809,7 +867,7 @@ WsPlan plan_ws(int dtype, int K, int h, int64_t E) {
   p.TM = kTM;
   p.ntiles = cdiv(E, p.TM);
   p.nunits = std::max<int64_t>(1, std::min<int64_t>(p.ntiles, num_cus()));
-  p.wsw_bytes = (size_t)p.KP * h * (bf ? 2 : 4);
+  p.wsw_bytes = (size_t)p.KP * h * (bf ? 2 : 4) + kZeroBytes;
   p.carry_elems = (size_t)p.nunits * 2 * h;
   return p;
 }
@@ -838,6 +896,7 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
   a.ntiles = p.ntiles;
   a.nunits = p.nunits;
   a.Wsw = Wsw;
+  a.zeros = static_cast<const char*>(Wsw) + (size_t)p.KP * f.h * (dtype == RELNN_BF16 ? 2 : 4);
   a.b = f.b;
   a.act_pre = f.act_pre;
   a.sg = f.sg;
@@ -861,5 +920,20 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
   }
   launch_fixup(f.sg, p.TM, f.h, p.ntiles, p.nunits, f.sink, carry, carry_arg, s);
 }
+
+// Explicit instantiations of the fused kernel: with implicit ones alone the
+// host pass left the launch stubs of some instances undefined.
+#define RELNN_DMA_INST(T, KP)                                                      \
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), false>(WsArgs); \
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true>(WsArgs);
+RELNN_DMA_INST(float, 64)
+RELNN_DMA_INST(float, 128)
+RELNN_DMA_INST(float, 256)
+RELNN_DMA_INST(float, 384)
+RELNN_DMA_INST(__bf16, 64)
+RELNN_DMA_INST(__bf16, 128)
+RELNN_DMA_INST(__bf16, 256)
+RELNN_DMA_INST(__bf16, 384)
+#undef RELNN_DMA_INST
 
 }  // namespace relnn
