@@ -166,6 +166,27 @@ __device__ __forceinline__ void sink_write(const Sink& k, int64_t s, int c, int 
     k.out[o] = act_apply(k.act_post, v);
 }
 
+// Columns c4 .. c4 + 3 of a finished SUM / MEAN group, for kernels whose
+// sink has no group constant, no row remap and no accumulation (c4 and h
+// multiples of 4).  MEAN scales by the reciprocal of the count.
+__device__ __forceinline__ void sink_write4(const Sink& k, int64_t s, int c4, int h, f32x4 v, int32_t cnt) {
+  if (k.agg == RELNN_MEAN) v *= __builtin_amdgcn_rcpf((float)cnt);
+  const int64_t o = s * h + c4;
+  if (k.pre) *reinterpret_cast<f32x4*>(k.pre + o) = v;
+  f32x4 w;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = act_apply(k.act_post, v[i]);
+  if (k.out_bf16) {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    bf16x4 b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] = (__bf16)w[i];
+    *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(k.out) + o) = b;
+  } else {
+    *reinterpret_cast<f32x4*>(k.out + o) = w;
+  }
+}
+
 // Reduces the rows [0, nv) of the LDS tile Ys (list positions e0..) per
 // segment.  Segments wholly inside the tile are finished and written; a
 // segment cut by the tile start leaves its partial in carry slot 0, one

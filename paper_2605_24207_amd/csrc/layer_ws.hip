@@ -293,10 +293,18 @@ struct DmaGeo {
 // the tuple's group number and lanes 32, 33 of wave 1 the group numbers of
 // the tuples just before and after the tile.  Every lane of every DMA wave
 // loads (atoms past k repeat atom 0, tuples past the tile repeat its last
-// one, the remaining lanes fill slot words nobody reads), so the load needs
-// no branch.
+// one, the remaining lanes fill slot words that the run table below
+// overwrites or nobody reads), so the load needs no branch.
+// For SUM / MEAN, DMA wave 0 then writes the tile's run table into the
+// words the rows of atoms 1..3 do not use: the header (number of runs,
+// whether the first run continues a group from before the tile, whether
+// the last one runs past it, tuples in the tile), and per run its first
+// row and its group.
 constexpr int kSlotSeg = 32;          // ints: group numbers of the tile
 constexpr int kSlotEdge = 64 + 32;    // ints: groups before and after it
+constexpr int kSlotHdr = 98;          // int: runs | prev_same << 8 | next_same << 9 | nv << 16
+constexpr int kSlotRunStart = 160;    // ints [32]: first row of run g
+constexpr int kSlotRunGroup = 224;    // ints [32]: group of run g
 
 // Per-lane plan of a DMA wave's share of a tile, fixed for the whole kernel:
 // load i of the wave moves 16 bytes from src[i] + row * stride[i] into its
@@ -370,6 +378,32 @@ struct DmaPlan {
       __builtin_amdgcn_global_load_lds(g, X + (dw * G::NIW + i) * 1024, 16, 0, 0);
     }
   }
+
+  // run table of tile u (wave 0, once its index slot has landed): runs of
+  // equal group start where a row's group differs from the row before
+  __device__ __forceinline__ static void run_table(const WsArgs& a, int64_t u, char* slot) {
+    const int lane = __lane_id();
+    int32_t* sw = reinterpret_cast<int32_t*>(slot);
+    const int32_t g = sw[lane < 32 ? kSlotSeg + lane : kSlotEdge + min(lane - 32, 1)];
+    const int64_t e0 = u * kTM;
+    const int nv = (int)min<int64_t>(kTM, a.E - e0);
+    const int32_t gup = __builtin_amdgcn_update_dpp(0, g, 0x138, 0xf, 0xf, false);   // row - 1
+    const bool start = lane < nv && (lane == 0 || gup != g);
+    const uint64_t runs = __ballot(start);
+    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(runs >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)runs, 0u));
+    const int nr = __popcll(runs);
+    const int32_t g_first = __builtin_amdgcn_readlane(g, 0);
+    const int32_t g_last = __builtin_amdgcn_readlane(g, nv - 1);
+    const int32_t g_before = __builtin_amdgcn_readlane(g, 32);
+    const int32_t g_after = __builtin_amdgcn_readlane(g, 33);
+    const int ps = e0 > 0 && g_before == g_first;
+    const int ns = e0 + nv < a.E && g_after == g_last;
+    if (start) {
+      sw[kSlotRunStart + rank] = lane;
+      sw[kSlotRunGroup + rank] = g;
+    }
+    if (lane == 0) sw[kSlotHdr] = nr | (ps << 8) | (ns << 9) | (nv << 16);
+  }
 };
 
 // Barriers of the DMA ring.  __syncthreads() is a release fence plus
@@ -380,11 +414,11 @@ struct DmaPlan {
 // accesses across it.
 //   DMA waves:     their loads of tile t+1 have landed in LDS (at most N
 //                  newer operations outstanding; vector memory retires in
-//                  order).
+//                  order), and their LDS writes (run tables) are done.
 //   compute waves: their LDS reads of tile t are complete.
 template <int N>
 __device__ __forceinline__ void dma_barrier() {
-  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 __device__ __forceinline__ void compute_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
@@ -491,6 +525,7 @@ __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArg
     for (int j = 0; j + 1 < NB; ++j) {
       P.index(a, min(tb + j + NB - 1, tl), irs + (j + NB - 1) * G::IRB, dw);
       P.tile(irs + j * G::IRB, smem + j * G::TILE, dw);
+      if (!kMax && dw == 0) P.run_table(a, min(tb + j, tl), irs + j * G::IRB);
     }
     dma_barrier<G::WAIT>();                                   // tile tb has landed
     int si = (2 * NB - 2) % G::NIR;                           // index slot of tile t + 2NB - 2
@@ -499,6 +534,7 @@ __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArg
     for (int64_t t = tb; t < te; ++t) {
       P.index(a, min(t + 2 * NB - 2, tl), irs + si * G::IRB, dw);
       P.tile(irs + sr * G::IRB, smem + rr * G::TILE, dw);
+      if (!kMax && dw == 0) P.run_table(a, min(t + NB - 1, tl), irs + sr * G::IRB);
       dma_barrier<G::WAIT>();                                 // tile t+1 has landed
       si = wrap(si + 1, G::NIR);
       sr = wrap(sr + 1, G::NIR);
@@ -521,14 +557,7 @@ __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArg
   // with it for the group numbers of the next tile) at every tile's MFMAs
   __builtin_amdgcn_s_waitcnt(0);
 
-  // state of the group open at the end of the previous tile: value per
-  // column, count and cut flag per wave
-  float oS = kMax ? -INFINITY : 0.0f, oC = 0.0f;
-  int32_t oArg = -1;
-  int oN = 0;
-  bool oCut = false;
   const int q4 = 4 * (lane >> 4);
-  const int64_t slot_base = bidx * 2 * h + col;
   const int r0 = lane & 15, r1 = 16 + (lane & 15);
   const int cq = lane >> 4;
   // A operand of step m: logical chunk 4m + cq of rows r0 / r1, stored at
@@ -543,17 +572,46 @@ __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArg
     b1[j] = G::EPC * chunk_base(r1 & G::SWM, j);
   }
 
+  // MAX: state of the group open at the end of the previous tile, per
+  // column (the 4 lanes of a column hold the same values)
+  float mS = -INFINITY;
+  int32_t mArg = -1;
+  int mN = 0;
+  bool mCut = false;
+  const int64_t slot_base = bidx * 2 * h + col;
+  // SUM / MEAN: run g of a tile is summed into column (g + off) % 16 of the
+  // reduce product, with off the column of the previous tile's last run, so
+  // a group that runs on from one tile to the next stays in the same lanes
+  // (no data movement).  Lane l of those lanes holds output columns
+  // 4 (l / 16) .. + 3 of the open group (sum, Kahan compensation, count).
+  f32x4 oS = {0.f, 0.f, 0.f, 0.f}, oC = {0.f, 0.f, 0.f, 0.f};
+  int oN = 0;
+  bool oCut = false;
+  int off = 0;
+  const int n16 = lane & 15;
+  const int col4 = cw * 16 + q4;                             // first of this lane's 4 reduce columns
+
   compute_barrier();                                         // (index slots staged)
   compute_barrier();                                         // tile tb is in LDS
   int rr = 0, ri = 0;                                        // ring tile, index slot of t
   for (int64_t t = tb; t < te; ++t) {
-    // group numbers of tile t: lane r < 32 row r (clamped), lane 32 the row
-    // before the tile, lane 33 the row after it (clamped; their validity
-    // follows from e0 and nv)
     const int32_t* gsl = reinterpret_cast<const int32_t*>(irs + ri * G::IRB);
-    const int32_t gcur = gsl[lane < 32 ? kSlotSeg + lane : kSlotEdge + min(lane - 32, 1)];
+    // MAX: group numbers of tile t (lane r < 32 row r, clamped; lane 32 the
+    // row before the tile, lane 33 the row after it).  SUM / MEAN: the run
+    // table, this lane's run of the first pass.
+    int32_t gcur = 0, hdr = 0, rs0 = 0, rn0 = 0, gid0 = 0;
+    const int gl = (n16 - off) & 15;
+    if constexpr (kMax) {
+      gcur = gsl[lane < 32 ? kSlotSeg + lane : kSlotEdge + min(lane - 32, 1)];
+    } else {
+      hdr = gsl[kSlotHdr];
+      rs0 = gsl[kSlotRunStart + gl];
+      rn0 = gsl[kSlotRunStart + gl + 1];
+      gid0 = gsl[kSlotRunGroup + gl];
+    }
     const char* X = smem + rr * G::TILE;
-    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    // the bias is the accumulators' initial value
+    f32x4 acc0 = {bc, bc, bc, bc}, acc1 = {bc, bc, bc, bc};
     if constexpr (std::is_same<T, float>::value) {
       const float* x0 = reinterpret_cast<const float*>(X) + r0 * KP;
       const float* x1 = reinterpret_cast<const float*>(X) + r1 * KP;
@@ -596,89 +654,150 @@ __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArg
         __builtin_amdgcn_sched_barrier(0);
       }
     }
-
-    // ---- per-group reduce of the tile (rows of this lane: q4 + i, 16 + q4 + i)
-    const int64_t e0 = t * TM;
-    const int nv = (int)min<int64_t>(TM, a.E - e0);
-    float y[8];
+    // tuple values y = act_pre(x W + b); this lane's rows: q4 + i (acc0)
+    // and 16 + q4 + i (acc1)
+    if (a.act_pre == RELNN_ACT_RELU) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {                    // tuple values y = act_pre(x W + b)
-      y[i] = act_apply(a.act_pre, acc0[i] + bc);
-      y[4 + i] = act_apply(a.act_pre, acc1[i] + bc);
+      for (int i = 0; i < 4; ++i) {
+        acc0[i] = fmaxf(acc0[i], 0.0f);
+        acc1[i] = fmaxf(acc1[i], 0.0f);
+      }
     }
-    // runs of equal group: lane r starts one if its group differs from
-    // lane r-1's (DPP wave shift right by one lane)
-    const int32_t gup = __builtin_amdgcn_update_dpp(0, gcur, 0x138, 0xf, 0xf, false);
-    const bool start = lane < nv && (lane == 0 || gup != gcur);
-    uint32_t runs = (uint32_t)__ballot(start);
-    const int32_t g_first = __builtin_amdgcn_readlane(gcur, 0);
-    const int32_t g_last = __builtin_amdgcn_readlane(gcur, nv - 1);
-    const int32_t g_before = __builtin_amdgcn_readlane(gcur, 32);
-    const int32_t g_after = __builtin_amdgcn_readlane(gcur, 33);
-    const bool prev_same = e0 > 0 && g_before == g_first;
-    const bool next_same = e0 + nv < a.E && g_after == g_last;
-    const bool keep_open = next_same && e0 + nv < range_hi;
-    bool first_run = true;
-    while (runs) {
-      const int rs = __builtin_ctz(runs);
-      runs &= runs - 1;
-      const int re = runs ? __builtin_ctz(runs) : nv;
-      const bool last_run = runs == 0;
-      // rows [rs, re) of the tile as a bit mask, then this lane's 4 + 4 bits
-      const uint32_t M = (re >= 32 ? 0xffffffffu : ((1u << re) - 1u)) & ~((1u << rs) - 1u);
-      const uint32_t m0 = M >> q4, m1 = M >> (16 + q4);
-      float part;
-      int32_t parg = INT32_MAX;
-      if constexpr (kMax) {
-        part = -INFINITY;
+    const int64_t e0 = t * TM;
+
+    if constexpr (!kMax) {
+      // ---- SUM / MEAN: per-run sums on the matrix cores.  With S the 0/1
+      // matrix [row][run] of the tile, D[c][n] = sum_row y[row][c] S[row][n]
+      // is one f32 16x16x4 product per accumulator register: its A operand
+      // is the register itself (lane l: row 4 (l/16) + i, column l % 16)
+      // and its B operand lane l: whether that row lies in the run of
+      // column l % 16.  D lane l holds columns 4 (l/16) .. + 3 of that run.
+      const int hd = __builtin_amdgcn_readfirstlane(hdr);
+      const int nr = hd & 63, nv = hd >> 16;
+      const bool prev_same = (hd >> 8) & 1, next_same = (hd >> 9) & 1;
+      const bool keep_open = next_same && e0 + nv < range_hi;
+      for (int pass = 0; 16 * pass < nr; ++pass) {
+        int g = gl, rs = rs0, rn = rn0, gid = gid0;
+        if (pass) {                                          // runs 16 .. 31 (rare)
+          g = 16 + gl;
+          rs = gsl[kSlotRunStart + g];
+          rn = gsl[kSlotRunStart + g + 1];
+          gid = gsl[kSlotRunGroup + g];
+        }
+        const bool valid = g < nr;
+        const int re = g + 1 < nr ? rn : nv;
+        const uint32_t M = valid ? (0xffffffffu >> (32 - (re - rs))) << rs : 0u;   // rows [rs, re)
+        const uint32_t m0 = M >> q4, m1 = M >> (16 + q4);
+        f32x4 D = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          D = __builtin_amdgcn_mfma_f32_16x16x4f32(acc0[i], keep_bit(1.0f, m0, i), D, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          D = __builtin_amdgcn_mfma_f32_16x16x4f32(acc1[i], keep_bit(1.0f, m1, i), D, 0, 0, 0);
+        const int cnt = re - rs;
+        const bool first = g == 0 && prev_same;              // continues the group open before the tile
+        const bool last = g == nr - 1 && next_same;          // runs on past the tile
+        f32x4 S = D, C = {0.f, 0.f, 0.f, 0.f};
+        int ntot = cnt;
+        bool cut = false;
+        if (prev_same) {
+          if (t > tb) {
+            if (first) {                                     // the block's open group
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                float si = oS[i], ci = oC[i];
+                kahan_add(si, ci, D[i]);
+                oS[i] = si;
+                oC[i] = ci;
+              }
+              S = oS;
+              C = oC;
+              ntot = oN + cnt;
+              cut = oCut;
+            }
+          } else {
+            cut = first;                                     // began before the block's range
+          }
+        }
+        if (valid) {
+          if (last && keep_open) {                           // stays open for the next tile
+            oS = S;
+            oC = C;
+            oN = ntot;
+            oCut = cut;
+          } else {
+            const f32x4 v = S - C;
+            if (last || cut) {                               // partial for the fix-up
+              const int slot = (last && !cut) ? 1 : 0;
+              *reinterpret_cast<f32x4*>(a.carry + (bidx * 2 + slot) * h + col4) = v;
+            } else {
+              sink_write4(a.sink, gid, col4, h, v, ntot);
+            }
+          }
+        }
+      }
+      off = (off + nr - 1) & 15;
+    } else {
+      // ---- MAX: per run, the rows of the run are kept by a bit mask, then
+      // the 4 lanes of each column are combined
+      const int nv = (int)min<int64_t>(TM, a.E - e0);
+      const int32_t gup = __builtin_amdgcn_update_dpp(0, gcur, 0x138, 0xf, 0xf, false);
+      const bool start = lane < nv && (lane == 0 || gup != gcur);
+      uint32_t runs = (uint32_t)__ballot(start);
+      const int32_t g_first = __builtin_amdgcn_readlane(gcur, 0);
+      const int32_t g_last = __builtin_amdgcn_readlane(gcur, nv - 1);
+      const int32_t g_before = __builtin_amdgcn_readlane(gcur, 32);
+      const int32_t g_after = __builtin_amdgcn_readlane(gcur, 33);
+      const bool prev_same = e0 > 0 && g_before == g_first;
+      const bool next_same = e0 + nv < a.E && g_after == g_last;
+      const bool keep_open = next_same && e0 + nv < range_hi;
+      bool first_run = true;
+      while (runs) {
+        const int rs = __builtin_ctz(runs);
+        runs &= runs - 1;
+        const int re = runs ? __builtin_ctz(runs) : nv;
+        const bool last_run = runs == 0;
+        const uint32_t M = (re >= 32 ? 0xffffffffu : ((1u << re) - 1u)) & ~((1u << rs) - 1u);
+        const uint32_t m0 = M >> q4, m1 = M >> (16 + q4);
+        float part = -INFINITY;
+        int32_t parg = INT32_MAX;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const uint32_t mb = i < 4 ? m0 : m1;
-          const bool in = (mb >> (i & 3)) & 1u;
+          const float yi = i < 4 ? acc0[i & 3] : acc1[i & 3];
+          const bool in = ((i < 4 ? m0 : m1) >> (i & 3)) & 1u;
           const int32_t rw = (int32_t)(e0 + (i < 4 ? 0 : 16) + q4 + (i & 3));
-          const bool take = in && (y[i] > part || parg == INT32_MAX);   // the run's first row always
-          part = take ? y[i] : part;
+          const bool take = in && (yi > part || parg == INT32_MAX);   // the run's first row always
+          part = take ? yi : part;
           parg = take ? rw : parg;
         }
         col_max4(part, parg);
-      } else {
-        const float s0 = keep_bit(y[0], m0, 0) + keep_bit(y[1], m0, 1);
-        const float s1 = keep_bit(y[2], m0, 2) + keep_bit(y[3], m0, 3);
-        const float s2 = keep_bit(y[4], m1, 0) + keep_bit(y[5], m1, 1);
-        const float s3 = keep_bit(y[6], m1, 2) + keep_bit(y[7], m1, 3);
-        part = col_sum4((s0 + s1) + (s2 + s3));
-      }
-      const int cnt = re - rs;
-      if (first_run && prev_same && t > tb) {              // the block's open group
-        if constexpr (kMax) {
-          if (part > oS) {
-            oS = part;
-            oArg = parg;
+        const int cnt = re - rs;
+        if (first_run && prev_same && t > tb) {            // the block's open group
+          if (part > mS) {
+            mS = part;
+            mArg = parg;
           }
-        } else {
-          kahan_add(oS, oC, part);
+          mN += cnt;
+        } else {                                           // a new group (cut if it began before the range)
+          mS = part;
+          mArg = parg;
+          mN = cnt;
+          mCut = first_run && prev_same;
         }
-        oN += cnt;
-      } else {                                             // a new group (cut if it began before the range)
-        oS = part;
-        oC = 0.0f;
-        oArg = parg;
-        oN = cnt;
-        oCut = first_run && prev_same;
-      }
-      first_run = false;
-      if (last_run && keep_open) break;                    // stays open for the next tile
-      if (lane < 16) {
-        const float v = kMax ? oS : oS - oC;
-        if (last_run && next_same) {                       // runs past the range end
-          const int64_t o = slot_base + (oCut ? 0 : h);
-          a.carry[o] = v;
-          if (kMax && a.carry_arg) a.carry_arg[o] = oArg;
-        } else if (!oCut) {
-          sink_write<true>(a.sink, __builtin_amdgcn_readlane(gcur, rs), col, h, v, oArg, oN);
-        } else {                                           // cut by the range start
-          a.carry[slot_base] = v;
-          if (kMax && a.carry_arg) a.carry_arg[slot_base] = oArg;
+        first_run = false;
+        if (last_run && keep_open) break;                  // stays open for the next tile
+        if (lane < 16) {
+          if (last_run && next_same) {                     // runs past the range end
+            const int64_t o = slot_base + (mCut ? 0 : h);
+            a.carry[o] = mS;
+            if (a.carry_arg) a.carry_arg[o] = mArg;
+          } else if (!mCut) {
+            sink_write<true>(a.sink, __builtin_amdgcn_readlane(gcur, rs), col, h, mS, mArg, mN);
+          } else {                                         // cut by the range start
+            a.carry[slot_base] = mS;
+            if (a.carry_arg) a.carry_arg[slot_base] = mArg;
+          }
         }
       }
     }
