@@ -252,7 +252,11 @@ __global__ void k_gather_plain(Atoms at, const int32_t* __restrict__ rows, int64
       const int64_t row = at.rows[j][e];
       v = *reinterpret_cast<const uint4*>(static_cast<const T*>(at.emb[j]) + row * at.d[j] + (el - at.koff[j]));
     }
-    *reinterpret_cast<uint4*>(X + e * Kp + el) = v;
+    // X is written once and read back by the GEMM from HBM: non-temporal
+    // stores keep it from evicting the cached embedding rows
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(X + e * Kp + el));
   }
 }
 

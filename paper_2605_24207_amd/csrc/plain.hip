@@ -25,6 +25,7 @@ namespace {
 constexpr int kRedTM = 64;            // unit boundaries fall on multiples of 64 rows
 constexpr int kRedWaves = 4;          // waves per block
 constexpr int kRedBatch = 16;         // rows loaded together per wave
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ void kahan(float& s, float& c, float x) {
   const float y = x - c;
@@ -109,7 +110,10 @@ __global__ void __launch_bounds__(kRedWaves * 64) k_seg_reduce(RedArgs a) {
 #pragma unroll
         for (int i = 0; i < kRedBatch; ++i) {
           const int64_t r = base + min(bt * kRedBatch + i, n - 1);
-          y[i] = *reinterpret_cast<const float2*>(a.Y + r * h + cc);
+          // Y is read once: non-temporal loads keep it from displacing
+          // cached lines
+          const f32x2 t2 = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(a.Y + r * h + cc));
+          y[i] = make_float2(t2.x, t2.y);
         }
 #pragma unroll
         for (int i = 0; i < kRedBatch; ++i) {
@@ -221,7 +225,7 @@ void blas_sgemv(int m, int n, const float* A, int lda, const float* x, float bet
 
 int64_t seg_reduce_units(int64_t E) {
   const int64_t ntiles = cdiv(std::max<int64_t>(E, 1), kRedTM);
-  return std::max<int64_t>(1, std::min<int64_t>(ntiles, 8192));
+  return std::max<int64_t>(1, std::min<int64_t>(ntiles, 32768));   // 128 waves per CU
 }
 
 void launch_seg_reduce(const float* Y, int64_t E, int h, const Seg& sg, const float* b, int act_pre,
