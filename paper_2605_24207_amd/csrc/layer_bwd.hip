@@ -17,7 +17,8 @@
 // an affine transform); otherwise this file's per-tuple kernel: the joined
 // rows x_tau are gathered again, never stored, and a persistent kernel
 // accumulates X^T dY over its contiguous run of tiles on the matrix cores
-// (FP32 16x16x4), then the per-block partials are summed in block order.
+// (FP32 16x16x4, tiles staged transposed and double-buffered in LDS), then
+// the per-block partials are summed in block order.
 #include "layer_fwd.hpp"
 
 namespace relnn {
@@ -26,7 +27,7 @@ namespace {
 
 constexpr int kDwTM = 32;
 constexpr int kDwThreads = 512;
-constexpr int kDwMaxB = 24;              // 16x16 accumulator blocks per wave
+constexpr int kDwTS = kDwTM + 4;         // LDS row stride (floats) of the transposed tiles
 
 struct Route {
   const float* dA;          // [G][h] dout * act_post'(pre), / |g| for MEAN
@@ -72,99 +73,271 @@ struct DwArgs {
   int64_t ntiles, nunits;
   float* part;              // [nunits][K16][h]
   float* dbpart;            // [nunits][h]
+  int vec4;                 // h % 4 == 0 and dA / argmax 16-byte aligned: routed dY read 4 columns at a time
+  int ncb;                  // column blocks per pass: 1, 2, 4 or 8
 };
 
+// Tiles are staged transposed in LDS, XT[k][tuple] and DT[n][tuple] (row
+// stride kDwTS floats), double-buffered: the global loads of tile t+1 are in
+// flight while tile t is multiplied.  MFMA step s (0..7) of a tile pairs
+// tuple 8 (l / 16) + s with lane l, so the 8 steps of a lane read 8
+// consecutive tuples of one row: two 16-byte LDS reads per operand per tile.
+// Wave w owns the 16x16 output blocks w, w + 8, ... (row block blk / ncb,
+// column block blk % ncb).
 template <class T>
+__device__ __forceinline__ float4 dw_load4(const T* p);
+template <>
+__device__ __forceinline__ float4 dw_load4<float>(const float* p) {
+  return *reinterpret_cast<const float4*>(p);
+}
+template <>
+__device__ __forceinline__ float4 dw_load4<__bf16>(const __bf16* p) {
+  const uint2 r = *reinterpret_cast<const uint2*>(p);
+  return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u), __uint_as_float(r.y << 16),
+                     __uint_as_float(r.y & 0xffff0000u));
+}
+
+// kRoute: 0 = routed dY one column at a time (any h); otherwise four
+// columns per load (h % 4 == 0, aligned inputs), bit 0: MAX routing by
+// argmax, bit 1: act_pre mask.  Each variant loads only what it uses, so no
+// load sits behind a branch.
+template <class T, int QB, int kRoute>
 __global__ void __launch_bounds__(kDwThreads) k_bwd_dw(DwArgs a) {
+  constexpr bool kVec = kRoute != 0, kArg = (kRoute & 1) != 0, kMask = (kRoute & 2) != 0;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int TM = kDwTM;
-  constexpr int EPC = 16 / sizeof(T);
-  const int XS = a.K16 + 4;
-  const int DS = a.hn + 4;
-  float* Xs = reinterpret_cast<float*>(smem);      // [TM][XS] gathered x, FP32
-  float* Ds = Xs + TM * XS;                         // [TM][DS] routed dY
-  const int h = a.R.h;
+  static_assert(TM == 32 && kDwThreads == 512, "4x4 staging blocks: 8 tuple groups per tile");
+  const int K16 = a.K16, hn = a.hn, h = a.R.h;
   const int lane = __lane_id();
   const int w = threadIdx.x / 64;
-  const int nrb = a.K16 / 16, ncb = a.hn / 16;
-  const int nblk = nrb * ncb;
+  const int tid = threadIdx.x;
+  const int nrb = K16 / 16, ncb = a.ncb;                   // ncb divides 8
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  const int cb = wu % ncb, rb0 = wu / ncb, rstep = 8 / ncb;  // this wave's blocks: (rb0 + rstep q, cb)
+  const int bufsz = (K16 + 16 * ncb) * kDwTS;               // floats per buffer
+  float* lds = reinterpret_cast<float*>(smem);
   const int64_t bidx = blockIdx.x;
   const int64_t tb = (a.ntiles * bidx) / a.nunits, te = (a.ntiles * (bidx + 1)) / a.nunits;
-  f32x4 acc[kDwMaxB];
-#pragma unroll
-  for (int q = 0; q < kDwMaxB; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float dbacc = 0.0f;
-  const int cpr = a.K16 / EPC;
 
-  for (int64_t t = tb; t < te; ++t) {
+  // staging work of this thread: X blocks i = tid, tid + 512 (4 tuples x 4
+  // columns each; column chunk kc = i % (K16/4), tuple group i / (K16/4)),
+  // and the dY block tid < 2 * 16 ncb (column chunk tid % (4 ncb), tuple
+  // group tid / (4 ncb))
+  const int kcs = K16 / 4, ncs = 4 * ncb;
+  const bool dy_on = tid < 8 * ncs;
+  const int dnc = tid % ncs, dtg = tid / ncs;
+  constexpr int NXB = 2;                                   // X blocks per thread (K16 <= 512)
+  float4 xr[NXB][4];
+  // Fixed per-thread load plan.  Every load is issued unconditionally from
+  // a clamped, valid address and the value is zeroed afterwards where it
+  // lies outside the tile or the columns (a load behind a branch makes the
+  // compiler wait for it at the join).  Row and group numbers are loaded
+  // one tile ahead of the data that they address.
+  const char* xsrc[NXB];
+  int xstride[NXB];
+  const int32_t* xrows[NXB];
+  bool xon[NXB];
+#pragma unroll
+  for (int bi = 0; bi < NXB; ++bi) {
+    const int i = tid + bi * kDwThreads;
+    const int kc = i % kcs, tg = i / kcs;
+    const int el = 4 * kc;
+    const int elc = min(el, a.K - 4);
+    int j = 0;
+#pragma unroll
+    for (int q = 1; q < kMaxAtoms; ++q)
+      if (q < a.at.k && elc >= a.at.koff[q]) j = q;
+    xsrc[bi] = reinterpret_cast<const char*>(static_cast<const T*>(a.at.emb[j]) + (elc - a.at.koff[j]));
+    xstride[bi] = a.at.d[j] * (int)sizeof(T);
+    xrows[bi] = a.at.rows[j];
+    xon[bi] = tg < 8 && el < a.K;
+  }
+  int32_t rn[NXB][4], gn[4], gn_prev[4];
+  auto fetch_idx = [&](int64_t t) {
     const int64_t e0 = t * TM;
     const int nv = (int)min<int64_t>(TM, a.E - e0);
-    for (int i = threadIdx.x; i < TM * cpr; i += blockDim.x) {
-      const int r = i / cpr, c = i - (i / cpr) * cpr;
-      const int el = c * EPC;
-      float vals[EPC];
 #pragma unroll
-      for (int u = 0; u < EPC; ++u) vals[u] = 0.0f;
-      if (r < nv && el < a.K) {
-        int j = 0;
+    for (int bi = 0; bi < NXB; ++bi) {
+      const int tg = min((tid + bi * kDwThreads) / kcs, 7);
 #pragma unroll
-        for (int q = 1; q < kMaxAtoms; ++q)
-          if (q < a.at.k && el >= a.at.koff[q]) j = q;
-        const int64_t row = a.at.rows[j][e0 + r];
-        const uint4 raw = *reinterpret_cast<const uint4*>(static_cast<const T*>(a.at.emb[j]) + row * a.at.d[j] +
-                                                          (el - a.at.koff[j]));
-        const T* tv = reinterpret_cast<const T*>(&raw);
-#pragma unroll
-        for (int u = 0; u < EPC; ++u) vals[u] = (float)tv[u];
-      }
-#pragma unroll
-      for (int u = 0; u < EPC; ++u) Xs[r * XS + el + u] = vals[u];
+      for (int r = 0; r < 4; ++r) rn[bi][r] = xrows[bi][e0 + min(4 * tg + r, nv - 1)];
     }
-    for (int i = threadIdx.x; i < TM * a.hn; i += blockDim.x) {
-      const int r = i / a.hn, n = i - (i / a.hn) * a.hn;
-      float v = 0.0f;
-      if (r < nv) {
-        const int64_t e = e0 + r;
-        v = route(a.R, e, a.R.tuple_group[e], a.n0 + n);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gn[r] = a.R.tuple_group[e0 + min(4 * min(dtg, 7) + r, nv - 1)];
+  };
+  auto keep_groups = [&]() {                                // group numbers of the tile just fetched
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gn_prev[r] = gn[r];
+  };
+  // data loads of a tile: raw values only; they are selected (tile rows,
+  // columns, MAX routing, act_pre mask) when stashed, after the products of
+  // the current tile, so that the loads stay in flight meanwhile
+  float4 draw[4];
+  int4 amraw[4];
+  uint32_t mraw[4];
+  auto fetch_data = [&](int64_t t) {
+    const int64_t e0 = t * TM;
+    const int nv = (int)min<int64_t>(TM, a.E - e0);
+#pragma unroll
+    for (int bi = 0; bi < NXB; ++bi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        xr[bi][r] = dw_load4<T>(reinterpret_cast<const T*>(xsrc[bi] + (int64_t)rn[bi][r] * xstride[bi]));
+    if constexpr (kVec) {
+      const int nc = min(4 * dnc, hn - 4);                    // hn is a multiple of 4 here
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t e = e0 + min(4 * dtg + r, nv - 1);
+        const int64_t o = (int64_t)gn[r] * h + a.n0 + nc;
+        draw[r] = *reinterpret_cast<const float4*>(a.R.dA + o);
+        if constexpr (kArg) amraw[r] = *reinterpret_cast<const int4*>(a.R.argmax + o);
+        if constexpr (kMask) mraw[r] = *reinterpret_cast<const uint32_t*>(a.R.mask + e * h + a.n0 + nc);
       }
-      Ds[r * DS + n] = v;
     }
-    __syncthreads();
-    // dW[k][n] += sum_e X[e][k] dY[e][n]: A = X^T (lane: X[e = 4ks + l/16][k]),
-    // B = dY (lane: dY[4ks + l/16][n]).
+  };
+  // registers -> transposed LDS tiles of buffer b (tile t)
+  auto stash = [&](int b, int64_t t) {
+    const int64_t e0 = t * TM;
+    const int nv = (int)min<int64_t>(TM, a.E - e0);
+    float* XT = lds + b * bufsz;
+    float* DT = XT + K16 * kDwTS;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int ks = 0; ks < TM / 4; ++ks) {
-      const int er = ks * 4 + (lane >> 4);
+    for (int bi = 0; bi < NXB; ++bi) {
+      const int i = tid + bi * kDwThreads;
+      const int kc = i % kcs, tg = i / kcs;
+      if (tg < 8) {
+        float4 x[4];
 #pragma unroll
-      for (int q = 0; q < kDwMaxB; ++q) {
-        const int blk = w + 8 * q;
-        if (blk < nblk) {
-          const int rb = blk / ncb, cb = blk - (blk / ncb) * ncb;
-          const float av = Xs[er * XS + rb * 16 + (lane & 15)];
-          const float bv = Ds[er * DS + cb * 16 + (lane & 15)];
-          acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[q], 0, 0, 0);
+        for (int r = 0; r < 4; ++r) x[r] = xon[bi] && 4 * tg + r < nv ? xr[bi][r] : z4;
+        *reinterpret_cast<float4*>(XT + (4 * kc + 0) * kDwTS + 4 * tg) = make_float4(x[0].x, x[1].x, x[2].x, x[3].x);
+        *reinterpret_cast<float4*>(XT + (4 * kc + 1) * kDwTS + 4 * tg) = make_float4(x[0].y, x[1].y, x[2].y, x[3].y);
+        *reinterpret_cast<float4*>(XT + (4 * kc + 2) * kDwTS + 4 * tg) = make_float4(x[0].z, x[1].z, x[2].z, x[3].z);
+        *reinterpret_cast<float4*>(XT + (4 * kc + 3) * kDwTS + 4 * tg) = make_float4(x[0].w, x[1].w, x[2].w, x[3].w);
+      }
+    }
+    if (dy_on) {
+      float4 d[4];
+      const int n = 4 * dnc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tr = 4 * dtg + r;
+        if constexpr (kVec) {
+          const int32_t ei = (int32_t)(e0 + min(tr, nv - 1));
+          // keep bits of the 4 columns (integer arithmetic: no branches)
+          uint32_t keep = (tr < nv && n < hn) ? 15u : 0u;
+          if constexpr (kArg) {
+            const int4 am = amraw[r];
+            keep &= (uint32_t)(am.x == ei) | ((uint32_t)(am.y == ei) << 1) | ((uint32_t)(am.z == ei) << 2) |
+                    ((uint32_t)(am.w == ei) << 3);
+          }
+          if constexpr (kMask) {
+            const uint32_t m = mraw[r];
+            keep &= (uint32_t)((m & 0xffu) != 0) | ((uint32_t)((m & 0xff00u) != 0) << 1) |
+                    ((uint32_t)((m & 0xff0000u) != 0) << 2) | ((uint32_t)((m & 0xff000000u) != 0) << 3);
+          }
+          const float4 v = draw[r];
+          d[r] = make_float4((keep & 1u) ? v.x : 0.0f, (keep & 2u) ? v.y : 0.0f, (keep & 4u) ? v.z : 0.0f,
+                             (keep & 8u) ? v.w : 0.0f);
+        } else {                                              // any h: one column at a time
+          float t4[4] = {0.f, 0.f, 0.f, 0.f};
+          if (tr < nv)
+            for (int u = 0; u < 4; ++u)
+              if (n + u < hn) t4[u] = route(a.R, e0 + tr, gn_prev[r], a.n0 + n + u);
+          d[r] = make_float4(t4[0], t4[1], t4[2], t4[3]);
         }
       }
+      *reinterpret_cast<float4*>(DT + (4 * dnc + 0) * kDwTS + 4 * dtg) = make_float4(d[0].x, d[1].x, d[2].x, d[3].x);
+      *reinterpret_cast<float4*>(DT + (4 * dnc + 1) * kDwTS + 4 * dtg) = make_float4(d[0].y, d[1].y, d[2].y, d[3].y);
+      *reinterpret_cast<float4*>(DT + (4 * dnc + 2) * kDwTS + 4 * dtg) = make_float4(d[0].z, d[1].z, d[2].z, d[3].z);
+      *reinterpret_cast<float4*>(DT + (4 * dnc + 3) * kDwTS + 4 * dtg) = make_float4(d[0].w, d[1].w, d[2].w, d[3].w);
     }
-    if (threadIdx.x < a.hn)
-      for (int r = 0; r < nv; ++r) dbacc += Ds[r * DS + threadIdx.x];
+  };
+
+  f32x4 acc[QB];
+#pragma unroll
+  for (int q = 0; q < QB; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float4 dbacc = make_float4(0.f, 0.f, 0.f, 0.f);          // dY column sums of this thread's dY block
+  const int lq = 8 * (lane >> 4), lm = lane & 15;
+
+  // the prefetches run unconditionally (the last tiles are fetched again,
+  // harmlessly): a skipped load on one path makes the compiler wait for
+  // every load where the paths meet
+  const int64_t tl = te - 1;
+  fetch_idx(tb);
+  fetch_data(tb);
+  keep_groups();
+  fetch_idx(min(tb + 1, tl));
+  stash(0, tb);
+  __syncthreads();
+  for (int64_t t = tb; t < te; ++t) {
+    const int b = (int)((t - tb) & 1);
+    fetch_data(min(t + 1, tl));
+    keep_groups();
+    fetch_idx(min(t + 2, tl));
+    const float* XT = lds + b * bufsz;
+    const float* DT = XT + K16 * kDwTS;
+#pragma unroll
+    for (int grp = 0; grp < 2; ++grp) {
+      const int to = lq + 4 * grp;                            // tuples to .. to+3 of this lane
+      const f32x4 bb = *reinterpret_cast<const f32x4*>(DT + (16 * cb + lm) * kDwTS + to);
+      const float* xa = XT + (16 * rb0 + lm) * kDwTS + to;
+      const int astep = 16 * rstep * kDwTS;
+      // the operand of block q + 1 is read while block q is multiplied
+      // blocks past the last row block multiply a repeated (valid) operand
+      // into accumulators that are never written out
+      const int qlast = (nrb - 1 - rb0) / rstep;
+      f32x4 an = *reinterpret_cast<const f32x4*>(xa);
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const f32x4 aa = an;
+        if (q + 1 < QB) an = *reinterpret_cast<const f32x4*>(xa + min(q + 1, qlast) * astep);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[u], bb[u], acc[q], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (dy_on) {                                              // db: this thread's dY block, tuple order
+      const float* d = DT + (4 * dnc) * kDwTS + 4 * dtg;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        dbacc.x += d[0 * kDwTS + r];
+        dbacc.y += d[1 * kDwTS + r];
+        dbacc.z += d[2 * kDwTS + r];
+        dbacc.w += d[3 * kDwTS + r];
+      }
+    }
+    stash(b ^ 1, min(t + 1, tl));
     __syncthreads();
   }
   // per-block partials
 #pragma unroll
-  for (int q = 0; q < kDwMaxB; ++q) {
-    const int blk = w + 8 * q;
-    if (blk < nblk) {
-      const int rb = blk / ncb, cb = blk - (blk / ncb) * ncb;
-      const int n = a.n0 + cb * 16 + (lane & 15);
+  for (int q = 0; q < QB; ++q) {
+    const int rb = rb0 + rstep * q;
+    if (rb < nrb) {
+      const int n = cb * 16 + lm;
+      if (n < hn) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = rb * 16 + 4 * (lane >> 4) + i;
-        a.part[(bidx * a.K16 + k) * h + n] = acc[q][i];
+        for (int i = 0; i < 4; ++i) {
+          const int k = rb * 16 + 4 * (lane >> 4) + i;
+          a.part[(bidx * K16 + k) * h + a.n0 + n] = acc[q][i];
+        }
       }
     }
   }
-  if (threadIdx.x < a.hn) a.dbpart[bidx * h + a.n0 + threadIdx.x] = dbacc;
+  // db partial: the 8 tuple groups of each column, in order
+  float* dbs = lds;                                           // [8][16 ncb] (the tiles are no longer read)
+  if (dy_on) {
+    const float v[4] = {dbacc.x, dbacc.y, dbacc.z, dbacc.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) dbs[dtg * ncs * 4 + 4 * dnc + u] = v[u];
+  }
+  __syncthreads();
+  if (tid < hn) {
+    float sdb = 0.0f;
+    for (int g8 = 0; g8 < 8; ++g8) sdb += dbs[g8 * ncs * 4 + tid];
+    a.dbpart[bidx * h + a.n0 + tid] = sdb;
+  }
 }
 
 // dW[k][n] (+)= sum over blocks b of part[b][k][n], in block order, Kahan.
@@ -218,7 +391,7 @@ int num_cus() {
 
 struct BwdPlan {
   FwdPlan F;
-  int K = 0, K16 = 0, hn = 0;
+  int K = 0, K16 = 0, hn = 0, ncb = 1;
   int64_t dw_tiles = 0, dw_units = 0;
   size_t dw_lds = 0;
   size_t ws_mask = 0, ws_fwsw = 0, ws_part = 0, ws_dbpart = 0, ws_dA = 0, total = 0;
@@ -231,13 +404,20 @@ BwdPlan plan_bwd(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   p.F = F;
   p.K = F.K;
   p.K16 = (int)round_up(F.K, 16);
-  int hn = (kDwMaxB * 8 * 16 * 16 / p.K16) / 16 * 16;
-  p.hn = std::max(16, std::min(L->h, hn));
+  // columns per pass: at most 8 column blocks, 16 accumulator blocks
+  // per wave, and two buffers of (K16 + columns) transposed rows in LDS
+  const int nrb = p.K16 / 16;
+  int ncb = 8;    // a power of two (each wave keeps one column block), at most 16 blocks per wave
+  while (ncb > 1 && (16 * (ncb / 2) >= L->h || nrb * ncb > 128 ||
+                     (size_t)2 * (p.K16 + 16 * ncb) * kDwTS * 4 > 160 * 1024))
+    ncb /= 2;
+  p.ncb = ncb;
+  p.hn = std::min(L->h, 16 * ncb);
   const int64_t E = idx->E;
   p.xs_dw = L->act_pre == RELNN_ACT_NONE && L->agg != RELNN_MAX;
   p.dw_tiles = cdiv(E, kDwTM);
   p.dw_units = std::max<int64_t>(1, std::min<int64_t>(p.dw_tiles, num_cus()));
-  p.dw_lds = (size_t)kDwTM * (p.K16 + 4) * 4 + (size_t)kDwTM * (p.hn + 4) * 4;
+  p.dw_lds = (size_t)2 * (p.K16 + 16 * p.ncb) * kDwTS * 4;
   size_t off = 0;
   p.ws_mask = off;
   if (L->act_pre != RELNN_ACT_NONE) off += round_up(std::max<int64_t>(E, 1) * L->h, 256);
@@ -254,6 +434,35 @@ BwdPlan plan_bwd(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   p.lin = plan_lin_bwd(idx, L, off, p.xs_dw);
   p.total = p.lin.total;
   return p;
+}
+
+template <class KernelT>
+void allow_lds(KernelT k, size_t bytes);
+
+// accumulator blocks per wave: 8 or 16 (the plan keeps nblk <= 128)
+template <class T, int QB, int kRoute>
+void launch_dw_q(const DwArgs& d, int64_t units, size_t lds, hipStream_t s) {
+  allow_lds(k_bwd_dw<T, QB, kRoute>, lds);
+  k_bwd_dw<T, QB, kRoute><<<(unsigned)units, kDwThreads, lds, s>>>(d);
+  RELNN_LAUNCHED();
+}
+template <class T, int QB>
+void launch_dw_r(const DwArgs& d, int64_t units, size_t lds, hipStream_t s) {
+  const int route = !d.vec4 ? 0 : (d.R.agg == RELNN_MAX ? 1 : 0) | (d.R.mask ? 2 : 0);
+  switch (route) {
+    case 1: launch_dw_q<T, QB, 1>(d, units, lds, s); break;
+    case 2: launch_dw_q<T, QB, 2>(d, units, lds, s); break;
+    case 3: launch_dw_q<T, QB, 3>(d, units, lds, s); break;
+    default: launch_dw_q<T, QB, 0>(d, units, lds, s); break;
+  }
+}
+template <class T>
+void launch_dw(const DwArgs& d, int64_t nblk, int64_t units, size_t lds, hipStream_t s) {
+  RELNN_REQUIRE(nblk <= 128, RELNN_E_HIP, "internal: %lld dW blocks", (long long)nblk);
+  if (nblk <= 64)
+    launch_dw_r<T, 8>(d, units, lds, s);
+  else
+    launch_dw_r<T, 16>(d, units, lds, s);
 }
 
 template <class KernelT>
@@ -356,18 +565,18 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
       d.nunits = P.dw_units;
       d.part = reinterpret_cast<float*>(w + P.ws_part);
       d.dbpart = reinterpret_cast<float*>(w + P.ws_dbpart);
+      const int64_t nblk = (P.K16 / 16) * P.ncb;
+      d.ncb = P.ncb;
+      d.vec4 = h % 4 == 0 && ((uintptr_t)dA & 15) == 0 && ((uintptr_t)argmax & 15) == 0;
+      RELNN_REQUIRE(P.K16 <= 512, RELNN_E_UNSUPPORTED, "dense dW: K = %d too wide", P.K);
       for (int n0 = 0; n0 < h; n0 += P.hn) {
         d.n0 = n0;
         d.hn = std::min(P.hn, h - n0);
         KTimer tm("bwd_dw", s);
-        if (L->dtype == RELNN_BF16) {
-          allow_lds(k_bwd_dw<__bf16>, P.dw_lds);
-          k_bwd_dw<__bf16><<<(unsigned)P.dw_units, kDwThreads, P.dw_lds, s>>>(d);
-        } else {
-          allow_lds(k_bwd_dw<float>, P.dw_lds);
-          k_bwd_dw<float><<<(unsigned)P.dw_units, kDwThreads, P.dw_lds, s>>>(d);
-        }
-        RELNN_LAUNCHED();
+        if (L->dtype == RELNN_BF16)
+          launch_dw<__bf16>(d, nblk, P.dw_units, P.dw_lds, s);
+        else
+          launch_dw<float>(d, nblk, P.dw_units, P.dw_lds, s);
       }
       k_dw_reduce<<<grid_for((int64_t)P.K * h + h), 256, 0, s>>>(d.part, d.dbpart, P.dw_units, P.K, P.K16, h, dW,
                                                                    db, accum ? 1 : 0);
