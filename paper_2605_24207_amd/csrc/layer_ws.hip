@@ -475,8 +475,201 @@ struct DmaMfma<__bf16> {                 // bf16 16x16x32, one 16-byte A read pe
   static constexpr int nks() { return KP / 32; }
 };
 
-template <class T, int KP, int NB, bool kMax>
-__global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArgs a) {
+// Compute waves of the BF16 SUM / MEAN kernel with 32 output columns per
+// wave (two 16-column slices of W): each A operand read from LDS feeds two
+// products, half the LDS traffic of 16-column waves, which bound the BF16
+// kernel.  The per-run sums are bf16 products on a two-term split of the
+// FP32 tuple values, y = hi + lo with hi = bf16(y) and lo = bf16(y - hi)
+// (about 16 significant bits, FP32 accumulation): one 16x16x32 product per
+// term covers all 32 rows of the tile.  Its A operand is the lane's 8
+// accumulator values (rows 4 (l/16) + i and 16 + 4 (l/16) + i, column
+// l % 16) and its B operand whether each of those rows lies in the run of
+// column l % 16, as in the FP32 kernel.
+template <int KP, int NB>
+__device__ __forceinline__ void fwd_wide_bf16(const WsArgs& a, char* smem, int64_t tb, int64_t te, int64_t range_hi,
+                                              int cw, int lane, int64_t bidx) {
+  using G = DmaGeo<__bf16, KP, NB>;
+  constexpr int NKS = KP / 32;
+  constexpr int TM = kTM;
+  const int h = a.h;
+  char* irs = smem + NB * G::TILE;
+  auto wrap = [](int v, int n) { return v >= n ? v - n : v; };
+  const int colA = 32 * cw + (lane & 15);
+  const float bcA = a.b ? a.b[colA] : 0.0f, bcB = a.b ? a.b[colA + 16] : 0.0f;
+  bf16x8 wA[NKS], wB[NKS];
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks) {
+    wA[ks] = reinterpret_cast<const bf16x8*>(a.Wsw)[((2 * cw) * NKS + ks) * 64 + lane];
+    wB[ks] = reinterpret_cast<const bf16x8*>(a.Wsw)[((2 * cw + 1) * NKS + ks) * 64 + lane];
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  const int q4 = 4 * (lane >> 4);
+  const int r0 = lane & 15, r1 = 16 + (lane & 15);
+  const int cq = lane >> 4;
+  auto chunk_base = [&](int sw, int j) { return 4 * (j ^ (sw >> 2)) + ((cq ^ sw) & 3); };
+  int b0[4], b1[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    b0[j] = G::EPC * chunk_base(r0 & G::SWM, j);
+    b1[j] = G::EPC * chunk_base(r1 & G::SWM, j);
+  }
+  // group open at the end of the previous tile, in the lanes of column off
+  f32x4 oSA = {0.f, 0.f, 0.f, 0.f}, oCA = oSA, oSB = oSA, oCB = oSA;
+  int oN = 0;
+  bool oCut = false;
+  int off = 0;
+  const int n16 = lane & 15;
+  const int col4 = 32 * cw + q4;
+
+  compute_barrier();                                         // (index slots staged)
+  compute_barrier();                                         // tile tb is in LDS
+  int rr = 0, ri = 0;
+  for (int64_t t = tb; t < te; ++t) {
+    const int32_t* gsl = reinterpret_cast<const int32_t*>(irs + ri * G::IRB);
+    const int gl = (n16 - off) & 15;
+    const int hdr = gsl[kSlotHdr];
+    const int rs0 = gsl[kSlotRunStart + gl];
+    const int rn0 = gsl[kSlotRunStart + gl + 1];
+    const int gid0 = gsl[kSlotRunGroup + gl];
+    const __bf16* x0 = reinterpret_cast<const __bf16*>(smem + rr * G::TILE) + r0 * KP;
+    const __bf16* x1 = reinterpret_cast<const __bf16*>(smem + rr * G::TILE) + r1 * KP;
+    f32x4 a0A = {bcA, bcA, bcA, bcA}, a1A = a0A, a0B = {bcB, bcB, bcB, bcB}, a1B = a0B;
+    constexpr int PD = NKS < 4 ? NKS : 4;
+    auto rd = [&](const __bf16* x, const int (&b)[4], int k) {
+      return *reinterpret_cast<const bf16x8*>(x + 32 * (k & ~3) + b[k & 3]);
+    };
+    bf16x8 c0[PD], c1[PD];
+#pragma unroll
+    for (int p = 0; p < PD; ++p) {
+      c0[p] = rd(x0, b0, p);
+      c1[p] = rd(x1, b1, p);
+    }
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const bf16x8 u0 = c0[ks % PD], u1 = c1[ks % PD];
+      if (ks + PD < NKS) {
+        c0[ks % PD] = rd(x0, b0, ks + PD);
+        c1[ks % PD] = rd(x1, b1, ks + PD);
+      }
+      a0A = __builtin_amdgcn_mfma_f32_16x16x32_bf16(u0, wA[ks], a0A, 0, 0, 0);
+      a1A = __builtin_amdgcn_mfma_f32_16x16x32_bf16(u1, wA[ks], a1A, 0, 0, 0);
+      a0B = __builtin_amdgcn_mfma_f32_16x16x32_bf16(u0, wB[ks], a0B, 0, 0, 0);
+      a1B = __builtin_amdgcn_mfma_f32_16x16x32_bf16(u1, wB[ks], a1B, 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (a.act_pre == RELNN_ACT_RELU) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a0A[i] = fmaxf(a0A[i], 0.0f);
+        a1A[i] = fmaxf(a1A[i], 0.0f);
+        a0B[i] = fmaxf(a0B[i], 0.0f);
+        a1B[i] = fmaxf(a1B[i], 0.0f);
+      }
+    }
+    // two-term bf16 split of this lane's 8 values of one column block, in
+    // operand order (rows q4 + i, then 16 + q4 + i)
+    auto split = [](const f32x4& y0, const f32x4& y1, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float y = i < 4 ? y0[i] : y1[i - 4];
+        const __bf16 hb = (__bf16)y;
+        hi[i] = hb;
+        lo[i] = (__bf16)(y - (float)hb);
+      }
+    };
+    bf16x8 hA, lA, hB, lB;
+    split(a0A, a1A, hA, lA);
+    split(a0B, a1B, hB, lB);
+
+    const int hd = __builtin_amdgcn_readfirstlane(hdr);
+    const int nr = hd & 63, nv = hd >> 16;
+    const bool prev_same = (hd >> 8) & 1, next_same = (hd >> 9) & 1;
+    const int64_t e0 = t * TM;
+    const bool keep_open = next_same && e0 + nv < range_hi;
+    for (int pass = 0; 16 * pass < nr; ++pass) {
+      int g = gl, rs = rs0, rn = rn0, gid = gid0;
+      if (pass) {                                            // runs 16 .. 31 (rare)
+        g = 16 + gl;
+        rs = gsl[kSlotRunStart + g];
+        rn = gsl[kSlotRunStart + g + 1];
+        gid = gsl[kSlotRunGroup + g];
+      }
+      const bool valid = g < nr;
+      const int re = g + 1 < nr ? rn : nv;
+      const uint32_t M = valid ? (0xffffffffu >> (32 - (re - rs))) << rs : 0u;   // rows [rs, re)
+      const uint32_t bits = ((M >> q4) & 15u) | (((M >> (16 + q4)) & 15u) << 4);
+      bf16x8 sel;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sel[i] = ((bits >> i) & 1u) ? (__bf16)1.0f : (__bf16)0.0f;
+      f32x4 DA = {0.f, 0.f, 0.f, 0.f}, DB = DA;
+      DA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hA, sel, DA, 0, 0, 0);
+      DB = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hB, sel, DB, 0, 0, 0);
+      DA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lA, sel, DA, 0, 0, 0);
+      DB = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lB, sel, DB, 0, 0, 0);
+      const int cnt = re - rs;
+      const bool first = g == 0 && prev_same;
+      const bool last = g == nr - 1 && next_same;
+      f32x4 SA = DA, CA = {0.f, 0.f, 0.f, 0.f}, SB = DB, CB = CA;
+      int ntot = cnt;
+      bool cut = false;
+      if (prev_same) {
+        if (t > tb) {
+          if (first) {                                       // the block's open group
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              float s1 = oSA[i], c1v = oCA[i];
+              kahan_add(s1, c1v, DA[i]);
+              oSA[i] = s1;
+              oCA[i] = c1v;
+              float s2 = oSB[i], c2v = oCB[i];
+              kahan_add(s2, c2v, DB[i]);
+              oSB[i] = s2;
+              oCB[i] = c2v;
+            }
+            SA = oSA;
+            CA = oCA;
+            SB = oSB;
+            CB = oCB;
+            ntot = oN + cnt;
+            cut = oCut;
+          }
+        } else {
+          cut = first;                                       // began before the block's range
+        }
+      }
+      if (valid) {
+        if (last && keep_open) {                             // stays open for the next tile
+          oSA = SA;
+          oCA = CA;
+          oSB = SB;
+          oCB = CB;
+          oN = ntot;
+          oCut = cut;
+        } else {
+          const f32x4 vA = SA - CA, vB = SB - CB;
+          if (last || cut) {                                 // partials for the fix-up
+            const int slot = (last && !cut) ? 1 : 0;
+            float* cp = a.carry + (bidx * 2 + slot) * h + col4;
+            *reinterpret_cast<f32x4*>(cp) = vA;
+            *reinterpret_cast<f32x4*>(cp + 16) = vB;
+          } else {
+            sink_write4(a.sink, gid, col4, h, vA, ntot);
+            sink_write4(a.sink, gid, col4 + 16, h, vB, ntot);
+          }
+        }
+      }
+    }
+    off = (off + nr - 1) & 15;
+    rr = wrap(rr + 1, NB);
+    ri = wrap(ri + 1, G::NIR);
+    compute_barrier();
+  }
+}
+
+// kWide: BF16 SUM / MEAN with h % 32 == 0 (32-column compute waves).
+template <class T, int KP, int NB, bool kMax, bool kWide>
+__global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves) * 64) k_fwd_dma(WsArgs a) {
+  static_assert(!kWide || (std::is_same<T, __bf16>::value && !kMax), "wide waves: BF16 SUM / MEAN");
   using G = DmaGeo<T, KP, NB>;
   using WT = typename DmaMfma<T>::W;
   constexpr int NKS = DmaMfma<T>::template nks<KP>();
@@ -490,7 +683,7 @@ __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArg
   }
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int h = a.h;
-  const int ncw = h / 16;
+  const int ncw = kWide ? h / 32 : h / 16;
   const int wave = threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   const int64_t bidx = blockIdx.x;
@@ -547,6 +740,10 @@ __global__ void __launch_bounds__((kHMax / 16 + kDmaWaves) * 64) k_fwd_dma(WsArg
   }
 
   // -------------------------------------------------------------- compute waves
+  if constexpr (kWide) {
+    fwd_wide_bf16<KP, NB>(a, smem, tb, te, range_hi, wave, lane, bidx);
+    return;
+  }
   const int cw = wave;
   const int col = cw * 16 + (lane & 15);
   const float bc = a.b ? a.b[col] : 0.0f;
@@ -902,11 +1099,11 @@ constexpr int ring_depth() {
   return fit < 6 ? fit : 6;
 }
 
-template <class T, int KP, int NB, bool kMax>
+template <class T, int KP, int NB, bool kMax, bool kWide>
 void launch_dma(const WsArgs& a, size_t lds, hipStream_t s) {
-  allow_lds(k_fwd_dma<T, KP, NB, kMax>, lds);
+  allow_lds(k_fwd_dma<T, KP, NB, kMax, kWide>, lds);
   KTimer tm("fwd_fused", s);
-  k_fwd_dma<T, KP, NB, kMax><<<(unsigned)a.nunits, (a.h / 16 + kDmaWaves) * 64, lds, s>>>(a);
+  k_fwd_dma<T, KP, NB, kMax, kWide><<<(unsigned)a.nunits, (a.h / (kWide ? 32 : 16) + kDmaWaves) * 64, lds, s>>>(a);
   RELNN_LAUNCHED();
 }
 
@@ -918,9 +1115,11 @@ void run_dma(const WsArgs& a, hipStream_t s) {
   const size_t lds = (size_t)NB * G::TILE + (size_t)G::NIR * G::IRB;
   RELNN_REQUIRE(lds <= 160 * 1024, RELNN_E_HIP, "internal: LDS ring of %zu bytes", lds);
   if (a.sink.agg == RELNN_MAX)
-    launch_dma<T, KP, NB, true>(a, lds, s);
+    launch_dma<T, KP, NB, true, false>(a, lds, s);
+  else if (std::is_same<T, __bf16>::value && a.h % 32 == 0)
+    launch_dma<T, KP, NB, false, std::is_same<T, __bf16>::value>(a, lds, s);
   else
-    launch_dma<T, KP, NB, false>(a, lds, s);
+    launch_dma<T, KP, NB, false, false>(a, lds, s);
 }
 
 int num_cus() {
@@ -1042,9 +1241,9 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
 
 // Explicit instantiations of the fused kernel: with implicit ones alone the
 // host pass left the launch stubs of some instances undefined.
-#define RELNN_DMA_INST(T, KP)                                                      \
-  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), false>(WsArgs); \
-  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true>(WsArgs);
+#define RELNN_DMA_INST(T, KP)                                                             \
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), false, false>(WsArgs); \
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false>(WsArgs);
 RELNN_DMA_INST(float, 64)
 RELNN_DMA_INST(float, 128)
 RELNN_DMA_INST(float, 256)
@@ -1053,6 +1252,10 @@ RELNN_DMA_INST(__bf16, 64)
 RELNN_DMA_INST(__bf16, 128)
 RELNN_DMA_INST(__bf16, 256)
 RELNN_DMA_INST(__bf16, 384)
+template __global__ void k_fwd_dma<__bf16, 64, ring_depth<__bf16, 64>(), false, true>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 128, ring_depth<__bf16, 128>(), false, true>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 256, ring_depth<__bf16, 256>(), false, true>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 384, ring_depth<__bf16, 384>(), false, true>(WsArgs);
 #undef RELNN_DMA_INST
 
 }  // namespace relnn

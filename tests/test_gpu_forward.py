@@ -142,7 +142,9 @@ def test_fwd_random_keyed_chains(agg):
 @pytest.mark.parametrize("d,h", [((8, 16, 8), 48),          # K 32 in a 64-wide tile (pad), 3 column waves
                                  ((24, 40, 64), 80),        # K 128, 5 column waves
                                  ((64, 72, 64), 112),       # K 200 in a 256-wide tile, 7 column waves
-                                 ((96, 104, 96), 128)])     # K 296 in a 384-wide tile
+                                 ((96, 104, 96), 128),      # K 296 in a 384-wide tile
+                                 ((16, 16, 8), 64),         # BF16: two 32-column waves
+                                 ((40, 40, 48), 96)])       # BF16: three 32-column waves
 @pytest.mark.parametrize("agg", ["sum", "mean", "max"])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_fwd_tile_shapes_and_long_ranges(d, h, agg, dtype):
