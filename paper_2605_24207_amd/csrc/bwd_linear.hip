@@ -55,16 +55,6 @@ __device__ __forceinline__ void kahan_add1(float& s, float& c, float x) {
   s = t;
 }
 
-__device__ __forceinline__ void kahan4(f32x4& s, f32x4& c, const f32x4& x) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float y = x[i] - c[i];
-    const float t = s[i] + y;
-    c[i] = (t - s[i]) - y;
-    s[i] = t;
-  }
-}
-
 // Four consecutive elements of column block cq of the joined row at list
 // position e, as FP32.  The atom of the block is picked with compile-time
 // indices (a run-time index into the argument's arrays would put it in
@@ -86,21 +76,36 @@ __device__ __forceinline__ GsAtom gs_atom(const GsArgs& a, int col) {
   return r;
 }
 
+// VW (4 or 2) consecutive elements of the joined row at list position e,
+// as FP32 (the unused lanes of an f32x4 are zero).
+template <int VW>
 __device__ __forceinline__ f32x4 gs_load(const GsArgs& a, const GsAtom& A, int32_t row, int col) {
   const int64_t o = (int64_t)row * A.d + (col - A.koff);
-  if (a.bf16) {
-    const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const __bf16*>(A.emb) + o);
-    return f32x4{__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u), __uint_as_float(v.y << 16),
-                 __uint_as_float(v.y & 0xffff0000u)};
+  if constexpr (VW == 4) {
+    if (a.bf16) {
+      const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const __bf16*>(A.emb) + o);
+      return f32x4{__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u), __uint_as_float(v.y << 16),
+                   __uint_as_float(v.y & 0xffff0000u)};
+    }
+    return *reinterpret_cast<const f32x4*>(static_cast<const float*>(A.emb) + o);
+  } else {
+    if (a.bf16) {
+      const uint32_t v = *reinterpret_cast<const uint32_t*>(static_cast<const __bf16*>(A.emb) + o);
+      return f32x4{__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u), 0.f, 0.f};
+    }
+    const float2 v = *reinterpret_cast<const float2*>(static_cast<const float*>(A.emb) + o);
+    return f32x4{v.x, v.y, 0.f, 0.f};
   }
-  return *reinterpret_cast<const f32x4*>(static_cast<const float*>(A.emb) + o);
 }
 
 // out[s] = sum over the positions e of segment s of the joined row at e.
 // One wavefront per unit of positions [pos(u), pos(u+1)), pos(u) = (ntiles
-// u / nunits) 64; lane l owns the four columns 4 (64 p + l) .. of pass p.  A
+// u / nunits) 64; lane l owns the VW columns VW (64 p + l) .. of pass p.  A
 // segment cut by a unit end leaves its partial in carry slot 0 (cut by the
 // start) or 1 (runs past the end); k_fixup combines them in unit order.
+// VW columns per lane: 4, or 2 for rows of at most 128 elements (all 64
+// lanes busy; a wave instruction costs the same with 32 or 64 lanes on).
+template <int VW>
 __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
   const int lane = threadIdx.x % 64;
   const int64_t u = (int64_t)blockIdx.x * kGsWaves + threadIdx.x / 64;
@@ -110,8 +115,8 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
   if (r0 >= r1) return;
   const int K = a.K;
 
-  for (int cb = 0; cb < K; cb += 256) {
-    const int col = cb + 4 * lane;
+  for (int cb = 0; cb < K; cb += 64 * VW) {
+    const int col = cb + VW * lane;
     const bool on = col < K;
     const GsAtom A = gs_atom(a, on ? col : 0);
     f32x4 s = {0.f, 0.f, 0.f, 0.f}, c = {0.f, 0.f, 0.f, 0.f};
@@ -125,7 +130,10 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
         const f32x4 v = s - c;
         float* dst = (cut_lo || cut_hi) ? a.carry + (u * 2 + (cut_lo ? 0 : 1)) * a.ldo + col
                                         : a.out + (int64_t)g * a.ldo + col;
-        *reinterpret_cast<f32x4*>(dst) = v;
+        if constexpr (VW == 4)
+          *reinterpret_cast<f32x4*>(dst) = v;
+        else
+          *reinterpret_cast<float2*>(dst) = make_float2(v[0], v[1]);
       }
       first = false;
       s = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -151,18 +159,26 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
             const int32_t rj = __builtin_amdgcn_readlane(R[j], q);
             row = A.j == j ? rj : row;
           }
-          v[i] = gs_load(a, A, row, on ? col : 0);
+          v[i] = gs_load<VW>(a, A, row, on ? col : 0);
           if (a.argmax || a.mask) {                     // route the gradient row of this tuple
             const int32_t tau = __builtin_amdgcn_readlane(R[1], q);
             if (a.argmax) {
-              const int4 am = *reinterpret_cast<const int4*>(a.argmax + (int64_t)row * a.d[0] + (on ? col : 0));
-              v[i][0] = am.x == tau ? v[i][0] : 0.0f;
-              v[i][1] = am.y == tau ? v[i][1] : 0.0f;
-              v[i][2] = am.z == tau ? v[i][2] : 0.0f;
-              v[i][3] = am.w == tau ? v[i][3] : 0.0f;
+              const int32_t* ap = a.argmax + (int64_t)row * a.d[0] + (on ? col : 0);
+              if constexpr (VW == 4) {
+                const int4 am = *reinterpret_cast<const int4*>(ap);
+                v[i][0] = am.x == tau ? v[i][0] : 0.0f;
+                v[i][1] = am.y == tau ? v[i][1] : 0.0f;
+                v[i][2] = am.z == tau ? v[i][2] : 0.0f;
+                v[i][3] = am.w == tau ? v[i][3] : 0.0f;
+              } else {
+                const int2 am = *reinterpret_cast<const int2*>(ap);
+                v[i][0] = am.x == tau ? v[i][0] : 0.0f;
+                v[i][1] = am.y == tau ? v[i][1] : 0.0f;
+              }
             }
             if (a.mask) {
-              const uint32_t m = *reinterpret_cast<const uint32_t*>(a.mask + (int64_t)tau * a.d[0] + (on ? col : 0));
+              const uint8_t* mp = a.mask + (int64_t)tau * a.d[0] + (on ? col : 0);
+              const uint32_t m = VW == 4 ? *reinterpret_cast<const uint32_t*>(mp) : *reinterpret_cast<const uint16_t*>(mp);
               v[i][0] = (m & 0xffu) ? v[i][0] : 0.0f;
               v[i][1] = (m & 0xff00u) ? v[i][1] : 0.0f;
               v[i][2] = (m & 0xff0000u) ? v[i][2] : 0.0f;
@@ -179,7 +195,13 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
             flush();
             g = gq;
           }
-          kahan4(s, c, v[i]);
+#pragma unroll
+          for (int x = 0; x < VW; ++x) {
+            float sx = s[x], cx = c[x];
+            kahan_add1(sx, cx, v[i][x]);
+            s[x] = sx;
+            c[x] = cx;
+          }
         }
       }
     }
@@ -240,7 +262,10 @@ void seg_gather_sum(GsArgs a, int64_t nseg_units_cap, hipStream_t s) {
   a.nunits = gs_units(a.n);
   RELNN_REQUIRE(a.nunits <= nseg_units_cap, RELNN_E_HIP, "internal: carry region too small");
   RELNN_REQUIRE(a.K % 4 == 0, RELNN_E_UNSUPPORTED, "row width %d is not a multiple of 4", a.K);
-  k_seg_gather_sum<<<(unsigned)cdiv(a.nunits, kGsWaves), kGsWaves * 64, 0, s>>>(a);
+  if (a.K <= 128)
+    k_seg_gather_sum<2><<<(unsigned)cdiv(a.nunits, kGsWaves), kGsWaves * 64, 0, s>>>(a);
+  else
+    k_seg_gather_sum<4><<<(unsigned)cdiv(a.nunits, kGsWaves), kGsWaves * 64, 0, s>>>(a);
   RELNN_LAUNCHED();
   // the fix-up reads carry slots and writes out rows with stride ldo
   Sink sk{};
