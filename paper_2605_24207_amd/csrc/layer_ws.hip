@@ -936,12 +936,18 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
       }
       off = (off + nr - 1) & 15;
     } else {
-      // ---- MAX: per run, the rows of the run are kept by a bit mask, then
-      // the 4 lanes of each column are combined
+      // ---- MAX: a segmented max-scan of the tile, whose cost does not
+      // depend on the number of runs.  A lane holds rows q4 .. q4+3 (acc0)
+      // and 16+q4 .. (acc1) of its column: each 4-row block is scanned in
+      // the lane, the block tails across the column's 4 lane rows with two
+      // row swaps (whether a block holds a run start follows from the
+      // wave-uniform start mask, so only values and positions move), and
+      // every row then holds the max of its run up to that row and the
+      // run's first maximiser.  The rows that end a run write it.
       const int nv = (int)min<int64_t>(TM, a.E - e0);
       const int32_t gup = __builtin_amdgcn_update_dpp(0, gcur, 0x138, 0xf, 0xf, false);
       const bool start = lane < nv && (lane == 0 || gup != gcur);
-      uint32_t runs = (uint32_t)__ballot(start);
+      const uint32_t runs = (uint32_t)__ballot(start);
       const int32_t g_first = __builtin_amdgcn_readlane(gcur, 0);
       const int32_t g_last = __builtin_amdgcn_readlane(gcur, nv - 1);
       const int32_t g_before = __builtin_amdgcn_readlane(gcur, 32);
@@ -949,53 +955,164 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
       const bool prev_same = e0 > 0 && g_before == g_first;
       const bool next_same = e0 + nv < a.E && g_after == g_last;
       const bool keep_open = next_same && e0 + nv < range_hi;
-      bool first_run = true;
-      while (runs) {
-        const int rs = __builtin_ctz(runs);
-        runs &= runs - 1;
-        const int re = runs ? __builtin_ctz(runs) : nv;
-        const bool last_run = runs == 0;
-        const uint32_t M = (re >= 32 ? 0xffffffffu : ((1u << re) - 1u)) & ~((1u << rs) - 1u);
-        const uint32_t m0 = M >> q4, m1 = M >> (16 + q4);
-        float part = -INFINITY;
-        int32_t parg = INT32_MAX;
+      const bool open_in = prev_same && t > tb;            // row 0 continues the block's open group
+      const uint32_t sm = open_in ? (runs & ~1u) : runs;   // starts as the scan sees them
+      const int qr = lane >> 4;                             // lane row of the column
+      // (lv, la) followed by (rv, ra): the later one wins only if strictly
+      // greater; (-inf, INT32_MAX) is the empty prefix
+      auto comb = [](float lv, int32_t la, float rv, int32_t ra, float& ov, int32_t& oa) {
+        const bool take = rv > lv || la == INT32_MAX;
+        ov = take ? rv : lv;
+        oa = take ? ra : la;
+      };
+      auto any_start = [&](int r0s, int n) { return ((sm >> r0s) & ((1u << n) - 1u)) != 0u; };
+      // carry into the first row
+      float cv = open_in ? mS : -INFINITY;
+      int32_t ca = open_in ? mArg : INT32_MAX;
+      float fv[8];                                         // per row: run max so far
+      int32_t fa[8];                                       // ... and its first maximiser
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const float yi = i < 4 ? acc0[i & 3] : acc1[i & 3];
-          const bool in = ((i < 4 ? m0 : m1) >> (i & 3)) & 1u;
-          const int32_t rw = (int32_t)(e0 + (i < 4 ? 0 : 16) + q4 + (i & 3));
-          const bool take = in && (yi > part || parg == INT32_MAX);   // the run's first row always
-          part = take ? yi : part;
-          parg = take ? rw : parg;
-        }
-        col_max4(part, parg);
-        const int cnt = re - rs;
-        if (first_run && prev_same && t > tb) {            // the block's open group
-          if (part > mS) {
-            mS = part;
-            mArg = parg;
-          }
-          mN += cnt;
-        } else {                                           // a new group (cut if it began before the range)
-          mS = part;
-          mArg = parg;
-          mN = cnt;
-          mCut = first_run && prev_same;
-        }
-        first_run = false;
-        if (last_run && keep_open) break;                  // stays open for the next tile
-        if (lane < 16) {
-          if (last_run && next_same) {                     // runs past the range end
-            const int64_t o = slot_base + (mCut ? 0 : h);
-            a.carry[o] = mS;
-            if (a.carry_arg) a.carry_arg[o] = mArg;
-          } else if (!mCut) {
-            sink_write<true>(a.sink, __builtin_amdgcn_readlane(gcur, rs), col, h, mS, mArg, mN);
-          } else {                                         // cut by the range start
-            a.carry[slot_base] = mS;
-            if (a.carry_arg) a.carry_arg[slot_base] = mArg;
+      for (int set = 0; set < 2; ++set) {
+        const int base = 16 * set;
+        float sv[4];
+        int32_t sa[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {                      // in-lane scan of the block
+          const int r = base + q4 + i;
+          const float y = set ? acc1[i] : acc0[i];
+          const int32_t pos = (int32_t)(e0 + r);
+          if (i == 0) {
+            sv[0] = y;
+            sa[0] = pos;
+          } else {
+            comb(sv[i - 1], sa[i - 1], y, pos, sv[i], sa[i]);
+            const bool st = (sm >> r) & 1u;
+            sv[i] = st ? y : sv[i];
+            sa[i] = st ? pos : sa[i];
           }
         }
+        // block tails across the lane rows: pairs (0,1), (2,3), then halves
+        const float tv = sv[3];
+        const int32_t ta = sa[3];
+        const auto p16v = __builtin_amdgcn_permlane16_swap(__float_as_uint(tv), __float_as_uint(tv), false, false);
+        const auto p16a = __builtin_amdgcn_permlane16_swap((uint32_t)ta, (uint32_t)ta, false, false);
+        const bool odd = qr & 1;
+        // the pair partner's tail (rows 0 <-> 1, 2 <-> 3)
+        const float xv = __uint_as_float(odd ? p16v[0] : p16v[1]);
+        const int32_t xa = (int32_t)(odd ? p16a[0] : p16a[1]);
+        const int pr = base + 4 * (qr & 2);                // first row of this lane's pair
+        // pair total: the later block's tail if it holds a start
+        float pv;
+        int32_t pa;
+        {
+          const float lv = odd ? xv : tv, rv = odd ? tv : xv;
+          const int32_t la = odd ? xa : ta, ra = odd ? ta : xa;
+          comb(lv, la, rv, ra, pv, pa);
+          const bool rf = any_start(pr + 4, 4);
+          pv = rf ? rv : pv;
+          pa = rf ? ra : pa;
+        }
+        const auto p32v = __builtin_amdgcn_permlane32_swap(__float_as_uint(pv), __float_as_uint(pv), false, false);
+        const auto p32a = __builtin_amdgcn_permlane32_swap((uint32_t)pa, (uint32_t)pa, false, false);
+        const bool hi = qr & 2;
+        const float ov = __uint_as_float(hi ? p32v[0] : p32v[1]);    // the other pair's total
+        const int32_t oa = (int32_t)(hi ? p32a[0] : p32a[1]);
+        // prefix of the blocks before this lane's block
+        float ev = -INFINITY;
+        int32_t ea = INT32_MAX;
+        if (qr == 1) {
+          ev = xv;
+          ea = xa;
+        } else if (qr == 2) {
+          ev = ov;
+          ea = oa;
+        } else if (qr == 3) {                              // pair (0,1), then block 2
+          comb(ov, oa, xv, xa, ev, ea);
+          const bool f2 = any_start(base + 8, 4);
+          ev = f2 ? xv : ev;
+          ea = f2 ? xa : ea;
+        }
+        // carry into this block: the set's carry, then that prefix
+        float kv;
+        int32_t ka;
+        comb(cv, ca, ev, ea, kv, ka);
+        const bool pf = any_start(base, q4);               // a start in an earlier block of the set
+        kv = pf ? ev : kv;
+        ka = pf ? ea : ka;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {                      // rows before the block's first start
+          float v;
+          int32_t ag;
+          comb(kv, ka, sv[i], sa[i], v, ag);
+          const bool own = any_start(base + q4, i + 1);
+          fv[4 * set + i] = own ? sv[i] : v;
+          fa[4 * set + i] = own ? sa[i] : ag;
+        }
+        // carry into the next set: the whole set after the current carry
+        float tot_v;
+        int32_t tot_a;
+        {
+          const float lv = hi ? ov : pv, rv = hi ? pv : ov;
+          const int32_t la = hi ? oa : pa, ra = hi ? pa : oa;
+          comb(lv, la, rv, ra, tot_v, tot_a);
+          const bool rf = any_start(base + 8, 8);
+          tot_v = rf ? rv : tot_v;
+          tot_a = rf ? ra : tot_a;
+        }
+        float nv2;
+        int32_t na2;
+        comb(cv, ca, tot_v, tot_a, nv2, na2);
+        const bool sf = any_start(base, 16);
+        cv = sf ? tot_v : nv2;
+        ca = sf ? tot_a : na2;
+      }
+      // outputs: rows that end a run
+      const uint32_t first_run_rows = (sm & ~1u) == 0u ? 0xffffffffu : ((sm & ~1u) & (0u - (sm & ~1u))) - 1u;
+      const bool cut0 = prev_same && (open_in ? mCut : true);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = (i < 4 ? 0 : 16) + q4 + (i & 3);
+        const bool ends = r < nv && (r == nv - 1 || ((runs >> (r + 1)) & 1u));
+        if (ends) {
+          const bool cut = ((first_run_rows >> r) & 1u) && cut0;
+          if (r == nv - 1 && next_same) {
+            if (!keep_open) {                              // runs past the range end
+              const int64_t o = slot_base + (cut ? 0 : h);
+              a.carry[o] = fv[i];
+              if (a.carry_arg) a.carry_arg[o] = fa[i];
+            }
+          } else if (cut) {                                // cut by the range start
+            a.carry[slot_base] = fv[i];
+            if (a.carry_arg) a.carry_arg[slot_base] = fa[i];
+          } else {
+            sink_write<true>(a.sink, gsl[kSlotSeg + r], col, h, fv[i], fa[i], 0);
+          }
+        }
+      }
+      if (keep_open) {                                     // row nv-1 to every lane row of the column
+        const int rl = nv - 1, ql = (rl & 15) >> 2, il = (rl & 3) + (rl >= 16 ? 4 : 0);
+        float v = fv[0];
+        int32_t ag = fa[0];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) {
+          v = il == i ? fv[i] : v;
+          ag = il == i ? fa[i] : ag;
+        }
+        const auto s16v = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        const auto s16a = __builtin_amdgcn_permlane16_swap((uint32_t)ag, (uint32_t)ag, false, false);
+        if ((qr & 1) != (ql & 1)) {
+          v = __uint_as_float((qr & 1) ? s16v[0] : s16v[1]);
+          ag = (int32_t)((qr & 1) ? s16a[0] : s16a[1]);
+        }
+        const auto s32v = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        const auto s32a = __builtin_amdgcn_permlane32_swap((uint32_t)ag, (uint32_t)ag, false, false);
+        if ((qr & 2) != (ql & 2)) {
+          v = __uint_as_float((qr & 2) ? s32v[0] : s32v[1]);
+          ag = (int32_t)((qr & 2) ? s32a[0] : s32a[1]);
+        }
+        mS = v;
+        mArg = ag;
+        mCut = ((first_run_rows >> rl) & 1u) && cut0;
       }
     }
     rr = wrap(rr + 1, NB);
