@@ -1,0 +1,178 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (one launch over all joined tuples of a rule), checked on seeded
+samples of the output that the oracle evaluates group by group or row by
+row.  Sampled groups include one large group whose tiles span several
+persistent blocks, so the carry fix-up is part of what is checked.
+
+Workload 2: the ER schema (User 1M, Item 500k, Category 1k, Buys 20M with
+item ~ Zipf 1.1), Item SUM (K = 384) and User MEAN (K = 256), FP32 and BF16.
+Workload 4: Node 2M x 128, Edge 10M (s ~ Zipf 1.2), the MAX layer forward
+and its backward (embedding-gradient rows of sampled nodes, and db, whose
+closed form is the column sums of dA).
+"""
+import copy
+
+import numpy as np
+import pytest
+
+import relgen
+from oracle import relnn_oracle as orc
+from tests.helpers import distinct_embs, gpu_index, gpu_layer, oracle_inputs, rel_rows, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16": 2e-2}
+
+
+@pytest.fixture(scope="module")
+def er():
+    return relgen.er_graph()
+
+
+@pytest.fixture(scope="module")
+def power():
+    return relgen.power_graph()
+
+
+def sample_keys(keys, n_rand, big, seed):
+    """n_rand random group keys that occur, plus the key whose group size is
+    closest to ``big``."""
+    cnt = np.bincount(keys)
+    nz = np.nonzero(cnt)[0]
+    rng = np.random.default_rng(seed)
+    hot = nz[np.argmin(np.abs(cnt[nz] - big))]
+    return np.unique(np.concatenate([rng.choice(nz, n_rand, replace=False), [hot]])), int(cnt[hot])
+
+
+def restrict(rule, keys):
+    """The same rule over the link rows of the sampled groups only."""
+    sub = copy.copy(rule)
+    sel = np.isin(rule.cols[rule.group_col], keys)
+    sub.cols = [c[sel] for c in rule.cols]
+    return sub
+
+
+def gpu_full_fwd(rule, dtype, index):
+    import torch
+
+    from paper_2605_24207_amd import layer_fwd
+
+    out, pre, am = layer_fwd(index, gpu_layer(rule, dtype), distinct_embs(rule, dtype), to_dev(rule.W, dtype),
+                             to_dev(rule.b))
+    torch.cuda.synchronize()
+    return out, pre, am
+
+
+def check_sampled_forward(rule, dtype, keys):
+    import torch
+
+    gi = gpu_index(rule)
+    out, pre, am = gpu_full_fwd(rule, dtype, gi)
+    ex = gi.export()
+    gk = ex["group_keys"].cpu().numpy()
+    goff = ex["offsets"].cpu().numpy()
+    sub = restrict(rule, keys)
+    ref = orc.build_index(sub)
+    np.testing.assert_array_equal(ref.group_keys, np.sort(keys))
+    pos = np.searchsorted(gk, ref.group_keys)
+    np.testing.assert_array_equal(gk[pos], ref.group_keys)
+    # index: group sizes and the joined rows of every sampled group, bit-exact
+    np.testing.assert_array_equal(goff[pos + 1] - goff[pos], np.diff(ref.offsets))
+    rows = ex["tuple_rows"].cpu().numpy()
+    for q, g in enumerate(pos):
+        s, e = goff[g], goff[g + 1]
+        for j in range(len(rule.atoms)):
+            np.testing.assert_array_equal(rows[j][s:e], ref.rows[j][ref.offsets[q]:ref.offsets[q + 1]])
+    # layer values
+    idx_t = torch.from_numpy(pos.astype(np.int64)).to(pre.device)
+    pre_g = pre.index_select(0, idx_t).float().cpu().numpy()
+    out_g = out.index_select(0, idx_t).float().cpu().numpy()
+    embs, W, b = oracle_inputs(rule, "f32")
+    o_out, o_pre, o_am = orc.layer_fwd(ref, embs, W, b, rule.agg, rule.act_pre, rule.act_post)
+    assert rel_rows(pre_g, o_pre).max() <= TOL[dtype]
+    assert rel_rows(out_g, o_out, scale_ref=o_pre).max() <= TOL[dtype]
+    am_ref, embs_k, W_k = o_am, embs, W
+    if dtype == "bf16":          # the kernel's arithmetic alone, on the rounded inputs
+        embs_k, W_k, _ = oracle_inputs(rule, "bf16")
+        _, b_pre, b_am = orc.layer_fwd(ref, embs_k, W_k, b, rule.agg, rule.act_pre, rule.act_post)
+        assert rel_rows(pre_g, b_pre).max() <= 1e-5 * np.sqrt(rule.K)
+        am_ref = b_am
+    if rule.agg == "max":        # maximiser position within its group
+        am_g = am.index_select(0, idx_t).cpu().numpy().astype(np.int64) - goff[pos][:, None]
+        am_r = am_ref - ref.offsets[:-1][:, None]
+        diff = np.nonzero(am_g != am_r)
+        for q, c in zip(*diff):
+            x = orc.gather_concat(ref, embs_k, [ref.offsets[q] + am_g[q, c]])
+            y = orc.transform(x, W_k, b, rule.act_pre)[0, c]
+            assert abs(y - o_pre[q, c]) <= 4 * TOL[dtype] * max(1.0, abs(o_pre[q, c]))
+        assert len(diff[0]) <= 0.01 * am_r.size + 1
+    return gi, (out, pre, am)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("which", ["item", "user"])
+def test_er_full_forward_sampled(er, which, dtype):
+    rule = relgen.er_item_rule(er) if which == "item" else relgen.er_user_rule(er)
+    keys, hot = sample_keys(rule.cols[rule.group_col], 300, 60_000, seed=17)
+    if which == "item":          # one group over many tiles and more than one block's range
+        assert hot > 20_000
+    check_sampled_forward(rule, dtype, keys)
+
+
+def test_power_full_max_forward_backward_sampled(power):
+    """Workload-4 MAX layer: sampled groups forward; backward at full size,
+    checked on the embedding-gradient rows of sampled nodes (all tuples that
+    join them, routed by the kernel's own argmax) and on db."""
+    import torch
+
+    from paper_2605_24207_amd import layer_bwd, layer_fwd
+
+    rule = relgen.power_rule(power, 1)
+    keys, _ = sample_keys(rule.cols[rule.group_col], 300, 0, seed=19)
+    check_sampled_forward(rule, "f32", keys)
+
+    gi = gpu_index(rule, bwd=True)
+    layer = gpu_layer(rule, "f32")
+    z = to_dev(rule.atoms[0].emb)
+    W, b = to_dev(rule.W), to_dev(rule.b)
+    out, pre, am = layer_fwd(gi, layer, [z, z], W, b)
+    dout_np = np.random.default_rng(3).standard_normal((gi.G, rule.h)).astype(np.float32)
+    dz = torch.zeros_like(z)
+    dW = torch.empty_like(W)
+    db = torch.empty_like(b)
+    layer_bwd(gi, layer, [z, z], W, b, pre, am, to_dev(dout_np), [dz, dz], dW, db)
+    torch.cuda.synchronize()
+
+    ref = orc.build_index(rule)                   # full canonical order: positions match the kernel's
+    ex = gi.export()
+    np.testing.assert_array_equal(ex["offsets"].cpu().numpy(), ref.offsets)
+    np.testing.assert_array_equal(ex["link_rows"].cpu().numpy(), ref.link_row)
+    am_np = am.cpu().numpy().astype(np.int64)
+    dA = dout_np.astype(np.float64)               # act_post none: dA = dout
+    # db: every group's dA[g][c] reaches exactly one tuple (its argmax)
+    db_ref = dA.sum(axis=0)
+    assert np.linalg.norm(db.cpu().numpy() - db_ref) <= 1e-5 * np.linalg.norm(db_ref)
+    # dz rows of sampled nodes, among them a hot source
+    deg = np.bincount(np.concatenate(rule.cols), minlength=rule.atoms[0].n_rows)
+    nz = np.nonzero(deg)[0]
+    rng = np.random.default_rng(23)
+    hot = nz[np.argmin(np.abs(deg[nz] - 30_000))]
+    nodes = np.unique(np.concatenate([rng.choice(nz, 150, replace=False), [hot]]))
+    W64 = rule.W.astype(np.float64)
+    d = rule.atoms[0].d
+    dz_ref = np.zeros((len(nodes), d))
+    sq = np.zeros(len(nodes))                    # sum of squared norms of the terms (error scale)
+    for j in range(2):
+        rows_j = ref.rows[j]
+        tup = np.nonzero(np.isin(rows_j, nodes))[0]        # canonical positions joined to a sampled node
+        g = ref.tuple_group[tup]
+        dy = np.where(am_np[g] == tup[:, None], dA[g], 0.0)   # MAX routing by the kernel's argmax
+        contrib = dy @ W64[j * d:(j + 1) * d].T
+        at = np.searchsorted(nodes, rows_j[tup])
+        np.add.at(dz_ref, at, contrib)
+        np.add.at(sq, at, (contrib ** 2).sum(axis=1))
+    dz_g = dz.cpu().numpy()[nodes].astype(np.float64)
+    scale = np.maximum(np.linalg.norm(dz_ref, axis=1), np.sqrt(sq))
+    err = np.linalg.norm(dz_g - dz_ref, axis=1) / np.maximum(scale, 1e-30)
+    assert err.max() <= 1e-5, err.max()
+    assert np.isfinite(dW.cpu().numpy()).all()
