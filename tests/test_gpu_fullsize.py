@@ -6,6 +6,7 @@ persistent blocks, so the carry fix-up is part of what is checked.
 
 Workload 2: the ER schema (User 1M, Item 500k, Category 1k, Buys 20M with
 item ~ Zipf 1.1), Item SUM (K = 384) and User MEAN (K = 256), FP32 and BF16.
+Workload 3: the two-hop co-buy rule on the same graph, BF16, h = 256, MAX.
 Workload 4: Node 2M x 128, Edge 10M (s ~ Zipf 1.2), the MAX layer forward
 and its backward (embedding-gradient rows of sampled nodes, and db, whose
 closed form is the column sums of dA).
@@ -176,3 +177,38 @@ def test_power_full_max_forward_backward_sampled(power):
     err = np.linalg.norm(dz_g - dz_ref, axis=1) / np.maximum(scale, 1e-30)
     assert err.max() <= 1e-5, err.max()
     assert np.isfinite(dW.cpu().numpy()).all()
+
+
+def test_cobuy_full_precision_form(er):
+    """Workload 3 at full size: Buys |x| Buys^T on item (at most 50 paths per
+    item, about 9.8M paths), BF16 MFMA with FP32 accumulation, h = 256, MAX.
+    The index is compared in full; the values on a 1% sample of the output
+    rows, against the FP64 oracle."""
+    import torch
+
+    rule = relgen.cobuy_rule(er, d=256, h=256, cap=50, agg="max")
+    gi = gpu_index(rule)
+    ref = orc.build_index(rule)
+    assert (gi.E, gi.G) == (ref.E, ref.G)
+    ex = {k: v.cpu().numpy() for k, v in gi.export().items()}
+    np.testing.assert_array_equal(ex["offsets"], ref.offsets)
+    np.testing.assert_array_equal(ex["link_rows"], ref.link_row)
+    for j in range(2):
+        np.testing.assert_array_equal(ex["tuple_rows"][j], ref.rows[j])
+    out, pre, am = gpu_full_fwd(rule, "bf16", gi)
+    rng = np.random.default_rng(29)
+    groups = np.sort(rng.choice(ref.G, ref.G // 100, replace=False))
+    sel = torch.from_numpy(groups.astype(np.int64)).to(pre.device)
+    pre_g = pre.index_select(0, sel).cpu().numpy()
+    embs, W, b = oracle_inputs(rule, "f32")
+    _, o_pre, _ = orc.layer_fwd(ref, embs, W, b, "max", groups=groups)
+    assert rel_rows(pre_g, o_pre).max() <= TOL["bf16"]
+    embs_k, W_k, _ = oracle_inputs(rule, "bf16")
+    _, b_pre, b_am = orc.layer_fwd(ref, embs_k, W_k, b, "max", groups=groups)
+    assert rel_rows(pre_g, b_pre).max() <= 1e-5 * np.sqrt(rule.K)
+    am_g = am.index_select(0, sel).cpu().numpy().astype(np.int64)
+    diff = np.nonzero(am_g != b_am)
+    for q, c in zip(*diff):
+        y = orc.transform(orc.gather_concat(ref, embs_k, [am_g[q, c]]), W_k, b, "none")[0, c]
+        assert abs(y - b_pre[q, c]) <= 1e-5 * np.sqrt(rule.K) * max(1.0, abs(b_pre[q, c]))
+    assert len(diff[0]) <= 0.01 * b_am.size + 1
