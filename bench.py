@@ -241,6 +241,56 @@ def fwd_bwd_leg(steps: int, warmup: int, scale: float):
             "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in kt.items()}}
 
 
+def cobuy_leg(D, steps: int, warmup: int):
+    """Precision form: CoBuy(u1; max(Lin(z_u1 (+) z_u2))) over the self-join
+    of Buys on item, at most 50 paths per item (about 9.8M paths), User
+    embeddings of width 256, h = 256, BF16 operands with FP32 accumulation.
+    A step is one layer evaluation over all paths."""
+    import torch
+
+    import relgen
+    from paper_2605_24207_amd import Index, Layer, api, layer_fwd, workspace_size
+
+    rule = relgen.cobuy_rule(D["g"], d=256, h=256, cap=50, agg="max")
+    nu = rule.atoms[0].n_rows
+    t0 = time.perf_counter()
+    ix = Index([D["bu"], D["bi"]], [(nu, 0, None), (nu, 2, None)], 0, two_hop=(1, 50))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    U = torch.from_numpy(rule.atoms[0].emb).to("cuda").to(torch.bfloat16).contiguous()
+    W = torch.from_numpy(rule.W).to("cuda").to(torch.bfloat16).contiguous()
+    b = torch.from_numpy(rule.b).to("cuda")
+    L = Layer([256, 256], 256, "bf16", "max", "none", "none")
+    ws = torch.empty(workspace_size(ix, L), dtype=torch.uint8, device="cuda")
+    out = torch.empty(ix.G, 256, dtype=torch.float32, device="cuda")
+
+    def step():
+        layer_fwd(ix, L, [U, U], W, b, want_pre=False, want_argmax=False, ws=ws, out=out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    api.timing_reset()
+    api.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    api.timing_enable(False)
+    k_ms, k_n = api.timing_read("fwd_fused")
+    api.timing_reset()
+    flops = ix.E * (2 * 512 * 256 + 2 * 256)
+    k_avg = k_ms / max(k_n, 1)
+    return {"value": ix.E * steps / dt, "unit": "tuples/s", "ms_per_step": dt / steps * 1e3,
+            "workload": "CoBuy(u1; max(Lin(z_u1 (+) z_u2))) :- Buys(u1,i), Buys(u2,i); <= 50 paths per item; "
+                        "User 1M x 256; h 256; BF16 in, FP32 accumulate",
+            "tuples_per_step": ix.E, "groups": ix.G, "steps": steps, "index_build_s": round(build_s, 3),
+            "kernel_ms_per_launch": k_avg,
+            "mfma_tflops": flops / (k_avg * 1e-3) / 1e12 if k_avg > 0 else None,
+            "mfma_peak_tflops": PEAK_TFLOPS["bf16"]}
+
+
 def serve_leg(D, dtype: str, rates, seconds: float):
     """Serving form: the resident ER graph, seed-item requests with sizes
     log-uniform over 1..4096, two hops with fanout 15 then 10, open-loop
@@ -365,8 +415,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
     ap.add_argument("--cpu-budget", type=int, default=9_000_000, help="oracle sample size in tuples")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="f32,plain,bf16,push_f32,push_bf16,serve,fwdbwd",
-                    help="comma list of f32,plain,bf16,push_f32,push_bf16,serve,fwdbwd")
+    ap.add_argument("--legs", default="f32,plain,bf16,push_f32,push_bf16,cobuy_bf16,serve,fwdbwd",
+                    help="comma list of f32,plain,bf16,push_f32,push_bf16,cobuy_bf16,serve,fwdbwd")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per serving rate")
     ap.add_argument("--serve-rates", default="200,500,1000,2000", help="Poisson arrival rates (req/s)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -448,6 +498,12 @@ def main():
                                                       if "plain" in res else None)
         line["fused_bf16"]["mfma_tflops"] = r["flops"] / (bk_n / r["steps"]) / (bk_ms / bk_n * 1e-3) / 1e12
         line["fused_bf16"]["hbm_gbs_algorithmic"] = gbs(r["bytes"]["fused"], r["steps"], r["kt"]["fwd_fused"])
+    if "cobuy_bf16" in legs:
+        cb = cobuy_leg(D, args.steps, args.warmup)
+        line["cobuy_bf16"] = cb
+        log(f"cobuy bf16: {cb['ms_per_step']:.2f} ms/step, {cb['value'] / 1e9:.3f} G tuples/s, "
+            f"{cb['kernel_ms_per_launch']:.3f} ms/launch")
+        torch.cuda.empty_cache()
     if "serve" in legs:
         rates = [float(x) for x in args.serve_rates.split(",")]
         line["serve"] = {"workload": "resident ER graph (Buys 20M); requests of log-uniform 1..4096 seed items, "
