@@ -70,6 +70,7 @@ void launch_fixup(const Seg& sg, int TM, int h, int64_t ntiles, int64_t nunits, 
 // is not covered and the tile kernel runs instead.
 struct WsPlan {
   int KP = 0, TM = 0;
+  int hc = 0, nch = 0;       // output columns per block, column chunks
   int64_t ntiles = 0, nunits = 0;
   size_t wsw_bytes = 0, carry_elems = 0;
 };

@@ -44,6 +44,7 @@ struct WsArgs {
   int64_t E;
   const int64_t* E_dev;      // if set: E (and the tile count) come from device memory
   int K, h;
+  int hc, nch;               // output columns per block, column chunks (h = nch hc)
   int64_t ntiles, nunits;
   const void* Wsw;
   const void* zeros;         // 64 zero bytes (source of the K..KP pad chunks)
@@ -674,19 +675,25 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
   using WT = typename DmaMfma<T>::W;
   constexpr int NKS = DmaMfma<T>::template nks<KP>();
   constexpr int TM = kTM;
+  // Block -> (tuple range, column chunk).  Workgroups are dealt to the 8
+  // XCDs in turn, so blocks b and b + 8 share an L2: the nch chunks of one
+  // range go to blocks 8 apart and start together, and the later gathers of
+  // a row find it in that L2.  With one chunk this is the identity.
+  const int64_t bid = blockIdx.x;
+  const int chunk = (int)((bid >> 3) % a.nch);
+  const int64_t bidx = (bid / (8 * a.nch)) * 8 + (bid & 7);
   if (a.E_dev) {                   // run-time size: as many units as tiles, at most the grid
     a.E = *a.E_dev;
     a.ntiles = (a.E + kTM - 1) / kTM;
     a.sg.n = a.E;
     a.nunits = max<int64_t>(1, min<int64_t>(a.nunits, a.ntiles));
-    if ((int64_t)blockIdx.x >= a.nunits) return;
   }
+  if (bidx >= a.nunits) return;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int h = a.h;
-  const int ncw = kWide ? h / 32 : h / 16;
+  const int ncw = kWide ? a.hc / 32 : a.hc / 16;             // compute waves of the block
   const int wave = threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
-  const int64_t bidx = blockIdx.x;
   const int64_t tb = (a.ntiles * bidx) / a.nunits;
   const int64_t te = (a.ntiles * (bidx + 1)) / a.nunits;
   const int64_t range_hi = min<int64_t>(te * TM, a.E);
@@ -741,10 +748,10 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
 
   // -------------------------------------------------------------- compute waves
   if constexpr (kWide) {
-    fwd_wide_bf16<KP, NB>(a, smem, tb, te, range_hi, wave, lane, bidx);
+    fwd_wide_bf16<KP, NB>(a, smem, tb, te, range_hi, chunk * ncw + wave, lane, bidx);
     return;
   }
-  const int cw = wave;
+  const int cw = chunk * ncw + wave;                         // 16-column slice of W and out
   const int col = cw * 16 + (lane & 15);
   const float bc = a.b ? a.b[col] : 0.0f;
   WT w[NKS];
@@ -1220,7 +1227,8 @@ template <class T, int KP, int NB, bool kMax, bool kWide>
 void launch_dma(const WsArgs& a, size_t lds, hipStream_t s) {
   allow_lds(k_fwd_dma<T, KP, NB, kMax, kWide>, lds);
   KTimer tm("fwd_fused", s);
-  k_fwd_dma<T, KP, NB, kMax, kWide><<<(unsigned)a.nunits, (a.h / (kWide ? 32 : 16) + kDmaWaves) * 64, lds, s>>>(a);
+  const int64_t grid = a.nch == 1 ? a.nunits : round_up(a.nunits, 8) * a.nch;
+  k_fwd_dma<T, KP, NB, kMax, kWide><<<(unsigned)grid, (a.hc / (kWide ? 32 : 16) + kDmaWaves) * 64, lds, s>>>(a);
   RELNN_LAUNCHED();
 }
 
@@ -1233,7 +1241,7 @@ void run_dma(const WsArgs& a, hipStream_t s) {
   RELNN_REQUIRE(lds <= 160 * 1024, RELNN_E_HIP, "internal: LDS ring of %zu bytes", lds);
   if (a.sink.agg == RELNN_MAX)
     launch_dma<T, KP, NB, true, false>(a, lds, s);
-  else if (std::is_same<T, __bf16>::value && a.h % 32 == 0)
+  else if (std::is_same<T, __bf16>::value && a.hc % 32 == 0)
     launch_dma<T, KP, NB, false, std::is_same<T, __bf16>::value>(a, lds, s);
   else
     launch_dma<T, KP, NB, false, false>(a, lds, s);
@@ -1249,10 +1257,18 @@ int num_cus() {
   return n;
 }
 
-int pick_kp(int K) {
+// Tile width: K rounded up to 64, 128, 256 or 384, and 512 for BF16 (an
+// FP32 tile that wide leaves room for two LDS tiles only, no loads ahead).
+int pick_kp(int K, bool bf) {
   for (int kp : {64, 128, 256, 384})
     if (K <= kp) return kp;
-  return 0;
+  return bf && K <= 512 ? 512 : 0;
+}
+
+// Output columns per block: all of h up to 128, else chunks of 128.
+int pick_hc(int h) {
+  if (h % 16 == 0 && h <= kHMax) return h;
+  return h % kHMax == 0 ? kHMax : 0;
 }
 
 }  // namespace
@@ -1293,15 +1309,17 @@ int64_t push_units(int64_t E) { return std::max<int64_t>(1, std::min<int64_t>(cd
 WsPlan plan_ws(int dtype, int K, int h, int64_t E) {
   WsPlan p;
   const bool bf = dtype == RELNN_BF16;
-  p.KP = pick_kp(K);
-  const bool h_ok = h % 16 == 0 && h <= kHMax;
-  if (!p.KP || !h_ok) {
+  p.KP = pick_kp(K, bf);
+  p.hc = pick_hc(h);
+  if (!p.KP || !p.hc) {
     p.KP = 0;
     return p;
   }
+  p.nch = h / p.hc;
   p.TM = kTM;
   p.ntiles = cdiv(E, p.TM);
-  p.nunits = std::max<int64_t>(1, std::min<int64_t>(p.ntiles, num_cus()));
+  // one block per CU: the column chunks of a range share the CUs
+  p.nunits = std::max<int64_t>(1, std::min<int64_t>(p.ntiles, std::max(1, num_cus() / p.nch)));
   p.wsw_bytes = (size_t)p.KP * h * (bf ? 2 : 4) + kZeroBytes;
   p.carry_elems = (size_t)p.nunits * 2 * h;
   return p;
@@ -1328,6 +1346,8 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
   a.E_dev = f.E_dev;
   a.K = f.K;
   a.h = f.h;
+  a.hc = p.hc;
+  a.nch = p.nch;
   a.ntiles = p.ntiles;
   a.nunits = p.nunits;
   a.Wsw = Wsw;
@@ -1343,7 +1363,8 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
       case 64: run_dma<__bf16, 64>(a, s); break;
       case 128: run_dma<__bf16, 128>(a, s); break;
       case 256: run_dma<__bf16, 256>(a, s); break;
-      default: run_dma<__bf16, 384>(a, s); break;
+      case 384: run_dma<__bf16, 384>(a, s); break;
+      default: run_dma<__bf16, 512>(a, s); break;
     }
   } else {
     switch (p.KP) {
@@ -1369,10 +1390,12 @@ RELNN_DMA_INST(__bf16, 64)
 RELNN_DMA_INST(__bf16, 128)
 RELNN_DMA_INST(__bf16, 256)
 RELNN_DMA_INST(__bf16, 384)
+RELNN_DMA_INST(__bf16, 512)
 template __global__ void k_fwd_dma<__bf16, 64, ring_depth<__bf16, 64>(), false, true>(WsArgs);
 template __global__ void k_fwd_dma<__bf16, 128, ring_depth<__bf16, 128>(), false, true>(WsArgs);
 template __global__ void k_fwd_dma<__bf16, 256, ring_depth<__bf16, 256>(), false, true>(WsArgs);
 template __global__ void k_fwd_dma<__bf16, 384, ring_depth<__bf16, 384>(), false, true>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 512, ring_depth<__bf16, 512>(), false, true>(WsArgs);
 #undef RELNN_DMA_INST
 
 }  // namespace relnn

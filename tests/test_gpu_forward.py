@@ -144,13 +144,24 @@ def test_fwd_random_keyed_chains(agg):
                                  ((64, 72, 64), 112),       # K 200 in a 256-wide tile, 7 column waves
                                  ((96, 104, 96), 128),      # K 296 in a 384-wide tile
                                  ((16, 16, 8), 64),         # BF16: two 32-column waves
-                                 ((40, 40, 48), 96)])       # BF16: three 32-column waves
+                                 ((40, 40, 48), 96),        # BF16: three 32-column waves
+                                 ((96, 104, 96), 256),      # two 128-column chunks per tuple range
+                                 ((200, 200, 64), 384)])    # BF16: K 464 in a 512-wide tile, three chunks
 @pytest.mark.parametrize("agg", ["sum", "mean", "max"])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_fwd_tile_shapes_and_long_ranges(d, h, agg, dtype):
     """~4k tiles (many per block, so the load ring wraps many times) over
     widths that leave a zero pad in the LDS tile and odd column-wave counts."""
     check_fwd(random_rule(21, agg=agg, n_link=150_000, d=d, h=h), dtype)
+
+
+@pytest.mark.parametrize("h", [256, 384])
+@pytest.mark.parametrize("agg", ["sum", "mean", "max"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_fwd_column_chunks_few_tiles(h, agg, dtype):
+    """Fewer tuple ranges than one round of XCDs: the column-chunked grid has
+    blocks with no range, which must leave at once."""
+    check_fwd(random_rule(33, agg=agg, n_link=150, d=(96, 104, 96), h=h), dtype)
 
 
 def test_fwd_empty_join():
