@@ -668,9 +668,10 @@ __device__ __forceinline__ void fwd_wide_bf16(const WsArgs& a, char* smem, int64
 }
 
 // kWide: BF16 SUM / MEAN with h % 32 == 0 (32-column compute waves).
-template <class T, int KP, int NB, bool kMax, bool kWide>
+template <class T, int KP, int NB, bool kMax, bool kWide, bool kArg>
 __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves) * 64) k_fwd_dma(WsArgs a) {
   static_assert(!kWide || (std::is_same<T, __bf16>::value && !kMax), "wide waves: BF16 SUM / MEAN");
+  static_assert(!kArg || kMax, "maximiser positions: MAX only");
   using G = DmaGeo<T, KP, NB>;
   using WT = typename DmaMfma<T>::W;
   constexpr int NKS = DmaMfma<T>::template nks<KP>();
@@ -967,10 +968,17 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
       const int qr = lane >> 4;                             // lane row of the column
       // (lv, la) followed by (rv, ra): the later one wins only if strictly
       // greater; (-inf, INT32_MAX) is the empty prefix
+      // Without positions (no argmax asked for) only the values are kept:
+      // the empty prefix is -inf, which any value replaces or equals.
       auto comb = [](float lv, int32_t la, float rv, int32_t ra, float& ov, int32_t& oa) {
-        const bool take = rv > lv || la == INT32_MAX;
-        ov = take ? rv : lv;
-        oa = take ? ra : la;
+        if constexpr (kArg) {
+          const bool take = rv > lv || la == INT32_MAX;
+          ov = take ? rv : lv;
+          oa = take ? ra : la;
+        } else {
+          ov = rv > lv ? rv : lv;
+          oa = 0;
+        }
       };
       auto any_start = [&](int r0s, int n) { return ((sm >> r0s) & ((1u << n) - 1u)) != 0u; };
       // carry into the first row
@@ -1076,23 +1084,65 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
       // outputs: rows that end a run
       const uint32_t first_run_rows = (sm & ~1u) == 0u ? 0xffffffffu : ((sm & ~1u) & (0u - (sm & ~1u))) - 1u;
       const bool cut0 = prev_same && (open_in ? mCut : true);
+      // Rows that end a run (a wave-uniform mask).  Row r lives in the lanes
+      // of lane row (r % 16) / 4, register (r % 4) + 4 (r / 16).  The ends
+      // are visited one by one, so the cost follows the number of runs.
+      const uint32_t valid = nv >= 32 ? 0xffffffffu : ((1u << nv) - 1u);
+      const uint32_t ends = ((runs >> 1) | (1u << (nv - 1))) & valid;
+      const uint32_t last_bit = 1u << (nv - 1);
+      const uint32_t first_end = ends & (0u - ends);       // end of the first run
+      auto row_val = [&](int r, float& v, int32_t& ag) {
+        const int i = (r & 3) + ((r >> 2) & 4);
+        v = fv[0];
+        ag = fa[0];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int r = (i < 4 ? 0 : 16) + q4 + (i & 3);
-        const bool ends = r < nv && (r == nv - 1 || ((runs >> (r + 1)) & 1u));
-        if (ends) {
-          const bool cut = ((first_run_rows >> r) & 1u) && cut0;
-          if (r == nv - 1 && next_same) {
-            if (!keep_open) {                              // runs past the range end
-              const int64_t o = slot_base + (cut ? 0 : h);
-              a.carry[o] = fv[i];
-              if (a.carry_arg) a.carry_arg[o] = fa[i];
-            }
-          } else if (cut) {                                // cut by the range start
-            a.carry[slot_base] = fv[i];
-            if (a.carry_arg) a.carry_arg[slot_base] = fa[i];
-          } else {
-            sink_write<true>(a.sink, gsl[kSlotSeg + r], col, h, fv[i], fa[i], 0);
+        for (int k = 1; k < 8; ++k) {
+          v = i == k ? fv[k] : v;
+          ag = i == k ? fa[k] : ag;
+        }
+      };
+      const bool has_pre = a.sink.pre != nullptr, has_arg = a.sink.argmax != nullptr;
+      const bool obf = a.sink.out_bf16;
+      uint32_t plain = ends & ~(next_same ? last_bit : 0u) & ~(cut0 ? first_end : 0u);
+      while (plain) {                                      // finished inside the tile
+        const int r = __builtin_ctz(plain);
+        plain &= plain - 1u;
+        float v;
+        int32_t ag;
+        row_val(r, v, ag);
+        const int32_t gid = __builtin_amdgcn_readlane(gcur, r);
+        if (qr == ((r >> 2) & 3)) {
+          const int64_t o = (int64_t)gid * h + col;
+          if (has_pre) a.sink.pre[o] = v;
+          if (kArg && has_arg) a.sink.argmax[o] = ag;
+          const float w = act_apply(a.sink.act_post, v);
+          if (obf)
+            reinterpret_cast<__bf16*>(a.sink.out)[o] = (__bf16)w;
+          else
+            a.sink.out[o] = w;
+        }
+      }
+      // the first run, cut by the range start, and the last one, running
+      // past the range end, leave partials in the block's carry slots
+      const bool first_cut = cut0 && !(first_end == last_bit && keep_open);
+      const bool last_out = next_same && !keep_open && !(cut0 && first_end == last_bit);
+      if (first_cut || last_out) {
+        float v;
+        int32_t ag;
+        if (first_cut) {
+          const int r = __builtin_ctz(first_end);
+          row_val(r, v, ag);
+          if (qr == ((r >> 2) & 3)) {
+            a.carry[slot_base] = v;
+            if (a.carry_arg) a.carry_arg[slot_base] = kArg ? ag : 0;
+          }
+        }
+        if (last_out) {
+          const int r = nv - 1;
+          row_val(r, v, ag);
+          if (qr == ((r >> 2) & 3)) {
+            a.carry[slot_base + h] = v;
+            if (a.carry_arg) a.carry_arg[slot_base + h] = kArg ? ag : 0;
           }
         }
       }
@@ -1223,12 +1273,12 @@ constexpr int ring_depth() {
   return fit < 6 ? fit : 6;
 }
 
-template <class T, int KP, int NB, bool kMax, bool kWide>
+template <class T, int KP, int NB, bool kMax, bool kWide, bool kArg>
 void launch_dma(const WsArgs& a, size_t lds, hipStream_t s) {
-  allow_lds(k_fwd_dma<T, KP, NB, kMax, kWide>, lds);
+  allow_lds(k_fwd_dma<T, KP, NB, kMax, kWide, kArg>, lds);
   KTimer tm("fwd_fused", s);
   const int64_t grid = a.nch == 1 ? a.nunits : round_up(a.nunits, 8) * a.nch;
-  k_fwd_dma<T, KP, NB, kMax, kWide><<<(unsigned)grid, (a.hc / (kWide ? 32 : 16) + kDmaWaves) * 64, lds, s>>>(a);
+  k_fwd_dma<T, KP, NB, kMax, kWide, kArg><<<(unsigned)grid, (a.hc / (kWide ? 32 : 16) + kDmaWaves) * 64, lds, s>>>(a);
   RELNN_LAUNCHED();
 }
 
@@ -1240,11 +1290,14 @@ void run_dma(const WsArgs& a, hipStream_t s) {
   const size_t lds = (size_t)NB * G::TILE + (size_t)G::NIR * G::IRB;
   RELNN_REQUIRE(lds <= 160 * 1024, RELNN_E_HIP, "internal: LDS ring of %zu bytes", lds);
   if (a.sink.agg == RELNN_MAX)
-    launch_dma<T, KP, NB, true, false>(a, lds, s);
+    if (a.sink.argmax)
+      launch_dma<T, KP, NB, true, false, true>(a, lds, s);
+    else                           // values only (the carry positions are written as 0)
+      launch_dma<T, KP, NB, true, false, false>(a, lds, s);
   else if (std::is_same<T, __bf16>::value && a.hc % 32 == 0)
-    launch_dma<T, KP, NB, false, std::is_same<T, __bf16>::value>(a, lds, s);
+    launch_dma<T, KP, NB, false, std::is_same<T, __bf16>::value, false>(a, lds, s);
   else
-    launch_dma<T, KP, NB, false, false>(a, lds, s);
+    launch_dma<T, KP, NB, false, false, false>(a, lds, s);
 }
 
 int num_cus() {
@@ -1380,8 +1433,9 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
 // Explicit instantiations of the fused kernel: with implicit ones alone the
 // host pass left the launch stubs of some instances undefined.
 #define RELNN_DMA_INST(T, KP)                                                             \
-  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), false, false>(WsArgs); \
-  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false>(WsArgs);
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), false, false, false>(WsArgs); \
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false, true>(WsArgs);   \
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false, false>(WsArgs);
 RELNN_DMA_INST(float, 64)
 RELNN_DMA_INST(float, 128)
 RELNN_DMA_INST(float, 256)
@@ -1391,11 +1445,11 @@ RELNN_DMA_INST(__bf16, 128)
 RELNN_DMA_INST(__bf16, 256)
 RELNN_DMA_INST(__bf16, 384)
 RELNN_DMA_INST(__bf16, 512)
-template __global__ void k_fwd_dma<__bf16, 64, ring_depth<__bf16, 64>(), false, true>(WsArgs);
-template __global__ void k_fwd_dma<__bf16, 128, ring_depth<__bf16, 128>(), false, true>(WsArgs);
-template __global__ void k_fwd_dma<__bf16, 256, ring_depth<__bf16, 256>(), false, true>(WsArgs);
-template __global__ void k_fwd_dma<__bf16, 384, ring_depth<__bf16, 384>(), false, true>(WsArgs);
-template __global__ void k_fwd_dma<__bf16, 512, ring_depth<__bf16, 512>(), false, true>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 64, ring_depth<__bf16, 64>(), false, true, false>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 128, ring_depth<__bf16, 128>(), false, true, false>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 256, ring_depth<__bf16, 256>(), false, true, false>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 384, ring_depth<__bf16, 384>(), false, true, false>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 512, ring_depth<__bf16, 512>(), false, true, false>(WsArgs);
 #undef RELNN_DMA_INST
 
 }  // namespace relnn

@@ -7,7 +7,7 @@ import pytest
 
 import relgen
 from oracle import relnn_oracle as orc
-from tests.helpers import gpu_fwd, gpu_index, oracle_fwd, oracle_inputs, rel_rows
+from tests.helpers import distinct_embs, gpu_fwd, gpu_index, gpu_layer, oracle_fwd, oracle_inputs, rel_rows, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -162,6 +162,35 @@ def test_fwd_column_chunks_few_tiles(h, agg, dtype):
     """Fewer tuple ranges than one round of XCDs: the column-chunked grid has
     blocks with no range, which must leave at once."""
     check_fwd(random_rule(33, agg=agg, n_link=150, d=(96, 104, 96), h=h), dtype)
+
+
+@pytest.mark.parametrize("case", ["hot_ragged", "long_ranges", "chunks_512"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_fwd_max_without_argmax(case, dtype):
+    """MAX asked for values only: the same values and outputs, bit for bit,
+    as with the maximiser positions, across tiles, blocks and column chunks."""
+    import torch
+
+    from paper_2605_24207_amd import layer_fwd
+
+    if case == "hot_ragged":
+        rule = relgen.node_edge(seed=9, n_nodes=700, n_edges=40_003, agg="max", act_pre="relu", bias_std=0.3)
+        rule.cols[1][:30_000] = 11
+    elif case == "long_ranges":
+        rule = random_rule(21, agg="max", n_link=150_000, d=(96, 104, 96), h=128)
+    else:
+        rule = random_rule(22, agg="max", n_link=60_000, d=(200, 200, 64), h=256)
+    gi = gpu_index(rule)
+    layer = gpu_layer(rule, dtype)
+    embs, W, b = distinct_embs(rule, dtype), to_dev(rule.W, dtype), to_dev(rule.b)
+    out1, pre1, am1 = layer_fwd(gi, layer, embs, W, b)
+    out2, pre2, am2 = layer_fwd(gi, layer, embs, W, b, want_argmax=False)
+    torch.cuda.synchronize()
+    assert am1 is not None and am2 is None
+    assert torch.equal(pre1, pre2) and torch.equal(out1, out2)
+    _, o_out, o_pre, _ = oracle_fwd(rule, "f32")
+    tol = TOL[dtype]
+    assert rel_rows(pre2.cpu().numpy(), o_pre).max() <= tol
 
 
 def test_fwd_empty_join():
