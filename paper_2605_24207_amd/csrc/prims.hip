@@ -196,7 +196,12 @@ __global__ void k_scatter(const uint32_t* keys, const int32_t* vals, int64_t n, 
   }
 }
 
-__global__ void k_key_range(const int32_t* v, const int32_t* idx, int64_t n, uint32_t* mm) {
+// Smallest and largest key (order-preserving unsigned form).  One atomic
+// pair per block: atomics from every wave to one address serialise in L2.
+constexpr int kRangeThreads = 256;
+constexpr unsigned kRangeBlocks = 1024;
+__global__ void __launch_bounds__(kRangeThreads) k_key_range(const int32_t* v, const int32_t* idx, int64_t n,
+                                                             uint32_t* mm) {
   uint32_t lo = 0xFFFFFFFFu, hi = 0u;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -209,7 +214,18 @@ __global__ void k_key_range(const int32_t* v, const int32_t* idx, int64_t n, uin
     lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
     hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
   }
+  __shared__ uint32_t wlo[kRangeThreads / 64], whi[kRangeThreads / 64];
+  const int w = threadIdx.x / 64;
   if (__lane_id() == 0) {
+    wlo[w] = lo;
+    whi[w] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = 1; j < kRangeThreads / 64; ++j) {
+      lo = min(lo, wlo[j]);
+      hi = max(hi, whi[j]);
+    }
     atomicMin(&mm[0], lo);
     atomicMax(&mm[1], hi);
   }
@@ -327,7 +343,7 @@ void key_range(const int32_t* v, const int32_t* idx, int64_t n, uint32_t* kmin, 
   DevBuf mm(2 * sizeof(uint32_t));
   uint32_t init[2] = {0xFFFFFFFFu, 0u};
   RELNN_HIP(hipMemcpyAsync(mm.p, init, sizeof(init), hipMemcpyHostToDevice, s));
-  k_key_range<<<grid_for(n), 256, 0, s>>>(v, idx, n, mm.as<uint32_t>());
+  k_key_range<<<std::min(grid_for(n), kRangeBlocks), kRangeThreads, 0, s>>>(v, idx, n, mm.as<uint32_t>());
   RELNN_LAUNCHED();
   uint32_t res[2];
   RELNN_HIP(hipMemcpyAsync(res, mm.p, sizeof(res), hipMemcpyDeviceToHost, s));
