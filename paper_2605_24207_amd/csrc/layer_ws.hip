@@ -796,10 +796,257 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
   const int n16 = lane & 15;
   const int col4 = cw * 16 + q4;                             // first of this lane's 4 reduce columns
 
+  // MAX: reduces tile t from its products (acc0, acc1) and group numbers.
+  auto max_tile = [&](int64_t t, f32x4 acc0, f32x4 acc1, int32_t gcur) {
+    const int64_t e0 = t * TM;
+    // ---- MAX: a segmented max-scan of the tile, whose cost does not
+    // depend on the number of runs.  A lane holds rows q4 .. q4+3 (acc0)
+    // and 16+q4 .. (acc1) of its column: each 4-row block is scanned in
+    // the lane, the block tails across the column's 4 lane rows with two
+    // row swaps (whether a block holds a run start follows from the
+    // wave-uniform start mask, so only values and positions move), and
+    // every row then holds the max of its run up to that row and the
+    // run's first maximiser.  The rows that end a run write it.
+    const int nv = (int)min<int64_t>(TM, a.E - e0);
+    const int32_t gup = __builtin_amdgcn_update_dpp(0, gcur, 0x138, 0xf, 0xf, false);
+    const bool start = lane < nv && (lane == 0 || gup != gcur);
+    const uint32_t runs = (uint32_t)__ballot(start);
+    const int32_t g_first = __builtin_amdgcn_readlane(gcur, 0);
+    const int32_t g_last = __builtin_amdgcn_readlane(gcur, nv - 1);
+    const int32_t g_before = __builtin_amdgcn_readlane(gcur, 32);
+    const int32_t g_after = __builtin_amdgcn_readlane(gcur, 33);
+    const bool prev_same = e0 > 0 && g_before == g_first;
+    const bool next_same = e0 + nv < a.E && g_after == g_last;
+    const bool keep_open = next_same && e0 + nv < range_hi;
+    const bool open_in = prev_same && t > tb;            // row 0 continues the block's open group
+    const uint32_t sm = open_in ? (runs & ~1u) : runs;   // starts as the scan sees them
+    const int qr = lane >> 4;                             // lane row of the column
+    // (lv, la) followed by (rv, ra): the later one wins only if strictly
+    // greater; (-inf, INT32_MAX) is the empty prefix
+    // Without positions (no argmax asked for) only the values are kept:
+    // the empty prefix is -inf, which any value replaces or equals.
+    auto comb = [](float lv, int32_t la, float rv, int32_t ra, float& ov, int32_t& oa) {
+      if constexpr (kArg) {
+        const bool take = rv > lv || la == INT32_MAX;
+        ov = take ? rv : lv;
+        oa = take ? ra : la;
+      } else {
+        ov = rv > lv ? rv : lv;
+        oa = 0;
+      }
+    };
+    auto any_start = [&](int r0s, int n) { return ((sm >> r0s) & ((1u << n) - 1u)) != 0u; };
+    // carry into the first row
+    float cv = open_in ? mS : -INFINITY;
+    int32_t ca = open_in ? mArg : INT32_MAX;
+    float fv[8];                                         // per row: run max so far
+    int32_t fa[8];                                       // ... and its first maximiser
+#pragma unroll
+    for (int set = 0; set < 2; ++set) {
+      const int base = 16 * set;
+      float sv[4];
+      int32_t sa[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {                      // in-lane scan of the block
+        const int r = base + q4 + i;
+        const float y = set ? acc1[i] : acc0[i];
+        const int32_t pos = (int32_t)(e0 + r);
+        if (i == 0) {
+          sv[0] = y;
+          sa[0] = pos;
+        } else {
+          comb(sv[i - 1], sa[i - 1], y, pos, sv[i], sa[i]);
+          const bool st = (sm >> r) & 1u;
+          sv[i] = st ? y : sv[i];
+          sa[i] = st ? pos : sa[i];
+        }
+      }
+      // block tails across the lane rows: pairs (0,1), (2,3), then halves
+      const float tv = sv[3];
+      const int32_t ta = sa[3];
+      const auto p16v = __builtin_amdgcn_permlane16_swap(__float_as_uint(tv), __float_as_uint(tv), false, false);
+      const auto p16a = __builtin_amdgcn_permlane16_swap((uint32_t)ta, (uint32_t)ta, false, false);
+      const bool odd = qr & 1;
+      // the pair partner's tail (rows 0 <-> 1, 2 <-> 3)
+      const float xv = __uint_as_float(odd ? p16v[0] : p16v[1]);
+      const int32_t xa = (int32_t)(odd ? p16a[0] : p16a[1]);
+      const int pr = base + 4 * (qr & 2);                // first row of this lane's pair
+      // pair total: the later block's tail if it holds a start
+      float pv;
+      int32_t pa;
+      {
+        const float lv = odd ? xv : tv, rv = odd ? tv : xv;
+        const int32_t la = odd ? xa : ta, ra = odd ? ta : xa;
+        comb(lv, la, rv, ra, pv, pa);
+        const bool rf = any_start(pr + 4, 4);
+        pv = rf ? rv : pv;
+        pa = rf ? ra : pa;
+      }
+      const auto p32v = __builtin_amdgcn_permlane32_swap(__float_as_uint(pv), __float_as_uint(pv), false, false);
+      const auto p32a = __builtin_amdgcn_permlane32_swap((uint32_t)pa, (uint32_t)pa, false, false);
+      const bool hi = qr & 2;
+      const float ov = __uint_as_float(hi ? p32v[0] : p32v[1]);    // the other pair's total
+      const int32_t oa = (int32_t)(hi ? p32a[0] : p32a[1]);
+      // prefix of the blocks before this lane's block
+      float ev = -INFINITY;
+      int32_t ea = INT32_MAX;
+      if (qr == 1) {
+        ev = xv;
+        ea = xa;
+      } else if (qr == 2) {
+        ev = ov;
+        ea = oa;
+      } else if (qr == 3) {                              // pair (0,1), then block 2
+        comb(ov, oa, xv, xa, ev, ea);
+        const bool f2 = any_start(base + 8, 4);
+        ev = f2 ? xv : ev;
+        ea = f2 ? xa : ea;
+      }
+      // carry into this block: the set's carry, then that prefix
+      float kv;
+      int32_t ka;
+      comb(cv, ca, ev, ea, kv, ka);
+      const bool pf = any_start(base, q4);               // a start in an earlier block of the set
+      kv = pf ? ev : kv;
+      ka = pf ? ea : ka;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {                      // rows before the block's first start
+        float v;
+        int32_t ag;
+        comb(kv, ka, sv[i], sa[i], v, ag);
+        const bool own = any_start(base + q4, i + 1);
+        fv[4 * set + i] = own ? sv[i] : v;
+        fa[4 * set + i] = own ? sa[i] : ag;
+      }
+      // carry into the next set: the whole set after the current carry
+      float tot_v;
+      int32_t tot_a;
+      {
+        const float lv = hi ? ov : pv, rv = hi ? pv : ov;
+        const int32_t la = hi ? oa : pa, ra = hi ? pa : oa;
+        comb(lv, la, rv, ra, tot_v, tot_a);
+        const bool rf = any_start(base + 8, 8);
+        tot_v = rf ? rv : tot_v;
+        tot_a = rf ? ra : tot_a;
+      }
+      float nv2;
+      int32_t na2;
+      comb(cv, ca, tot_v, tot_a, nv2, na2);
+      const bool sf = any_start(base, 16);
+      cv = sf ? tot_v : nv2;
+      ca = sf ? tot_a : na2;
+    }
+    // outputs: rows that end a run
+    const uint32_t first_run_rows = (sm & ~1u) == 0u ? 0xffffffffu : ((sm & ~1u) & (0u - (sm & ~1u))) - 1u;
+    const bool cut0 = prev_same && (open_in ? mCut : true);
+    // Rows that end a run (a wave-uniform mask).  Row r lives in the lanes
+    // of lane row (r % 16) / 4, register (r % 4) + 4 (r / 16).  The ends
+    // are visited one by one, so the cost follows the number of runs.
+    const uint32_t valid = nv >= 32 ? 0xffffffffu : ((1u << nv) - 1u);
+    const uint32_t ends = ((runs >> 1) | (1u << (nv - 1))) & valid;
+    const uint32_t last_bit = 1u << (nv - 1);
+    const uint32_t first_end = ends & (0u - ends);       // end of the first run
+    auto row_val = [&](int r, float& v, int32_t& ag) {
+      const int i = (r & 3) + ((r >> 2) & 4);
+      v = fv[0];
+      ag = fa[0];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        v = i == k ? fv[k] : v;
+        ag = i == k ? fa[k] : ag;
+      }
+    };
+    const bool has_pre = a.sink.pre != nullptr, has_arg = a.sink.argmax != nullptr;
+    const bool obf = a.sink.out_bf16;
+    uint32_t plain = ends & ~(next_same ? last_bit : 0u) & ~(cut0 ? first_end : 0u);
+    while (plain) {                                      // finished inside the tile
+      const int r = __builtin_ctz(plain);
+      plain &= plain - 1u;
+      float v;
+      int32_t ag;
+      row_val(r, v, ag);
+      const int32_t gid = __builtin_amdgcn_readlane(gcur, r);
+      if (qr == ((r >> 2) & 3)) {
+        const int64_t o = (int64_t)gid * h + col;
+        if (has_pre) a.sink.pre[o] = v;
+        if (kArg && has_arg) a.sink.argmax[o] = ag;
+        const float w = act_apply(a.sink.act_post, v);
+        if (obf)
+          reinterpret_cast<__bf16*>(a.sink.out)[o] = (__bf16)w;
+        else
+          a.sink.out[o] = w;
+      }
+    }
+    // the first run, cut by the range start, and the last one, running
+    // past the range end, leave partials in the block's carry slots
+    const bool first_cut = cut0 && !(first_end == last_bit && keep_open);
+    const bool last_out = next_same && !keep_open && !(cut0 && first_end == last_bit);
+    if (first_cut || last_out) {
+      float v;
+      int32_t ag;
+      if (first_cut) {
+        const int r = __builtin_ctz(first_end);
+        row_val(r, v, ag);
+        if (qr == ((r >> 2) & 3)) {
+          a.carry[slot_base] = v;
+          if (a.carry_arg) a.carry_arg[slot_base] = kArg ? ag : 0;
+        }
+      }
+      if (last_out) {
+        const int r = nv - 1;
+        row_val(r, v, ag);
+        if (qr == ((r >> 2) & 3)) {
+          a.carry[slot_base + h] = v;
+          if (a.carry_arg) a.carry_arg[slot_base + h] = kArg ? ag : 0;
+        }
+      }
+    }
+    if (keep_open) {                                     // row nv-1 to every lane row of the column
+      const int rl = nv - 1, ql = (rl & 15) >> 2, il = (rl & 3) + (rl >= 16 ? 4 : 0);
+      float v = fv[0];
+      int32_t ag = fa[0];
+#pragma unroll
+      for (int i = 1; i < 8; ++i) {
+        v = il == i ? fv[i] : v;
+        ag = il == i ? fa[i] : ag;
+      }
+      const auto s16v = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+      const auto s16a = __builtin_amdgcn_permlane16_swap((uint32_t)ag, (uint32_t)ag, false, false);
+      if ((qr & 1) != (ql & 1)) {
+        v = __uint_as_float((qr & 1) ? s16v[0] : s16v[1]);
+        ag = (int32_t)((qr & 1) ? s16a[0] : s16a[1]);
+      }
+      const auto s32v = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+      const auto s32a = __builtin_amdgcn_permlane32_swap((uint32_t)ag, (uint32_t)ag, false, false);
+      if ((qr & 2) != (ql & 2)) {
+        v = __uint_as_float((qr & 2) ? s32v[0] : s32v[1]);
+        ag = (int32_t)((qr & 2) ? s32a[0] : s32a[1]);
+      }
+      mS = v;
+      mArg = ag;
+      mCut = ((first_run_rows >> rl) & 1u) && cut0;
+    }
+  };
+  // MAX with more than 4 compute waves: waves 4.. (which share SIMDs with
+  // waves 0..3) reduce each tile one iteration late, before the products of
+  // the next one, so that on every SIMD one wave runs the scan while the
+  // other keeps the matrix core busy.  Only the group numbers are read from
+  // the tile's index slot, and they move to the next iteration in a
+  // register.
+  // (not for FP32 tiles 384 wide, whose W slice leaves no registers for
+  // the late tile's products)
+  constexpr bool kLag = kMax && !(std::is_same<T, float>::value && KP >= 384);
+  const bool lag = kLag && ncw > 4 && wave >= 4;
+  f32x4 lacc0 = {0.f, 0.f, 0.f, 0.f}, lacc1 = lacc0;
+  int32_t lgcur = 0;
+
   compute_barrier();                                         // (index slots staged)
   compute_barrier();                                         // tile tb is in LDS
   int rr = 0, ri = 0;                                        // ring tile, index slot of t
   for (int64_t t = tb; t < te; ++t) {
+    if constexpr (kMax) {
+      if (lag && t > tb) max_tile(t - 1, lacc0, lacc1, lgcur);
+    }
     const int32_t* gsl = reinterpret_cast<const int32_t*>(irs + ri * G::IRB);
     // MAX: group numbers of tile t (lane r < 32 row r, clamped; lane 32 the
     // row before the tile, lane 33 the row after it).  SUM / MEAN: the run
@@ -943,238 +1190,19 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
         }
       }
       off = (off + nr - 1) & 15;
+    } else if (lag) {                  // reduced in the next iteration
+      lacc0 = acc0;
+      lacc1 = acc1;
+      lgcur = gcur;
     } else {
-      // ---- MAX: a segmented max-scan of the tile, whose cost does not
-      // depend on the number of runs.  A lane holds rows q4 .. q4+3 (acc0)
-      // and 16+q4 .. (acc1) of its column: each 4-row block is scanned in
-      // the lane, the block tails across the column's 4 lane rows with two
-      // row swaps (whether a block holds a run start follows from the
-      // wave-uniform start mask, so only values and positions move), and
-      // every row then holds the max of its run up to that row and the
-      // run's first maximiser.  The rows that end a run write it.
-      const int nv = (int)min<int64_t>(TM, a.E - e0);
-      const int32_t gup = __builtin_amdgcn_update_dpp(0, gcur, 0x138, 0xf, 0xf, false);
-      const bool start = lane < nv && (lane == 0 || gup != gcur);
-      const uint32_t runs = (uint32_t)__ballot(start);
-      const int32_t g_first = __builtin_amdgcn_readlane(gcur, 0);
-      const int32_t g_last = __builtin_amdgcn_readlane(gcur, nv - 1);
-      const int32_t g_before = __builtin_amdgcn_readlane(gcur, 32);
-      const int32_t g_after = __builtin_amdgcn_readlane(gcur, 33);
-      const bool prev_same = e0 > 0 && g_before == g_first;
-      const bool next_same = e0 + nv < a.E && g_after == g_last;
-      const bool keep_open = next_same && e0 + nv < range_hi;
-      const bool open_in = prev_same && t > tb;            // row 0 continues the block's open group
-      const uint32_t sm = open_in ? (runs & ~1u) : runs;   // starts as the scan sees them
-      const int qr = lane >> 4;                             // lane row of the column
-      // (lv, la) followed by (rv, ra): the later one wins only if strictly
-      // greater; (-inf, INT32_MAX) is the empty prefix
-      // Without positions (no argmax asked for) only the values are kept:
-      // the empty prefix is -inf, which any value replaces or equals.
-      auto comb = [](float lv, int32_t la, float rv, int32_t ra, float& ov, int32_t& oa) {
-        if constexpr (kArg) {
-          const bool take = rv > lv || la == INT32_MAX;
-          ov = take ? rv : lv;
-          oa = take ? ra : la;
-        } else {
-          ov = rv > lv ? rv : lv;
-          oa = 0;
-        }
-      };
-      auto any_start = [&](int r0s, int n) { return ((sm >> r0s) & ((1u << n) - 1u)) != 0u; };
-      // carry into the first row
-      float cv = open_in ? mS : -INFINITY;
-      int32_t ca = open_in ? mArg : INT32_MAX;
-      float fv[8];                                         // per row: run max so far
-      int32_t fa[8];                                       // ... and its first maximiser
-#pragma unroll
-      for (int set = 0; set < 2; ++set) {
-        const int base = 16 * set;
-        float sv[4];
-        int32_t sa[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {                      // in-lane scan of the block
-          const int r = base + q4 + i;
-          const float y = set ? acc1[i] : acc0[i];
-          const int32_t pos = (int32_t)(e0 + r);
-          if (i == 0) {
-            sv[0] = y;
-            sa[0] = pos;
-          } else {
-            comb(sv[i - 1], sa[i - 1], y, pos, sv[i], sa[i]);
-            const bool st = (sm >> r) & 1u;
-            sv[i] = st ? y : sv[i];
-            sa[i] = st ? pos : sa[i];
-          }
-        }
-        // block tails across the lane rows: pairs (0,1), (2,3), then halves
-        const float tv = sv[3];
-        const int32_t ta = sa[3];
-        const auto p16v = __builtin_amdgcn_permlane16_swap(__float_as_uint(tv), __float_as_uint(tv), false, false);
-        const auto p16a = __builtin_amdgcn_permlane16_swap((uint32_t)ta, (uint32_t)ta, false, false);
-        const bool odd = qr & 1;
-        // the pair partner's tail (rows 0 <-> 1, 2 <-> 3)
-        const float xv = __uint_as_float(odd ? p16v[0] : p16v[1]);
-        const int32_t xa = (int32_t)(odd ? p16a[0] : p16a[1]);
-        const int pr = base + 4 * (qr & 2);                // first row of this lane's pair
-        // pair total: the later block's tail if it holds a start
-        float pv;
-        int32_t pa;
-        {
-          const float lv = odd ? xv : tv, rv = odd ? tv : xv;
-          const int32_t la = odd ? xa : ta, ra = odd ? ta : xa;
-          comb(lv, la, rv, ra, pv, pa);
-          const bool rf = any_start(pr + 4, 4);
-          pv = rf ? rv : pv;
-          pa = rf ? ra : pa;
-        }
-        const auto p32v = __builtin_amdgcn_permlane32_swap(__float_as_uint(pv), __float_as_uint(pv), false, false);
-        const auto p32a = __builtin_amdgcn_permlane32_swap((uint32_t)pa, (uint32_t)pa, false, false);
-        const bool hi = qr & 2;
-        const float ov = __uint_as_float(hi ? p32v[0] : p32v[1]);    // the other pair's total
-        const int32_t oa = (int32_t)(hi ? p32a[0] : p32a[1]);
-        // prefix of the blocks before this lane's block
-        float ev = -INFINITY;
-        int32_t ea = INT32_MAX;
-        if (qr == 1) {
-          ev = xv;
-          ea = xa;
-        } else if (qr == 2) {
-          ev = ov;
-          ea = oa;
-        } else if (qr == 3) {                              // pair (0,1), then block 2
-          comb(ov, oa, xv, xa, ev, ea);
-          const bool f2 = any_start(base + 8, 4);
-          ev = f2 ? xv : ev;
-          ea = f2 ? xa : ea;
-        }
-        // carry into this block: the set's carry, then that prefix
-        float kv;
-        int32_t ka;
-        comb(cv, ca, ev, ea, kv, ka);
-        const bool pf = any_start(base, q4);               // a start in an earlier block of the set
-        kv = pf ? ev : kv;
-        ka = pf ? ea : ka;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {                      // rows before the block's first start
-          float v;
-          int32_t ag;
-          comb(kv, ka, sv[i], sa[i], v, ag);
-          const bool own = any_start(base + q4, i + 1);
-          fv[4 * set + i] = own ? sv[i] : v;
-          fa[4 * set + i] = own ? sa[i] : ag;
-        }
-        // carry into the next set: the whole set after the current carry
-        float tot_v;
-        int32_t tot_a;
-        {
-          const float lv = hi ? ov : pv, rv = hi ? pv : ov;
-          const int32_t la = hi ? oa : pa, ra = hi ? pa : oa;
-          comb(lv, la, rv, ra, tot_v, tot_a);
-          const bool rf = any_start(base + 8, 8);
-          tot_v = rf ? rv : tot_v;
-          tot_a = rf ? ra : tot_a;
-        }
-        float nv2;
-        int32_t na2;
-        comb(cv, ca, tot_v, tot_a, nv2, na2);
-        const bool sf = any_start(base, 16);
-        cv = sf ? tot_v : nv2;
-        ca = sf ? tot_a : na2;
-      }
-      // outputs: rows that end a run
-      const uint32_t first_run_rows = (sm & ~1u) == 0u ? 0xffffffffu : ((sm & ~1u) & (0u - (sm & ~1u))) - 1u;
-      const bool cut0 = prev_same && (open_in ? mCut : true);
-      // Rows that end a run (a wave-uniform mask).  Row r lives in the lanes
-      // of lane row (r % 16) / 4, register (r % 4) + 4 (r / 16).  The ends
-      // are visited one by one, so the cost follows the number of runs.
-      const uint32_t valid = nv >= 32 ? 0xffffffffu : ((1u << nv) - 1u);
-      const uint32_t ends = ((runs >> 1) | (1u << (nv - 1))) & valid;
-      const uint32_t last_bit = 1u << (nv - 1);
-      const uint32_t first_end = ends & (0u - ends);       // end of the first run
-      auto row_val = [&](int r, float& v, int32_t& ag) {
-        const int i = (r & 3) + ((r >> 2) & 4);
-        v = fv[0];
-        ag = fa[0];
-#pragma unroll
-        for (int k = 1; k < 8; ++k) {
-          v = i == k ? fv[k] : v;
-          ag = i == k ? fa[k] : ag;
-        }
-      };
-      const bool has_pre = a.sink.pre != nullptr, has_arg = a.sink.argmax != nullptr;
-      const bool obf = a.sink.out_bf16;
-      uint32_t plain = ends & ~(next_same ? last_bit : 0u) & ~(cut0 ? first_end : 0u);
-      while (plain) {                                      // finished inside the tile
-        const int r = __builtin_ctz(plain);
-        plain &= plain - 1u;
-        float v;
-        int32_t ag;
-        row_val(r, v, ag);
-        const int32_t gid = __builtin_amdgcn_readlane(gcur, r);
-        if (qr == ((r >> 2) & 3)) {
-          const int64_t o = (int64_t)gid * h + col;
-          if (has_pre) a.sink.pre[o] = v;
-          if (kArg && has_arg) a.sink.argmax[o] = ag;
-          const float w = act_apply(a.sink.act_post, v);
-          if (obf)
-            reinterpret_cast<__bf16*>(a.sink.out)[o] = (__bf16)w;
-          else
-            a.sink.out[o] = w;
-        }
-      }
-      // the first run, cut by the range start, and the last one, running
-      // past the range end, leave partials in the block's carry slots
-      const bool first_cut = cut0 && !(first_end == last_bit && keep_open);
-      const bool last_out = next_same && !keep_open && !(cut0 && first_end == last_bit);
-      if (first_cut || last_out) {
-        float v;
-        int32_t ag;
-        if (first_cut) {
-          const int r = __builtin_ctz(first_end);
-          row_val(r, v, ag);
-          if (qr == ((r >> 2) & 3)) {
-            a.carry[slot_base] = v;
-            if (a.carry_arg) a.carry_arg[slot_base] = kArg ? ag : 0;
-          }
-        }
-        if (last_out) {
-          const int r = nv - 1;
-          row_val(r, v, ag);
-          if (qr == ((r >> 2) & 3)) {
-            a.carry[slot_base + h] = v;
-            if (a.carry_arg) a.carry_arg[slot_base + h] = kArg ? ag : 0;
-          }
-        }
-      }
-      if (keep_open) {                                     // row nv-1 to every lane row of the column
-        const int rl = nv - 1, ql = (rl & 15) >> 2, il = (rl & 3) + (rl >= 16 ? 4 : 0);
-        float v = fv[0];
-        int32_t ag = fa[0];
-#pragma unroll
-        for (int i = 1; i < 8; ++i) {
-          v = il == i ? fv[i] : v;
-          ag = il == i ? fa[i] : ag;
-        }
-        const auto s16v = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-        const auto s16a = __builtin_amdgcn_permlane16_swap((uint32_t)ag, (uint32_t)ag, false, false);
-        if ((qr & 1) != (ql & 1)) {
-          v = __uint_as_float((qr & 1) ? s16v[0] : s16v[1]);
-          ag = (int32_t)((qr & 1) ? s16a[0] : s16a[1]);
-        }
-        const auto s32v = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-        const auto s32a = __builtin_amdgcn_permlane32_swap((uint32_t)ag, (uint32_t)ag, false, false);
-        if ((qr & 2) != (ql & 2)) {
-          v = __uint_as_float((qr & 2) ? s32v[0] : s32v[1]);
-          ag = (int32_t)((qr & 2) ? s32a[0] : s32a[1]);
-        }
-        mS = v;
-        mArg = ag;
-        mCut = ((first_run_rows >> rl) & 1u) && cut0;
-      }
+      max_tile(t, acc0, acc1, gcur);
     }
     rr = wrap(rr + 1, NB);
     ri = wrap(ri + 1, G::NIR);
     compute_barrier();
+  }
+  if constexpr (kMax) {
+    if (lag) max_tile(te - 1, lacc0, lacc1, lgcur);
   }
 }
 
