@@ -1,7 +1,7 @@
 // Backward of a relational layer through sums over groups and over joined
 // rows.  With dY_tau the gradient of tuple tau's transformed value
 // (dA_g = dout_g * act_post'(pre_g), divided by |g| for MEAN; routed to the
-// argmax tuple per column for MAX; masked by act_pre' when act_pre is
+// maximiser tuple per column for MAX; masked by act_pre' when act_pre is
 // ReLU), the map from x_tau to y_tau is affine, so for every layer
 //
 //   dz_j[r] += (sum_{tau joined to row r} dY_tau) W_j^T  =  DS_j[r] W_j^T
@@ -44,7 +44,8 @@ struct GsArgs {
   int64_t ntiles, nunits;
   // routing of a gathered gradient row (one atom, dA of width h; rows[0] is
   // the group of the tuple at each position, rows[1] its canonical position)
-  const int32_t* argmax;           // [G][h]: keep column c only where argmax == tuple (MAX)
+  const uint32_t* own;             // [E][own_w] bits: keep column c only where the tuple owns it (MAX)
+  int own_w;
   const uint8_t* mask;             // [E][h]: act_pre' of the tuple
 };
 
@@ -160,21 +161,13 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
             row = A.j == j ? rj : row;
           }
           v[i] = gs_load<VW>(a, A, row, on ? col : 0);
-          if (a.argmax || a.mask) {                     // route the gradient row of this tuple
+          if (a.own || a.mask) {                        // route the gradient row of this tuple
             const int32_t tau = __builtin_amdgcn_readlane(R[1], q);
-            if (a.argmax) {
-              const int32_t* ap = a.argmax + (int64_t)row * a.d[0] + (on ? col : 0);
-              if constexpr (VW == 4) {
-                const int4 am = *reinterpret_cast<const int4*>(ap);
-                v[i][0] = am.x == tau ? v[i][0] : 0.0f;
-                v[i][1] = am.y == tau ? v[i][1] : 0.0f;
-                v[i][2] = am.z == tau ? v[i][2] : 0.0f;
-                v[i][3] = am.w == tau ? v[i][3] : 0.0f;
-              } else {
-                const int2 am = *reinterpret_cast<const int2*>(ap);
-                v[i][0] = am.x == tau ? v[i][0] : 0.0f;
-                v[i][1] = am.y == tau ? v[i][1] : 0.0f;
-              }
+            if (a.own) {                                // VW columns of one 32-column word
+              const int cc = on ? col : 0;
+              const uint32_t bits = a.own[(int64_t)tau * a.own_w + (cc >> 5)] >> (cc & 31);
+#pragma unroll
+              for (int x = 0; x < VW; ++x) v[i][x] = ((bits >> x) & 1u) ? v[i][x] : 0.0f;
             }
             if (a.mask) {
               const uint8_t* mp = a.mask + (int64_t)tau * a.d[0] + (on ? col : 0);
@@ -361,7 +354,7 @@ void lin_bwd_dw(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
 }
 
 void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdPlan& P, const void* W,
-                const float* dA, const int32_t* argmax, const uint8_t* mask, float* const* demb, char* w,
+                const float* dA, const uint32_t* own, int own_w, const uint8_t* mask, float* const* demb, char* w,
                 hipStream_t s) {
   const int h = L->h;
   const int64_t E = idx->E;
@@ -375,7 +368,7 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
     RELNN_LAUNCHED();
     W32 = w32;
   }
-  const bool routed = argmax != nullptr || mask != nullptr;
+  const bool routed = own != nullptr || mask != nullptr;
   // dz_j = DS_j W_j^T, added into the rows of atom j
   for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
     const int d = L->d[j];
@@ -400,7 +393,8 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
     a.out = ds;
     a.ldo = h;
     a.carry = reinterpret_cast<float*>(w + P.ws_carry);
-    a.argmax = argmax;
+    a.own = own;
+    a.own_w = own_w;
     a.mask = mask;
     seg_gather_sum(a, P.units, s);
     // DZ [nseg][d] = DS [nseg][h] W_j^T, W_j = rows koff.. of W ([d][h]):

@@ -46,6 +46,36 @@ __device__ __forceinline__ float route(const Route& R, int64_t e, int64_t g, int
   return v;
 }
 
+// MAX routing as bits: bit c % 32 of word c / 32 of tuple t is set where t
+// is its group's maximiser in column c (argmax[g][c] == t).  The argmax row
+// of a group is read by its consecutive tuples (from L2 after the first),
+// and the sums over joined rows then read 4 bytes per 32 columns of a tuple
+// instead of its argmax row.
+__global__ void k_own_bits(const int32_t* argmax, const int32_t* tuple_group, int64_t E, int h, int nw,
+                           uint32_t* own) {
+  const bool vec = (h & 31) == 0 && (((uintptr_t)argmax) & 15) == 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E * nw;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = i / nw;
+    const int w = (int)(i - t * nw);
+    const int32_t* am = argmax + (int64_t)tuple_group[t] * h + 32 * w;
+    const int32_t tt = (int32_t)t;
+    uint32_t bits = 0;
+    if (vec) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int4 v = reinterpret_cast<const int4*>(am)[q];
+        bits |= (uint32_t)(v.x == tt) << (4 * q) | (uint32_t)(v.y == tt) << (4 * q + 1) |
+                (uint32_t)(v.z == tt) << (4 * q + 2) | (uint32_t)(v.w == tt) << (4 * q + 3);
+      }
+    } else {
+      const int nb = min(32, h - 32 * w);
+      for (int b = 0; b < nb; ++b) bits |= (uint32_t)(am[b] == tt) << b;
+    }
+    own[i] = bits;
+  }
+}
+
 // dA[g][n] = dout[g][n] * act_post'(pre[g][n]) (ReLU'(0) = 0), divided by
 // the group's tuple count for MEAN: the per-group part of the routing.
 __global__ void k_route_prep(const float* dout, const float* pre, const int32_t* offsets, int64_t G, int h, int agg,
@@ -394,7 +424,7 @@ struct BwdPlan {
   int K = 0, K16 = 0, hn = 0, ncb = 1;
   int64_t dw_tiles = 0, dw_units = 0;
   size_t dw_lds = 0;
-  size_t ws_mask = 0, ws_fwsw = 0, ws_part = 0, ws_dbpart = 0, ws_dA = 0, total = 0;
+  size_t ws_mask = 0, ws_fwsw = 0, ws_part = 0, ws_dbpart = 0, ws_dA = 0, ws_own = 0, total = 0;
   bool xs_dw = false;        // dW through the per-group sums (SUM / MEAN, affine)
   LinBwdPlan lin;
 };
@@ -431,6 +461,8 @@ BwdPlan plan_bwd(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   }
   p.ws_dA = off;
   off += round_up(std::max<int64_t>(idx->G, 1) * L->h * 4, 256);
+  p.ws_own = off;                                        // MAX: ownership bits [E][ceil(h / 32)]
+  if (L->agg == RELNN_MAX) off += round_up(std::max<int64_t>(E, 1) * cdiv(L->h, 32) * 4, 256);
   p.lin = plan_lin_bwd(idx, L, off, p.xs_dw);
   p.total = p.lin.total;
   return p;
@@ -584,6 +616,13 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
     }
 
     // dz_j for every atom, in body order (through the per-row sums of dY)
-    lin_bwd_dx(idx, L, P.lin, W, dA, L->agg == RELNN_MAX ? argmax : nullptr, R.mask, demb, w, s);
+    uint32_t* own = nullptr;
+    const int nw = (int)cdiv(h, 32);
+    if (L->agg == RELNN_MAX) {
+      own = reinterpret_cast<uint32_t*>(w + P.ws_own);
+      k_own_bits<<<grid_for(E * nw), 256, 0, s>>>(argmax, idx->tuple_group, E, h, nw, own);
+      RELNN_LAUNCHED();
+    }
+    lin_bwd_dx(idx, L, P.lin, W, dA, own, nw, R.mask, demb, w, s);
   });
 }

@@ -107,8 +107,10 @@ struct LinBwdPlan {
 LinBwdPlan plan_lin_bwd(const relnn_index* idx, const relnn_layer_desc* L, size_t base, bool xs_dw);
 void lin_bwd_dw(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdPlan& P, const void* const* emb,
                 const float* dA, float* dW, float* db, bool accum, char* ws, hipStream_t s);
+// own: MAX routing bits [E][own_w] (bit c % 32 of word c / 32: the tuple is
+// its group's maximiser in column c), or null
 void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdPlan& P, const void* W,
-                const float* dA, const int32_t* argmax, const uint8_t* mask, float* const* demb, char* ws,
+                const float* dA, const uint32_t* own, int own_w, const uint8_t* mask, float* const* demb, char* ws,
                 hipStream_t s);
 size_t bwd_workspace(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P);
 
