@@ -140,7 +140,9 @@ class Layer:
     def torch_dtype(self):
         return _DTYPES[self.dtype][1]
 
-    def desc(self, dw_accum=False) -> L.LayerDesc:
+    def desc(self, dw_accum=False, bwd=False) -> L.LayerDesc:
+        """The ABI descriptor; for the backward without the output-storage
+        flag (the backward reads pre and dout, not the stored output)."""
         d = L.LayerDesc()
         d.k = len(self.dims)
         d.d = self._d
@@ -150,13 +152,14 @@ class Layer:
         d.act_pre = _ACTS[self.act_pre]
         d.act_post = _ACTS[self.act_post]
         d.flags = ((L.PLAIN if self.plain else L.FUSED) | (L.DW_ACCUM if dw_accum else 0)
-                   | (L.OUT_BF16 if self.out_dtype == "bf16" else 0) | (L.PUSHDOWN if self.pushdown else 0))
+                   | (L.OUT_BF16 if self.out_dtype == "bf16" and not bwd else 0)
+                   | (L.PUSHDOWN if self.pushdown else 0))
         return d
 
 
 def workspace_size(index: Index, layer: Layer, bwd: bool = False) -> int:
     n = C.c_size_t()
-    d = layer.desc()
+    d = layer.desc(bwd=bwd)
     check(lib().relnn_workspace_size(index.handle, C.byref(d), int(bwd), C.byref(n)))
     return int(n.value)
 
@@ -207,13 +210,32 @@ def layer_bwd(index: Index, layer: Layer, embs: Sequence[torch.Tensor], W: torch
               ws: Optional[torch.Tensor] = None, stream=None):
     """relnn_layer_bwd.  demb entries are accumulated (+=) and may alias."""
     _check_embs(layer, embs)
+    G, h = index.G, layer.h
+
+    def f32(t, shape, what):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise TypeError(f"{what} must be a contiguous float32 CUDA tensor of shape {shape}")
+
+    f32(dout, (G, h), "dout")
+    f32(dW, (layer.K, h), "dW")
+    if db is not None:
+        f32(db, (h,), "db")
+    if pre is not None:
+        f32(pre, (G, h), "pre")
+    if argmax is not None and (argmax.dtype != torch.int32 or not argmax.is_contiguous()
+                               or tuple(argmax.shape) != (G, h)):
+        raise TypeError(f"argmax must be a contiguous int32 tensor of shape {(G, h)}")
+    if len(demb) != len(embs):
+        raise ValueError("one gradient buffer per atom is required")
+    for j, (g, e) in enumerate(zip(demb, embs)):
+        f32(g, tuple(e.shape), f"demb[{j}]")
     if ws is None:
         ws = workspace(index, layer, True)
     emb_arr = (C.c_void_p * len(embs))(*[e.data_ptr() for e in embs])
     demb_arr = (C.c_void_p * len(demb))(*[g.data_ptr() for g in demb])
-    d = layer.desc(dw_accum=dw_accum)
+    d = layer.desc(dw_accum=dw_accum, bwd=True)
     check(lib().relnn_layer_bwd(index.handle, C.byref(d), emb_arr, _vp(W), _vp(b), _vp(pre), _vp(argmax),
-                                _vp(dout.contiguous()), demb_arr, _vp(dW), _vp(db), _vp(ws), ws.numel(),
+                                _vp(dout), demb_arr, _vp(dW), _vp(db), _vp(ws), ws.numel(),
                                 _stream(stream)))
 
 
@@ -246,6 +268,8 @@ class RelLayerFn(torch.autograd.Function):
             else:
                 grads.append(None)
         demb = [bufs[e.data_ptr()] for e in embs]
+        # the ABI takes an FP32 gradient (a bf16 output receives a bf16 one)
+        dout = dout.to(torch.float32).contiguous()
         dW = torch.empty(layer.K, layer.h, dtype=torch.float32, device=dev)
         db = torch.empty(layer.h, dtype=torch.float32, device=dev) if b is not None else None
         layer_bwd(index, layer, embs, W, b, pre, am, dout, demb, dW, db)

@@ -185,3 +185,73 @@ def test_autograd_two_layer_power_net():
     assert fro(W1.grad.cpu().numpy(), dW1) <= 1e-5
     assert fro(b1.grad.cpu().numpy(), db1) <= 1e-5
     assert row_err(z.grad.cpu().numpy(), d1[0] + d1[1]).max() <= 1e-5
+
+
+def test_autograd_bf16_chain_matches_explicit_calls():
+    """BF16 two-layer net through RelLayerFn: layer 1 writes a bf16 output
+    that layer 2 reads, so autograd hands layer 1 a bf16 gradient, which the
+    binding widens to the FP32 gradient the ABI takes.  The gradients equal,
+    bit for bit, those of explicit layer_fwd / layer_bwd calls that apply the
+    same rounding (the per-layer BF16 arithmetic is checked against the
+    oracle by the tests above)."""
+    import torch
+
+    from paper_2605_24207_amd import Index, Layer, RelLayerFn, layer_bwd, layer_fwd
+
+    p = relgen.power_graph(seed=7, n_nodes=2000, n_edges=10_000, d=128, h=128)
+    dev = "cuda"
+    s = torch.from_numpy(p.s).to(dev)
+    t = torch.from_numpy(p.t).to(dev)
+    n = p.z.shape[0]
+    ix1 = Index([s, t], [(n, 0, None), (n, 1, None)], 1, bwd=True)
+    keys1 = ix1.export()["group_keys"]
+    ix2 = Index([s, t], [(ix1.G, 0, keys1), (ix1.G, 1, keys1)], 1, bwd=True)
+    L1 = Layer([128, 128], 128, "bf16", "sum", "none", "relu", out_dtype="bf16")
+    L2 = Layer([128, 128], 128, "bf16", "max", "none", "none")
+    bf = lambda a: torch.from_numpy(a).to(dev).to(torch.bfloat16)
+    z0, W10, W20 = bf(p.z), bf(p.W[0]), bf(p.W[1])
+    b10 = torch.from_numpy(p.b[0]).to(dev)
+    b20 = torch.from_numpy(p.b[1]).to(dev)
+    C = torch.from_numpy(np.random.default_rng(5).standard_normal((ix2.G, 128)).astype(np.float32)).to(dev)
+
+    z, W1, W2 = (x.clone().requires_grad_(True) for x in (z0, W10, W20))
+    b1, b2 = (x.clone().requires_grad_(True) for x in (b10, b20))
+    h1 = RelLayerFn.apply(ix1, L1, W1, b1, z, z)
+    h2 = RelLayerFn.apply(ix2, L2, W2, b2, h1, h1)
+    assert h1.dtype == torch.bfloat16 and h2.dtype == torch.float32
+    (h2 * C).sum().backward()
+
+    o1, pre1, am1 = layer_fwd(ix1, L1, [z0, z0], W10, b10)
+    o2, pre2, am2 = layer_fwd(ix2, L2, [o1, o1], W20, b20)
+    dh1 = torch.zeros(o1.shape, dtype=torch.float32, device=dev)
+    dW2 = torch.empty(256, 128, device=dev)
+    db2 = torch.empty(128, device=dev)
+    layer_bwd(ix2, L2, [o1, o1], W20, b20, pre2, am2, C, [dh1, dh1], dW2, db2)
+    dout1 = dh1.to(torch.bfloat16).to(torch.float32)          # the gradient of a bf16 tensor
+    dz = torch.zeros(z0.shape, dtype=torch.float32, device=dev)
+    dW1 = torch.empty(256, 128, device=dev)
+    db1 = torch.empty(128, device=dev)
+    layer_bwd(ix1, L1, [z0, z0], W10, b10, pre1, am1, dout1, [dz, dz], dW1, db1)
+    torch.cuda.synchronize()
+    assert torch.equal(h2.detach(), o2)
+    assert torch.equal(W2.grad, dW2.to(torch.bfloat16)) and torch.equal(b2.grad, db2)
+    assert torch.equal(W1.grad, dW1.to(torch.bfloat16)) and torch.equal(b1.grad, db1)
+    assert torch.equal(z.grad, dz.to(torch.bfloat16))
+
+
+def test_backward_rejects_wrong_gradient_dtype():
+    """The ABI reads dout as FP32: another dtype is refused, not reinterpreted."""
+    import torch
+
+    from paper_2605_24207_amd import layer_bwd, layer_fwd
+
+    rule = relgen.node_edge(agg="sum")
+    gi = gpu_index(rule, bwd=True)
+    layer = gpu_layer(rule, "f32")
+    embs = distinct_embs(rule, "f32")
+    W, b = to_dev(rule.W), to_dev(rule.b)
+    out, pre, am = layer_fwd(gi, layer, embs, W, b)
+    dz = torch.zeros_like(embs[0])
+    with pytest.raises(TypeError, match="dout"):
+        layer_bwd(gi, layer, [embs[0], embs[0]], W, b, pre, am, out.to(torch.bfloat16), [dz, dz],
+                  torch.empty_like(W), torch.empty_like(b))
