@@ -188,8 +188,9 @@ relnn_status relnn_workspace_size(const relnn_index* idx, const relnn_layer_desc
  * group_keys[q].  pre: device
  * [G, h] FP32 aggregate before act_post, or NULL (needed by the backward
  * when act_post != NONE).  argmax: device [G, h] int32 canonical tuple
- * position of the first maximiser, MAX only, or NULL.  ws: device
- * workspace of relnn_workspace_size(.., 0) bytes. */
+ * position of the first maximiser, MAX only, or NULL (then the fused
+ * kernels track values only; out and pre are the same bit for bit).  ws:
+ * device workspace of relnn_workspace_size(.., 0) bytes. */
 relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_layer_desc* L,
                              const void* const* emb, const void* W, const float* b,
                              float* out, float* pre, int32_t* argmax,
