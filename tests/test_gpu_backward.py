@@ -125,6 +125,13 @@ def test_bwd_er_three_atoms(dtype):
     check(relgen.er_user_rule(g), dtype)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_bwd_max_width_not_multiple_of_32(dtype):
+    """MAX routing bits with a partial last word (h = 48: 32 + 16 columns)."""
+    rule = relgen.node_edge(seed=24, d=32, h=48, agg="max", act_post="relu", bias_std=0.3)
+    check(rule, dtype)
+
+
 def test_bwd_dw_accumulate():
     check(relgen.node_edge(seed=22, agg="mean", bias_std=0.2), "f32", dw_accum=True)
 
