@@ -7,16 +7,16 @@
 // with the earliest maximiser), so a block leaves at most two partials, for
 // the groups cut by its range ends; k_fixup combines those in block order.
 //
-// k_fwd_dma (FP32 and BF16; one instance for SUM/MEAN and one for MAX) has
-// two kinds of waves:
-//  * h/16 compute waves, 16 output columns each, whose W slice stays in
-//    VGPRs for the whole kernel.  They multiply a tile on the matrix cores
-//    (f32 16x16x4 or bf16 16x16x32, FP32 accumulation) and reduce it per
-//    group straight from the accumulators: a lane holds 8 rows of one
-//    column; for each run of equal group the rows of the run are kept by a
-//    bit mask (no per-row branch), summed per lane and across the 4 lanes of
-//    the column by two row swaps, and the group left open at the end of a
-//    tile stays in registers for the next one.
+// k_fwd_dma (FP32 and BF16; SUM/MEAN and MAX instances) has two kinds of
+// waves:
+//  * compute waves for up to 128 output columns (16 each, or 32 for BF16
+//    SUM/MEAN), whose W slice stays in VGPRs for the whole kernel.  They
+//    multiply a tile on the matrix cores (f32 16x16x4 or bf16 16x16x32,
+//    FP32 accumulation) and reduce it per group straight from the
+//    accumulators: SUM/MEAN as one more matrix product per accumulator
+//    register with the 0/1 row-in-run matrix, MAX as a segmented max-scan
+//    in registers.  The group left open at the end of a tile stays in
+//    registers for the next one.  Wider layers run as 128-column chunks.
 //  * 4 DMA waves that move tiles from HBM into an NB-deep LDS ring with
 //    16-byte global->LDS loads (no registers in between): while tile t is
 //    multiplied, tiles t+1 .. t+NB-2 are in flight and t+NB-1 is issued.
@@ -28,7 +28,8 @@
 // MFMA operand load fall into 16 different bank groups.
 // One barrier per tile.
 //
-// k_push (pushdown) keeps the LDS-staged reduce (ws_reduce).
+// k_push_sum (pushdown) is a segmented gather-sum of node products, one wave
+// per range of tuples.
 #include "layer_fwd.hpp"
 
 namespace relnn {
@@ -56,162 +57,11 @@ struct WsArgs {
   int32_t* carry_arg;
 };
 
-// Group structure of one tile, staged in LDS.
-struct TileInfo {
-  int32_t nv;                // tuples in the tile
-  int32_t nruns;             // runs of equal group
-  int32_t prev_same;         // the first run's group started before the tile
-  int32_t next_same;         // the last run's group continues after it
-  int32_t rstart[kTM + 1];   // first row of each run, rstart[nruns] = nv
-  int32_t rgrp[kTM];         // group of each run
-};
-
-// Running state of the group left open at the end of the previous tile
-// (double-buffered by tile parity), per output column.
-struct OpenState {
-  float s[2][kHMax];         // sum (or max)
-  float c[2][kHMax];         // Kahan compensation
-  int32_t arg[2][kHMax];     // argmax (MAX)
-  int32_t n[2][kHMax];       // tuples so far
-  int32_t cut[2][kHMax];     // the group started before the block's range
-  float bias[kHMax];         // b (zero if none), staged once per block
-};
-
-// Stages b in LDS so that the reduce issues no global load of its own
-// (such a load would wait for every gather load in flight before it).
-__device__ __forceinline__ void stage_bias(OpenState* op, const WsArgs& a, int tid, int nthr) {
-  for (int c = tid; c < a.h; c += nthr) op->bias[c] = a.b ? a.b[c] : 0.0f;
-}
-
 __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
   const float y = x - c;
   const float t = s + y;
   c = (t - s) - y;
   s = t;
-}
-
-// Group ids a wave needs to stage one tile: lane r < nv holds the group of
-// row r; lane 0 also holds the groups just before and after the tile (-1
-// at the ends of the list).
-struct SegLoad {
-  int32_t g, before, after;
-};
-
-__device__ __forceinline__ SegLoad seg_load(const WsArgs& a, int64_t t) {
-  const int lane = __lane_id();
-  const int64_t e0 = t * kTM;
-  const int nv = (int)min<int64_t>(kTM, a.E - e0);
-  SegLoad L{-1, -1, -1};
-  if (lane < nv) L.g = a.sg.seg_of[e0 + lane];
-  if (lane == 0) {
-    if (e0 > 0) L.before = a.sg.seg_of[e0 - 1];
-    if (e0 + nv < a.E) L.after = a.sg.seg_of[e0 + nv];
-  }
-  return L;
-}
-
-// Whole wave: turns the loaded group ids into runs (ballot of run starts).
-__device__ __forceinline__ void seg_stage(TileInfo* ti, const WsArgs& a, int64_t t, const SegLoad& L) {
-  const int lane = __lane_id();
-  const int nv = (int)min<int64_t>(kTM, a.E - t * kTM);
-  const int32_t prev = __shfl_up(L.g, 1, 64);
-  const bool start = lane < nv && (lane == 0 || prev != L.g);
-  const uint64_t m = __ballot(start);
-  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int rank = __popcll(m & lt);
-  if (start) {
-    ti->rstart[rank] = lane;
-    ti->rgrp[rank] = L.g;
-  }
-  const int32_t first = __shfl(L.g, 0, 64);
-  const int32_t last = __shfl(L.g, nv - 1, 64);
-  if (lane == 0) {
-    const int nr = __popcll(m);
-    ti->nv = nv;
-    ti->nruns = nr;
-    ti->rstart[nr] = nv;
-    ti->prev_same = L.before >= 0 && L.before == first;
-    ti->next_same = L.after >= 0 && L.after == last;
-  }
-}
-
-// Per-group reduce of the FP32 result tile Y (rows = tuples of tile t),
-// threads tid = 0..nthr-1: bias and act_pre per tuple, then SUM / MEAN /
-// MAX per run; finished groups are written, the open group is carried to
-// the next tile of the block, groups cut by the block's range ends leave a
-// partial (slot 0: cut by the range start, slot 1: runs past the end).
-template <bool kStoreOnly>
-__device__ __forceinline__ void ws_reduce(const WsArgs& a, int64_t t, const float* Y, int YS, const TileInfo* ti,
-                                          int64_t tb, int64_t range_hi, OpenState* op, int tid, int nthr) {
-  const int h = a.h;
-  const int64_t e0 = t * kTM;
-  const int nv = ti->nv, nr = ti->nruns;
-  const int rd = (int)((t - tb) & 1), wr = rd ^ 1;
-  const bool maxagg = a.sink.agg == RELNN_MAX;
-  const int64_t bidx = blockIdx.x;
-  for (int p = tid; p < nr * h; p += nthr) {
-    const int q = p / h;
-    const int c = p - q * h;
-    const int r0 = ti->rstart[q], r1 = ti->rstart[q + 1];
-    const int64_t s = ti->rgrp[q];
-    const float bc = op->bias[c];
-    float S, Cc = 0.0f;
-    int32_t am = -1;
-    if (maxagg) {
-      S = act_apply(a.act_pre, Y[r0 * YS + c] + bc);
-      am = (int32_t)(e0 + r0);
-      for (int r = r0 + 1; r < r1; ++r) {
-        const float y = act_apply(a.act_pre, Y[r * YS + c] + bc);
-        if (y > S) {
-          S = y;
-          am = (int32_t)(e0 + r);
-        }
-      }
-    } else {
-      S = 0.0f;
-      for (int r = r0; r < r1; ++r) S += act_apply(a.act_pre, Y[r * YS + c] + bc);
-    }
-    int32_t cnt = r1 - r0;
-    bool cut = false;
-    if (q == 0 && ti->prev_same) {
-      if (t > tb) {                                // the block's open group
-        if (maxagg) {
-          const float ov = op->s[rd][c];
-          if (!(S > ov)) {
-            S = ov;
-            am = op->arg[rd][c];
-          }
-        } else {
-          float os = op->s[rd][c], oc = op->c[rd][c];
-          kahan_add(os, oc, S);
-          S = os;
-          Cc = oc;
-        }
-        cnt += op->n[rd][c];
-        cut = op->cut[rd][c] != 0;
-      } else {
-        cut = true;                                // began before the range
-      }
-    }
-    if (q == nr - 1 && ti->next_same) {            // continues past this tile
-      if (e0 + nv < range_hi) {
-        op->s[wr][c] = S;
-        op->c[wr][c] = Cc;
-        op->arg[wr][c] = am;
-        op->n[wr][c] = cnt;
-        op->cut[wr][c] = cut ? 1 : 0;
-      } else {
-        const int slot = cut ? 0 : 1;
-        a.carry[(bidx * 2 + slot) * h + c] = S - Cc;
-        if (a.carry_arg) a.carry_arg[(bidx * 2 + slot) * h + c] = am;
-      }
-    } else if (!cut) {                             // complete inside this block
-      sink_write<kStoreOnly>(a.sink, s, c, h, S - Cc, am, cnt);
-    } else {                                       // cut by the range start
-      a.carry[(bidx * 2 + 0) * h + c] = S - Cc;
-      if (a.carry_arg) a.carry_arg[(bidx * 2 + 0) * h + c] = am;
-    }
-  }
 }
 
 // W for the BF16 kernel, 16-column slices: fragment ks of slice cw, lane l
@@ -1209,75 +1059,124 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
 // ---------------------------------------------------------------- pushdown
 // Transform pushed below the join (affine tau only): with P_j = Z_j W_j
 // computed once per row of atom j, the tuple value is sum_j P_j[r_j] + b.
-// This kernel sums the P rows of the atoms that vary inside a group (the
-// others, and b, are one constant per group added by the sink) into the
-// FP32 tile in LDS, then reduces it per group exactly like the fused
-// kernels.  Loads of tile t+1 are in flight while tile t is reduced.
+// The P rows of the atoms that vary inside a group are summed per tuple and
+// aggregated per group; the others, and b, are one constant per group that
+// the sink adds.  This is a segmented gather-sum over the sorted tuple list:
+// one wave per contiguous range of positions (boundaries on multiples of
+// kPsTM), lane l owning columns 2 l, 2 l + 1 of each 128-column block, rows
+// of kPsBatch tuples loaded together.  SUM / MEAN accumulate with Kahan
+// compensation, MAX keeps the value and its first maximiser; a group cut by
+// a range end leaves its partial in carry slot 0 (cut by the start) or 1
+// (runs past the end), which k_fixup combines in range order.
 struct PushArgs {
   int n;                                  // atoms gathered per tuple
   const float* P[RELNN_MAX_ATOMS];        // [n_rows_j][h]
   const int32_t* rows[RELNN_MAX_ATOMS];   // [E] joined row per tuple
 };
 
-template <int NW>
-__global__ void __launch_bounds__(NW * 64) k_push(WsArgs a, PushArgs pa) {
-  constexpr int TM = kTM;
-  constexpr int nthr = NW * 64;
-  constexpr int CH = (TM * (kHMax / 4) + nthr - 1) / nthr;
-  extern __shared__ __attribute__((aligned(16))) char smem[];
+constexpr int kPsTM = 64;       // range boundaries on multiples of 64 positions
+constexpr int kPsWaves = 4;     // waves per block
+constexpr int kPsBatch = 8;     // tuples whose rows are loaded together
+
+__global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs pa) {
+  const int lane = threadIdx.x % 64;
+  const int64_t u = (int64_t)blockIdx.x * kPsWaves + threadIdx.x / 64;
+  if (u >= a.nunits) return;
+  const int64_t r0 = ((a.ntiles * u) / a.nunits) * kPsTM;
+  const int64_t r1 = min<int64_t>(((a.ntiles * (u + 1)) / a.nunits) * kPsTM, a.E);
+  if (r0 >= r1) return;
   const int h = a.h;
-  const int YS = h + 4;
-  const int C4 = h / 4;
-  float* Yb = reinterpret_cast<float*>(smem);            // [2][TM][YS]
-  OpenState* op = reinterpret_cast<OpenState*>(Yb + 2 * TM * YS);
-  TileInfo* tinfo = reinterpret_cast<TileInfo*>(op + 1);   // [4]
-  const int wave = threadIdx.x / 64;
-  const int64_t tb = (a.ntiles * (int64_t)blockIdx.x) / a.nunits;
-  const int64_t te = (a.ntiles * ((int64_t)blockIdx.x + 1)) / a.nunits;
-  const int64_t range_hi = min<int64_t>(te * TM, a.E);
-  if (tb >= te) return;
-  stage_bias(op, a, threadIdx.x, blockDim.x);
-
-  f32x4 acc[CH];
-  SegLoad L{-1, -1, -1};
-  auto load = [&](int64_t t) {
-    const int64_t e0 = t * TM;
-    const int nv = (int)min<int64_t>(TM, a.E - e0);
+  const bool is_max = a.sink.agg == RELNN_MAX;
+  for (int cb = 0; cb < h; cb += 128) {
+    const int col = cb + 2 * lane;
+    const bool on = col < h;
+    const int cc = on ? col : 0;
+    const float s_init = is_max ? -INFINITY : 0.0f;
+    float s0 = s_init, s1 = s_init, c0 = 0.0f, c1 = 0.0f;
+    int32_t m0 = -1, m1 = -1;                              // MAX: first maximiser, -1 before any tuple
+    int32_t g = a.sg.seg_of[r0];
+    bool first = true;
+    auto flush = [&]() {
+      const int64_t g0 = a.sg.offsets[g], g1 = a.sg.offsets[g + 1];
+      const bool cut_lo = first && g0 < r0;
+      const bool cut_hi = g1 > r1;
+      if (on) {
+        const float v0 = is_max ? s0 : s0 - c0, v1 = is_max ? s1 : s1 - c1;
+        if (cut_lo || cut_hi) {
+          const int64_t o = (u * 2 + (cut_lo ? 0 : 1)) * h + col;
+          a.carry[o] = v0;
+          a.carry[o + 1] = v1;
+          if (a.carry_arg) {
+            a.carry_arg[o] = m0;
+            a.carry_arg[o + 1] = m1;
+          }
+        } else {
+          const int32_t cnt = (int32_t)(g1 - g0);
+          sink_write(a.sink, g, col, h, v0, m0, cnt);
+          sink_write(a.sink, g, col + 1, h, v1, m1, cnt);
+        }
+      }
+      first = false;
+      s0 = s_init;
+      s1 = s_init;
+      c0 = 0.0f;
+      c1 = 0.0f;
+      m0 = -1;
+      m1 = -1;
+    };
+    for (int64_t base = r0; base < r1; base += 64) {
+      const int n = (int)min<int64_t>(64, r1 - base);
+      const int64_t e = base + min(lane, n - 1);
+      const int32_t gl = a.sg.seg_of[e];
+      // row numbers of the 64 positions, one vector per atom (compile-time
+      // atom indices: a run-time index into the argument would put it in
+      // scratch memory)
+      int32_t R[RELNN_MAX_ATOMS];
 #pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int i = threadIdx.x + q * nthr;
-      acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-      const int r = i / C4;
-      if (i < TM * C4 && r < nv) {
-        const int c4 = i - r * C4;
-        for (int j = 0; j < pa.n; ++j)
-          acc[q] += *reinterpret_cast<const f32x4*>(pa.P[j] + (int64_t)pa.rows[j][e0 + r] * h + 4 * c4);
+      for (int j = 0; j < RELNN_MAX_ATOMS; ++j) R[j] = j < pa.n ? pa.rows[j][e] : 0;
+      for (int bt = 0; bt < n; bt += kPsBatch) {
+        float2 v[kPsBatch];
+#pragma unroll
+        for (int i = 0; i < kPsBatch; ++i) {
+          const int q = min(bt + i, n - 1);                 // clamped: every load is valid
+          v[i] = make_float2(0.0f, 0.0f);
+#pragma unroll
+          for (int j = 0; j < RELNN_MAX_ATOMS; ++j) {
+            if (j < pa.n) {
+              const int32_t row = __builtin_amdgcn_readlane(R[j], q);
+              const float2 p = *reinterpret_cast<const float2*>(pa.P[j] + (int64_t)row * h + cc);
+              v[i].x += p.x;
+              v[i].y += p.y;
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < kPsBatch; ++i) {
+          const int q = bt + i;
+          if (q >= n) break;
+          const int32_t gq = __builtin_amdgcn_readlane(gl, q);
+          if (gq != g) {                                     // a group ends
+            flush();
+            g = gq;
+          }
+          if (is_max) {
+            const int32_t pos = (int32_t)(base + q);
+            if (v[i].x > s0 || m0 < 0) {
+              s0 = v[i].x;
+              m0 = pos;
+            }
+            if (v[i].y > s1 || m1 < 0) {
+              s1 = v[i].y;
+              m1 = pos;
+            }
+          } else {
+            kahan_add(s0, c0, v[i].x);
+            kahan_add(s1, c1, v[i].y);
+          }
+        }
       }
     }
-    if (wave == 0) L = seg_load(a, t);
-  };
-  auto store = [&](float* Y, TileInfo* ti, int64_t t) {
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int i = threadIdx.x + q * nthr;
-      if (i < TM * C4) {
-        const int r = i / C4, c4 = i - (i / C4) * C4;
-        *reinterpret_cast<f32x4*>(Y + r * YS + 4 * c4) = acc[q];
-      }
-    }
-    if (wave == 0) seg_stage(ti, a, t, L);
-  };
-
-  load(tb);
-  store(Yb, &tinfo[0], tb);
-  __syncthreads();
-  for (int64_t t = tb; t < te; ++t) {
-    const int buf = (int)((t - tb) & 1);
-    const bool more = t + 1 < te;
-    if (more) load(t + 1);
-    ws_reduce<false>(a, t, Yb + buf * TM * YS, YS, &tinfo[(t - tb) & 3], tb, range_hi, op, threadIdx.x, nthr);
-    if (more) store(Yb + (buf ^ 1) * TM * YS, &tinfo[(t + 1 - tb) & 3], t + 1);
-    __syncthreads();
+    flush();
   }
 }
 
@@ -1288,8 +1187,6 @@ void allow_lds(KernelT k, size_t bytes) {
   RELNN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
-
-constexpr size_t kStateBytes = sizeof(OpenState) + 4 * sizeof(TileInfo);
 
 // LDS ring depth NB: as many tiles as fit with their 2 NB - 1 index slots,
 // at most 6 (tiles t+1 .. t+4 in flight while t is multiplied).
@@ -1361,7 +1258,7 @@ void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P,
   a.at = f.at;
   a.E = f.E;
   a.h = f.h;
-  a.ntiles = cdiv(f.E, kTM);
+  a.ntiles = cdiv(f.E, kPsTM);
   a.nunits = std::max<int64_t>(1, std::min<int64_t>(a.ntiles, nunits));
   a.b = nullptr;                      // the bias is part of the group constant
   a.act_pre = RELNN_ACT_NONE;
@@ -1375,17 +1272,16 @@ void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P,
     pa.P[j] = P[j];
     pa.rows[j] = rows[j];
   }
-  const size_t lds = 2 * kTM * (f.h + 4) * 4 + kStateBytes;
-  allow_lds(k_push<4>, lds);
   {
     KTimer tm("fwd_push", s);
-    k_push<4><<<(unsigned)a.nunits, 256, lds, s>>>(a, pa);
+    k_push_sum<<<(unsigned)cdiv(a.nunits, kPsWaves), kPsWaves * 64, 0, s>>>(a, pa);
     RELNN_LAUNCHED();
   }
-  launch_fixup(f.sg, kTM, f.h, a.ntiles, a.nunits, f.sink, carry, carry_arg, s);
+  launch_fixup(f.sg, kPsTM, f.h, a.ntiles, a.nunits, f.sink, carry, carry_arg, s);
 }
 
-int64_t push_units(int64_t E) { return std::max<int64_t>(1, std::min<int64_t>(cdiv(E, kTM), num_cus())); }
+// ranges of the pushdown gather-sum (and carry pairs): up to 8192 waves
+int64_t push_units(int64_t E) { return std::max<int64_t>(1, std::min<int64_t>(cdiv(E, kPsTM), 8192)); }
 
 WsPlan plan_ws(int dtype, int K, int h, int64_t E) {
   WsPlan p;
