@@ -187,13 +187,14 @@ def time_net(net: Net, steps: int, warmup: int, kernels):
     return dt, ktime
 
 
-def fwd_bwd_leg(steps: int, warmup: int, scale: float, dtype: str = "f32"):
+def fwd_bwd_leg(steps: int, warmup: int, scale: float, dtype: str = "f32", pushdown: bool = False):
     """Differentiation form: Node [2M, 128], Edge 10M with s ~ Zipf(1.2), t
     uniform; layer 1 SUM + ReLU, layer 2 MAX, MSE against N(0,1) targets.  A
     step is forward and backward of both layers through RelLayerFn (20M
     joined tuples, each through fwd + bwd).  BF16: embeddings, weights and
     the layer-1 output in bf16, FP32 accumulation and FP32 gradients inside
-    the library."""
+    the library.  pushdown: both (affine) layers evaluate the transform once
+    per node in the forward; the backward is the same."""
     import torch
 
     import relgen
@@ -207,8 +208,8 @@ def fwd_bwd_leg(steps: int, warmup: int, scale: float, dtype: str = "f32"):
     ix1 = Index([s, t], [(n, 0, None), (n, 1, None)], 1, bwd=True)
     k1 = ix1.export()["group_keys"]
     ix2 = Index([s, t], [(ix1.G, 0, k1), (ix1.G, 1, k1)], 1, bwd=True)
-    L1 = Layer([128, 128], 128, dtype, "sum", "none", "relu", out_dtype=dtype)
-    L2 = Layer([128, 128], 128, dtype, "max", "none", "none")
+    L1 = Layer([128, 128], 128, dtype, "sum", "none", "relu", out_dtype=dtype, pushdown=pushdown)
+    L2 = Layer([128, 128], 128, dtype, "max", "none", "none", pushdown=pushdown)
     tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
     z = torch.from_numpy(p.z).to(dev).to(tdt).requires_grad_(True)
     W1 = torch.from_numpy(p.W[0]).to(dev).to(tdt).requires_grad_(True)
@@ -235,14 +236,14 @@ def fwd_bwd_leg(steps: int, warmup: int, scale: float, dtype: str = "f32"):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     api.timing_enable(False)
-    kt = {k: api.timing_read(k) for k in ("fwd_fused", "bwd_dw", "bwd_dx")}
+    kt = {k: api.timing_read(k) for k in ("fwd_fused", "fwd_push", "bwd_dw", "bwd_dx")}
     api.timing_reset()
     tuples = ix1.E + ix2.E
     return {"value": tuples * steps / dt, "unit": "tuples/s (fwd+bwd, per layer)", "ms_per_step": dt / steps * 1e3,
             "workload": "Node 2M x 128, Edge 10M (s ~ Zipf 1.2, t uniform); L1 SUM+ReLU, L2 MAX; MSE; "
-                        + ("BF16" if dtype == "bf16" else "FP32"),
+                        + ("BF16" if dtype == "bf16" else "FP32") + ("; forward with pushdown" if pushdown else ""),
             "tuples_per_step": tuples, "steps": steps,
-            "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in kt.items()}}
+            "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in kt.items() if v[1]}}
 
 
 def cobuy_leg(D, steps: int, warmup: int):
@@ -419,8 +420,10 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
     ap.add_argument("--cpu-budget", type=int, default=9_000_000, help="oracle sample size in tuples")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="f32,plain,bf16,push_f32,push_bf16,cobuy_bf16,serve,fwdbwd,fwdbwd_bf16",
-                    help="comma list of f32,plain,bf16,push_f32,push_bf16,cobuy_bf16,serve,fwdbwd,fwdbwd_bf16")
+    ap.add_argument("--legs", default="f32,plain,bf16,push_f32,push_bf16,cobuy_bf16,serve,fwdbwd,fwdbwd_bf16,"
+                                      "fwdbwd_push",
+                    help="comma list of f32,plain,bf16,push_f32,push_bf16,cobuy_bf16,serve,fwdbwd,fwdbwd_bf16,"
+                         "fwdbwd_push")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per serving rate")
     ap.add_argument("--serve-rates", default="200,500,1000,2000", help="Poisson arrival rates (req/s)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -515,15 +518,16 @@ def main():
                          "fused_f32": serve_leg(D, "f32", rates, args.serve_seconds),
                          "fused_bf16": serve_leg(D, "bf16", rates, args.serve_seconds)}
     g_host = D["g"]
-    if "fwdbwd" in legs or "fwdbwd_bf16" in legs:
+    if legs & {"fwdbwd", "fwdbwd_bf16", "fwdbwd_push"}:
         del D
         torch.cuda.empty_cache()
-    for leg, dt in (("fwdbwd", "f32"), ("fwdbwd_bf16", "bf16")):
+    for leg, dt, key in (("fwdbwd", "f32", "fwd_bwd_f32"), ("fwdbwd_bf16", "bf16", "fwd_bwd_bf16"),
+                         ("fwdbwd_push", "f32", "fwd_bwd_f32_pushdown")):
         if leg not in legs:
             continue
-        fb = fwd_bwd_leg(max(1, args.steps // 2), args.warmup, args.scale, dt)
-        line["fwd_bwd_" + dt] = fb
-        log(f"fwd+bwd {dt}: {fb['ms_per_step']:.2f} ms/step, {fb['value'] / 1e9:.3f} G tuples/s; " +
+        fb = fwd_bwd_leg(max(1, args.steps // 2), args.warmup, args.scale, dt, pushdown=leg == "fwdbwd_push")
+        line[key] = fb
+        log(f"fwd+bwd {leg}: {fb['ms_per_step']:.2f} ms/step, {fb['value'] / 1e9:.3f} G tuples/s; " +
             ", ".join(f"{k} {v:.3f} ms" for k, v in fb["kernels_ms_per_launch"].items()))
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

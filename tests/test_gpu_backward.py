@@ -143,10 +143,12 @@ def test_bwd_large_segment_ragged():
     check(rule, "f32")
 
 
-def test_autograd_two_layer_power_net():
+@pytest.mark.parametrize("pushdown", [False, True])
+def test_autograd_two_layer_power_net(pushdown):
     """The differentiation form on a small instance: layer 1 SUM + ReLU, layer
     2 MAX, MSE against targets; torch.autograd drives the hand-written
-    backward.  Gradients of W1, W2 and z against the FP64 oracle chain."""
+    backward.  Gradients of W1, W2 and z against the FP64 oracle chain, with
+    the forward fused or pushed below the join (both layers are affine)."""
     import torch
 
     from paper_2605_24207_amd import RelLayerFn
@@ -161,8 +163,8 @@ def test_autograd_two_layer_power_net():
     ix1 = Index([s, t], [(n, 0, None), (n, 1, None)], 1, bwd=True)
     keys1 = ix1.export()["group_keys"]
     ix2 = Index([s, t], [(ix1.G, 0, keys1), (ix1.G, 1, keys1)], 1, bwd=True)
-    L1 = Layer([128, 128], 128, "f32", "sum", "none", "relu")
-    L2 = Layer([128, 128], 128, "f32", "max", "none", "none")
+    L1 = Layer([128, 128], 128, "f32", "sum", "none", "relu", pushdown=pushdown)
+    L2 = Layer([128, 128], 128, "f32", "max", "none", "none", pushdown=pushdown)
     z = torch.from_numpy(p.z).to(dev).requires_grad_(True)
     W1 = torch.from_numpy(p.W[0]).to(dev).requires_grad_(True)
     W2 = torch.from_numpy(p.W[1]).to(dev).requires_grad_(True)
@@ -262,3 +264,4 @@ def test_backward_rejects_wrong_gradient_dtype():
     with pytest.raises(TypeError, match="dout"):
         layer_bwd(gi, layer, [embs[0], embs[0]], W, b, pre, am, out.to(torch.bfloat16), [dz, dz],
                   torch.empty_like(W), torch.empty_like(b))
+
