@@ -132,6 +132,17 @@ def test_bwd_max_width_not_multiple_of_32(dtype):
     check(rule, dtype)
 
 
+@pytest.mark.parametrize("case", ["one_tuple", "one_group"])
+@pytest.mark.parametrize("agg", ["sum", "mean", "max"])
+def test_bwd_degenerate_sizes(case, agg):
+    """Backward of a one-tuple join, and of one group holding every tuple."""
+    n_edges = 1 if case == "one_tuple" else 20_000
+    rule = relgen.node_edge(seed=32, n_nodes=300, n_edges=n_edges, agg=agg, bias_std=0.3)
+    if case == "one_group":
+        rule.cols[1][:] = 5
+    check(rule, "f32")
+
+
 def test_bwd_dw_accumulate():
     check(relgen.node_edge(seed=22, agg="mean", bias_std=0.2), "f32", dw_accum=True)
 

@@ -193,6 +193,21 @@ def test_fwd_max_without_argmax(case, dtype):
     assert rel_rows(pre2.cpu().numpy(), o_pre).max() <= tol
 
 
+@pytest.mark.parametrize("case", ["one_tuple", "one_group"])
+@pytest.mark.parametrize("agg", ["sum", "mean", "max"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("h", [32, 256])
+def test_fwd_degenerate_sizes(case, agg, dtype, h):
+    """A join of one tuple, and one group holding every tuple of many blocks'
+    ranges (the whole output is one carried group)."""
+    n_edges = 1 if case == "one_tuple" else 20_000
+    rule = relgen.node_edge(seed=31, n_nodes=300, n_edges=n_edges, d=32, h=h, agg=agg, bias_std=0.3)
+    if case == "one_group":
+        rule.cols[1][:] = 5
+    res = check_fwd(rule, dtype)
+    assert res["out"].shape[0] == 1
+
+
 def test_fwd_empty_join():
     rule = index_rules()["all_dangling"]
     res = gpu_fwd(rule, "f32")
