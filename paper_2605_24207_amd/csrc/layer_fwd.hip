@@ -364,6 +364,8 @@ FwdPlan plan_fwd(const relnn_index* idx, const relnn_layer_desc* L) {
     o += round_up(P.carry_units * 2 * h * 4, 256);
     P.ws_carry_arg = o;
     if (L->agg == RELNN_MAX) o += round_up(P.carry_units * 2 * h * 4, 256);
+    P.ws_push_v = o;
+    o += round_up(std::max<int64_t>(idx->G, 1) * h * 4, 256);
     P.ws_push = o;
   }
   return P;
@@ -544,7 +546,8 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
       a.sink = sk;
       a.carry = reinterpret_cast<float*>(w + P.ws_carry);
       a.carry_arg = L->agg == RELNN_MAX ? reinterpret_cast<int32_t*>(w + P.ws_carry_arg) : nullptr;
-      launch_push(a, push_units(idx->E), n, gp, gr, a.carry, a.carry_arg, s);
+      launch_push(a, push_units(idx->E), n, gp, gr, a.carry, a.carry_arg, idx->G,
+                  reinterpret_cast<float*>(w + P.ws_push_v), s);
       return;
     }
     const WsPlan wp = plan_ws(L->dtype, P.K, L->h, idx->E);

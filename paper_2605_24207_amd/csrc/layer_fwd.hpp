@@ -39,6 +39,7 @@ struct FwdPlan {
   int64_t ntiles = 0;
   int64_t carry_units = 0;   // units the carry region holds (max over kernels)
   size_t ws_push_p[RELNN_MAX_ATOMS] = {};   // pushdown: node products of atom j
+  size_t ws_push_v = 0;                     // pushdown: per-group aggregates before the group constant
   size_t ws_push = 0;                       // pushdown total
   size_t ws_wsw = 0, ws_carry = 0, ws_carry_arg = 0, ws_x = 0, ws_y = 0;
   size_t ws_fused = 0, ws_plain = 0;
@@ -81,9 +82,11 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
 
 // Pushed-down transform: gather-sum of the node products P (n atoms per
 // tuple) and per-group reduce (layer_ws.hip); the sink carries the group
-// constant.  push_units: blocks (and carry units) it uses for E tuples.
+// constant, which a second pass over the G groups adds (V: [G][h] FP32
+// workspace for the aggregates before it).  push_units: waves (and carry
+// units) it uses for E tuples.
 void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P, const int32_t* const* rows,
-                 float* carry, int32_t* carry_arg, hipStream_t s);
+                 float* carry, int32_t* carry_arg, int64_t G, float* V, hipStream_t s);
 int64_t push_units(int64_t E);
 
 // Column-major rocBLAS FP32 products: C = op(A) op(B) + beta C,

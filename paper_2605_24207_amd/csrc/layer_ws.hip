@@ -1074,6 +1074,47 @@ struct PushArgs {
   const int32_t* rows[RELNN_MAX_ATOMS];   // [E] joined row per tuple
 };
 
+// Second pass of the pushdown: V holds each group's aggregate of the varying
+// atoms (MEAN already divided by the count); the group constant is added
+// (count times for SUM) and the result written through the sink.  One
+// thread per (group, column): the constant's loads are independent here,
+// where in the gather-sum they would stall a wave at every group end.
+__global__ void k_push_finish(const float* V, int64_t G, int h, Sink k) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  const int C4 = h / 4;                                     // h % 4 == 0 for the pushdown
+  const GroupConst& gc = k.gc;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G * C4;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = i / C4;
+    const int c = 4 * (int)(i - s * C4);
+    const int64_t e0 = gc.offsets[s];
+    f32x4 g = gc.bias ? *reinterpret_cast<const f32x4*>(gc.bias + c) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < RELNN_MAX_ATOMS; ++j)    // constant trip count: no run-time index into the argument
+      if (j < gc.n) g += *reinterpret_cast<const f32x4*>(gc.P[j] + (int64_t)gc.rows[j][e0] * h + c);
+    const float cnt = (float)(gc.offsets[s + 1] - e0);
+    f32x4 v = *reinterpret_cast<const f32x4*>(V + s * h + c);
+    v += k.agg == RELNN_SUM ? cnt * g : g;
+    const int64_t o = (k.out_row ? (int64_t)k.out_row[s] : s) * h + c;
+    if (k.pre) *reinterpret_cast<f32x4*>(k.pre + o) = v;
+    if (k.accumulate) {
+      *reinterpret_cast<f32x4*>(k.out + o) += v;
+    } else {
+      f32x4 w;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[q] = act_apply(k.act_post, v[q]);
+      if (k.out_bf16) {
+        bf16x4 b;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = (__bf16)w[q];
+        *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(k.out) + o) = b;
+      } else {
+        *reinterpret_cast<f32x4*>(k.out + o) = w;
+      }
+    }
+  }
+}
+
 constexpr int kPsTM = 64;       // range boundaries on multiples of 64 positions
 constexpr int kPsWaves = 4;     // waves per block
 constexpr int kPsBatch = 8;     // tuples whose rows are loaded together
@@ -1252,7 +1293,7 @@ int pick_hc(int h) {
 }  // namespace
 
 void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P, const int32_t* const* rows,
-                 float* carry, int32_t* carry_arg, hipStream_t s) {
+                 float* carry, int32_t* carry_arg, int64_t G, float* V, hipStream_t s) {
   RELNN_REQUIRE(f.h % 4 == 0 && f.h <= kHMax, RELNN_E_UNSUPPORTED, "pushdown needs h %% 4 == 0 and h <= %d", kHMax);
   WsArgs a{};
   a.at = f.at;
@@ -1263,7 +1304,15 @@ void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P,
   a.b = nullptr;                      // the bias is part of the group constant
   a.act_pre = RELNN_ACT_NONE;
   a.sg = f.sg;
-  a.sink = f.sink;
+  // the gather-sum and its fix-up write the aggregate of the varying atoms
+  // into V (MEAN divided, maximisers to argmax); k_push_finish adds the
+  // group constant and applies the rest of the sink
+  Sink raw{};
+  raw.agg = f.sink.agg;
+  raw.act_post = RELNN_ACT_NONE;
+  raw.out = V;
+  raw.argmax = f.sink.argmax;
+  a.sink = raw;
   a.carry = carry;
   a.carry_arg = carry_arg;
   PushArgs pa{};
@@ -1272,12 +1321,19 @@ void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P,
     pa.P[j] = P[j];
     pa.rows[j] = rows[j];
   }
-  {
-    KTimer tm("fwd_push", s);
-    k_push_sum<<<(unsigned)cdiv(a.nunits, kPsWaves), kPsWaves * 64, 0, s>>>(a, pa);
+  KTimer tm("fwd_push", s);                // gather-sum, fix-up and finish
+  k_push_sum<<<(unsigned)cdiv(a.nunits, kPsWaves), kPsWaves * 64, 0, s>>>(a, pa);
+  RELNN_LAUNCHED();
+  launch_fixup(f.sg, kPsTM, f.h, a.ntiles, a.nunits, raw, carry, carry_arg, s);
+  Sink fin = f.sink;
+  fin.argmax = nullptr;
+  fin.gc.offsets = f.sg.offsets;
+  const int64_t n4 = G * (f.h / 4);
+  if (n4 > 0) {
+    k_push_finish<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n4, 256), 1 << 16)), 256, 0, s>>>(
+        V, G, f.h, fin);
     RELNN_LAUNCHED();
   }
-  launch_fixup(f.sg, kPsTM, f.h, a.ntiles, a.nunits, f.sink, carry, carry_arg, s);
 }
 
 // ranges of the pushdown gather-sum (and carry pairs): up to 8192 waves
