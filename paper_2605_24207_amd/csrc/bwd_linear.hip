@@ -122,11 +122,14 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
     const GsAtom A = gs_atom(a, on ? col : 0);
     f32x4 s = {0.f, 0.f, 0.f, 0.f}, c = {0.f, 0.f, 0.f, 0.f};
     int32_t g = a.sg.seg_of[r0];
+    // only the range's first segment can have begun before r0, and only its
+    // last one can run past r1: one list read at each end instead of two
+    // dependent offset reads at every segment end
+    const bool lo_cont = r0 > 0 && a.sg.seg_of[r0 - 1] == g;
     bool first = true;
-    auto flush = [&]() {
-      const int64_t g0 = a.sg.offsets[g], g1 = a.sg.offsets[g + 1];
-      const bool cut_lo = first && g0 < r0;
-      const bool cut_hi = g1 > r1;
+    auto flush = [&](bool last_seg) {
+      const bool cut_lo = first && lo_cont;
+      const bool cut_hi = last_seg && r1 < a.n && a.sg.seg_of[r1] == g;
       if (on) {
         const f32x4 v = s - c;
         float* dst = (cut_lo || cut_hi) ? a.carry + (u * 2 + (cut_lo ? 0 : 1)) * a.ldo + col
@@ -185,7 +188,7 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
           if (q >= n) break;
           const int32_t gq = __builtin_amdgcn_readlane(gl, q);
           if (__builtin_expect(gq != g, 0)) {         // a segment ends
-            flush();
+            flush(false);
             g = gq;
           }
 #pragma unroll
@@ -198,7 +201,7 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
         }
       }
     }
-    flush();
+    flush(true);
   }
 }
 

@@ -1136,11 +1136,15 @@ __global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs p
     float s0 = s_init, s1 = s_init, c0 = 0.0f, c1 = 0.0f;
     int32_t m0 = -1, m1 = -1;                              // MAX: first maximiser, -1 before any tuple
     int32_t g = a.sg.seg_of[r0];
+    // only the range's first group can have begun before r0, and only its
+    // last one can run past r1 (one list read at each end); a group wholly
+    // inside the range has the count of tuples seen here
+    const bool lo_cont = r0 > 0 && a.sg.seg_of[r0 - 1] == g;
     bool first = true;
-    auto flush = [&]() {
-      const int64_t g0 = a.sg.offsets[g], g1 = a.sg.offsets[g + 1];
-      const bool cut_lo = first && g0 < r0;
-      const bool cut_hi = g1 > r1;
+    int32_t cnt = 0;
+    auto flush = [&](bool last_seg) {
+      const bool cut_lo = first && lo_cont;
+      const bool cut_hi = last_seg && r1 < a.E && a.sg.seg_of[r1] == g;
       if (on) {
         const float v0 = is_max ? s0 : s0 - c0, v1 = is_max ? s1 : s1 - c1;
         if (cut_lo || cut_hi) {
@@ -1152,12 +1156,12 @@ __global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs p
             a.carry_arg[o + 1] = m1;
           }
         } else {
-          const int32_t cnt = (int32_t)(g1 - g0);
           sink_write(a.sink, g, col, h, v0, m0, cnt);
           sink_write(a.sink, g, col + 1, h, v1, m1, cnt);
         }
       }
       first = false;
+      cnt = 0;
       s0 = s_init;
       s1 = s_init;
       c0 = 0.0f;
@@ -1197,9 +1201,10 @@ __global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs p
           if (q >= n) break;
           const int32_t gq = __builtin_amdgcn_readlane(gl, q);
           if (gq != g) {                                     // a group ends
-            flush();
+            flush(false);
             g = gq;
           }
+          ++cnt;
           if (is_max) {
             const int32_t pos = (int32_t)(base + q);
             if (v[i].x > s0 || m0 < 0) {
@@ -1217,7 +1222,7 @@ __global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs p
         }
       }
     }
-    flush();
+    flush(true);
   }
 }
 
