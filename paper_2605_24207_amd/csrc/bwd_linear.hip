@@ -236,13 +236,16 @@ __global__ void k_bf16_to_f32(const __bf16* x, int64_t n, float* y) {
     y[i] = (float)x[i];
 }
 
-// demb[row[s]][:] += dz[s][:], each row named by at most one segment.
+// demb[row[s]][:] += dz[s][:], each row named by at most one segment;
+// four columns per thread (d % 4 == 0).
 __global__ void k_scatter_add_rows(const float* dz, const int32_t* row, int64_t nseg, int d, float* demb) {
-  const int64_t total = nseg * d;
+  const int d4 = d / 4;
+  const int64_t total = nseg * d4;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = i / d;
-    const int c = (int)(i - s * d);
-    demb[(int64_t)row[s] * d + c] += dz[i];
+    const int64_t s = i / d4;
+    const int c = 4 * (int)(i - s * d4);
+    f32x4* o = reinterpret_cast<f32x4*>(demb + (int64_t)row[s] * d + c);
+    *o += *reinterpret_cast<const f32x4*>(dz + s * d + c);
   }
 }
 
@@ -403,7 +406,8 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
     // DZ [nseg][d] = DS [nseg][h] W_j^T, W_j = rows koff.. of W ([d][h]):
     // column-major DZ^T (d x nseg) = W_j^T' (d x h) DS^T (h x nseg)
     blas_sgemm(true, false, d, (int)nseg, h, W32 + (size_t)koff * h, h, ds, h, 0.0f, dz, d, s);
-    k_scatter_add_rows<<<grid_n(nseg * d), 256, 0, s>>>(dz, idx->t_segrow[j], nseg, d, demb[j]);
+    RELNN_REQUIRE(d % 4 == 0, RELNN_E_UNSUPPORTED, "backward needs d %% 4 == 0");
+    k_scatter_add_rows<<<grid_n(nseg * d / 4), 256, 0, s>>>(dz, idx->t_segrow[j], nseg, d, demb[j]);
     RELNN_LAUNCHED();
   }
 }
