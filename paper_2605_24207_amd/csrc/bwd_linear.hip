@@ -301,8 +301,6 @@ LinBwdPlan plan_lin_bwd(const relnn_index* idx, const relnn_layer_desc* L, size_
     p.ws_xs = take((size_t)G * p.ldx * 4);
     p.ws_part = take((size_t)p.nchunk * (K + 1) * h * 4);
   }
-  p.ws_tg = take((size_t)E * 4);
-  p.ws_tp = take((size_t)E * 4);
   p.ws_ds = take((size_t)nseg * h * 4);
   p.ws_dz = take((size_t)nseg * dmax * 4);
   p.ws_w32 = take((size_t)K * h * 4);
@@ -380,11 +378,10 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
     const int d = L->d[j];
     const int64_t nseg = idx->t_nseg[j];
     if (nseg == 0) continue;
-    int32_t* tg = reinterpret_cast<int32_t*>(w + P.ws_tg);
+    const int32_t* tg = idx->t_grp[j];                               // group of each transposed tuple
     float* ds = reinterpret_cast<float*>(w + P.ws_ds);
     float* dz = reinterpret_cast<float*>(w + P.ws_dz);
     KTimer tm("bwd_dx", s);
-    prim::gather_i32(idx->tuple_group, idx->t_pos[j], E, tg, s);     // group of each transposed tuple
     GsArgs a{};
     a.emb[0] = dA;
     a.rows[0] = tg;

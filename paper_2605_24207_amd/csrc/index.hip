@@ -341,6 +341,8 @@ extern "C" relnn_status relnn_build_index(const relnn_join_desc* D, relnn_stream
                                tk.as<uint32_t>(), tv.as<int32_t>(), E,
                                prim::bits_for((uint64_t)std::max<int64_t>(nr - 1, 0)), s);
         prim::csr_from_sorted(reinterpret_cast<uint32_t*>(idx->t_row[j]), E, nr, idx->t_off[j], s);
+        idx->t_grp[j] = idx->alloc<int32_t>(E);
+        prim::gather_i32(idx->tuple_group, idx->t_pos[j], E, idx->t_grp[j], s);
         DevBuf so((E + 1) * sizeof(int32_t)), sr(std::max<int64_t>(E, 1) * sizeof(int32_t));
         idx->t_seg[j] = idx->alloc<int32_t>(E);
         const int64_t ns = prim::segments(idx->t_row[j], E, idx->t_seg[j], so.as<int32_t>(), sr.as<int32_t>(), s);

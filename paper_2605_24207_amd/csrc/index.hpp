@@ -22,6 +22,7 @@ struct relnn_index {
   int32_t* t_off[RELNN_MAX_ATOMS] = {};   // [n_rows+1]
   int32_t* t_row[RELNN_MAX_ATOMS] = {};   // [E] joined row, ascending
   int32_t* t_pos[RELNN_MAX_ATOMS] = {};   // [E] canonical tuple position
+  int32_t* t_grp[RELNN_MAX_ATOMS] = {};   // [E] group of that tuple
   // Its non-empty rows as segments: t_seg[E] segment of each position,
   // t_segoff[nseg+1], t_segrow[nseg] the row of each segment.
   int64_t t_nseg[RELNN_MAX_ATOMS] = {0, 0, 0, 0};

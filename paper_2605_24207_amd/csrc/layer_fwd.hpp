@@ -105,7 +105,7 @@ void blas_sgemv(int m, int n, const float* A, int lda, const float* x, float bet
 struct LinBwdPlan {
   int64_t units = 0;
   int ldx = 0, nchunk = 1;
-  size_t ws_xs = 0, ws_part = 0, ws_tg = 0, ws_tp = 0, ws_ds = 0, ws_dz = 0, ws_w32 = 0, ws_carry = 0, total = 0;
+  size_t ws_xs = 0, ws_part = 0, ws_ds = 0, ws_dz = 0, ws_w32 = 0, ws_carry = 0, total = 0;
 };
 LinBwdPlan plan_lin_bwd(const relnn_index* idx, const relnn_layer_desc* L, size_t base, bool xs_dw);
 void lin_bwd_dw(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdPlan& P, const void* const* emb,
