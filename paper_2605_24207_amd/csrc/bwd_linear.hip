@@ -205,6 +205,25 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
   }
 }
 
+// demb[row of g][:] += w_g dz[g][:] for an atom whose FK is the group column
+// (group g joins one row of it, rows[offsets[g]], and no other group does):
+// the per-row sum of the routed gradients is w_g dA_g with w_g = |g| (SUM,
+// MEAN: every tuple carries dA_g) or 1 (MAX: each column goes to exactly
+// one tuple of the group), so dz = dA W^T needs no pass over the tuples.
+// Four columns per thread (d % 4 == 0).
+__global__ void k_scatter_add_groups(const float* dz, const int32_t* rows, const int32_t* offsets, int64_t G, int d,
+                                     int unit_weight, float* demb) {
+  const int d4 = d / 4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G * d4; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = i / d4;
+    const int c = 4 * (int)(i - g * d4);
+    const int64_t e0 = offsets[g];
+    const float wg = unit_weight ? 1.0f : (float)(offsets[g + 1] - e0);
+    f32x4* o = reinterpret_cast<f32x4*>(demb + (int64_t)rows[e0] * d + c);
+    *o += wg * *reinterpret_cast<const f32x4*>(dz + g * d + c);
+  }
+}
+
 // xs[g][K] = |g|: the extra column turns db into one more row of the dW product.
 __global__ void k_counts_col(const int32_t* offsets, int64_t G, int K, int ldx, float* xs) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x)
@@ -378,6 +397,16 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
     const int d = L->d[j];
     const int64_t nseg = idx->t_nseg[j];
     if (nseg == 0) continue;
+    RELNN_REQUIRE(d % 4 == 0, RELNN_E_UNSUPPORTED, "backward needs d %% 4 == 0");
+    if (idx->atom_gk[j] && mask == nullptr) {                       // one row per group: DS_j = w_g dA
+      float* dz = reinterpret_cast<float*>(w + P.ws_dz);            // [G][d], G = nseg here
+      KTimer tm("bwd_dx", s);
+      blas_sgemm(true, false, d, (int)idx->G, h, W32 + (size_t)koff * h, h, dA, h, 0.0f, dz, d, s);
+      k_scatter_add_groups<<<grid_n(idx->G * d / 4), 256, 0, s>>>(dz, idx->rows + (int64_t)j * E, idx->offsets,
+                                                                  idx->G, d, L->agg == RELNN_MAX ? 1 : 0, demb[j]);
+      RELNN_LAUNCHED();
+      continue;
+    }
     const int32_t* tg = idx->t_grp[j];                               // group of each transposed tuple
     float* ds = reinterpret_cast<float*>(w + P.ws_ds);
     float* dz = reinterpret_cast<float*>(w + P.ws_dz);
@@ -403,7 +432,6 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
     // DZ [nseg][d] = DS [nseg][h] W_j^T, W_j = rows koff.. of W ([d][h]):
     // column-major DZ^T (d x nseg) = W_j^T' (d x h) DS^T (h x nseg)
     blas_sgemm(true, false, d, (int)nseg, h, W32 + (size_t)koff * h, h, ds, h, 0.0f, dz, d, s);
-    RELNN_REQUIRE(d % 4 == 0, RELNN_E_UNSUPPORTED, "backward needs d %% 4 == 0");
     k_scatter_add_rows<<<grid_n(nseg * d / 4), 256, 0, s>>>(dz, idx->t_segrow[j], nseg, d, demb[j]);
     RELNN_LAUNCHED();
   }

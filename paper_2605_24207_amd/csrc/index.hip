@@ -300,7 +300,10 @@ extern "C" relnn_status relnn_build_index(const relnn_join_desc* D, relnn_stream
     }
 
     // canonical order: LSD over atom FK columns (reverse body order), then head key
-    for (int j = 0; j < D->n_atoms; ++j) idx->atom_fd[j] = fd[D->atoms[j].col];
+    for (int j = 0; j < D->n_atoms; ++j) {
+      idx->atom_fd[j] = fd[D->atoms[j].col];
+      idx->atom_gk[j] = D->atoms[j].col == D->group_col;
+    }
     std::vector<int> order;
     for (int j = 0; j < D->n_atoms; ++j) {
       const int c = D->atoms[j].col;

@@ -18,6 +18,7 @@ struct relnn_index {
   bool has_bwd = false;
   int64_t n_rows[RELNN_MAX_ATOMS] = {0, 0, 0, 0};
   bool atom_fd[RELNN_MAX_ATOMS] = {};     // atom's FK is a function of the head key
+  bool atom_gk[RELNN_MAX_ATOMS] = {};     // atom's FK is the group column: one joined row per group
   // Transpose CSR of atom j (backward): tuples sorted by joined row.
   int32_t* t_off[RELNN_MAX_ATOMS] = {};   // [n_rows+1]
   int32_t* t_row[RELNN_MAX_ATOMS] = {};   // [E] joined row, ascending
