@@ -230,10 +230,11 @@ __global__ void k_counts_col(const int32_t* offsets, int64_t G, int K, int ldx, 
     xs[g * ldx + K] = (float)(offsets[g + 1] - offsets[g]);
 }
 
-// dW[k][c] (+)= sum_b part[b][k][c] for k < K, db[c] (+)= sum_b part[b][K][c]:
-// the split-K partials added in chunk order.
-__global__ void k_sum_parts(const float* part, int nb, int K, int h, float* dW, float* db, int accumulate) {
-  const int64_t total = (int64_t)(K + 1) * h;
+// dW[k][c] (+)= sum_b part[b][k][c] for k < K, db[c] (+)= sum_b part[b][K][c]
+// (when part has nrow = K + 1 rows): the split-K partials added in chunk
+// order.
+__global__ void k_sum_parts(const float* part, int nb, int nrow, int K, int h, float* dW, float* db, int accumulate) {
+  const int64_t total = (int64_t)nrow * h;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     float acc = 0.0f, comp = 0.0f;
     for (int b = 0; b < nb; ++b) kahan_add1(acc, comp, part[(int64_t)b * total + i]);
@@ -372,7 +373,41 @@ void lin_bwd_dw(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
                                nb - 1, s);
   blas_sgemm(false, true, h, K + 1, (int)rest, dA + (int64_t)(nb - 1) * m * h, h, xs + (int64_t)(nb - 1) * m * P.ldx,
              P.ldx, 0.0f, part + (int64_t)(nb - 1) * spart, h, s);
-  k_sum_parts<<<grid_n(spart), 256, 0, s>>>(part, nb, K, h, dW, db, accum ? 1 : 0);
+  k_sum_parts<<<grid_n(spart), 256, 0, s>>>(part, nb, K + 1, K, h, dW, db, accum ? 1 : 0);
+  RELNN_LAUNCHED();
+}
+
+// X[g][:] = the row of the atom that group g joins (rows[offsets[g]]), FP32.
+template <class T>
+__global__ void k_group_rows(const T* emb, const int32_t* rows, const int32_t* offsets, int64_t G, int d, float* X) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G * d; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = i / d;
+    const int c = (int)(i - g * d);
+    X[i] = (float)emb[(int64_t)rows[offsets[g]] * d + c];
+  }
+}
+
+int gk_dw_chunks(int64_t G) { return (int)std::max<int64_t>(1, std::min<int64_t>(64, G / 4096)); }
+
+void gk_dw(const relnn_index* idx, int j, const void* emb, bool bf16, int d, int h, const float* dA, float* dW_rows,
+           bool accum, float* X, float* part, hipStream_t s) {
+  const int64_t G = idx->G, E = idx->E;
+  if (G == 0) return;
+  const int32_t* rows = idx->rows + (int64_t)j * E;
+  if (bf16)
+    k_group_rows<__bf16><<<grid_n(G * d), 256, 0, s>>>(static_cast<const __bf16*>(emb), rows, idx->offsets, G, d, X);
+  else
+    k_group_rows<float><<<grid_n(G * d), 256, 0, s>>>(static_cast<const float*>(emb), rows, idx->offsets, G, d, X);
+  RELNN_LAUNCHED();
+  // column-major partial b (h x d) = dA_b^T' (h x m) X_b (m x d)
+  const int nb = gk_dw_chunks(G);
+  const int64_t m = G / nb, rest = G - m * (nb - 1);
+  const int64_t spart = (int64_t)d * h;
+  if (nb > 1)
+    blas_sgemm_strided_batched(false, true, h, d, (int)m, dA, h, m * h, X, d, m * d, part, h, spart, nb - 1, s);
+  blas_sgemm(false, true, h, d, (int)rest, dA + (int64_t)(nb - 1) * m * h, h, X + (int64_t)(nb - 1) * m * d, d, 0.0f,
+             part + (int64_t)(nb - 1) * spart, h, s);
+  k_sum_parts<<<grid_n(spart), 256, 0, s>>>(part, nb, d, d, h, dW_rows, nullptr, accum ? 1 : 0);
   RELNN_LAUNCHED();
 }
 

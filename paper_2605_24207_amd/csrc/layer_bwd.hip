@@ -425,6 +425,8 @@ struct BwdPlan {
   int64_t dw_tiles = 0, dw_units = 0;
   size_t dw_lds = 0;
   size_t ws_mask = 0, ws_fwsw = 0, ws_part = 0, ws_dbpart = 0, ws_dA = 0, ws_own = 0, total = 0;
+  int kv = 0;                // MAX: atoms dW takes per tuple (the others are keyed by the group column)
+  size_t ws_gkx = 0, ws_gkpart = 0;
   bool xs_dw = false;        // dW through the per-group sums (SUM / MEAN, affine)
   LinBwdPlan lin;
 };
@@ -463,6 +465,22 @@ BwdPlan plan_bwd(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   off += round_up(std::max<int64_t>(idx->G, 1) * L->h * 4, 256);
   p.ws_own = off;                                        // MAX: ownership bits [E][ceil(h / 32)]
   if (L->agg == RELNN_MAX) off += round_up(std::max<int64_t>(E, 1) * cdiv(L->h, 32) * 4, 256);
+  // MAX without act_pre: trailing atoms keyed by the group column leave the
+  // per-tuple dW for a product over the groups (their routed gradients add
+  // up to dA_g per group)
+  p.kv = L->k;
+  if (L->agg == RELNN_MAX && L->act_pre == RELNN_ACT_NONE)
+    while (p.kv > 1 && idx->atom_gk[p.kv - 1]) --p.kv;
+  p.ws_gkx = off;
+  p.ws_gkpart = off;
+  if (p.kv < L->k) {
+    int dmax = 0;
+    for (int j = p.kv; j < L->k; ++j) dmax = std::max(dmax, L->d[j]);
+    const int64_t G = std::max<int64_t>(idx->G, 1);
+    off += round_up(G * dmax * 4, 256);
+    p.ws_gkpart = off;
+    off += round_up((int64_t)gk_dw_chunks(G) * dmax * L->h * 4, 256);
+  }
   p.lin = plan_lin_bwd(idx, L, off, p.xs_dw);
   p.total = p.lin.total;
   return p;
@@ -588,16 +606,19 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
     } else {
       DwArgs d{};
       d.at = at;
+      d.at.k = P.kv;                          // per tuple: atoms 0 .. kv-1, the leading rows of dW
+      int Kv = 0;
+      for (int j = 0; j < P.kv; ++j) Kv += L->d[j];
       d.rows = idx->rows;
       d.E = E;
-      d.K = P.K;
-      d.K16 = P.K16;
+      d.K = Kv;
+      d.K16 = (int)round_up(Kv, 16);
       d.R = R;
       d.ntiles = P.dw_tiles;
       d.nunits = P.dw_units;
       d.part = reinterpret_cast<float*>(w + P.ws_part);
       d.dbpart = reinterpret_cast<float*>(w + P.ws_dbpart);
-      const int64_t nblk = (P.K16 / 16) * P.ncb;
+      const int64_t nblk = (d.K16 / 16) * P.ncb;
       d.ncb = P.ncb;
       d.vec4 = h % 4 == 0 && ((uintptr_t)dA & 15) == 0 && ((uintptr_t)argmax & 15) == 0;
       RELNN_REQUIRE(P.K16 <= 512, RELNN_E_UNSUPPORTED, "dense dW: K = %d too wide", P.K);
@@ -610,9 +631,14 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
         else
           launch_dw<float>(d, nblk, P.dw_units, P.dw_lds, s);
       }
-      k_dw_reduce<<<grid_for((int64_t)P.K * h + h), 256, 0, s>>>(d.part, d.dbpart, P.dw_units, P.K, P.K16, h, dW,
-                                                                   db, accum ? 1 : 0);
+      k_dw_reduce<<<grid_for((int64_t)Kv * h + h), 256, 0, s>>>(d.part, d.dbpart, P.dw_units, Kv, d.K16, h, dW,
+                                                                  db, accum ? 1 : 0);
       RELNN_LAUNCHED();
+      for (int j = P.kv, koff = Kv; j < L->k; koff += L->d[j], ++j) {
+        KTimer tm("bwd_dw", s);
+        gk_dw(idx, j, emb[j], L->dtype == RELNN_BF16, L->d[j], h, dA, dW + (int64_t)koff * h, accum,
+              reinterpret_cast<float*>(w + P.ws_gkx), reinterpret_cast<float*>(w + P.ws_gkpart), s);
+      }
     }
 
     // dz_j for every atom, in body order (through the per-row sums of dY)

@@ -116,5 +116,11 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
                 const float* dA, const uint32_t* own, int own_w, const uint8_t* mask, float* const* demb, char* ws,
                 hipStream_t s);
 size_t bwd_workspace(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P);
+// dW rows [d][h] of atom j when its FK is the group column, for MAX without
+// act_pre: sum_g x_j(g)^T dA_g over the groups (X: [G][d] FP32 workspace,
+// part: [gk_dw_chunks(G)][d][h] FP32 workspace).
+int gk_dw_chunks(int64_t G);
+void gk_dw(const relnn_index* idx, int j, const void* emb, bool bf16, int d, int h, const float* dA, float* dW_rows,
+           bool accum, float* X, float* part, hipStream_t s);
 
 }  // namespace relnn
