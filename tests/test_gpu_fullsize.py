@@ -123,7 +123,9 @@ def test_er_full_forward_sampled(er, which, dtype):
 def test_power_full_max_forward_backward_sampled(power):
     """Workload-4 MAX layer: sampled groups forward; backward at full size,
     checked on the embedding-gradient rows of sampled nodes (all tuples that
-    join them, routed by the kernel's own argmax) and on db."""
+    join them, routed by the kernel's own argmax), on db, on the dW rows of
+    the atom keyed by the group column in full and on sampled dW columns of
+    the other atom."""
     import torch
 
     from paper_2605_24207_amd import layer_bwd, layer_fwd
@@ -176,7 +178,20 @@ def test_power_full_max_forward_backward_sampled(power):
     scale = np.maximum(np.linalg.norm(dz_ref, axis=1), np.sqrt(sq))
     err = np.linalg.norm(dz_g - dz_ref, axis=1) / np.maximum(scale, 1e-30)
     assert err.max() <= 1e-5, err.max()
-    assert np.isfinite(dW.cpu().numpy()).all()
+    # dW, rows of atom t (keyed by the group column: every tuple of g joins
+    # the same row, and the routed gradients of g add up to dA_g) in full
+    dW_np = dW.cpu().numpy().astype(np.float64)
+    z64 = rule.atoms[0].emb.astype(np.float64)
+    x_t = z64[ref.rows[1][ref.offsets[:-1]]]
+    ref_t = x_t.T @ dA
+    del x_t
+    assert np.linalg.norm(dW_np[d:] - ref_t) <= 1e-5 * np.linalg.norm(ref_t)
+    # rows of atom s on sampled output columns: column c of g goes to the
+    # tuple the kernel chose, so dW_s[:, c] = sum_g dA[g, c] z[s row of that tuple]
+    for c in np.random.default_rng(29).choice(rule.h, 3, replace=False):
+        x_s = z64[ref.rows[0][am_np[:, c]]]
+        col = x_s.T @ dA[:, c]
+        assert np.linalg.norm(dW_np[:d, c] - col) <= 1e-5 * np.linalg.norm(col)
 
 
 def test_cobuy_full_precision_form(er):
