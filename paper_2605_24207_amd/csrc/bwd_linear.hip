@@ -377,13 +377,24 @@ void lin_bwd_dw(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
   RELNN_LAUNCHED();
 }
 
-// X[g][:] = the row of the atom that group g joins (rows[offsets[g]]), FP32.
+// X[g][:] = the row of the atom that group g joins (rows[offsets[g]]), FP32;
+// four columns per thread (d % 4 == 0).
 template <class T>
 __global__ void k_group_rows(const T* emb, const int32_t* rows, const int32_t* offsets, int64_t G, int d, float* X) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G * d; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t g = i / d;
-    const int c = (int)(i - g * d);
-    X[i] = (float)emb[(int64_t)rows[offsets[g]] * d + c];
+  const int d4 = d / 4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G * d4; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = i / d4;
+    const int c = 4 * (int)(i - g * d4);
+    const T* src = emb + (int64_t)rows[offsets[g]] * d + c;
+    f32x4 v;
+    if constexpr (std::is_same<T, float>::value) {
+      v = *reinterpret_cast<const f32x4*>(src);
+    } else {
+      const uint2 u = *reinterpret_cast<const uint2*>(src);
+      v = f32x4{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
+                __uint_as_float(u.y & 0xffff0000u)};
+    }
+    *reinterpret_cast<f32x4*>(X + g * d + c) = v;
   }
 }
 
@@ -395,9 +406,10 @@ void gk_dw(const relnn_index* idx, int j, const void* emb, bool bf16, int d, int
   if (G == 0) return;
   const int32_t* rows = idx->rows + (int64_t)j * E;
   if (bf16)
-    k_group_rows<__bf16><<<grid_n(G * d), 256, 0, s>>>(static_cast<const __bf16*>(emb), rows, idx->offsets, G, d, X);
+    k_group_rows<__bf16><<<grid_n(G * d / 4), 256, 0, s>>>(static_cast<const __bf16*>(emb), rows, idx->offsets, G, d,
+                                                           X);
   else
-    k_group_rows<float><<<grid_n(G * d), 256, 0, s>>>(static_cast<const float*>(emb), rows, idx->offsets, G, d, X);
+    k_group_rows<float><<<grid_n(G * d / 4), 256, 0, s>>>(static_cast<const float*>(emb), rows, idx->offsets, G, d, X);
   RELNN_LAUNCHED();
   // column-major partial b (h x d) = dA_b^T' (h x m) X_b (m x d)
   const int nb = gk_dw_chunks(G);
