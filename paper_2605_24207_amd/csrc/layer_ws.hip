@@ -273,38 +273,6 @@ __device__ __forceinline__ void dma_barrier() {
 }
 __device__ __forceinline__ void compute_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// Combining the 4 lanes of one output column (lanes c, c+16, c+32, c+48)
-// with the gfx950 row swaps (VALU, no LDS): after the 16-lane swap a lane
-// holds the values of its row pair, after the 32-lane swap all four.  The
-// operands are taken in the same order in every lane, so all four lanes end
-// with the same bits.
-__device__ __forceinline__ float col_sum4(float v) {
-  const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  const float s = __uint_as_float(p[0]) + __uint_as_float(p[1]);
-  const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
-  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
-}
-
-// Max with the earliest maximiser (ties: smaller tuple position).
-__device__ __forceinline__ void max_pick(float& v, int32_t& a, float v1, int32_t a1) {
-  const bool take = v1 > v || (v1 == v && a1 < a);
-  v = take ? v1 : v;
-  a = take ? a1 : a;
-}
-
-__device__ __forceinline__ void col_max4(float& v, int32_t& a) {
-  const auto pv = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  const auto pa = __builtin_amdgcn_permlane16_swap((uint32_t)a, (uint32_t)a, false, false);
-  v = __uint_as_float(pv[0]);
-  a = (int32_t)pa[0];
-  max_pick(v, a, __uint_as_float(pv[1]), (int32_t)pa[1]);
-  const auto qv = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  const auto qa = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)a, false, false);
-  v = __uint_as_float(qv[0]);
-  a = (int32_t)qa[0];
-  max_pick(v, a, __uint_as_float(qv[1]), (int32_t)qa[1]);
-}
-
 // y if bit i of m is set, else +0 (a bit mask, not a multiply: exact for
 // every y, infinities included)
 __device__ __forceinline__ float keep_bit(float y, uint32_t m, int i) {
