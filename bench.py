@@ -433,8 +433,8 @@ def main():
         copy_calibration(args.copy_gib)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(it would shard the tuple list by group ranges; not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
