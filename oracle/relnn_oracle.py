@@ -249,15 +249,3 @@ def layer_bwd(idx: Index, embs, W, b, pre, argmax, dout, agg="sum",
         demb.append(acc)
         off += d
     return demb, dW, db
-
-
-# ---------------------------------------------------------------------------
-# error measures (the relative bound of the precision forms)
-# ---------------------------------------------------------------------------
-def row_rel_err(z: np.ndarray, ref: np.ndarray) -> np.ndarray:
-    """Per output row ||z - ref||_2 / max(||ref||_2, 1e-30)."""
-    z = np.asarray(z, np.float64)
-    ref = np.asarray(ref, np.float64)
-    num = np.linalg.norm(z - ref, axis=-1)
-    den = np.maximum(np.linalg.norm(ref, axis=-1), 1e-30)
-    return num / den

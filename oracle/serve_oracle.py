@@ -6,9 +6,12 @@ future work (Section 6), so this part is a reading of ours, stated here and
 in the library header: a request is a set of seed items; hop 1 samples up to
 fanout1 buyers of each seed, hop 2 up to fanout2 Buys rows of each sampled
 buyer; a two-layer network of join rules (Section 3.1) runs on the sampled
-rows.  Parity unpinned by the paper: the sampler is pinned by SplitMix64's
-published test vectors and by properties of Floyd's algorithm, the network
-by the layer oracle of relnn_oracle (pinned on its own).
+rows.  Parity unpinned by the paper (sampling is not in it): the sampler is
+pinned by SplitMix64's published test vectors and by properties of Floyd's
+algorithm; the network by a hand-worked two-seed request
+(tests/golden/serve_two_seeds.json: several buyers per seed, several hop-2
+rows per buyer, biases) and by the three join rules of relnn_oracle (pinned
+on its own) evaluated on the same sampled link rows.
 
 SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
 generators", OOPSLA 2014) and Floyd's sampling algorithm (Bentley and

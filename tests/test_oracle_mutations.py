@@ -126,3 +126,58 @@ def test_planted_mistake_is_caught(name, monkeypatch):
 
 def test_unmutated_oracle_passes_every_pin(monkeypatch):
     assert not caught(monkeypatch)
+
+
+# ------------------------------------------------------------ serving oracle
+# Each mutant is a one-token slip applied to the source text of
+# oracle/serve_oracle.py; the mutated module replaces the real one and the
+# serving pins run against it.
+import inspect
+import types
+
+from oracle import serve_oracle as so
+from tests import test_serve_oracle as serve_pins
+
+SERVE_PINS = [
+    serve_pins.test_evaluate_golden_two_seeds,
+    serve_pins.test_evaluate_single_buyer_reduces_to_layer_formulas,
+    serve_pins.test_evaluate_matches_layer_oracle_on_sampled_rows,
+    serve_pins.test_splitmix64_published_vectors,
+    serve_pins.test_floyd_takes_everything_when_k_equals_n,
+    serve_pins.test_adjacency_orders,
+]
+
+SERVE_MUTANTS = {
+    "user_mean_as_sum": (".sum(axis=0) / k2", ".sum(axis=0)"),
+    "layer2_concat_swapped": ("[np.array(u1), np.repeat(i1[None], k1, 0)", "[np.repeat(i1[None], k1, 0), np.array(u1)"),
+    "k2_without_min": ("k2 = min(fanout2, du)", "k2 = fanout2"),
+    "layer2_bias_dropped": ("_lin(x, W[2], b[2])", "_lin(x, W[2], None)"),
+    "item1_cat_of_first_item": ("c = int(item_cat[s])", "c = int(item_cat[0])"),
+    "user_layer_no_relu": ("u1.append(np.maximum(_lin(x, W[0], b[0]).sum(axis=0) / k2, 0.0))",
+                           "u1.append(_lin(x, W[0], b[0]).sum(axis=0) / k2)"),
+}
+
+
+def _serve_caught():
+    for pin in SERVE_PINS:
+        try:
+            pin()
+        except Exception:
+            return True
+    return False
+
+
+@pytest.mark.parametrize("name", sorted(SERVE_MUTANTS))
+def test_planted_serving_mistake_is_caught(name, monkeypatch):
+    old, new = SERVE_MUTANTS[name]
+    src = inspect.getsource(so)
+    assert src.count(old) == 1, f"mutant {name} no longer matches the oracle's source"
+    mod = types.ModuleType("serve_oracle_mutant")
+    exec(compile(src.replace(old, new), "<serve_oracle mutant>", "exec"), mod.__dict__)
+    for attr in ("mix64", "splitmix64_stream", "stream_base", "draw", "floyd", "adjacency", "evaluate"):
+        monkeypatch.setattr(so, attr, getattr(mod, attr))
+    assert _serve_caught(), f"no pin caught the planted serving mistake {name}"
+
+
+def test_unmutated_serving_oracle_passes_every_pin():
+    assert not _serve_caught()
