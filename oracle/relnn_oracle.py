@@ -179,6 +179,11 @@ def gather_concat(idx: Index, embs: Sequence[np.ndarray], sel=slice(None)) -> np
     return np.concatenate(parts, axis=1)
 
 
+def act_pre_mask(idx: Index, embs, W, b) -> np.ndarray:
+    """[E, h] decisions x W + b > 0 of every joined tuple (ReLU'(0) = 0)."""
+    return gather_concat(idx, embs) @ np.asarray(W, np.float64) + np.asarray(b, np.float64) > 0
+
+
 def transform(x: np.ndarray, W: np.ndarray, b: np.ndarray, act_pre: str) -> np.ndarray:
     return _act(act_pre, x @ np.asarray(W, np.float64) + np.asarray(b, np.float64))
 
@@ -215,13 +220,15 @@ def layer_fwd(idx: Index, embs, W, b, agg="sum", act_pre="none", act_post="none"
 
 
 def layer_bwd(idx: Index, embs, W, b, pre, argmax, dout, agg="sum",
-              act_pre="none", act_post="none"):
+              act_pre="none", act_post="none", pre_mask=None):
     """Gradients of sum(out * dout) with respect to every atom's embedding,
     W and b (chain rule through the layer of ``layer_fwd``).
 
-    Returns (demb, dW, db); demb[j] has the shape of embs[j].  Atoms that
-    share one embedding relation (self-joins) get separate entries, which the
-    caller adds."""
+    ``pre_mask`` ([E, h] booleans, optional) gives the per-tuple decisions
+    act_pre'(x W + b) > 0 when they were taken in another precision (the
+    kernel's); by default they are computed here.  Returns (demb, dW, db);
+    demb[j] has the shape of embs[j].  Atoms that share one embedding
+    relation (self-joins) get separate entries, which the caller adds."""
     W64 = np.asarray(W, np.float64)
     dA = np.asarray(dout, np.float64) * _act_grad(act_post, np.asarray(pre, np.float64))
     x = gather_concat(idx, embs)
@@ -237,7 +244,10 @@ def layer_bwd(idx: Index, embs, W, b, pre, argmax, dout, agg="sum",
     else:
         raise ValueError(agg)
     if act_pre != "none":
-        dY = dY * _act_grad(act_pre, x @ W64 + np.asarray(b, np.float64))
+        if pre_mask is not None:
+            dY = dY * np.asarray(pre_mask, np.float64)
+        else:
+            dY = dY * _act_grad(act_pre, x @ W64 + np.asarray(b, np.float64))
     dW = x.T @ dY
     db = dY.sum(axis=0)
     dX = dY @ W64.T

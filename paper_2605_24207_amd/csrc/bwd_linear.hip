@@ -12,11 +12,11 @@
 //   dW = sum_g (sum_{tau in g} x_tau)^T dA_g = XS^T dA,   db = sum_g |g| dA_g.
 //
 // XS [G, K] and DS_j [rows of j, h] are segmented gather-sums over sorted
-// lists (k_seg_gather_sum: atomic-free, deterministic); the products are
-// library GEMMs on them, far smaller than the per-tuple ones.  dW of the
-// other layers is the per-tuple product of layer_bwd.hip.
-#include <rocblas/rocblas.h>
-
+// lists (k_seg_gather_sum: atomic-free, deterministic); the products on them
+// (gemm.hip: FP32 or, for bf16 layers, bf16 matrix-core products with FP32
+// accumulation) are far smaller than the per-tuple ones.  dW of the other
+// layers is the per-tuple product of layer_bwd.hip.
+#include "gemm.hpp"
 #include "layer_fwd.hpp"
 #include "prims.hpp"
 
@@ -205,72 +205,6 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
   }
 }
 
-// demb[row of g][:] += w_g dz[g][:] for an atom whose FK is the group column
-// (group g joins one row of it, rows[offsets[g]], and no other group does):
-// the per-row sum of the routed gradients is w_g dA_g with w_g = |g| (SUM,
-// MEAN: every tuple carries dA_g) or 1 (MAX: each column goes to exactly
-// one tuple of the group), so dz = dA W^T needs no pass over the tuples.
-// Four columns per thread (d % 4 == 0).
-__global__ void k_scatter_add_groups(const float* dz, const int32_t* rows, const int32_t* offsets, int64_t G, int d,
-                                     int unit_weight, float* demb) {
-  const int d4 = d / 4;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G * d4; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t g = i / d4;
-    const int c = 4 * (int)(i - g * d4);
-    const int64_t e0 = offsets[g];
-    const float wg = unit_weight ? 1.0f : (float)(offsets[g + 1] - e0);
-    f32x4* o = reinterpret_cast<f32x4*>(demb + (int64_t)rows[e0] * d + c);
-    *o += wg * *reinterpret_cast<const f32x4*>(dz + g * d + c);
-  }
-}
-
-// xs[g][K] = |g|: the extra column turns db into one more row of the dW product.
-__global__ void k_counts_col(const int32_t* offsets, int64_t G, int K, int ldx, float* xs) {
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x)
-    xs[g * ldx + K] = (float)(offsets[g + 1] - offsets[g]);
-}
-
-// dW[k][c] (+)= sum_b part[b][k][c] for k < K, db[c] (+)= sum_b part[b][K][c]
-// (when part has nrow = K + 1 rows): the split-K partials added in chunk
-// order.
-__global__ void k_sum_parts(const float* part, int nb, int nrow, int K, int h, float* dW, float* db, int accumulate) {
-  const int64_t total = (int64_t)nrow * h;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    float acc = 0.0f, comp = 0.0f;
-    for (int b = 0; b < nb; ++b) kahan_add1(acc, comp, part[(int64_t)b * total + i]);
-    const float v = acc - comp;
-    // part is column-major h x (K+1): i = k h + c
-    const int64_t k = i / h;
-    const int c = (int)(i - k * h);
-    if (k < K) {
-      float* o = dW + k * h + c;
-      *o = accumulate ? *o + v : v;
-    } else if (db) {
-      db[c] = accumulate ? db[c] + v : v;
-    }
-  }
-}
-
-__global__ void k_bf16_to_f32(const __bf16* x, int64_t n, float* y) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = (float)x[i];
-}
-
-// demb[row[s]][:] += dz[s][:], each row named by at most one segment;
-// four columns per thread (d % 4 == 0).
-__global__ void k_scatter_add_rows(const float* dz, const int32_t* row, int64_t nseg, int d, float* demb) {
-  const int d4 = d / 4;
-  const int64_t total = nseg * d4;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = i / d4;
-    const int c = 4 * (int)(i - s * d4);
-    f32x4* o = reinterpret_cast<f32x4*>(demb + (int64_t)row[s] * d + c);
-    *o += *reinterpret_cast<const f32x4*>(dz + s * d + c);
-  }
-}
-
-unsigned grid_n(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 1 << 16)); }
-
 int64_t gs_units(int64_t n) {
   const int64_t nt = cdiv(std::max<int64_t>(n, 1), kGsTM);
   return std::max<int64_t>(1, std::min<int64_t>(nt, 8192));
@@ -299,11 +233,8 @@ void seg_gather_sum(GsArgs a, int64_t nseg_units_cap, hipStream_t s) {
 // Workspace of the aggregated backward, after `base` bytes.
 LinBwdPlan plan_lin_bwd(const relnn_index* idx, const relnn_layer_desc* L, size_t base, bool xs_dw) {
   LinBwdPlan p;
-  int K = 0, dmax = 0;
-  for (int j = 0; j < L->k; ++j) {
-    K += L->d[j];
-    dmax = std::max(dmax, L->d[j]);
-  }
+  int K = 0;
+  for (int j = 0; j < L->k; ++j) K += L->d[j];
   int64_t nseg = 1;
   for (int j = 0; j < L->k; ++j) nseg = std::max<int64_t>(nseg, idx->t_nseg[j]);
   const int64_t G = std::max<int64_t>(idx->G, 1), E = std::max<int64_t>(idx->E, 1);
@@ -315,15 +246,12 @@ LinBwdPlan plan_lin_bwd(const relnn_index* idx, const relnn_layer_desc* L, size_
     return o;
   };
   p.units = gs_units(E);
-  p.ldx = (int)round_up(K + 1, 4);
-  p.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, G / 4096));
+  p.ldx = K;
   if (xs_dw) {
     p.ws_xs = take((size_t)G * p.ldx * 4);
-    p.ws_part = take((size_t)p.nchunk * (K + 1) * h * 4);
+    p.ws_part = take((size_t)gemm_tn_ws_floats(G, K, h) * 4);
   }
   p.ws_ds = take((size_t)nseg * h * 4);
-  p.ws_dz = take((size_t)nseg * dmax * 4);
-  p.ws_w32 = take((size_t)K * h * 4);
   p.ws_carry = take((size_t)p.units * 2 * std::max(p.ldx, h) * 4);
   p.total = off;
   return p;
@@ -338,7 +266,7 @@ void lin_bwd_dw(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
   float* xs = reinterpret_cast<float*>(w + P.ws_xs);
   KTimer tm("bwd_dw", s);
   // XS: per-group sums of the joined rows (canonical order, groups as
-  // segments), with |g| in column K
+  // segments)
   {
     GsArgs a{};
     int koff = 0;
@@ -358,69 +286,22 @@ void lin_bwd_dw(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
     a.ldo = P.ldx;
     a.carry = reinterpret_cast<float*>(w + P.ws_carry);
     seg_gather_sum(a, P.units, s);
-    k_counts_col<<<grid_n(G), 256, 0, s>>>(idx->offsets, G, K, P.ldx, xs);
-    RELNN_LAUNCHED();
   }
-  // [dW; db] = [XS, |g|]^T dA, split over nchunk chunks of groups (one
-  // batched product), then the partials summed in chunk order.  Column-major
-  // partial b (h x (K+1)) = dA_b^T' (h x m) XS_b (m x (K+1)).
-  float* part = reinterpret_cast<float*>(w + P.ws_part);
-  const int nb = P.nchunk;
-  const int64_t m = G / nb, rest = G - m * (nb - 1);
-  const int64_t spart = (int64_t)(K + 1) * h;
-  if (nb > 1)
-    blas_sgemm_strided_batched(false, true, h, K + 1, (int)m, dA, h, m * h, xs, P.ldx, m * P.ldx, part, h, spart,
-                               nb - 1, s);
-  blas_sgemm(false, true, h, K + 1, (int)rest, dA + (int64_t)(nb - 1) * m * h, h, xs + (int64_t)(nb - 1) * m * P.ldx,
-             P.ldx, 0.0f, part + (int64_t)(nb - 1) * spart, h, s);
-  k_sum_parts<<<grid_n(spart), 256, 0, s>>>(part, nb, K + 1, K, h, dW, db, accum ? 1 : 0);
-  RELNN_LAUNCHED();
+  // dW = XS^T dA and db = sum_g |g| dA_g, split over chunks of groups whose
+  // partials are added in chunk order
+  gemm_tn(L->dtype == RELNN_BF16, xs, false, P.ldx, nullptr, nullptr, dA, h, G, K, h, idx->offsets, dW, db, accum,
+          reinterpret_cast<float*>(w + P.ws_part), s);
 }
 
-// X[g][:] = the row of the atom that group g joins (rows[offsets[g]]), FP32;
-// four columns per thread (d % 4 == 0).
-template <class T>
-__global__ void k_group_rows(const T* emb, const int32_t* rows, const int32_t* offsets, int64_t G, int d, float* X) {
-  const int d4 = d / 4;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G * d4; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t g = i / d4;
-    const int c = 4 * (int)(i - g * d4);
-    const T* src = emb + (int64_t)rows[offsets[g]] * d + c;
-    f32x4 v;
-    if constexpr (std::is_same<T, float>::value) {
-      v = *reinterpret_cast<const f32x4*>(src);
-    } else {
-      const uint2 u = *reinterpret_cast<const uint2*>(src);
-      v = f32x4{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
-                __uint_as_float(u.y & 0xffff0000u)};
-    }
-    *reinterpret_cast<f32x4*>(X + g * d + c) = v;
-  }
-}
+int64_t gk_dw_ws_floats(int64_t G, int d, int h) { return gemm_tn_ws_floats(G, d, h); }
 
-int gk_dw_chunks(int64_t G) { return (int)std::max<int64_t>(1, std::min<int64_t>(64, G / 4096)); }
-
+// dW rows of atom j = sum_g x_j(g)^T dA_g, x_j(g) the row group g joins
+// (rows[offsets[g]]), gathered by the product itself.
 void gk_dw(const relnn_index* idx, int j, const void* emb, bool bf16, int d, int h, const float* dA, float* dW_rows,
-           bool accum, float* X, float* part, hipStream_t s) {
+           bool accum, float* part, hipStream_t s) {
   const int64_t G = idx->G, E = idx->E;
-  if (G == 0) return;
-  const int32_t* rows = idx->rows + (int64_t)j * E;
-  if (bf16)
-    k_group_rows<__bf16><<<grid_n(G * d / 4), 256, 0, s>>>(static_cast<const __bf16*>(emb), rows, idx->offsets, G, d,
-                                                           X);
-  else
-    k_group_rows<float><<<grid_n(G * d / 4), 256, 0, s>>>(static_cast<const float*>(emb), rows, idx->offsets, G, d, X);
-  RELNN_LAUNCHED();
-  // column-major partial b (h x d) = dA_b^T' (h x m) X_b (m x d)
-  const int nb = gk_dw_chunks(G);
-  const int64_t m = G / nb, rest = G - m * (nb - 1);
-  const int64_t spart = (int64_t)d * h;
-  if (nb > 1)
-    blas_sgemm_strided_batched(false, true, h, d, (int)m, dA, h, m * h, X, d, m * d, part, h, spart, nb - 1, s);
-  blas_sgemm(false, true, h, d, (int)rest, dA + (int64_t)(nb - 1) * m * h, h, X + (int64_t)(nb - 1) * m * d, d, 0.0f,
-             part + (int64_t)(nb - 1) * spart, h, s);
-  k_sum_parts<<<grid_n(spart), 256, 0, s>>>(part, nb, d, d, h, dW_rows, nullptr, accum ? 1 : 0);
-  RELNN_LAUNCHED();
+  gemm_tn(bf16, emb, bf16, d, idx->rows + (int64_t)j * E, idx->offsets, dA, h, G, d, h, nullptr, dW_rows, nullptr,
+          accum, part, s);
 }
 
 void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdPlan& P, const void* W,
@@ -428,35 +309,31 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
                 hipStream_t s) {
   const int h = L->h;
   const int64_t E = idx->E;
-  int K = 0;
-  for (int j = 0; j < L->k; ++j) K += L->d[j];
-  // W in FP32 for the products
-  const float* W32 = static_cast<const float*>(W);
-  if (L->dtype == RELNN_BF16) {
-    float* w32 = reinterpret_cast<float*>(w + P.ws_w32);
-    k_bf16_to_f32<<<grid_n((int64_t)K * h), 256, 0, s>>>(static_cast<const __bf16*>(W), (int64_t)K * h, w32);
-    RELNN_LAUNCHED();
-    W32 = w32;
-  }
+  const bool bf16 = L->dtype == RELNN_BF16;
+  const size_t esz = bf16 ? 2 : 4;
   const bool routed = own != nullptr || mask != nullptr;
-  // dz_j = DS_j W_j^T, added into the rows of atom j
+  // dz_j = DS_j W_j^T, added into the rows of atom j.  W_j = rows koff.. of
+  // W ([d][h]), so the product's B[k][n] = W[koff + n][k] (k < h, n < d).
   for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
     const int d = L->d[j];
     const int64_t nseg = idx->t_nseg[j];
     if (nseg == 0) continue;
     RELNN_REQUIRE(d % 4 == 0, RELNN_E_UNSUPPORTED, "backward needs d %% 4 == 0");
-    if (idx->atom_gk[j] && mask == nullptr) {                       // one row per group: DS_j = w_g dA
-      float* dz = reinterpret_cast<float*>(w + P.ws_dz);            // [G][d], G = nseg here
+    const void* Wj = static_cast<const char*>(W) + (size_t)koff * h * esz;
+    if (idx->atom_gk[j] && mask == nullptr) {
+      // one row per group: DS_j[row of g] = w_g dA_g, w_g = |g| (SUM, MEAN)
+      // or 1 (MAX: each column goes to exactly one tuple of the group)
       KTimer tm("bwd_dx", s);
-      blas_sgemm(true, false, d, (int)idx->G, h, W32 + (size_t)koff * h, h, dA, h, 0.0f, dz, d, s);
-      k_scatter_add_groups<<<grid_n(idx->G * d / 4), 256, 0, s>>>(dz, idx->rows + (int64_t)j * E, idx->offsets,
-                                                                  idx->G, d, L->agg == RELNN_MAX ? 1 : 0, demb[j]);
-      RELNN_LAUNCHED();
+      RowsEpi epi;
+      epi.orow = idx->rows + (int64_t)j * E;
+      epi.oidx = idx->offsets;
+      epi.wcnt = L->agg == RELNN_MAX ? nullptr : idx->offsets;
+      epi.accumulate = true;
+      gemm_rows(bf16, dA, false, h, idx->G, h, Wj, bf16, true, h, d, demb[j], d, epi, s);
       continue;
     }
     const int32_t* tg = idx->t_grp[j];                               // group of each transposed tuple
     float* ds = reinterpret_cast<float*>(w + P.ws_ds);
-    float* dz = reinterpret_cast<float*>(w + P.ws_dz);
     KTimer tm("bwd_dx", s);
     GsArgs a{};
     a.emb[0] = dA;
@@ -476,11 +353,10 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
     a.own_w = own_w;
     a.mask = mask;
     seg_gather_sum(a, P.units, s);
-    // DZ [nseg][d] = DS [nseg][h] W_j^T, W_j = rows koff.. of W ([d][h]):
-    // column-major DZ^T (d x nseg) = W_j^T' (d x h) DS^T (h x nseg)
-    blas_sgemm(true, false, d, (int)nseg, h, W32 + (size_t)koff * h, h, ds, h, 0.0f, dz, d, s);
-    k_scatter_add_rows<<<grid_n(nseg * d / 4), 256, 0, s>>>(dz, idx->t_segrow[j], nseg, d, demb[j]);
-    RELNN_LAUNCHED();
+    RowsEpi epi;
+    epi.orow = idx->t_segrow[j];
+    epi.accumulate = true;
+    gemm_rows(bf16, ds, false, h, nseg, h, Wj, bf16, true, h, d, demb[j], d, epi, s);
   }
 }
 

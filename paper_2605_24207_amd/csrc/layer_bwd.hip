@@ -426,7 +426,7 @@ struct BwdPlan {
   size_t dw_lds = 0;
   size_t ws_mask = 0, ws_fwsw = 0, ws_part = 0, ws_dbpart = 0, ws_dA = 0, ws_own = 0, total = 0;
   int kv = 0;                // MAX: atoms dW takes per tuple (the others are keyed by the group column)
-  size_t ws_gkx = 0, ws_gkpart = 0;
+  size_t ws_gkpart = 0;
   bool xs_dw = false;        // dW through the per-group sums (SUM / MEAN, affine)
   LinBwdPlan lin;
 };
@@ -471,15 +471,11 @@ BwdPlan plan_bwd(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   p.kv = L->k;
   if (L->agg == RELNN_MAX && L->act_pre == RELNN_ACT_NONE)
     while (p.kv > 1 && idx->atom_gk[p.kv - 1]) --p.kv;
-  p.ws_gkx = off;
   p.ws_gkpart = off;
   if (p.kv < L->k) {
-    int dmax = 0;
-    for (int j = p.kv; j < L->k; ++j) dmax = std::max(dmax, L->d[j]);
-    const int64_t G = std::max<int64_t>(idx->G, 1);
-    off += round_up(G * dmax * 4, 256);
-    p.ws_gkpart = off;
-    off += round_up((int64_t)gk_dw_chunks(G) * dmax * L->h * 4, 256);
+    int64_t nf = 0;
+    for (int j = p.kv; j < L->k; ++j) nf = std::max(nf, gk_dw_ws_floats(idx->G, L->d[j], L->h));
+    off += round_up(nf * 4, 256);
   }
   p.lin = plan_lin_bwd(idx, L, off, p.xs_dw);
   p.total = p.lin.total;
@@ -637,7 +633,7 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
       for (int j = P.kv, koff = Kv; j < L->k; koff += L->d[j], ++j) {
         KTimer tm("bwd_dw", s);
         gk_dw(idx, j, emb[j], L->dtype == RELNN_BF16, L->d[j], h, dA, dW + (int64_t)koff * h, accum,
-              reinterpret_cast<float*>(w + P.ws_gkx), reinterpret_cast<float*>(w + P.ws_gkpart), s);
+              reinterpret_cast<float*>(w + P.ws_gkpart), s);
       }
     }
 

@@ -16,6 +16,7 @@
 // Y = [E, h] in HBM, the shape of a library pipeline (index_select + cat
 // -> Linear -> scatter).
 #include "layer_common.hpp"
+#include "gemm.hpp"
 #include "layer_fwd.hpp"
 
 namespace relnn {
@@ -519,8 +520,10 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
       for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
         Pj[j] = reinterpret_cast<const float*>(w + P.ws_push_p[j]);
         KTimer t("node_gemm", s);
-        plain_gemm(L->dtype, emb[j], idx->n_rows[j], L->d[j], L->d[j],
-                   static_cast<const char*>(W) + (size_t)koff * L->h * esz, L->h, const_cast<float*>(Pj[j]), s);
+        const bool bf16 = L->dtype == RELNN_BF16;
+        gemm_rows(bf16, emb[j], bf16, L->d[j], idx->n_rows[j], L->d[j],
+                  static_cast<const char*>(W) + (size_t)koff * L->h * esz, bf16, false, L->h, L->h,
+                  const_cast<float*>(Pj[j]), L->h, RowsEpi{}, s);
       }
       // atoms varying inside a group are gathered per tuple; the others
       // (and the bias) are one constant per group

@@ -89,23 +89,14 @@ void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P,
                  float* carry, int32_t* carry_arg, int64_t G, float* V, hipStream_t s);
 int64_t push_units(int64_t E);
 
-// Column-major rocBLAS FP32 products: C = op(A) op(B) + beta C,
-// batch of C_i = op(A_i) op(B_i) (strides in elements), y = A x + beta y.
-void blas_sgemm(bool ta, bool tb, int m, int n, int k, const float* A, int lda, const float* B, int ldb, float beta,
-                float* C, int ldc, hipStream_t s);
-void blas_sgemm_strided_batched(bool ta, bool tb, int m, int n, int k, const float* A, int lda, int64_t sa,
-                                const float* B, int ldb, int64_t sb, float* C, int ldc, int64_t sc, int batch,
-                                hipStream_t s);
-void blas_sgemv(int m, int n, const float* A, int lda, const float* x, float beta, float* y, hipStream_t s);
-
 // Backward through sums over groups and joined rows (bwd_linear.hip).
 // lin_bwd_dx: dz_j of every atom, for any layer (routed by argmax for MAX,
 // masked by act_pre'); lin_bwd_dw: dW and db when the transform is affine
 // and the aggregate SUM or MEAN (xs_dw).
 struct LinBwdPlan {
   int64_t units = 0;
-  int ldx = 0, nchunk = 1;
-  size_t ws_xs = 0, ws_part = 0, ws_ds = 0, ws_dz = 0, ws_w32 = 0, ws_carry = 0, total = 0;
+  int ldx = 0;
+  size_t ws_xs = 0, ws_part = 0, ws_ds = 0, ws_carry = 0, total = 0;
 };
 LinBwdPlan plan_lin_bwd(const relnn_index* idx, const relnn_layer_desc* L, size_t base, bool xs_dw);
 void lin_bwd_dw(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdPlan& P, const void* const* emb,
@@ -117,10 +108,10 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
                 hipStream_t s);
 size_t bwd_workspace(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P);
 // dW rows [d][h] of atom j when its FK is the group column, for MAX without
-// act_pre: sum_g x_j(g)^T dA_g over the groups (X: [G][d] FP32 workspace,
-// part: [gk_dw_chunks(G)][d][h] FP32 workspace).
-int gk_dw_chunks(int64_t G);
+// act_pre: sum_g x_j(g)^T dA_g over the groups (part: gk_dw_ws_floats(G, d,
+// h) FP32 workspace).
+int64_t gk_dw_ws_floats(int64_t G, int d, int h);
 void gk_dw(const relnn_index* idx, int j, const void* emb, bool bf16, int d, int h, const float* dA, float* dW_rows,
-           bool accum, float* X, float* part, hipStream_t s);
+           bool accum, float* part, hipStream_t s);
 
 }  // namespace relnn

@@ -185,44 +185,6 @@ void plain_gemm(int dtype, const void* X, int64_t n, int K, int ldx, const void*
   }
 }
 
-void blas_sgemm(bool ta, bool tb, int m, int n, int k, const float* A, int lda, const float* B, int ldb, float beta,
-                float* C, int ldc, hipStream_t s) {
-  if (m <= 0 || n <= 0) return;
-  std::lock_guard<std::mutex> lk(g_blas_mu);
-  rocblas_handle hb = blas_for_current_device();
-  RELNN_REQUIRE(rocblas_set_stream(hb, s) == rocblas_status_success, RELNN_E_HIP, "rocblas_set_stream failed");
-  const float one = 1.0f;
-  const rocblas_status st =
-      rocblas_sgemm(hb, ta ? rocblas_operation_transpose : rocblas_operation_none,
-                    tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &one, A, lda, B, ldb, &beta, C, ldc);
-  RELNN_REQUIRE(st == rocblas_status_success, RELNN_E_HIP, "rocBLAS sgemm failed (status %d)", (int)st);
-}
-
-void blas_sgemm_strided_batched(bool ta, bool tb, int m, int n, int k, const float* A, int lda, int64_t sa,
-                                const float* B, int ldb, int64_t sb, float* C, int ldc, int64_t sc, int batch,
-                                hipStream_t s) {
-  if (m <= 0 || n <= 0 || batch <= 0) return;
-  std::lock_guard<std::mutex> lk(g_blas_mu);
-  rocblas_handle hb = blas_for_current_device();
-  RELNN_REQUIRE(rocblas_set_stream(hb, s) == rocblas_status_success, RELNN_E_HIP, "rocblas_set_stream failed");
-  const float one = 1.0f, zero = 0.0f;
-  const rocblas_status st = rocblas_sgemm_strided_batched(
-      hb, ta ? rocblas_operation_transpose : rocblas_operation_none,
-      tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &one, A, lda, sa, B, ldb, sb, &zero, C, ldc,
-      sc, batch);
-  RELNN_REQUIRE(st == rocblas_status_success, RELNN_E_HIP, "rocBLAS batched sgemm failed (status %d)", (int)st);
-}
-
-void blas_sgemv(int m, int n, const float* A, int lda, const float* x, float beta, float* y, hipStream_t s) {
-  if (m <= 0) return;
-  std::lock_guard<std::mutex> lk(g_blas_mu);
-  rocblas_handle hb = blas_for_current_device();
-  RELNN_REQUIRE(rocblas_set_stream(hb, s) == rocblas_status_success, RELNN_E_HIP, "rocblas_set_stream failed");
-  const float one = 1.0f;
-  const rocblas_status st = rocblas_sgemv(hb, rocblas_operation_none, m, n, &one, A, lda, x, 1, &beta, y, 1);
-  RELNN_REQUIRE(st == rocblas_status_success, RELNN_E_HIP, "rocBLAS sgemv failed (status %d)", (int)st);
-}
-
 int64_t seg_reduce_units(int64_t E) {
   const int64_t ntiles = cdiv(std::max<int64_t>(E, 1), kRedTM);
   return std::max<int64_t>(1, std::min<int64_t>(ntiles, 32768));   // 128 waves per CU

@@ -365,3 +365,27 @@ def test_bf16_round():
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == np.float32(1.0078125)
     assert r[3] == np.float32(1.015625) and r[4] == -2.5
     assert abs(r[5] - 3.0e-3) <= 3.0e-3 * 2 ** -8
+
+
+def test_bwd_given_act_pre_mask_equals_computed():
+    """Passing the act_pre' decisions computed from the same inputs changes
+    nothing; flipping one decision changes only the gradients it feeds."""
+    rule = relgen.node_edge(seed=3, n_nodes=40, n_edges=120, d=8, h=8, agg="sum", act_pre="relu",
+                            act_post="none", bias_std=0.3)
+    idx = orc.build_index(rule)
+    embs = [a.emb for a in rule.atoms]
+    _, pre, am = orc.layer_fwd(idx, embs, rule.W, rule.b, "sum", "relu", "none")
+    dout = np.random.default_rng(0).standard_normal(pre.shape)
+    base = orc.layer_bwd(idx, embs, rule.W, rule.b, pre, am, dout, "sum", "relu", "none")
+    mask = orc.act_pre_mask(idx, embs, rule.W, rule.b)
+    given = orc.layer_bwd(idx, embs, rule.W, rule.b, pre, am, dout, "sum", "relu", "none", pre_mask=mask)
+    for a, b in zip(base[0] + [base[1], base[2]], given[0] + [given[1], given[2]]):
+        np.testing.assert_array_equal(a, b)
+    flipped = mask.copy()
+    flipped[0, 0] = not flipped[0, 0]
+    _, dW, db = orc.layer_bwd(idx, embs, rule.W, rule.b, pre, am, dout, "sum", "relu", "none", pre_mask=flipped)
+    sign = 1.0 if flipped[0, 0] else -1.0
+    np.testing.assert_allclose(db - base[2], sign * np.eye(8)[0] * dout[idx.tuple_group[0], 0], atol=1e-12)
+    x0 = orc.gather_concat(idx, embs, [0])[0]
+    np.testing.assert_allclose(dW - base[1], sign * np.outer(x0, np.eye(8)[0]) * dout[idx.tuple_group[0], 0],
+                               atol=1e-12)
