@@ -289,7 +289,10 @@ void lin_bwd_dw(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
   }
   // dW = XS^T dA and db = sum_g |g| dA_g, split over chunks of groups whose
   // partials are added in chunk order
-  gemm_tn(L->dtype == RELNN_BF16, xs, false, P.ldx, nullptr, nullptr, dA, h, G, K, h, idx->offsets, dW, db, accum,
+  TnB B;
+  B.B = dA;
+  B.ldb = h;
+  gemm_tn(L->dtype == RELNN_BF16, xs, false, P.ldx, nullptr, nullptr, B, G, K, h, idx->offsets, dW, db, accum,
           reinterpret_cast<float*>(w + P.ws_part), s);
 }
 
@@ -300,7 +303,10 @@ int64_t gk_dw_ws_floats(int64_t G, int d, int h) { return gemm_tn_ws_floats(G, d
 void gk_dw(const relnn_index* idx, int j, const void* emb, bool bf16, int d, int h, const float* dA, float* dW_rows,
            bool accum, float* part, hipStream_t s) {
   const int64_t G = idx->G, E = idx->E;
-  gemm_tn(bf16, emb, bf16, d, idx->rows + (int64_t)j * E, idx->offsets, dA, h, G, d, h, nullptr, dW_rows, nullptr,
+  TnB B;
+  B.B = dA;
+  B.ldb = h;
+  gemm_tn(bf16, emb, bf16, d, idx->rows + (int64_t)j * E, idx->offsets, B, G, d, h, nullptr, dW_rows, nullptr,
           accum, part, s);
 }
 

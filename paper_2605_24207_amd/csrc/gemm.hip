@@ -33,7 +33,7 @@ namespace relnn {
 
 namespace {
 
-constexpr int kRowsWaves = 4;
+constexpr int kRowsWaves = 8;
 constexpr int kRowsTM = 16 * kRowsWaves;     // rows per tile of gemm_rows
 constexpr int kKC = 64;                      // k per register chunk
 constexpr int kSlabBytes = 64 * 1024;        // B fragments per block (two blocks per CU)
@@ -198,20 +198,44 @@ __global__ void __launch_bounds__(kRowsWaves * 64) k_gemm_rows(RowsArgs a) {
       }
     }
   };
+  // Epilogue of a tile: destination rows and scales are looked up one tile
+  // ahead (they depend on index loads), and the values a tile adds into are
+  // loaded before its products, so neither wait sits in front of the stores.
+  int64_t dst_cur[4], dst_nxt[4];
+  float sc_cur[4], sc_nxt[4];
+  float cv[4][NCB];
+  auto epi_rows = [&](int64_t tt, int64_t (&dst)[4], float (&sc)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = min<int64_t>(tt * kRowsTM + 16 * w + 4 * lg + r, a.M - 1);
+      dst[r] = a.epi.orow ? (int64_t)a.epi.orow[a.epi.oidx ? a.epi.oidx[m] : m] : m;
+      sc[r] = a.epi.wcnt ? (float)(a.epi.wcnt[m + 1] - a.epi.wcnt[m]) : 1.0f;
+    }
+  };
+  auto epi_load = [&](int64_t tt) {
+    if (!a.epi.accumulate) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool on = tt * kRowsTM + 16 * w + 4 * lg + r < a.M;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int n = min(n0 + 16 * cb + lm, a.N - 1);
+        cv[r][cb] = on ? a.C[dst_cur[r] * a.ldc + n] : 0.0f;
+      }
+    }
+  };
   auto epilogue = [&](int64_t tt) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t m = tt * kRowsTM + 16 * w + 4 * lg + r;
       if (m < a.M) {
-        const int64_t dst = a.epi.orow ? (int64_t)a.epi.orow[a.epi.oidx ? a.epi.oidx[m] : m] : m;
-        const float sc = a.epi.wcnt ? (float)(a.epi.wcnt[m + 1] - a.epi.wcnt[m]) : 1.0f;
-        float* crow = a.C + dst * a.ldc;
+        float* crow = a.C + dst_cur[r] * a.ldc;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
           const int n = n0 + 16 * cb + lm;
           if (n < a.N) {
-            const float v = sc * acc[cb][r];
-            crow[n] = a.epi.accumulate ? crow[n] + v : v;
+            const float v = sc_cur[r] * acc[cb][r];
+            crow[n] = a.epi.accumulate ? cv[r][cb] + v : v;
           }
         }
       }
@@ -222,6 +246,9 @@ __global__ void __launch_bounds__(kRowsWaves * 64) k_gemm_rows(RowsArgs a) {
 
   uint4 cur[4], nxt[4];
   load_chunk(t, 0, cur);
+  epi_rows(t, dst_cur, sc_cur);
+  epi_rows(min<int64_t>(t + gridDim.x, a.ntiles - 1), dst_nxt, sc_nxt);
+  epi_load(t);
   int c = 0;
   for (;;) {
     int64_t tn = t;
@@ -235,6 +262,13 @@ __global__ void __launch_bounds__(kRowsWaves * 64) k_gemm_rows(RowsArgs a) {
     if (cn == 0) {
       epilogue(t);
       if (tn >= a.ntiles) break;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        dst_cur[r] = dst_nxt[r];
+        sc_cur[r] = sc_nxt[r];
+      }
+      epi_load(tn);
+      epi_rows(min<int64_t>(tn + gridDim.x, a.ntiles - 1), dst_nxt, sc_nxt);
     }
     t = tn;
     c = cn;
@@ -273,11 +307,11 @@ struct TnArgs {
   int64_t lda;
   const int32_t* arow;
   const int32_t* aidx;
-  const float* B;
-  int64_t ldb;
+  TnB b;
   int64_t M;
   int Ka, N;
-  const int32_t* wcnt;
+  const int32_t* wcnt;   // db weights (null: 1)
+  int do_db;
   float* part;     // [nchunk][Ka][N]
   float* dbpart;   // [nchunk][N]
   int64_t ntiles, nchunk;
@@ -302,7 +336,8 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
   const int i0 = blockIdx.y * 128, n0 = blockIdx.z * 128;
   const int64_t ch = blockIdx.x;
   const int64_t tb = a.ntiles * ch / a.nchunk, te = a.ntiles * (ch + 1) / a.nchunk;
-  const bool do_db = a.wcnt != nullptr && blockIdx.y == 0;
+  const bool do_db = a.do_db && blockIdx.y == 0;
+  const bool route = a.b.own != nullptr || a.b.mask != nullptr;
   const bool wave_on = i0 + 16 * w < a.Ka;
 
   int unit_mat[PER], unit_mg[PER], unit_cg[PER];
@@ -316,7 +351,8 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
   }
   int64_t rn[PER][4];                              // source rows of the A units (next tile to load)
   f32x4 x[PER][4];                                 // loaded values, one f32x4 per unit row
-  int32_t cnt[PER][4];                             // group sizes of the B unit rows (db)
+  int32_t cnt[PER][4] = {};                        // db weights of the B unit rows
+  uint32_t keep[PER][4] = {};                      // routing of the B unit rows: one bit per column
   auto fetch_idx = [&](int64_t t) {
 #pragma unroll
     for (int p = 0; p < PER; ++p)
@@ -325,6 +361,8 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
         const int64_t m = min<int64_t>(t * MT + 4 * unit_mg[p] + r, a.M - 1);
         if (unit_mat[p] == 0 && a.arow)
           rn[p][r] = a.arow[a.aidx ? a.aidx[m] : m];
+        else if (unit_mat[p] == 1 && a.b.brow)
+          rn[p][r] = a.b.brow[m];
         else
           rn[p][r] = m;
       }
@@ -347,8 +385,19 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
         const int col = min(n0 + 4 * unit_cg[p], a.N - 4);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          x[p][r] = *reinterpret_cast<const f32x4*>(a.B + rn[p][r] * a.ldb + col);
-          if (do_db) cnt[p][r] = a.wcnt[rn[p][r] + 1] - a.wcnt[rn[p][r]];
+          const int64_t m = min<int64_t>(t * MT + 4 * unit_mg[p] + r, a.M - 1);
+          x[p][r] = *reinterpret_cast<const f32x4*>(a.b.B + rn[p][r] * a.b.ldb + col);
+          if (do_db && a.wcnt) cnt[p][r] = a.wcnt[m + 1] - a.wcnt[m];
+          if (route) {                              // the four columns col .. col + 3 of row m
+            uint32_t k = 15u;
+            if (a.b.own) k &= a.b.own[m * a.b.own_w + (col >> 5)] >> (col & 31);
+            if (a.b.mask) {
+              const uint32_t mb = *reinterpret_cast<const uint32_t*>(a.b.mask + m * a.b.mask_ld + col);
+              k &= (uint32_t)((mb & 0xffu) != 0) | ((uint32_t)((mb & 0xff00u) != 0) << 1) |
+                   ((uint32_t)((mb & 0xff0000u) != 0) << 2) | ((uint32_t)((mb & 0xff000000u) != 0) << 3);
+            }
+            keep[p][r] = k;
+          }
         }
       }
     }
@@ -365,7 +414,11 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
       for (int r = 0; r < 4; ++r) {
         const bool on = col_on && t * MT + 4 * mg + r < a.M;
         v[r] = on ? x[p][r] : f32x4{0.f, 0.f, 0.f, 0.f};
-        if (mat == 1 && do_db) dbacc += (on ? (float)cnt[p][r] : 0.0f) * v[r];
+        if (mat == 1 && route) {
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) v[r][cc] = ((keep[p][r] >> cc) & 1u) ? v[r][cc] : 0.0f;
+        }
+        if (mat == 1 && do_db) dbacc += (on ? (a.wcnt ? (float)cnt[p][r] : 1.0f) : 0.0f) * v[r];
       }
       LT* dst = base + (mat * 128 + 4 * cg) * TS + 4 * mg;
 #pragma unroll
@@ -555,15 +608,15 @@ int64_t gemm_tn_ws_floats(int64_t M, int Ka, int N) {
 }
 
 void gemm_tn(bool mfma_bf16, const void* Asrc, bool a_bf16, int64_t lda, const int32_t* arow, const int32_t* aidx,
-             const float* B, int64_t ldb, int64_t M, int Ka, int N, const int32_t* wcnt, float* D, float* db,
-             bool accumulate, float* ws, hipStream_t s) {
+             const TnB& B, int64_t M, int Ka, int N, const int32_t* wcnt, float* D, float* db, bool accumulate,
+             float* ws, hipStream_t s) {
   if (Ka <= 0 || N <= 0) return;
-  RELNN_REQUIRE(Ka % 4 == 0 && N % 4 == 0 && lda % 4 == 0 && ldb % 4 == 0, RELNN_E_UNSUPPORTED,
-                "product widths %d x %d not supported", Ka, N);
+  RELNN_REQUIRE(Ka % 4 == 0 && N % 4 == 0 && lda % 4 == 0 && B.ldb % 4 == 0 && (!B.mask || B.mask_ld % 4 == 0),
+                RELNN_E_UNSUPPORTED, "product widths %d x %d not supported", Ka, N);
   if (M <= 0) {
     k_zero_or_keep<<<grid_1d((int64_t)Ka * N), 256, 0, s>>>(D, (int64_t)Ka * N, accumulate ? 1 : 0);
     RELNN_LAUNCHED();
-    if (db && wcnt) {
+    if (db) {
       k_zero_or_keep<<<1, 256, 0, s>>>(db, N, accumulate ? 1 : 0);
       RELNN_LAUNCHED();
     }
@@ -574,12 +627,12 @@ void gemm_tn(bool mfma_bf16, const void* Asrc, bool a_bf16, int64_t lda, const i
   a.lda = lda;
   a.arow = arow;
   a.aidx = aidx;
-  a.B = B;
-  a.ldb = ldb;
+  a.b = B;
   a.M = M;
   a.Ka = Ka;
   a.N = N;
-  a.wcnt = (db != nullptr) ? wcnt : nullptr;
+  a.wcnt = wcnt;
+  a.do_db = db != nullptr;
   a.nchunk = tn_chunks(M, Ka, N);
   a.part = ws;
   a.dbpart = ws + a.nchunk * Ka * N;
@@ -594,8 +647,8 @@ void gemm_tn(bool mfma_bf16, const void* Asrc, bool a_bf16, int64_t lda, const i
     else
       launch_tn<float, false>(a, s);
   }
-  k_tn_sum<<<grid_1d((int64_t)Ka * N + N), 256, 0, s>>>(a.part, a.dbpart, a.nchunk, Ka, N, D,
-                                                         a.wcnt ? db : nullptr, accumulate ? 1 : 0);
+  k_tn_sum<<<grid_1d((int64_t)Ka * N + N), 256, 0, s>>>(a.part, a.dbpart, a.nchunk, Ka, N, D, db,
+                                                         accumulate ? 1 : 0);
   RELNN_LAUNCHED();
 }
 

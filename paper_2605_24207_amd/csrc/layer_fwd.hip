@@ -337,10 +337,14 @@ FwdPlan plan_fwd(const relnn_index* idx, const relnn_layer_desc* L) {
   }
   const int64_t E = idx->E;
   P.ntiles = P.TM ? cdiv(E, P.TM) : 0;
-  // carry partials: one pair per unit of whichever forward kernel runs
+  // carry partials: one pair per unit of the forward kernel that runs (the
+  // plain path's segmented reduce; else the persistent fused kernel where it
+  // covers the shape, the tile kernel otherwise)
   const WsPlan wp = plan_ws(L->dtype, K, h, E);
-  P.carry_units = std::max<int64_t>(1, std::max<int64_t>(P.ntiles, wp.KP ? wp.nunits : 0));
-  const size_t wsw = std::max<size_t>((size_t)P.Kp * h * esz, wp.KP ? wp.wsw_bytes : 0);
+  const bool plain = (L->flags & RELNN_PLAIN) != 0;
+  P.carry_units = std::max<int64_t>(1, plain ? seg_reduce_units(E) : wp.KP ? wp.nunits : P.ntiles);
+  // the weight as the kernel that runs reads it (the plain path reads W as given)
+  const size_t wsw = plain ? 0 : wp.KP ? wp.wsw_bytes : (size_t)P.Kp * h * esz;
   size_t off = 0;
   P.ws_wsw = off;
   off += round_up(wsw, 256);
@@ -461,11 +465,17 @@ extern "C" relnn_status relnn_workspace_size(const relnn_index* idx, const relnn
   });
 }
 
-extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_layer_desc* L,
-                                        const void* const* emb, const void* W, const float* b, float* out,
-                                        float* pre, int32_t* argmax, void* ws, size_t ws_bytes,
-                                        relnn_stream_t stream) {
-  return guard([&] {
+namespace relnn {
+
+size_t layer_fwd_ws_bytes(const relnn_index* idx, const relnn_layer_desc* L) {
+  const FwdPlan P = checked_plan(idx, L);
+  return (L->flags & RELNN_PUSHDOWN) ? P.ws_push : (L->flags & RELNN_PLAIN) ? P.ws_plain : P.ws_fused;
+}
+
+void layer_fwd_run(const relnn_index* idx, const relnn_layer_desc* L, const void* const* emb, const void* W,
+                   const float* b, float* out, float* pre, int32_t* argmax, void* ws, size_t ws_bytes,
+                   hipStream_t stream) {
+  {
     FwdPlan P = checked_plan(idx, L);
     const bool plain = (L->flags & RELNN_PLAIN) != 0;
     const bool push = (L->flags & RELNN_PUSHDOWN) != 0;
@@ -492,7 +502,6 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
     if (idx->E == 0) return;
     hipStream_t s = (hipStream_t)stream;
     char* w = static_cast<char*>(ws);
-    if (!push) swizzle_w(W, L->dtype, P.K, P.Kp, L->h, w + P.ws_wsw, s);
     FwdArgs a{};
     a.at = make_atoms(L, emb, idx);
     a.rows = idx->rows;
@@ -554,14 +563,28 @@ extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_laye
       return;
     }
     const WsPlan wp = plan_ws(L->dtype, P.K, L->h, idx->E);
-    RELNN_REQUIRE(P.ntiles <= P.carry_units && (!wp.KP || wp.nunits <= P.carry_units) &&
-                      (!wp.KP || wp.wsw_bytes <= P.ws_carry - P.ws_wsw),
-                  RELNN_E_HIP, "internal: workspace plan does not cover the launch");
     if (!plain && wp.KP) {
+      RELNN_REQUIRE(wp.nunits <= P.carry_units && wp.wsw_bytes <= P.ws_carry - P.ws_wsw, RELNN_E_HIP,
+                    "internal: workspace plan does not cover the launch");
       swizzle_ws(W, L->dtype, P.K, wp.KP, L->h, w + P.ws_wsw, s);
       launch_ws(wp, L->dtype, a, w + P.ws_wsw, a.carry, a.carry_arg, s);
       return;
     }
+    if (!plain) {
+      RELNN_REQUIRE(P.ntiles <= P.carry_units && (size_t)P.Kp * L->h * (L->dtype == RELNN_BF16 ? 2 : 4) <=
+                                                     P.ws_carry - P.ws_wsw,
+                    RELNN_E_HIP, "internal: workspace plan does not cover the launch");
+      swizzle_w(W, L->dtype, P.K, P.Kp, L->h, w + P.ws_wsw, s);
+    }
     launch_fwd(P, a, L->dtype, plain, s);
-  });
+  }
+}
+
+}  // namespace relnn
+
+extern "C" relnn_status relnn_layer_fwd(const relnn_index* idx, const relnn_layer_desc* L,
+                                        const void* const* emb, const void* W, const float* b, float* out,
+                                        float* pre, int32_t* argmax, void* ws, size_t ws_bytes,
+                                        relnn_stream_t stream) {
+  return guard([&] { layer_fwd_run(idx, L, emb, W, b, out, pre, argmax, ws, ws_bytes, (hipStream_t)stream); });
 }

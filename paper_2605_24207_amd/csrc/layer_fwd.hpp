@@ -46,6 +46,12 @@ struct FwdPlan {
 };
 
 FwdPlan plan_fwd(const relnn_index* idx, const relnn_layer_desc* L);
+// relnn_layer_fwd without the status mapping (throws Fail), and the
+// workspace bytes it needs for this index and layer.
+void layer_fwd_run(const relnn_index* idx, const relnn_layer_desc* L, const void* const* emb, const void* W,
+                   const float* b, float* out, float* pre, int32_t* argmax, void* ws, size_t ws_bytes,
+                   hipStream_t stream);
+size_t layer_fwd_ws_bytes(const relnn_index* idx, const relnn_layer_desc* L);
 // Validates the index / layer pair, then plans (RELNN_E_* on failure).
 FwdPlan checked_plan(const relnn_index* idx, const relnn_layer_desc* L);
 Atoms make_atoms(const relnn_layer_desc* L, const void* const* emb, const relnn_index* idx);

@@ -8,8 +8,11 @@ Workload 2: the ER schema (User 1M, Item 500k, Category 1k, Buys 20M with
 item ~ Zipf 1.1), Item SUM (K = 384) and User MEAN (K = 256), FP32 and BF16.
 Workload 3: the two-hop co-buy rule on the same graph, BF16, h = 256, MAX.
 Workload 4: Node 2M x 128, Edge 10M (s ~ Zipf 1.2), the MAX layer forward
-and its backward (embedding-gradient rows of sampled nodes, and db, whose
-closed form is the column sums of dA).
+and the backward of both layers (SUM + ReLU and MAX), FP32 and BF16:
+embedding-gradient rows of sampled nodes (the hottest source, about 1.9M
+tuples, among them), db against its closed form, the dW rows of the atom
+keyed by the group column in full and sampled dW columns of the other one.
+Workload 5: the server at the benchmark's settings on the full ER graph.
 """
 import copy
 
@@ -53,22 +56,22 @@ def restrict(rule, keys):
     return sub
 
 
-def gpu_full_fwd(rule, dtype, index):
+def gpu_full_fwd(rule, dtype, index, pushdown=False):
     import torch
 
     from paper_2605_24207_amd import layer_fwd
 
-    out, pre, am = layer_fwd(index, gpu_layer(rule, dtype), distinct_embs(rule, dtype), to_dev(rule.W, dtype),
-                             to_dev(rule.b))
+    out, pre, am = layer_fwd(index, gpu_layer(rule, dtype, pushdown=pushdown), distinct_embs(rule, dtype),
+                             to_dev(rule.W, dtype), to_dev(rule.b))
     torch.cuda.synchronize()
     return out, pre, am
 
 
-def check_sampled_forward(rule, dtype, keys):
+def check_sampled_forward(rule, dtype, keys, pushdown=False):
     import torch
 
     gi = gpu_index(rule)
-    out, pre, am = gpu_full_fwd(rule, dtype, gi)
+    out, pre, am = gpu_full_fwd(rule, dtype, gi, pushdown)
     ex = gi.export()
     gk = ex["group_keys"].cpu().numpy()
     goff = ex["offsets"].cpu().numpy()
@@ -110,57 +113,93 @@ def check_sampled_forward(rule, dtype, keys):
     return gi, (out, pre, am)
 
 
+@pytest.mark.parametrize("mode", ["fused", "pushdown"])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("which", ["item", "user"])
-def test_er_full_forward_sampled(er, which, dtype):
+def test_er_full_forward_sampled(er, which, dtype, mode):
+    """300 sampled groups and one of about 60k tuples, with the transform
+    evaluated per tuple (fused) or pushed below the join (node products)."""
     rule = relgen.er_item_rule(er) if which == "item" else relgen.er_user_rule(er)
     keys, hot = sample_keys(rule.cols[rule.group_col], 300, 60_000, seed=17)
     if which == "item":          # one group over many tiles and more than one block's range
         assert hot > 20_000
+    check_sampled_forward(rule, dtype, keys, pushdown=mode == "pushdown")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_er_full_forward_hottest_group(er, dtype):
+    """The hottest Item group (about 2.5M of the 20M tuples, spread over
+    many persistent blocks): its SUM crosses tens of thousands of tiles
+    (Kahan-compensated inside a block) and dozens of block ranges (the carry
+    fix-up).  Checked with a few random groups against the FP64 oracle."""
+    rule = relgen.er_item_rule(er)
+    gk = rule.cols[rule.group_col]
+    cnt = np.bincount(gk)
+    hot = int(np.argmax(cnt))
+    assert cnt[hot] > 2_000_000
+    rng = np.random.default_rng(31)
+    keys = np.unique(np.concatenate([rng.choice(np.nonzero(cnt)[0], 20, replace=False), [hot]]))
     check_sampled_forward(rule, dtype, keys)
 
 
-def test_power_full_max_forward_backward_sampled(power):
-    """Workload-4 MAX layer: sampled groups forward; backward at full size,
-    checked on the embedding-gradient rows of sampled nodes (all tuples that
-    join them, routed by the kernel's own argmax), on db, on the dW rows of
-    the atom keyed by the group column in full and on sampled dW columns of
-    the other atom."""
-    import torch
-
-    from paper_2605_24207_amd import layer_bwd, layer_fwd
-
+def test_power_full_max_forward_sampled(power):
     rule = relgen.power_rule(power, 1)
     keys, _ = sample_keys(rule.cols[rule.group_col], 300, 0, seed=19)
     check_sampled_forward(rule, "f32", keys)
 
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("layer", [0, 1])
+def test_power_full_backward(power, layer, dtype):
+    """Workload-4 backward at full size (E = 10M), layer 1 (SUM, ReLU after
+    the aggregate) or layer 2 (MAX), FP32 or BF16.  Checked against FP64
+    sums over the FP32 master values, with the integer decisions (ReLU
+    signs, maximisers) taken from the kernel's forward: the embedding-
+    gradient rows of sampled nodes (the hottest source, about 1.9M tuples,
+    and one of about 30k among them), db (closed form: sum_g w_g dA_g, w_g =
+    |g| for SUM, 1 for MAX), the dW rows of the atom keyed by the group
+    column in full and sampled dW columns of the other atom."""
+    import torch
+
+    from paper_2605_24207_amd import layer_bwd, layer_fwd
+
+    tol = TOL[dtype]
+    rule = relgen.power_rule(power, layer)
     gi = gpu_index(rule, bwd=True)
-    layer = gpu_layer(rule, "f32")
-    z = to_dev(rule.atoms[0].emb)
-    W, b = to_dev(rule.W), to_dev(rule.b)
-    out, pre, am = layer_fwd(gi, layer, [z, z], W, b)
+    lay = gpu_layer(rule, dtype)
+    z = to_dev(rule.atoms[0].emb, dtype)
+    W, b = to_dev(rule.W, dtype), to_dev(rule.b)
+    out, pre, am = layer_fwd(gi, lay, [z, z], W, b)
     dout_np = np.random.default_rng(3).standard_normal((gi.G, rule.h)).astype(np.float32)
-    dz = torch.zeros_like(z)
-    dW = torch.empty_like(W)
+    dz = torch.zeros(z.shape, dtype=torch.float32, device="cuda")
+    dW = torch.empty(W.shape, dtype=torch.float32, device="cuda")
     db = torch.empty_like(b)
-    layer_bwd(gi, layer, [z, z], W, b, pre, am, to_dev(dout_np), [dz, dz], dW, db)
+    layer_bwd(gi, lay, [z, z], W, b, pre, am, to_dev(dout_np), [dz, dz], dW, db)
     torch.cuda.synchronize()
 
     ref = orc.build_index(rule)                   # full canonical order: positions match the kernel's
     ex = gi.export()
     np.testing.assert_array_equal(ex["offsets"].cpu().numpy(), ref.offsets)
     np.testing.assert_array_equal(ex["link_rows"].cpu().numpy(), ref.link_row)
-    am_np = am.cpu().numpy().astype(np.int64)
-    dA = dout_np.astype(np.float64)               # act_post none: dA = dout
-    # db: every group's dA[g][c] reaches exactly one tuple (its argmax)
-    db_ref = dA.sum(axis=0)
-    assert np.linalg.norm(db.cpu().numpy() - db_ref) <= 1e-5 * np.linalg.norm(db_ref)
-    # dz rows of sampled nodes, among them a hot source
+    is_max = rule.agg == "max"
+    am_np = am.cpu().numpy().astype(np.int64) if is_max else None
+    dA = dout_np.astype(np.float64)
+    if rule.act_post == "relu":
+        dA = dA * (pre.cpu().numpy() > 0)         # the kernel's ReLU decisions
+    cnt = np.diff(ref.offsets).astype(np.float64)
+    wg = np.ones_like(cnt) if is_max else cnt
+    rel = lambda a, r: np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+    # db: every dA[g][c] reaches one tuple (MAX) or all |g| tuples (SUM)
+    db_ref = (wg[:, None] * dA).sum(axis=0)
+    assert rel(db.cpu().numpy(), db_ref) <= tol
+    # dz rows of sampled nodes: the hottest source and one of about 30k
     deg = np.bincount(np.concatenate(rule.cols), minlength=rule.atoms[0].n_rows)
     nz = np.nonzero(deg)[0]
     rng = np.random.default_rng(23)
-    hot = nz[np.argmin(np.abs(deg[nz] - 30_000))]
-    nodes = np.unique(np.concatenate([rng.choice(nz, 150, replace=False), [hot]]))
+    hot = int(np.argmax(np.bincount(rule.cols[0])))
+    mid = nz[np.argmin(np.abs(deg[nz] - 30_000))]
+    nodes = np.unique(np.concatenate([rng.choice(nz, 150, replace=False), [hot, mid]]))
+    assert deg[hot] > 1_000_000
     W64 = rule.W.astype(np.float64)
     d = rule.atoms[0].d
     dz_ref = np.zeros((len(nodes), d))
@@ -169,29 +208,67 @@ def test_power_full_max_forward_backward_sampled(power):
         rows_j = ref.rows[j]
         tup = np.nonzero(np.isin(rows_j, nodes))[0]        # canonical positions joined to a sampled node
         g = ref.tuple_group[tup]
-        dy = np.where(am_np[g] == tup[:, None], dA[g], 0.0)   # MAX routing by the kernel's argmax
+        dy = np.where(am_np[g] == tup[:, None], dA[g], 0.0) if is_max else dA[g]
         contrib = dy @ W64[j * d:(j + 1) * d].T
         at = np.searchsorted(nodes, rows_j[tup])
         np.add.at(dz_ref, at, contrib)
         np.add.at(sq, at, (contrib ** 2).sum(axis=1))
+        del dy, contrib
     dz_g = dz.cpu().numpy()[nodes].astype(np.float64)
     scale = np.maximum(np.linalg.norm(dz_ref, axis=1), np.sqrt(sq))
     err = np.linalg.norm(dz_g - dz_ref, axis=1) / np.maximum(scale, 1e-30)
-    assert err.max() <= 1e-5, err.max()
-    # dW, rows of atom t (keyed by the group column: every tuple of g joins
-    # the same row, and the routed gradients of g add up to dA_g) in full
+    assert err.max() <= tol, err.max()
+    # dW rows of atom t (keyed by the group column: every tuple of g joins
+    # the same row; the gradients of g add up to w_g dA_g) in full
     dW_np = dW.cpu().numpy().astype(np.float64)
     z64 = rule.atoms[0].emb.astype(np.float64)
     x_t = z64[ref.rows[1][ref.offsets[:-1]]]
-    ref_t = x_t.T @ dA
+    ref_t = x_t.T @ (wg[:, None] * dA)
     del x_t
-    assert np.linalg.norm(dW_np[d:] - ref_t) <= 1e-5 * np.linalg.norm(ref_t)
-    # rows of atom s on sampled output columns: column c of g goes to the
-    # tuple the kernel chose, so dW_s[:, c] = sum_g dA[g, c] z[s row of that tuple]
+    assert rel(dW_np[d:], ref_t) <= tol
+    # rows of atom s on sampled output columns
     for c in np.random.default_rng(29).choice(rule.h, 3, replace=False):
-        x_s = z64[ref.rows[0][am_np[:, c]]]
-        col = x_s.T @ dA[:, c]
-        assert np.linalg.norm(dW_np[:d, c] - col) <= 1e-5 * np.linalg.norm(col)
+        if is_max:                                # column c of g goes to the tuple the kernel chose
+            col = z64[ref.rows[0][am_np[:, c]]].T @ dA[:, c]
+        else:                                     # sum over tuples of z_s(tau) dA[g(tau), c]
+            w = np.bincount(ref.rows[0], weights=dA[ref.tuple_group, c], minlength=z64.shape[0])
+            col = z64.T @ w
+        assert rel(dW_np[:d, c], col) <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_power_full_pushdown_forward_sampled(power, dtype):
+    """Workload-4 layer 1 with the transform pushed below the join, at full
+    size, on sampled groups."""
+    rule = relgen.power_rule(power, 0)
+    keys, _ = sample_keys(rule.cols[rule.group_col], 300, 0, seed=37)
+    check_sampled_forward(rule, dtype, keys, pushdown=True)
+
+
+def test_serve_full_graph_bench_settings(er):
+    """Serving at the benchmark's settings on the full ER graph (Buys 20M):
+    max_seeds 4096, max_slots 64, a 64 GiB budget; six requests submitted
+    together, one of them 4096 seeds, FP32 and BF16, each against the FP64
+    serving oracle on the FP32 master values (1e-5 and 2e-2 per row)."""
+    from oracle import serve_oracle as so
+    from tests.test_gpu_serve import make_server, rows_close
+
+    adj = so.adjacency(er.buys_u, er.buys_i, er.item.shape[0], er.user.shape[0])
+    rng = np.random.default_rng(41)
+    reqs = [(rng.choice(er.item.shape[0], size=n, replace=False).astype(np.int32), int(rng.integers(0, 2**62)))
+            for n in (4096, 1, 300, 2000, 17, 4096)]
+    emb = (er.user, er.item, er.cat, er.belongs_cat)
+    Wr = (er.W_user[0], er.W_item[0], er.W_item[1])
+    refs = [so.evaluate(adj, emb, Wr, (None, None, None), s, rs, 15, 10) for s, rs in reqs]
+    for dtype, tol in (("f32", 1e-5), ("bf16", 2e-2)):
+        srv = make_server(er, dtype, max_seeds=4096, max_slots=64, budget_bytes=64 << 30)
+        tickets = [srv.submit(s, rs) for s, rs in reqs]
+        for (s, rs), t, (r_out, r_pres, r_tuples) in zip(reqs, tickets, refs):
+            out, present, st = srv.wait(t, len(s))
+            assert present.tolist() == r_pres.tolist()
+            assert st["tuples"] == r_tuples
+            assert rows_close(out, r_out, tol)
+        srv.close()
 
 
 def test_cobuy_full_precision_form(er):

@@ -75,28 +75,45 @@ def test_serve_matches_oracle(dtype, tol):
 
 
 def test_serve_same_alone_and_in_the_mix():
+    """The same request alone and inside a concurrent mix: its step must have
+    carried other requests, and its result must match.  Bitwise equality is
+    not claimed: in the mix its tuples sit at other list positions, so the
+    tile boundaries inside its groups (where partial sums meet) differ and
+    FP32 rounding may differ.  Each run is within 1e-5 of the FP64 oracle
+    per row, so the two differ by at most 2e-5 per row; that is asserted."""
     g = small_graph(seed=12)
     srv = make_server(g, "f32", max_seeds=256, max_slots=16)
+    ref = oracle_for(g, "f32")
     probe = (np.random.default_rng(5).choice(g.item.shape[0], 200, replace=False).astype(np.int32), 777)
     alone, _, _ = srv.wait(srv.submit(*probe), 200)
     # now the same request among concurrent submitters
     others = requests(g, 60, seed=9, max_seeds=256)
-    got = {}
+    tickets = []
+    lock = threading.Lock()
 
     def submitter(chunk):
         for s, rs in chunk:
-            srv.submit(s, rs)
+            t = srv.submit(s, rs)
+            with lock:
+                tickets.append((t, len(s)))
             time.sleep(0.0005)
 
-    th = [threading.Thread(target=submitter, args=(others[i::3],)) for i in range(3)]
+    th = [threading.Thread(target=submitter, args=(others[i:40:3],)) for i in range(3)]
     for x in th:
         x.start()
+    for s, rs in others[40:50]:                 # a burst just before the probe: it queues with them
+        tickets.append((srv.submit(s, rs), len(s)))
     t_probe = srv.submit(*probe)
+    for s, rs in others[50:]:
+        tickets.append((srv.submit(s, rs), len(s)))
     for x in th:
         x.join()
     mixed, _, st = srv.wait(t_probe, 200)
-    assert rows_close(mixed, alone, 1e-6)
-    got["bitwise"] = bool(np.array_equal(mixed, alone))
+    steps = [srv.wait(t, n)[2]["step"] for t, n in tickets]
+    assert st["step"] in steps, "the probe ran alone"
+    r_out = ref(*probe)[0]
+    assert rows_close(alone, r_out, 1e-5) and rows_close(mixed, r_out, 1e-5)
+    assert rows_close(mixed, alone, 2e-5)
     srv.close()
 
 

@@ -389,3 +389,105 @@ def test_bwd_given_act_pre_mask_equals_computed():
     x0 = orc.gather_concat(idx, embs, [0])[0]
     np.testing.assert_allclose(dW - base[1], sign * np.outer(x0, np.eye(8)[0]) * dout[idx.tuple_group[0], 0],
                                atol=1e-12)
+
+
+def _fd_check(loss, params, grads, coords, eps, decisions):
+    """Central differences of ``loss`` at the listed coordinates; a
+    coordinate whose +-eps probes change an integer decision (a ReLU sign or
+    a MAX maximiser) is skipped.  Returns the number checked."""
+    checked = 0
+    for pi, pos in coords:
+        arr = params[pi]
+        old = arr[pos]
+        arr[pos] = old + eps
+        lp, dp = loss(), decisions()
+        arr[pos] = old - eps
+        lm, dm = loss(), decisions()
+        arr[pos] = old
+        if any(not np.array_equal(a, b) for a, b in zip(dp, dm)):
+            continue
+        g_fd = (lp - lm) / (2 * eps)
+        g = grads[pi][pos]
+        assert abs(g_fd - g) <= 1e-6 * max(1.0, abs(g)), (pi, pos, g_fd, g)
+        checked += 1
+    return checked
+
+
+@pytest.mark.parametrize("layer", [0, 1])
+def test_grad_finite_differences_power_law_instance(layer):
+    """The differentiation workload's gradient instance: 2k nodes, 10k edges,
+    s ~ Zipf(1.2), t uniform, width 128; layer 1 (SUM, ReLU after the
+    aggregate) and layer 2 (MAX).  Central differences in FP64 of
+    sum(out * dout) at sampled coordinates of z (the hottest source row
+    among them), W and b against the analytic gradient."""
+    p = relgen.power_graph(seed=5, n_nodes=2000, n_edges=10_000, d=128, h=128, bias_std=0.2)
+    rule = relgen.power_rule(p, layer)
+    idx = orc.build_index(rule)
+    z = rule.atoms[0].emb.astype(np.float64)
+    W = rule.W.astype(np.float64)
+    b = rule.b.astype(np.float64)
+    agg, post = rule.agg, rule.act_post
+    out, pre, am = orc.layer_fwd(idx, [z, z], W, b, agg, "none", post)
+    dout = np.random.default_rng(8).standard_normal(out.shape)
+    demb, dW, db = orc.layer_bwd(idx, [z, z], W, b, pre, am, dout, agg, "none", post)
+    dz = demb[0] + demb[1]                      # both atoms read Node
+
+    def loss():
+        o, _, _ = orc.layer_fwd(idx, [z, z], W, b, agg, "none", post)
+        return float((o * dout).sum())
+
+    def decisions():
+        _, pr, a = orc.layer_fwd(idx, [z, z], W, b, agg, "none", post)
+        return (np.sign(pr),) if agg != "max" else (np.sign(pr), a)
+
+    rng = np.random.default_rng(9)
+    deg = np.bincount(p.s, minlength=2000)
+    hot = int(np.argmax(deg))
+    coords = [(0, (hot, int(c))) for c in rng.integers(0, 128, 4)]
+    coords += [(0, (int(rng.integers(0, 2000)), int(rng.integers(0, 128)))) for _ in range(6)]
+    coords += [(1, (int(rng.integers(0, 256)), int(rng.integers(0, 128)))) for _ in range(8)]
+    coords += [(2, (int(rng.integers(0, 128)),)) for _ in range(4)]
+    n = _fd_check(loss, [z, W, b], [dz, dW, db], coords, 1e-6, decisions)
+    assert deg[hot] > 100 and n >= 16, (deg[hot], n)
+
+
+def test_grad_finite_differences_power_law_two_layer_mse():
+    """The two-layer net of the differentiation workload on its gradient
+    instance, MSE against N(0, 1) targets: central differences of the loss
+    through both layers (the chain the autograd wrapper drives) against the
+    chained analytic gradients."""
+    p = relgen.power_graph(seed=6, n_nodes=2000, n_edges=10_000, d=128, h=128, bias_std=0.2)
+    z = p.z.astype(np.float64)
+    W1, W2 = p.W[0].astype(np.float64), p.W[1].astype(np.float64)
+    b1, b2 = p.b[0].astype(np.float64), p.b[1].astype(np.float64)
+    r1 = relgen.power_rule(p, 0)
+    i1 = orc.build_index(r1)
+    o1 = orc.layer_fwd(i1, [z, z], W1, b1, "sum", "none", "relu")[0]
+    r2 = relgen.power_rule(p, 1, z=o1, z_keys=i1.group_keys.astype(np.int32))
+    i2 = orc.build_index(r2)
+    tg = p.target[i2.group_keys].astype(np.float64)
+
+    def forward():
+        o1, pre1, am1 = orc.layer_fwd(i1, [z, z], W1, b1, "sum", "none", "relu")
+        o2, pre2, am2 = orc.layer_fwd(i2, [o1, o1], W2, b2, "max", "none", "none")
+        return o1, pre1, am1, o2, pre2, am2
+
+    def loss():
+        o2 = forward()[3]
+        return float(((o2 - tg) ** 2).mean())
+
+    def decisions():
+        _, pre1, _, _, pre2, am2 = forward()
+        return np.sign(pre1), am2
+
+    o1, pre1, am1, o2, pre2, am2 = forward()
+    dout2 = 2.0 * (o2 - tg) / o2.size
+    d2, dW2, db2 = orc.layer_bwd(i2, [o1, o1], W2, b2, pre2, am2, dout2, "max", "none", "none")
+    d1, dW1, db1 = orc.layer_bwd(i1, [z, z], W1, b1, pre1, am1, d2[0] + d2[1], "sum", "none", "relu")
+    rng = np.random.default_rng(10)
+    coords = [(0, (int(rng.integers(0, 2000)), int(rng.integers(0, 128)))) for _ in range(6)]
+    coords += [(1, (int(rng.integers(0, 256)), int(rng.integers(0, 128)))) for _ in range(4)]
+    coords += [(2, (int(rng.integers(0, 256)), int(rng.integers(0, 128)))) for _ in range(4)]
+    coords += [(3, (int(rng.integers(0, 128)),)), (4, (int(rng.integers(0, 128)),))]
+    n = _fd_check(loss, [z, W1, W2, b1, b2], [d1[0] + d1[1], dW1, dW2, db1, db2], coords, 1e-6, decisions)
+    assert n >= 12, n
