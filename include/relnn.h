@@ -209,6 +209,24 @@ relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_layer_desc* L,
                              float* const* demb, float* dW, float* db,
                              void* ws, size_t ws_bytes, relnn_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward of relnn_layer_fwd with the same arguments except the workspace.
+ * Its workspace is a static device array of relnn_static_scratch_bytes()
+ * bytes (32 MiB) on each GPU the library runs on, held until the process
+ * ends; no call allocates or frees anything.  A layer whose workspace
+ * (relnn_workspace_size(.., 0)) exceeds the array: RELNN_E_RANGE, nothing
+ * launched.  RELNN_PLAIN (a library GEMM, which may allocate):
+ * RELNN_E_UNSUPPORTED.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads) race and
+ * must be serialised by the caller.  Nothing in the array has to start
+ * at zero; it keeps the last call's contents.  Results equal those of
+ * relnn_layer_fwd bit for bit. */
+relnn_status relnn_static_scratch_bytes(size_t* bytes);
+relnn_status relnn_layer_fwd_static(const relnn_index* idx, const relnn_layer_desc* L,
+                                    const void* const* emb, const void* W, const float* b,
+                                    float* out, float* pre, int32_t* argmax, relnn_stream_t stream);
+
 /* ---------------------------------------------------------------- serve */
 
 /* Serving of the two-layer ER network on sampled neighbourhoods.  The

@@ -203,6 +203,39 @@ def layer_fwd(index: Index, layer: Layer, embs: Sequence[torch.Tensor], W: torch
     return out, pre, am
 
 
+def layer_fwd_static(index: Index, layer: Layer, embs: Sequence[torch.Tensor], W: torch.Tensor,
+                     b: Optional[torch.Tensor] = None, out: torch.Tensor = None, pre: Optional[torch.Tensor] = None,
+                     argmax: Optional[torch.Tensor] = None, stream=None):
+    """relnn_layer_fwd_static: the forward without a workspace argument (the
+    library's static per-device scratch).  The caller passes the outputs, so
+    the call itself allocates nothing."""
+    _check_embs(layer, embs)
+    if W.dtype != layer.torch_dtype or W.shape != (layer.K, layer.h) or not W.is_contiguous():
+        raise TypeError(f"W must be a contiguous {layer.torch_dtype} [{layer.K}, {layer.h}] tensor")
+    if b is not None and (b.dtype != torch.float32 or b.numel() != layer.h):
+        raise TypeError("b must be float32 [h]")
+    G, h = index.G, layer.h
+    odt = torch.bfloat16 if layer.out_dtype == "bf16" else torch.float32
+    if out is None or out.dtype != odt or tuple(out.shape) != (G, h) or not out.is_contiguous():
+        raise TypeError(f"out must be a contiguous {odt} tensor of shape {(G, h)}")
+    if pre is not None and (pre.dtype != torch.float32 or tuple(pre.shape) != (G, h) or not pre.is_contiguous()):
+        raise TypeError(f"pre must be a contiguous float32 tensor of shape {(G, h)}")
+    if argmax is not None and (argmax.dtype != torch.int32 or tuple(argmax.shape) != (G, h)
+                               or not argmax.is_contiguous()):
+        raise TypeError(f"argmax must be a contiguous int32 tensor of shape {(G, h)}")
+    emb_arr = (C.c_void_p * len(embs))(*[e.data_ptr() for e in embs])
+    d = layer.desc()
+    check(lib().relnn_layer_fwd_static(index.handle, C.byref(d), emb_arr, _vp(W), _vp(b), _vp(out), _vp(pre),
+                                       _vp(argmax), _stream(stream)))
+    return out, pre, argmax
+
+
+def static_scratch_bytes() -> int:
+    n = C.c_size_t()
+    check(lib().relnn_static_scratch_bytes(C.byref(n)))
+    return n.value
+
+
 def layer_bwd(index: Index, layer: Layer, embs: Sequence[torch.Tensor], W: torch.Tensor,
               b: Optional[torch.Tensor], pre: Optional[torch.Tensor], argmax: Optional[torch.Tensor],
               dout: torch.Tensor, demb: Sequence[torch.Tensor], dW: torch.Tensor,

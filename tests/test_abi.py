@@ -73,3 +73,19 @@ def test_more_validation_errors_without_gpu():
     ms, cnt = ctypes.c_double(), ctypes.c_int64()
     assert L.relnn_timing_read(b"fwd_fused", ctypes.byref(ms), ctypes.byref(cnt)) == _lib.OK
     assert cnt.value == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librelnn.so not built")
+def test_static_variant_host_checks_without_gpu():
+    from paper_2605_24207_amd import _lib
+
+    L = _lib.lib()
+    n = ctypes.c_size_t()
+    assert L.relnn_static_scratch_bytes(ctypes.byref(n)) == _lib.OK and n.value == 32 << 20
+    assert L.relnn_static_scratch_bytes(None) == _lib.E_INVALID
+    ld = _lib.LayerDesc()
+    assert L.relnn_layer_fwd_static(None, ctypes.byref(ld), None, None, None, None, None, None, None) == \
+        _lib.E_INVALID
+    ld.flags = _lib.PLAIN
+    assert L.relnn_layer_fwd_static(None, ctypes.byref(ld), None, None, None, None, None, None, None) == \
+        _lib.E_UNSUPPORTED
