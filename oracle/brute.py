@@ -1,9 +1,11 @@
 """Pure-Python brute force for tiny inputs.  TEST INFRASTRUCTURE ONLY.
 
-Enumerates every combination of a link row with one row of every body atom
-and keeps those whose keys agree (the natural join of Section 2.2, written as
-a nested loop over all row combinations), then applies the transform and the
-multiset aggregate of Section 2.2 with plain Python floats.  It shares no
+Enumerates every combination of a link row, a row of every further link
+relation and a row of every body atom, and keeps those whose keys agree (the
+natural join of Section 2.2, written as a nested loop over all row
+combinations) and that satisfy every filter predicate (the selection of
+Section 3.1), then applies the transform and the multiset aggregate of
+Section 2.2 with plain Python floats.  It shares no
 code with ``relnn_oracle`` and exists to pin it.
 """
 from __future__ import annotations
@@ -15,16 +17,45 @@ def _key(keys, r):
     return r if keys is None else int(keys[r])
 
 
-def join(rule):
-    """List of (link_row, (r_1..r_k), columns) for every joined tuple, in
-    link-row order; no index or hashing, a full nested loop."""
+_OPS = {"eq": lambda v: v == 0, "ne": lambda v: v != 0, "lt": lambda v: v < 0, "le": lambda v: v <= 0,
+        "gt": lambda v: v > 0, "ge": lambda v: v >= 0}
+
+
+def _holds(p, cols):
+    v = p.add
+    if p.a >= 0:
+        v += p.mul_a * cols[p.a]
+    if p.b >= 0:
+        v += p.mul_b * cols[p.b]
+    return _OPS[p.op](v)
+
+
+def _link_tuples(rule):
+    """(source rows, columns) of every tuple of the link relation joined with
+    the further link relations: a nested loop over all row combinations,
+    kept where the join columns agree."""
     base = [[int(v) for v in c] for c in rule.cols]
-    n_link = len(base[0])
+    cur = [((ell,), [c[ell] for c in base]) for ell in range(len(base[0]))]
+    for st in getattr(rule, "steps", ()):
+        S = [[int(v) for v in c] for c in st.cols]
+        nxt = []
+        for src, cols in cur:
+            for r in range(len(S[0])):
+                if all(cols[o] == S[k][r] for o, k in zip(st.on, st.key)):
+                    nxt.append((src + (r,), cols + [c[r] for c in S]))
+        cur = nxt
+    return cur
+
+
+def join(rule):
+    """List of (source rows, (r_1..r_k), columns) for every joined tuple, in
+    source-row order (link row, then the row of each further link relation);
+    no index or hashing, a full nested loop."""
     if rule.two_hop_mid >= 0:
-        raise NotImplementedError("use join_two_hop")
+        raise NotImplementedError("two-hop paths are pinned separately")
     out = []
-    for ell in range(n_link):
-        cols = [c[ell] for c in base]
+    for ell, cols in _link_tuples(rule):
+        cols = list(cols)
         ok = True
         for ch in rule.chains:
             hits = [r for r in range(ch.n_rows) if _key(ch.keys, r) == cols[ch.src_col]]
@@ -35,11 +66,13 @@ def join(rule):
                 cols.append(int(ch.vals[hits[0]]))
         if not ok:
             continue
+        if not all(_holds(p, cols) for p in getattr(rule, "preds", ())):
+            continue
         cand = []
         for a in rule.atoms:
             cand.append([r for r in range(a.n_rows) if _key(a.keys, r) == cols[a.col]])
         for combo in itertools.product(*cand):
-            out.append((ell, tuple(combo), tuple(cols)))
+            out.append((ell if len(ell) > 1 else ell[0], tuple(combo), tuple(cols)))
     return out
 
 

@@ -6,9 +6,13 @@ shares no code with it; the two meet only at the seeded inputs of ``relgen``.
 
 What it computes, and where the paper defines it:
 
-* join (Section 2.2, "Join"): natural join of the link relation with each
-  body atom on the atom's key; the embedding of a joined tuple is the
-  concatenation of the contributing embeddings in body-atom order;
+* join (Section 2.2, "Join"): natural join of the link relation (and of
+  further link relations joined on shared columns: many-to-many and cyclic
+  joins) with each body atom on the atom's key; the embedding of a joined
+  tuple is the concatenation of the contributing embeddings in body-atom
+  order;
+* selection (Section 2.2 "Other operators", Section 3.1 filter expression):
+  the joined tuples that satisfy the conjunction of the filter predicates;
 * transformation (Section 2.2, "Transformation"): tau applied independently
   to every joined tuple, here tau = act_pre(Linear(Concat(...)));
 * projected union with k = 1 (Section 2.2, "Projected union"): the output
@@ -93,6 +97,47 @@ def two_hop_paths(cols: Sequence[np.ndarray], mid: int, cap: int):
     return np.array(la, np.int64), np.array(lb, np.int64)
 
 
+def join_step(cols: List[np.ndarray], step) -> List[np.ndarray]:
+    """Natural join of the tuples so far with a further link relation S (the
+    join of Section 2.2 applied once more, bag semantics): every pair of a
+    tuple and a row r of S with cols[on[q]] == S.cols[key[q]][r] for all q
+    is a tuple.  The result has the columns so far followed by those of S,
+    ordered by (position so far, row of S).  Many-to-many and cyclic joins
+    (a column pair that closes a cycle) are both this step."""
+    S = [np.asarray(c, np.int64) for c in step.cols]
+    rows_of = {}
+    for r in range(step.n_rows):                 # an index nested loop: key -> rows of S
+        rows_of.setdefault(tuple(int(S[k][r]) for k in step.key), []).append(r)
+    src, srow = [], []
+    for i in range(len(cols[0]) if cols else 0):
+        for r in rows_of.get(tuple(int(cols[o][i]) for o in step.on), ()):
+            src.append(i)
+            srow.append(r)
+    src = np.array(src, np.int64)
+    srow = np.array(srow, np.int64)
+    return [c[src] for c in cols] + [c[srow] for c in S]
+
+
+_CMP = {"eq": np.equal, "ne": np.not_equal, "lt": np.less, "le": np.less_equal,
+        "gt": np.greater, "ge": np.greater_equal}
+
+
+def selection(cols: List[np.ndarray], preds) -> np.ndarray:
+    """The selection of a filter expression (Section 3.1): the conjunction of
+    its atomic predicates e1 theta e2, each written as mul_a * col[a] +
+    mul_b * col[b] + add theta 0 in integer arithmetic."""
+    n = len(cols[0]) if cols else 0
+    keep = np.ones(n, dtype=bool)
+    for p in preds:
+        v = np.full(n, p.add, np.int64)
+        if p.a >= 0:
+            v = v + p.mul_a * np.asarray(cols[p.a], np.int64)
+        if p.b >= 0:
+            v = v + p.mul_b * np.asarray(cols[p.b], np.int64)
+        keep &= _CMP[p.op](v, 0)
+    return keep
+
+
 @dataclass
 class Index:
     """Join result in canonical order plus the group structure."""
@@ -118,12 +163,15 @@ def build_index(rule) -> Index:
     if rule.two_hop_mid >= 0:
         la, lb = two_hop_paths(rule.cols, rule.two_hop_mid, rule.two_hop_cap)
         cols = [c[la] for c in cols] + [c[lb] for c in cols]
+    for st in getattr(rule, "steps", ()):        # further link relations, in order
+        cols = join_step(cols, st)
     n_link = len(cols[0])
     valid = np.ones(n_link, dtype=bool)
     for ch in rule.chains:                       # derived columns, in order
         r = lookup_rows(ch.n_rows, ch.keys, cols[ch.src_col])
         valid &= r >= 0
         cols.append(np.where(r >= 0, np.asarray(ch.vals, np.int64)[np.maximum(r, 0)], 0))
+    valid &= selection(cols, getattr(rule, "preds", ()))
     rows = []
     for a in rule.atoms:
         r = lookup_rows(a.n_rows, a.keys, cols[a.col])

@@ -61,6 +61,36 @@ class Chain:
 
 
 @dataclass
+class Step:
+    """A further link relation joined into the tuples so far (general and
+    cyclic joins): columns ``cols``, matched where column ``on[q]`` of the
+    tuples so far equals column ``key[q]`` of this relation, for every q."""
+    cols: List[np.ndarray]         # int32 [n_rows] each
+    on: List[int]
+    key: List[int]
+
+    @property
+    def n_rows(self) -> int:
+        return int(self.cols[0].shape[0])
+
+
+# comparison operators of a filter predicate, in the library's numbering
+CMP = ("eq", "ne", "lt", "le", "gt", "ge")
+
+
+@dataclass
+class Pred:
+    """One atomic predicate of a filter expression: mul_a * col[a] + mul_b *
+    col[b] + add  <op>  0 (a or b = -1: the term is absent)."""
+    a: int
+    op: str
+    b: int = -1
+    mul_a: int = 1
+    mul_b: int = -1
+    add: int = 0
+
+
+@dataclass
 class Rule:
     cols: List[np.ndarray]         # link relation columns, int32 [n_link] each
     atoms: List[Atom]
@@ -73,6 +103,8 @@ class Rule:
     chains: List[Chain] = field(default_factory=list)
     two_hop_mid: int = -1          # column the link relation is self-joined on
     two_hop_cap: int = 0           # paths kept per mid key
+    steps: List[Step] = field(default_factory=list)   # further link relations joined in
+    preds: List[Pred] = field(default_factory=list)   # filter expression (a conjunction)
 
     @property
     def K(self) -> int:
@@ -255,6 +287,41 @@ def power_rule(p: PowerGraph, layer: int, z=None, z_keys=None) -> Rule:
     agg, post = ("sum", "relu") if layer == 0 else ("max", "none")
     return Rule(cols=[p.s, p.t], atoms=[Atom(0, zz, z_keys), Atom(1, zz, z_keys)],
                 group_col=1, W=p.W[layer], b=p.b[layer], agg=agg, act_post=post)
+
+
+# --------------------------------------------------------------------------
+# Cyclic joins: the triangle rule of the paper's DHN encoding (Section 5.2),
+# on many small graphs like its graph-classification sets (Section 5.1).
+# Each graph has n_nodes nodes with global ids (graph g holds g n .. g n +
+# n - 1) and random undirected edges stored in both directions as
+# Edge(g, src, dst); H0 gives every node an N(0, 1) embedding.
+#
+#   C3(n; sum(Lin(h_n (+) h_v (+) h_w))) :- Edge(g,n,v), Edge(g,v,w), Edge(g,w,n),
+#                                           H0(n; h_n), H0(v; h_v), H0(w; h_w)
+#
+# as a link relation Edge (columns 0 g, 1 n, 2 v) with two further Edge
+# relations: the first on v = src and g = g (adding columns 3 g, 4 v, 5 w),
+# the second on w = src and n = dst (adding 6 g, 7 w, 8 n), which closes the
+# cycle.  W ~ N(0, 1/sqrt(3d)).
+# --------------------------------------------------------------------------
+def triangle_rule(seed=SEED, n_graphs=150, n_nodes=40, avg_degree=6, d=64, h=64, agg="sum",
+                  act_post="relu", bias_std=0.0) -> Rule:
+    r = rngs(seed + 7, 5)
+    n_und = n_graphs * n_nodes * avg_degree // 2
+    g = r[0].integers(0, n_graphs, n_und)
+    a = r[1].integers(0, n_nodes, n_und)
+    b = (a + 1 + r[2].integers(0, n_nodes - 1, n_und)) % n_nodes       # no self-loops
+    src = np.concatenate([g * n_nodes + a, g * n_nodes + b]).astype(np.int32)
+    dst = np.concatenate([g * n_nodes + b, g * n_nodes + a]).astype(np.int32)
+    gg = np.concatenate([g, g]).astype(np.int32)
+    edge = [gg, src, dst]
+    z = normal(r[3], (n_graphs * n_nodes, d))
+    W = normal(r[4], (3 * d, h), 1.0 / np.sqrt(3 * d))
+    bb = normal(r[4], (h,), bias_std) if bias_std > 0 else np.zeros(h, np.float32)
+    steps = [Step(cols=[c.copy() for c in edge], on=[2, 0], key=[1, 0]),
+             Step(cols=[c.copy() for c in edge], on=[5, 1], key=[1, 2])]
+    return Rule(cols=edge, atoms=[Atom(1, z), Atom(2, z), Atom(5, z)], group_col=1, W=W, b=bb,
+                agg=agg, act_post=act_post, steps=steps)
 
 
 # --------------------------------------------------------------------------

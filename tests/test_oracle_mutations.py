@@ -133,6 +133,7 @@ def test_unmutated_oracle_passes_every_pin(monkeypatch):
 # oracle/serve_oracle.py; the mutated module replaces the real one and the
 # serving pins run against it.
 import inspect
+import sys
 import types
 
 from oracle import serve_oracle as so
@@ -181,3 +182,61 @@ def test_planted_serving_mistake_is_caught(name, monkeypatch):
 
 def test_unmutated_serving_oracle_passes_every_pin():
     assert not _serve_caught()
+
+
+# ------------------------------------------------- selection and general joins
+# One-token slips in the source text of the join steps and the selection of
+# oracle/relnn_oracle.py; the mutated functions replace the real ones and the
+# pins of tests/test_oracle_joins.py run against them.
+from tests import test_oracle_joins as join_pins
+
+JOIN_PINS = [
+    lambda: join_pins.test_selection_matches_nested_loop(0, "sum"),
+    lambda: join_pins.test_selection_matches_nested_loop(2, "max"),
+    lambda: join_pins.test_selection_matches_nested_loop(4, "mean"),
+    join_pins.test_selection_closed_form,
+    lambda: join_pins.test_many_to_many_join_matches_nested_loop("sum"),
+    join_pins.test_triangle_join_matches_nested_loop,
+    join_pins.test_triangle_count_is_diagonal_of_A_cubed,
+    join_pins.test_triangle_linear_closed_form,
+    join_pins.test_step_with_no_match_and_filter_rejecting_all,
+    join_pins.test_filter_applies_to_derived_columns,
+]
+
+JOIN_MUTANTS = {
+    "step_second_pair_ignored": [("for k in step.key)", "for k in step.key[:1])"),
+                                 ("for o in step.on)", "for o in step.on[:1])")],
+    "step_rows_in_reverse": [("for k in step.key), []).append(r)", "for k in step.key), []).insert(0, r)")],
+    "lt_as_le": [('"lt": np.less,', '"lt": np.less_equal,')],
+    "mul_b_sign": [("v = v + p.mul_b *", "v = v - p.mul_b *")],
+    "filter_dropped": [('valid &= selection(cols, getattr(rule, "preds", ()))', "valid &= True")],
+    "step_matches_any_key": [("rows_of.get(tuple(int(cols[o][i]) for o in step.on), ())",
+                              "[r for v in rows_of.values() for r in v]")],
+}
+
+
+def _join_caught():
+    for pin in JOIN_PINS:
+        try:
+            pin()
+        except Exception:
+            return True
+    return False
+
+
+@pytest.mark.parametrize("name", sorted(JOIN_MUTANTS))
+def test_planted_join_mistake_is_caught(name, monkeypatch):
+    src = inspect.getsource(orc)
+    for old, new in JOIN_MUTANTS[name]:
+        assert src.count(old) == 1, f"mutant {name} no longer matches the oracle's source"
+        src = src.replace(old, new)
+    mod = types.ModuleType("relnn_oracle_mutant")
+    monkeypatch.setitem(sys.modules, "relnn_oracle_mutant", mod)      # dataclasses look their module up
+    exec(compile(src, "<relnn_oracle mutant>", "exec"), mod.__dict__)
+    for attr in ("join_step", "selection", "build_index"):
+        monkeypatch.setattr(orc, attr, getattr(mod, attr))
+    assert _join_caught(), f"no pin caught the planted join mistake {name}"
+
+
+def test_unmutated_join_oracle_passes_every_pin():
+    assert not _join_caught()
