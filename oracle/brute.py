@@ -107,3 +107,52 @@ def layer(rule, embs=None, W=None, b=None):
         o = [max(v, 0.0) for v in a] if rule.act_post == "relu" else list(a)
         res[g] = (a, o)
     return res
+
+
+def tuple_values(rule, embs=None, W=None, b=None):
+    """(head key, transformed embedding as a list) of every joined tuple of
+    the nested loop, in source-row order."""
+    embs = [a.emb for a in rule.atoms] if embs is None else embs
+    W = rule.W if W is None else W
+    b = rule.b if b is None else b
+    K, h = len(W), len(W[0])
+    out = []
+    for ell, rows, cols in join(rule):
+        x = []
+        for e, r in zip(embs, rows):
+            x.extend(float(v) for v in e[r])
+        y = []
+        for c in range(h):
+            acc = float(b[c])
+            for q in range(K):
+                acc += x[q] * float(W[q][c])
+            if rule.act_pre == "relu":
+                acc = max(acc, 0.0)
+            y.append(acc)
+        out.append((cols[rule.group_col], y))
+    return out
+
+
+def union_layer(rules, agg, act_post="none", W_post=None, b_post=None):
+    """dict head key -> (aggregate, output) of the projected union of the
+    rules' joined and transformed tuples: every tuple of every rule with
+    the key is one member of the key's multiset, aggregated once."""
+    members = {}
+    for rule in rules:
+        for key, y in tuple_values(rule):
+            members.setdefault(key, []).append(y)
+    res = {}
+    for key, ys in members.items():
+        if agg == "sum":
+            a = [sum(col) for col in zip(*ys)]
+        elif agg == "mean":
+            a = [sum(col) / len(ys) for col in zip(*ys)]
+        else:
+            a = [max(col) for col in zip(*ys)]
+        v = list(a)
+        if W_post is not None:
+            v = [sum(a[i] * float(W_post[i][c]) for i in range(len(a))) + (0.0 if b_post is None else float(b_post[c]))
+                 for c in range(len(W_post[0]))]
+        o = [max(x, 0.0) for x in v] if act_post == "relu" else v
+        res[key] = (a, o)
+    return res

@@ -307,3 +307,51 @@ def layer_bwd(idx: Index, embs, W, b, pre, argmax, dout, agg="sum",
         demb.append(acc)
         off += d
     return demb, dW, db
+
+
+# ---------------------------------------------------------------------------
+# k-ary projected union (Section 2.2) and union rules (Section 3.1)
+# ---------------------------------------------------------------------------
+def union_fwd(branches, agg="sum", act_post="none", W_post=None, b_post=None):
+    """The projected union over k branches with one aggregate applied once.
+
+    ``branches`` is a list of (idx, embs, W, b, act_pre): the join result of
+    one rule (its index) and the transform tau_i of that rule.  The output
+    content is the set of head keys that occur in any branch (ascending);
+    the multiset B_t of a key t holds every tuple of every branch with that
+    key, each with its own branch's transformed embedding tau_i(x); alpha is
+    applied once over all of B_t (MEAN = sum over B_t / |B_t|, not a mean of
+    the branches' means).  For MAX the maximiser is the first one in the
+    order (branch, canonical position in the branch).
+
+    A union rule (Section 3.1) applies its transform after the union:
+    ``W_post`` [h, h2] and ``b_post`` give tau(v) = v W_post + b_post on the
+    aggregate, then act_post.  Returns (keys, out, pre, arg) with pre the
+    aggregate (before tau_post and act_post) and arg [G, h] pairs (branch,
+    position) for MAX, else None."""
+    keys = sorted(set().union(*[set(int(k) for k in b[0].group_keys) for b in branches]))
+    h = np.asarray(branches[0][2]).shape[1]
+    pre = np.zeros((len(keys), h))
+    arg = np.full((len(keys), h, 2), -1, np.int64) if agg == "max" else None
+    for q, key in enumerate(keys):
+        ys, origin = [], []
+        for bi, (idx, embs, W, b, act_pre) in enumerate(branches):
+            g = np.searchsorted(idx.group_keys, key)
+            if g < idx.G and idx.group_keys[g] == key:
+                s, e = int(idx.offsets[g]), int(idx.offsets[g + 1])
+                ys.append(transform(gather_concat(idx, embs, slice(s, e)), W, b, act_pre))
+                origin += [(bi, p) for p in range(s, e)]
+        y = np.concatenate(ys, axis=0)
+        if agg == "sum":
+            pre[q] = y.sum(axis=0)
+        elif agg == "mean":
+            pre[q] = y.sum(axis=0) / y.shape[0]
+        elif agg == "max":
+            j = np.argmax(y, axis=0)                 # first maximiser in (branch, position) order
+            pre[q] = y[j, np.arange(h)]
+            arg[q] = np.array([origin[i] for i in j])
+        else:
+            raise ValueError(agg)
+    v = pre if W_post is None else pre @ np.asarray(W_post, np.float64) + (
+        0.0 if b_post is None else np.asarray(b_post, np.float64))
+    return np.array(keys, np.int64), _act(act_post, v), pre, arg

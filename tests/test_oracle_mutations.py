@@ -240,3 +240,52 @@ def test_planted_join_mistake_is_caught(name, monkeypatch):
 
 def test_unmutated_join_oracle_passes_every_pin():
     assert not _join_caught()
+
+
+# --------------------------------------------------------- projected union
+from tests import test_oracle_union as union_pins
+
+UNION_PINS = [
+    lambda: union_pins.test_union_matches_nested_loop("mean", 2),
+    lambda: union_pins.test_union_matches_nested_loop("max", 3),
+    lambda: union_pins.test_union_matches_nested_loop("sum", 3),
+    lambda: union_pins.test_union_of_one_is_the_projection("max"),
+    union_pins.test_self_union,
+    union_pins.test_mean_is_applied_once_across_relations,
+    union_pins.test_keys_are_the_union_of_the_branches,
+    union_pins.test_union_rule_transform_after_the_union,
+]
+
+UNION_MUTANTS = {
+    "mean_of_means": [("pre[q] = y.sum(axis=0) / y.shape[0]",
+                       "pre[q] = np.mean([v.mean(axis=0) for v in ys], axis=0)")],
+    "keys_intersected": [("keys = sorted(set().union(*", "keys = sorted(set.intersection(*")],
+    "max_last_branch_first": [("y = np.concatenate(ys, axis=0)", "y = np.concatenate(ys[::-1], axis=0)")],
+    "post_bias_dropped": [("0.0 if b_post is None else np.asarray(b_post, np.float64))", "0.0)")],
+}
+
+
+def _union_caught():
+    for pin in UNION_PINS:
+        try:
+            pin()
+        except Exception:
+            return True
+    return False
+
+
+@pytest.mark.parametrize("name", sorted(UNION_MUTANTS))
+def test_planted_union_mistake_is_caught(name, monkeypatch):
+    src = inspect.getsource(orc)
+    for old, new in UNION_MUTANTS[name]:
+        assert src.count(old) == 1, f"mutant {name} no longer matches the oracle's source"
+        src = src.replace(old, new)
+    mod = types.ModuleType("relnn_oracle_union_mutant")
+    monkeypatch.setitem(sys.modules, "relnn_oracle_union_mutant", mod)
+    exec(compile(src, "<relnn_oracle mutant>", "exec"), mod.__dict__)
+    monkeypatch.setattr(orc, "union_fwd", mod.union_fwd)
+    assert _union_caught(), f"no pin caught the planted union mistake {name}"
+
+
+def test_unmutated_union_oracle_passes_every_pin():
+    assert not _union_caught()
