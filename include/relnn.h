@@ -69,8 +69,8 @@ typedef struct {
   int64_t n_rows;          /* |R_j| */
   const int32_t* keys;     /* device [n_rows] primary key; NULL => dense ids
                               0..n_rows-1 (row = key) */
-  int32_t col;             /* link column (0..n_cols-1) or derived column
-                              (n_cols + chain number) holding the FK */
+  int32_t col;             /* column of the joined link tuples holding the
+                              FK (see relnn_join_desc for the numbering) */
 } relnn_atom;
 
 /* A derived column: for every link tuple, the value vals[r] of the row r of
@@ -85,9 +85,47 @@ typedef struct {
 
 #define RELNN_IDX_BWD 1u   /* also build per-atom transpose CSRs (backward) */
 
+/* A further link relation S joined into the link tuples built so far: the
+ * natural join of Section 2.2 on one or two column pairs, bag semantics.
+ * Every pair of a tuple and a row r of S with col[on[q]] == S.cols[key[q]][r]
+ * for all q < n_on is a tuple, with S's columns appended after the columns
+ * so far.  Chained steps give many-to-many joins; a step whose second pair
+ * closes a cycle gives cyclic joins (the triangle Edge(n,v), Edge(v,w),
+ * Edge(w,n) of the paper's DHN encoding, Section 5.2). */
+typedef struct {
+  int64_t n_rows;
+  int32_t n_cols;
+  const int32_t* const* cols;     /* host [n_cols] of device [n_rows] */
+  int32_t n_on;                   /* 1 or 2 column pairs */
+  int32_t on[2];                  /* columns of the tuples so far */
+  int32_t key[2];                 /* columns of S */
+} relnn_join_step;
+
+typedef enum { RELNN_CMP_EQ = 0, RELNN_CMP_NE = 1, RELNN_CMP_LT = 2, RELNN_CMP_LE = 3,
+               RELNN_CMP_GT = 4, RELNN_CMP_GE = 5 } relnn_cmp;
+
+/* One atomic predicate e1 theta e2 of a filter expression (Section 3.1),
+ * over the content variables of the joined tuples and constants, written as
+ *     mul_a * col[a] + mul_b * col[b] + add   theta   0
+ * in 64-bit two's-complement integer arithmetic (a or b = -1 leaves that
+ * term out).  A filter is the conjunction of its predicates; the selection
+ * (Section 2.2) keeps the tuples that satisfy it. */
+typedef struct {
+  int32_t a, b;
+  int64_t mul_a, mul_b, add;
+  int32_t op;                     /* relnn_cmp */
+} relnn_pred;
+
 /* The join of one rule: the link relation (bag semantics: every stored row
- * is a tuple), its FK chains, its body atoms in Concat order, and the head
- * key (the projection attribute of the projected union). */
+ * is a tuple), further link relations joined into it, its FK chains, its
+ * body atoms in Concat order, a filter, and the head key (the projection
+ * attribute of the projected union).
+ *
+ * Column numbering of the joined link tuples: the link relation's columns
+ * 0..n_cols-1 (with two_hop: 0..2 n_cols-1, see relnn_build_index), then the
+ * columns of each step in step order, then one derived column per chain in
+ * chain order.  Chains may read any earlier column; atoms, the head key and
+ * predicates any column. */
 typedef struct {
   int64_t n_link;                 /* rows of the link relation */
   int32_t n_cols;                 /* its columns */
@@ -101,6 +139,10 @@ typedef struct {
                                      relation is self-joined first */
   int32_t two_hop_cap;            /* paths kept per mid key (two-hop only) */
   uint32_t flags;                 /* RELNN_IDX_BWD */
+  int32_t n_steps;                /* further link relations, joined in order */
+  const relnn_join_step* steps;   /* host [n_steps] */
+  int32_t n_preds;                /* filter expression: conjunction of */
+  const relnn_pred* preds;        /* host [n_preds] predicates */
 } relnn_join_desc;
 
 #define RELNN_MAX_ATOMS 4
@@ -121,6 +163,13 @@ typedef struct relnn_index relnn_index;   /* opaque, device-resident */
  * relation has 2*n_cols columns: 0..n_cols-1 from b_i, n_cols.. from b_j;
  * atoms, chains and group_col refer to those.  "link row" then means the
  * path number (mid keys ascending, then p).
+ *
+ * Steps: each joined tuple extends one tuple so far by one row of S; the
+ * joined link tuples are numbered in the order (link row or path number,
+ * row of step 1's relation, row of step 2's ...), and "link row" means that
+ * number.  The filter applies after the chains; a tuple that fails it is
+ * dropped before the atoms are matched.  More than 2^31 - 1 joined link
+ * tuples: RELNN_E_RANGE.
  *
  * Synchronises `stream`.  *out is owned by the caller through
  * relnn_index_free. */
@@ -208,6 +257,53 @@ relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_layer_desc* L,
                              const float* pre, const int32_t* argmax, const float* dout,
                              float* const* demb, float* dW, float* db,
                              void* ws, size_t ws_bytes, relnn_stream_t stream);
+
+/* ---------------------------------------------------------------- union */
+
+/* The k-ary projected union (Section 2.2) of the join results of k rules
+ * with one head, e.g. the several bodies of one head relation:
+ *
+ *     Out(g; act_post(tau_post(alpha(...))))  over  T_1(join_1) | ... | T_k(join_k)
+ *
+ * The output content is the set of head keys of all k indices (ascending);
+ * the multiset of a key holds every joined tuple of every branch with that
+ * key, each with its own branch's transform tau_i; alpha is applied once
+ * over the whole multiset (MEAN is the sum over all members divided by
+ * their number, not a mean of the branches' means).  A union rule
+ * (Section 3.1) applies its transform after the union: tau_post(v) =
+ * v W_post + b_post on each key's aggregate. */
+#define RELNN_MAX_UNION 8
+
+typedef struct relnn_union relnn_union;   /* opaque, device-resident */
+
+/* Builds the union's keys and maps every branch group to its union row.
+ * The branch indices stay caller-owned and must outlive the union.
+ * Synchronises `stream`. */
+relnn_status relnn_union_build(const relnn_index* const* branches, int32_t k, relnn_stream_t stream,
+                               relnn_union** out);
+relnn_status relnn_union_query(const relnn_union* u, int64_t* n_groups);
+/* keys [G] ascending and counts [G] (members over all branches), device,
+ * either may be NULL.  Async. */
+relnn_status relnn_union_export(const relnn_union* u, int32_t* keys, int32_t* counts, relnn_stream_t stream);
+relnn_status relnn_union_free(relnn_union* u);
+
+/* Workspace bytes of relnn_union_fwd for these branch layers. */
+relnn_status relnn_union_workspace_size(const relnn_union* u, const relnn_layer_desc* const* L, int32_t agg,
+                                        size_t* bytes);
+
+/* Forward.  L: host [k] layer descriptors of the branches (widths, dtype,
+ * act_pre; all the same h; their agg, act_post and flags are not used).
+ * agg: the union's aggregate (SUM, MEAN, MAX; MAX gives values only).  emb:
+ * host [k] of the branch's host [k_i] device embedding pointers; W: host
+ * [k] device [K_i, h]; b: host [k] of device [h] or NULL (or b NULL).
+ * W_post: device [h, h_out] FP32 row-major or NULL (then h_out = h);
+ * b_post: device [h_out] or NULL.  out: device [G, h_out] FP32 =
+ * act_post(tau_post(aggregate)); pre: device [G, h] FP32 aggregate or NULL.
+ * Row u is the union's key u. */
+relnn_status relnn_union_fwd(const relnn_union* u, const relnn_layer_desc* const* L, int32_t agg,
+                             int32_t act_post, const void* const* const* emb, const void* const* W,
+                             const float* const* b, const float* W_post, const float* b_post, int32_t h_out,
+                             float* out, float* pre, void* ws, size_t ws_bytes, relnn_stream_t stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the

@@ -30,12 +30,26 @@ class Chain(C.Structure):
                 ("vals", C.c_void_p)]
 
 
+class JoinStep(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("n_cols", C.c_int32), ("cols", C.POINTER(C.c_void_p)),
+                ("n_on", C.c_int32), ("on", C.c_int32 * 2), ("key", C.c_int32 * 2)]
+
+
+class Pred(C.Structure):
+    _fields_ = [("a", C.c_int32), ("b", C.c_int32), ("mul_a", C.c_int64), ("mul_b", C.c_int64),
+                ("add", C.c_int64), ("op", C.c_int32)]
+
+
+CMP = {"eq": 0, "ne": 1, "lt": 2, "le": 3, "gt": 4, "ge": 5}
+
+
 class JoinDesc(C.Structure):
     _fields_ = [("n_link", C.c_int64), ("n_cols", C.c_int32), ("cols", C.POINTER(C.c_void_p)),
                 ("n_chains", C.c_int32), ("chains", C.POINTER(Chain)),
                 ("n_atoms", C.c_int32), ("atoms", C.POINTER(Atom)),
                 ("group_col", C.c_int32), ("two_hop_mid", C.c_int32), ("two_hop_cap", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("n_steps", C.c_int32), ("steps", C.POINTER(JoinStep)),
+                ("n_preds", C.c_int32), ("preds", C.POINTER(Pred))]
 
 
 class LayerDesc(C.Structure):
@@ -84,6 +98,16 @@ _SIGS = {
     "relnn_layer_fwd_static": (C.c_int, [C.c_void_p, C.POINTER(LayerDesc), C.POINTER(C.c_void_p), C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "relnn_static_scratch_bytes": (C.c_int, [C.POINTER(C.c_size_t)]),
+    "relnn_union_build": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "relnn_union_query": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "relnn_union_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "relnn_union_free": (C.c_int, [C.c_void_p]),
+    "relnn_union_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(C.POINTER(LayerDesc)), C.c_int32,
+                                             C.POINTER(C.c_size_t)]),
+    "relnn_union_fwd": (C.c_int, [C.c_void_p, C.POINTER(C.POINTER(LayerDesc)), C.c_int32, C.c_int32,
+                                  C.POINTER(C.POINTER(C.c_void_p)), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_size_t, C.c_void_p]),
     "relnn_layer_bwd": (C.c_int, [C.c_void_p, C.POINTER(LayerDesc), C.POINTER(C.c_void_p), C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p),
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),

@@ -40,10 +40,13 @@ class Index:
     cols: link columns, int32 [n_link] each.  atoms: (n_rows, col, keys)
     per body atom in Concat order (keys None = dense ids).  chains:
     (src_col, vals, keys) derived columns.  two_hop: (mid_col, cap) or None.
+    steps: (cols, on, key) further link relations joined in order (on / key:
+    one or two column numbers).  preds: (a, op, b, mul_a, mul_b, add)
+    filter predicates, op one of eq ne lt le gt ge.
     """
 
     def __init__(self, cols: Sequence[torch.Tensor], atoms, group_col: int, chains=(),
-                 two_hop=None, bwd: bool = False, stream=None):
+                 two_hop=None, bwd: bool = False, steps=(), preds=(), stream=None):
         lib()
         self._handle = None
         cols = [_i32(c, "link column") for c in cols]
@@ -74,6 +77,27 @@ class Index:
         d.group_col = int(group_col)
         d.two_hop_mid, d.two_hop_cap = (-1, 0) if two_hop is None else (int(two_hop[0]), int(two_hop[1]))
         d.flags = L.IDX_BWD if bwd else 0
+        sa = (L.JoinStep * max(1, len(steps)))()
+        for i, (scols, on, key) in enumerate(steps):
+            scols = [_i32(c, "step column") for c in scols]
+            arr = (C.c_void_p * len(scols))(*[c.data_ptr() for c in scols])
+            keep += scols + [arr]
+            sa[i].n_rows = int(scols[0].numel())
+            sa[i].n_cols = len(scols)
+            sa[i].cols = arr
+            if len(on) != len(key) or not 1 <= len(on) <= 2:
+                raise ValueError("a step joins on one or two column pairs")
+            sa[i].n_on = len(on)
+            for q in range(len(on)):
+                sa[i].on[q] = int(on[q])
+                sa[i].key[q] = int(key[q])
+        pa = (L.Pred * max(1, len(preds)))()
+        for i, (a, op, b, mul_a, mul_b, add) in enumerate(preds):
+            pa[i].a, pa[i].b = int(a), int(b)
+            pa[i].mul_a, pa[i].mul_b, pa[i].add = int(mul_a), int(mul_b), int(add)
+            pa[i].op = L.CMP[op]
+        d.n_steps, d.steps = len(steps), sa
+        d.n_preds, d.preds = len(preds), pa
         h = C.c_void_p()
         check(lib().relnn_build_index(C.byref(d), _stream(stream), C.byref(h)))
         self._handle = h
@@ -109,6 +133,82 @@ class Index:
             self.free()
         except Exception:
             pass
+
+
+class Union:
+    """relnn_union_build: the k-ary projected union of the head keys of k
+    join indices (device-resident, library-owned; the indices must outlive
+    it)."""
+
+    def __init__(self, branches: Sequence["Index"], stream=None):
+        lib()
+        self._handle = None
+        self.branches = list(branches)
+        arr = (C.c_void_p * len(branches))(*[b.handle.value for b in branches])
+        h = C.c_void_p()
+        check(lib().relnn_union_build(arr, len(branches), _stream(stream), C.byref(h)))
+        self._handle = h
+        G = C.c_int64()
+        check(lib().relnn_union_query(h, C.byref(G)))
+        self.G = G.value
+        self.k = len(branches)
+        self.device = branches[0].device
+
+    @property
+    def handle(self):
+        return self._handle
+
+    def export(self, stream=None):
+        keys = torch.empty(self.G, dtype=torch.int32, device=self.device)
+        cnt = torch.empty(self.G, dtype=torch.int32, device=self.device)
+        check(lib().relnn_union_export(self._handle, _vp(keys), _vp(cnt), _stream(stream)))
+        return {"keys": keys, "counts": cnt}
+
+    def free(self):
+        if self._handle is not None and _lib_alive():
+            check(lib().relnn_union_free(self._handle))
+        self._handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def union_fwd(union: Union, layers: Sequence["Layer"], agg: str, act_post: str, embs, Ws, bs=None,
+              W_post: Optional[torch.Tensor] = None, b_post: Optional[torch.Tensor] = None, want_pre: bool = True,
+              stream=None):
+    """relnn_union_fwd.  embs[i]: the branch's embedding tensors; Ws[i],
+    bs[i]: its transform.  Returns (out [G, h_out], pre [G, h] or None)."""
+    k = union.k
+    if not (len(layers) == len(embs) == len(Ws) == k):
+        raise ValueError("one layer, embedding list and W per branch")
+    descs = [l.desc() for l in layers]
+    dptr = (C.POINTER(L.LayerDesc) * k)(*[C.pointer(d) for d in descs])
+    emb_arrs = [(C.c_void_p * len(e))(*[t.data_ptr() for t in e]) for e in embs]
+    for l, e, W in zip(layers, embs, Ws):
+        _check_embs(l, e)
+        if W.dtype != l.torch_dtype or W.shape != (l.K, l.h) or not W.is_contiguous():
+            raise TypeError(f"W must be a contiguous {l.torch_dtype} [{l.K}, {l.h}] tensor")
+    emb_pp = (C.POINTER(C.c_void_p) * k)(*[C.cast(a, C.POINTER(C.c_void_p)) for a in emb_arrs])
+    W_arr = (C.c_void_p * k)(*[W.data_ptr() for W in Ws])
+    b_arr = None if bs is None else (C.c_void_p * k)(*[None if b is None else b.data_ptr() for b in bs])
+    h = layers[0].h
+    h_out = h if W_post is None else int(W_post.shape[1])
+    if W_post is not None and (W_post.dtype != torch.float32 or tuple(W_post.shape) != (h, h_out)
+                               or not W_post.is_contiguous()):
+        raise TypeError(f"W_post must be a contiguous float32 [{h}, h_out] tensor")
+    dev = union.device
+    out = torch.empty(union.G, h_out, dtype=torch.float32, device=dev)
+    pre = torch.empty(union.G, h, dtype=torch.float32, device=dev) if want_pre else None
+    n = C.c_size_t()
+    check(lib().relnn_union_workspace_size(union.handle, dptr, _AGGS[agg], C.byref(n)))
+    ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=dev)
+    check(lib().relnn_union_fwd(union.handle, dptr, _AGGS[agg], _ACTS[act_post], emb_pp, W_arr, b_arr,
+                                _vp(W_post), _vp(b_post), h_out, _vp(out), _vp(pre), _vp(ws), ws.numel(),
+                                _stream(stream)))
+    return out, pre
 
 
 def _lib_alive():

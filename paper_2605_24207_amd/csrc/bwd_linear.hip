@@ -79,18 +79,18 @@ __device__ __forceinline__ GsAtom gs_atom(const GsArgs& a, int col) {
 
 // VW (4 or 2) consecutive elements of the joined row at list position e,
 // as FP32 (the unused lanes of an f32x4 are zero).
-template <int VW>
+template <int VW, bool kBF16>
 __device__ __forceinline__ f32x4 gs_load(const GsArgs& a, const GsAtom& A, int32_t row, int col) {
   const int64_t o = (int64_t)row * A.d + (col - A.koff);
   if constexpr (VW == 4) {
-    if (a.bf16) {
+    if constexpr (kBF16) {
       const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const __bf16*>(A.emb) + o);
       return f32x4{__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u), __uint_as_float(v.y << 16),
                    __uint_as_float(v.y & 0xffff0000u)};
     }
     return *reinterpret_cast<const f32x4*>(static_cast<const float*>(A.emb) + o);
   } else {
-    if (a.bf16) {
+    if constexpr (kBF16) {
       const uint32_t v = *reinterpret_cast<const uint32_t*>(static_cast<const __bf16*>(A.emb) + o);
       return f32x4{__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u), 0.f, 0.f};
     }
@@ -106,7 +106,7 @@ __device__ __forceinline__ f32x4 gs_load(const GsArgs& a, const GsAtom& A, int32
 // start) or 1 (runs past the end); k_fixup combines them in unit order.
 // VW columns per lane: 4, or 2 for rows of at most 128 elements (all 64
 // lanes busy; a wave instruction costs the same with 32 or 64 lanes on).
-template <int VW>
+template <int VW, bool kBF16>
 __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
   const int lane = threadIdx.x % 64;
   const int64_t u = (int64_t)blockIdx.x * kGsWaves + threadIdx.x / 64;
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
             const int32_t rj = __builtin_amdgcn_readlane(R[j], q);
             row = A.j == j ? rj : row;
           }
-          v[i] = gs_load<VW>(a, A, row, on ? col : 0);
+          v[i] = gs_load<VW, kBF16>(a, A, row, on ? col : 0);
           if (a.own || a.mask) {                        // route the gradient row of this tuple
             const int32_t tau = __builtin_amdgcn_readlane(R[1], q);
             if (a.own) {                                // VW columns of one 32-column word
@@ -215,10 +215,18 @@ void seg_gather_sum(GsArgs a, int64_t nseg_units_cap, hipStream_t s) {
   a.nunits = gs_units(a.n);
   RELNN_REQUIRE(a.nunits <= nseg_units_cap, RELNN_E_HIP, "internal: carry region too small");
   RELNN_REQUIRE(a.K % 4 == 0, RELNN_E_UNSUPPORTED, "row width %d is not a multiple of 4", a.K);
-  if (a.K <= 128)
-    k_seg_gather_sum<2><<<(unsigned)cdiv(a.nunits, kGsWaves), kGsWaves * 64, 0, s>>>(a);
-  else
-    k_seg_gather_sum<4><<<(unsigned)cdiv(a.nunits, kGsWaves), kGsWaves * 64, 0, s>>>(a);
+  const unsigned g = (unsigned)cdiv(a.nunits, kGsWaves);
+  if (a.K <= 128) {
+    if (a.bf16)
+      k_seg_gather_sum<2, true><<<g, kGsWaves * 64, 0, s>>>(a);
+    else
+      k_seg_gather_sum<2, false><<<g, kGsWaves * 64, 0, s>>>(a);
+  } else {
+    if (a.bf16)
+      k_seg_gather_sum<4, true><<<g, kGsWaves * 64, 0, s>>>(a);
+    else
+      k_seg_gather_sum<4, false><<<g, kGsWaves * 64, 0, s>>>(a);
+  }
   RELNN_LAUNCHED();
   // the fix-up reads carry slots and writes out rows with stride ldo
   Sink sk{};

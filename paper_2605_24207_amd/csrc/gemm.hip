@@ -235,7 +235,12 @@ __global__ void __launch_bounds__(kRowsWaves * 64) k_gemm_rows(RowsArgs a) {
           const int n = n0 + 16 * cb + lm;
           if (n < a.N) {
             const float v = sc_cur[r] * acc[cb][r];
-            crow[n] = a.epi.accumulate ? cv[r][cb] + v : v;
+            if (a.epi.accumulate) {
+              crow[n] = cv[r][cb] + v;
+            } else {
+              const float u = a.epi.bias ? v + a.epi.bias[n] : v;
+              crow[n] = a.epi.act == RELNN_ACT_RELU ? fmaxf(u, 0.0f) : u;
+            }
           }
         }
       }
@@ -349,10 +354,13 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
     unit_mg[p] = idx / 32;
     unit_cg[p] = idx % 32;
   }
-  int64_t rn[PER][4];                              // source rows of the A units (next tile to load)
-  f32x4 x[PER][4];                                 // loaded values, one f32x4 per unit row
-  int32_t cnt[PER][4] = {};                        // db weights of the B unit rows
-  uint32_t keep[PER][4] = {};                      // routing of the B unit rows: one bit per column
+  int64_t rn[PER][4];                              // source rows of the units (next tile to load)
+  struct Stage {                                   // one tile's loads, in registers
+    f32x4 x[PER][4];                               // one f32x4 per unit row
+    int32_t cnt[PER][4];                           // db weights of the B unit rows
+    uint32_t keep[PER][4];                         // routing of the B unit rows: one bit per column
+  };
+  Stage st0, st1;
   auto fetch_idx = [&](int64_t t) {
 #pragma unroll
     for (int p = 0; p < PER; ++p)
@@ -367,7 +375,7 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
           rn[p][r] = m;
       }
   };
-  auto fetch_data = [&](int64_t t) {
+  auto fetch_data = [&](int64_t t, Stage& S) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
       if (unit_mat[p] == 0) {
@@ -376,9 +384,9 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
         for (int r = 0; r < 4; ++r) {
           if constexpr (kA16) {
             const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const __bf16*>(a.A) + rn[p][r] * a.lda + col);
-            x[p][r] = bf4_f32(v.x, v.y);
+            S.x[p][r] = bf4_f32(v.x, v.y);
           } else {
-            x[p][r] = *reinterpret_cast<const f32x4*>(static_cast<const float*>(a.A) + rn[p][r] * a.lda + col);
+            S.x[p][r] = *reinterpret_cast<const f32x4*>(static_cast<const float*>(a.A) + rn[p][r] * a.lda + col);
           }
         }
       } else {
@@ -386,8 +394,8 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t m = min<int64_t>(t * MT + 4 * unit_mg[p] + r, a.M - 1);
-          x[p][r] = *reinterpret_cast<const f32x4*>(a.b.B + rn[p][r] * a.b.ldb + col);
-          if (do_db && a.wcnt) cnt[p][r] = a.wcnt[m + 1] - a.wcnt[m];
+          S.x[p][r] = *reinterpret_cast<const f32x4*>(a.b.B + rn[p][r] * a.b.ldb + col);
+          if (do_db && a.wcnt) S.cnt[p][r] = a.wcnt[m + 1] - a.wcnt[m];
           if (route) {                              // the four columns col .. col + 3 of row m
             uint32_t k = 15u;
             if (a.b.own) k &= a.b.own[m * a.b.own_w + (col >> 5)] >> (col & 31);
@@ -396,14 +404,14 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
               k &= (uint32_t)((mb & 0xffu) != 0) | ((uint32_t)((mb & 0xff00u) != 0) << 1) |
                    ((uint32_t)((mb & 0xff0000u) != 0) << 2) | ((uint32_t)((mb & 0xff000000u) != 0) << 3);
             }
-            keep[p][r] = k;
+            S.keep[p][r] = k;
           }
         }
       }
     }
   };
   f32x4 dbacc = {0.f, 0.f, 0.f, 0.f};              // db of this thread's B unit columns (do_db)
-  auto stash = [&](int b, int64_t t) {
+  auto stash = [&](int b, int64_t t, const Stage& S) {
     LT* base = lds + b * BUF;
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
@@ -413,12 +421,12 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const bool on = col_on && t * MT + 4 * mg + r < a.M;
-        v[r] = on ? x[p][r] : f32x4{0.f, 0.f, 0.f, 0.f};
+        v[r] = on ? S.x[p][r] : f32x4{0.f, 0.f, 0.f, 0.f};
         if (mat == 1 && route) {
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) v[r][cc] = ((keep[p][r] >> cc) & 1u) ? v[r][cc] : 0.0f;
+          for (int cc = 0; cc < 4; ++cc) v[r][cc] = ((S.keep[p][r] >> cc) & 1u) ? v[r][cc] : 0.0f;
         }
-        if (mat == 1 && do_db) dbacc += (on ? (a.wcnt ? (float)cnt[p][r] : 1.0f) : 0.0f) * v[r];
+        if (mat == 1 && do_db) dbacc += (on ? (a.wcnt ? (float)S.cnt[p][r] : 1.0f) : 0.0f) * v[r];
       }
       LT* dst = base + (mat * 128 + 4 * cg) * TS + 4 * mg;
 #pragma unroll
@@ -470,22 +478,49 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
     }
   };
 
-  // loads of row numbers run two tiles ahead and of values one tile ahead;
-  // the prefetches past the chunk's last tile repeat it (valid, unused)
+  // FP32 tiles carry enough products per load to hide the loads one tile
+  // ahead; bf16 tiles (eight times fewer product cycles per byte) load two
+  // tiles ahead, alternating between two register stages so that the ring
+  // index is known at compile time.  Row numbers run one tile ahead of the
+  // values they address.  Tile t is multiplied from LDS buffer (t - tb) & 1
+  // while tile t + 1 is stashed into the other.  Prefetches past the
+  // chunk's last tile repeat it (valid, unused).
   const int64_t tl = te - 1;
-  fetch_idx(tb);
-  fetch_data(tb);
-  fetch_idx(min(tb + 1, tl));
-  stash(0, tb);
-  __syncthreads();
-  for (int64_t t = tb; t < te; ++t) {
-    const int b = (int)((t - tb) & 1);
-    const bool more = t + 1 < te;
-    fetch_data(min(t + 1, tl));
-    fetch_idx(min(t + 2, tl));
-    compute(b);
-    if (more) stash(b ^ 1, t + 1);
+  if constexpr (!kB16) {
+    fetch_idx(tb);
+    fetch_data(tb, st0);
+    fetch_idx(min(tb + 1, tl));
+    stash(0, tb, st0);
     __syncthreads();
+    for (int64_t t = tb; t < te; ++t) {
+      const int b = (int)((t - tb) & 1);
+      fetch_data(min(t + 1, tl), st0);
+      fetch_idx(min(t + 2, tl));
+      compute(b);
+      if (t + 1 < te) stash(b ^ 1, t + 1, st0);
+      __syncthreads();
+    }
+  } else {
+    fetch_idx(tb);
+    fetch_data(tb, st0);
+    fetch_idx(min(tb + 1, tl));
+    fetch_data(min(tb + 1, tl), st1);
+    fetch_idx(min(tb + 2, tl));
+    stash(0, tb, st0);
+    __syncthreads();
+    for (int64_t t = tb; t < te; t += 2) {
+      fetch_data(min(t + 2, tl), st0);
+      fetch_idx(min(t + 3, tl));
+      compute(0);
+      if (t + 1 < te) stash(1, t + 1, st1);
+      __syncthreads();
+      if (t + 1 >= te) break;
+      fetch_data(min(t + 3, tl), st1);
+      fetch_idx(min(t + 4, tl));
+      compute(1);
+      if (t + 2 < te) stash(0, t + 2, st0);
+      __syncthreads();
+    }
   }
   if (wave_on) {
 #pragma unroll

@@ -10,12 +10,15 @@ namespace relnn {
 
 // Where a row of gemm_rows' result goes: C row orow[oidx[m]] (oidx null:
 // orow[m]; orow null: m), scaled by wcnt[m+1] - wcnt[m] (wcnt null: 1), added
-// into C (accumulate) or stored.  Destination rows must be distinct.
+// into C (accumulate) or stored (plus bias, then the activation act).
+// Destination rows must be distinct.
 struct RowsEpi {
   const int32_t* orow = nullptr;
   const int32_t* oidx = nullptr;
   const int32_t* wcnt = nullptr;
   bool accumulate = false;
+  const float* bias = nullptr;    // stored rows only: + bias[n], then act
+  int act = RELNN_ACT_NONE;
 };
 
 // C[dst(m)][n] (+)= s_m sum_{k < Kd} A[m][k] B[k][n] for m < M, n < N.

@@ -6,6 +6,14 @@
 // 2.2) groups the joined tuples by the head key; its content is the set of
 // keys that occur, so empty groups never appear.
 //
+// Further link relations (general, many-to-many and cyclic joins) are joined
+// by sort-and-probe: the relation's rows are radix-sorted by their key
+// columns, every tuple so far finds its range of matches by binary search on
+// the key pair, the counts are scanned, and one pass writes for every output
+// tuple the tuple it extends and the matching row.  A filter (the selection
+// of Section 3.1) clears the valid flag of the tuples that fail it, before
+// the compaction.
+//
 // GPU plan: key tables of keyed relations are radix-sorted and probed by
 // binary search; dense relations are direct-addressed.  Valid tuples are
 // compacted by a scan, then put in canonical order by a stable LSD radix
@@ -202,6 +210,123 @@ int64_t expand_two_hop(std::vector<const int32_t*>& col, int64_t n_link, int mid
   return P;
 }
 
+// Range [lo, lo + cnt) of the rows of S (sorted by (k0, k1)) whose key pair
+// equals (v0[i], v1[i]) (k1 / v1 null: one column).
+__global__ void k_probe(const int32_t* v0, const int32_t* v1, int64_t n, const int32_t* k0, const int32_t* k1,
+                        int64_t ns, int32_t* lo_out, int64_t* cnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = v0[i];
+    const int32_t b = v1 ? v1[i] : 0;
+    auto less = [&](int64_t m, bool upper) {      // key[m] < (a, b), or <= for the upper bound
+      const int32_t x = k0[m];
+      if (x != a) return x < a;
+      if (!k1) return upper;
+      const int32_t y = k1[m];
+      return upper ? y <= b : y < b;
+    };
+    int64_t lo = 0, hi = ns;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (less(mid, false)) lo = mid + 1; else hi = mid;
+    }
+    int64_t lo2 = lo, hi2 = ns;
+    while (lo2 < hi2) {
+      const int64_t mid = (lo2 + hi2) >> 1;
+      if (less(mid, true)) lo2 = mid + 1; else hi2 = mid;
+    }
+    lo_out[i] = (int32_t)lo;
+    cnt[i] = lo2 - lo;
+  }
+}
+
+// Output tuple p extends tuple i (the last i with off[i] <= p) with row
+// perm[lo[i] + p - off[i]] of S.
+__global__ void k_expand(const int64_t* off, const int32_t* lo, int64_t n, const int32_t* perm, int64_t P,
+                         int32_t* src, int32_t* srow) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    int64_t a = 0, b = n;
+    while (b - a > 1) {
+      const int64_t mid = (a + b) >> 1;
+      if (off[mid] <= p) a = mid; else b = mid;
+    }
+    src[p] = (int32_t)a;
+    srow[p] = perm[lo[a] + (p - off[a])];
+  }
+}
+
+// Joins further link relation st into the tuples so far (n of them, columns
+// col); col and n are replaced by the joined tuples.
+int64_t expand_step(std::vector<const int32_t*>& col, int64_t n, const relnn_join_step& st, BufList& owned,
+                    hipStream_t s) {
+  const int64_t ns = st.n_rows;
+  std::vector<const int32_t*> out;
+  if (n == 0 || ns == 0) {
+    for (size_t c = 0; c < col.size() + (size_t)st.n_cols; ++c) out.push_back(new_buf(owned, 0));
+    col = out;
+    return 0;
+  }
+  // rows of S sorted by (key0, key1, row): stable passes, least significant first
+  DevBuf perm(ns * sizeof(int32_t));
+  prim::iota_i32(perm.as<int32_t>(), ns, s);
+  if (st.n_on == 2) sort_by_column(st.cols[st.key[1]], perm.as<int32_t>(), ns, s);
+  sort_by_column(st.cols[st.key[0]], perm.as<int32_t>(), ns, s);
+  DevBuf k0(ns * sizeof(int32_t)), k1(st.n_on == 2 ? ns * sizeof(int32_t) : 0);
+  prim::gather_i32(st.cols[st.key[0]], perm.as<int32_t>(), ns, k0.as<int32_t>(), s);
+  if (st.n_on == 2) prim::gather_i32(st.cols[st.key[1]], perm.as<int32_t>(), ns, k1.as<int32_t>(), s);
+  DevBuf lo(n * sizeof(int32_t)), cnt(n * sizeof(int64_t)), off(n * sizeof(int64_t));
+  k_probe<<<grid_for(n), 256, 0, s>>>(col[st.on[0]], st.n_on == 2 ? col[st.on[1]] : nullptr, n, k0.as<int32_t>(),
+                                      st.n_on == 2 ? k1.as<int32_t>() : nullptr, ns, lo.as<int32_t>(),
+                                      cnt.as<int64_t>());
+  RELNN_LAUNCHED();
+  int64_t P = 0;
+  prim::scan_i64(cnt.as<int64_t>(), n, off.as<int64_t>(), &P, s);
+  RELNN_REQUIRE(P < (int64_t)INT32_MAX, RELNN_E_RANGE, "joined link tuples %lld exceed 2^31 - 1", (long long)P);
+  DevBuf src(std::max<int64_t>(P, 1) * sizeof(int32_t)), srow(std::max<int64_t>(P, 1) * sizeof(int32_t));
+  if (P > 0) {
+    k_expand<<<grid_for(P), 256, 0, s>>>(off.as<int64_t>(), lo.as<int32_t>(), n, perm.as<int32_t>(), P,
+                                         src.as<int32_t>(), srow.as<int32_t>());
+    RELNN_LAUNCHED();
+  }
+  for (const int32_t* c : col) {
+    int32_t* a = new_buf(owned, P);
+    prim::gather_i32(c, src.as<int32_t>(), P, a, s);
+    out.push_back(a);
+  }
+  for (int c = 0; c < st.n_cols; ++c) {
+    int32_t* a = new_buf(owned, P);
+    prim::gather_i32(st.cols[c], srow.as<int32_t>(), P, a, s);
+    out.push_back(a);
+  }
+  RELNN_HIP(hipStreamSynchronize(s));
+  col = out;
+  return P;
+}
+
+// valid[i] &= (mul_a ca[i] + mul_b cb[i] + add) op 0, in int64 arithmetic
+// (wrapping as two's complement).
+__global__ void k_pred(const int32_t* ca, const int32_t* cb, int64_t mul_a, int64_t mul_b, int64_t add, int op,
+                       int64_t n, uint8_t* valid) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t v = (uint64_t)add;
+    if (ca) v += (uint64_t)mul_a * (uint64_t)(int64_t)ca[i];
+    if (cb) v += (uint64_t)mul_b * (uint64_t)(int64_t)cb[i];
+    const int64_t x = (int64_t)v;
+    bool ok;
+    switch (op) {
+      case RELNN_CMP_EQ: ok = x == 0; break;
+      case RELNN_CMP_NE: ok = x != 0; break;
+      case RELNN_CMP_LT: ok = x < 0; break;
+      case RELNN_CMP_LE: ok = x <= 0; break;
+      case RELNN_CMP_GT: ok = x > 0; break;
+      default: ok = x >= 0; break;
+    }
+    if (!ok) valid[i] = 0;
+  }
+}
+
 void validate(const relnn_join_desc* D) {
   RELNN_REQUIRE(D != nullptr, RELNN_E_INVALID, "join descriptor is NULL");
   RELNN_REQUIRE(D->n_link >= 0 && D->n_link < (int64_t)INT32_MAX, RELNN_E_RANGE,
@@ -214,7 +339,21 @@ void validate(const relnn_join_desc* D) {
     RELNN_REQUIRE(D->two_hop_mid < D->n_cols, RELNN_E_INVALID, "two_hop_mid out of range");
     RELNN_REQUIRE(D->two_hop_cap >= 1, RELNN_E_INVALID, "two_hop_cap must be >= 1");
   }
-  const int base = two ? 2 * D->n_cols : D->n_cols;
+  int base = two ? 2 * D->n_cols : D->n_cols;
+  RELNN_REQUIRE(D->n_steps >= 0 && (D->n_steps == 0 || D->steps != nullptr), RELNN_E_INVALID, "steps NULL");
+  for (int i = 0; i < D->n_steps; ++i) {
+    const relnn_join_step& st = D->steps[i];
+    RELNN_REQUIRE(st.n_rows >= 0 && st.n_rows < (int64_t)INT32_MAX, RELNN_E_RANGE, "step %d n_rows", i);
+    RELNN_REQUIRE(st.n_cols >= 1 && st.cols != nullptr, RELNN_E_INVALID, "step %d has no columns", i);
+    for (int c = 0; c < st.n_cols; ++c)
+      RELNN_REQUIRE(st.cols[c] != nullptr || st.n_rows == 0, RELNN_E_INVALID, "step %d column %d is NULL", i, c);
+    RELNN_REQUIRE(st.n_on == 1 || st.n_on == 2, RELNN_E_INVALID, "step %d: n_on must be 1 or 2", i);
+    for (int q = 0; q < st.n_on; ++q) {
+      RELNN_REQUIRE(st.on[q] >= 0 && st.on[q] < base, RELNN_E_INVALID, "step %d on[%d] out of range", i, q);
+      RELNN_REQUIRE(st.key[q] >= 0 && st.key[q] < st.n_cols, RELNN_E_INVALID, "step %d key[%d] out of range", i, q);
+    }
+    base += st.n_cols;
+  }
   RELNN_REQUIRE(D->n_chains >= 0 && (D->n_chains == 0 || D->chains != nullptr), RELNN_E_INVALID,
                 "chains NULL");
   for (int i = 0; i < D->n_chains; ++i) {
@@ -233,6 +372,13 @@ void validate(const relnn_join_desc* D) {
     RELNN_REQUIRE(a.n_rows >= 0 && a.n_rows < (int64_t)INT32_MAX, RELNN_E_RANGE, "atom %d n_rows", j);
   }
   RELNN_REQUIRE(D->group_col >= 0 && D->group_col < ncol, RELNN_E_INVALID, "group_col out of range");
+  RELNN_REQUIRE(D->n_preds >= 0 && (D->n_preds == 0 || D->preds != nullptr), RELNN_E_INVALID, "preds NULL");
+  for (int i = 0; i < D->n_preds; ++i) {
+    const relnn_pred& p = D->preds[i];
+    RELNN_REQUIRE(p.a >= -1 && p.a < ncol && p.b >= -1 && p.b < ncol, RELNN_E_INVALID,
+                  "predicate %d column out of range", i);
+    RELNN_REQUIRE(p.op >= RELNN_CMP_EQ && p.op <= RELNN_CMP_GE, RELNN_E_INVALID, "predicate %d: unknown op", i);
+  }
   RELNN_REQUIRE((D->flags & ~RELNN_IDX_BWD) == 0, RELNN_E_INVALID, "unknown index flags");
 }
 
@@ -256,6 +402,13 @@ extern "C" relnn_status relnn_build_index(const relnn_join_desc* D, relnn_stream
       n = expand_two_hop(col, n, D->two_hop_mid, D->two_hop_cap, owned, s);
     else if (D->two_hop_mid >= 0)
       col.resize(2 * D->n_cols, nullptr);
+    for (int i = 0; i < D->n_steps; ++i) {
+      if (n > 0) {
+        n = expand_step(col, n, D->steps[i], owned, s);
+      } else {
+        for (int c = 0; c < D->steps[i].n_cols; ++c) col.push_back(nullptr);
+      }
+    }
     const int base = (int)col.size();
     std::vector<bool> fd(base + D->n_chains, false);   // functionally dependent on the head key
 
@@ -272,6 +425,12 @@ extern "C" relnn_status relnn_build_index(const relnn_join_desc* D, relnn_stream
       lookup(col[ch.src_col], n, t, ch.vals, dcol, valid.as<uint8_t>(), s);
       RELNN_HIP(hipStreamSynchronize(s));
       col.push_back(dcol);
+    }
+    for (int i = 0; i < D->n_preds && n > 0; ++i) {      // the filter: a conjunction
+      const relnn_pred& p = D->preds[i];
+      k_pred<<<grid_for(n), 256, 0, s>>>(p.a >= 0 ? col[p.a] : nullptr, p.b >= 0 ? col[p.b] : nullptr, p.mul_a,
+                                         p.mul_b, p.add, p.op, n, valid.as<uint8_t>());
+      RELNN_LAUNCHED();
     }
     for (int c = 0; c < (int)fd.size(); ++c) {
       fd[c] = (c == D->group_col);

@@ -16,7 +16,9 @@ def gpu_index(rule, bwd=False, device="cuda"):
     atoms = [(a.n_rows, a.col, None if a.keys is None else t(a.keys)) for a in rule.atoms]
     chains = [(c.src_col, t(c.vals), None if c.keys is None else t(c.keys)) for c in rule.chains]
     two = None if rule.two_hop_mid < 0 else (rule.two_hop_mid, rule.two_hop_cap)
-    return Index(cols, atoms, rule.group_col, chains=chains, two_hop=two, bwd=bwd)
+    steps = [([t(c) for c in st.cols], st.on, st.key) for st in rule.steps]
+    preds = [(p.a, p.op, p.b, p.mul_a, p.mul_b, p.add) for p in rule.preds]
+    return Index(cols, atoms, rule.group_col, chains=chains, two_hop=two, bwd=bwd, steps=steps, preds=preds)
 
 
 def gpu_layer(rule, dtype="f32", plain=False, pushdown=False):
