@@ -355,3 +355,65 @@ def union_fwd(branches, agg="sum", act_post="none", W_post=None, b_post=None):
     v = pre if W_post is None else pre @ np.asarray(W_post, np.float64) + (
         0.0 if b_post is None else np.asarray(b_post, np.float64))
     return np.array(keys, np.int64), _act(act_post, v), pre, arg
+
+
+# ---------------------------------------------------------------------------
+# product transforms and segmented softmax (Section 1's attention example,
+# Section 5.2's HGT head)
+# ---------------------------------------------------------------------------
+def _head_scores(qr, kr, heads, scale):
+    """scale * <q_h, k_h> per head: the product transform q*k of the paper's
+    Score rule, summed over each head's features.  [n, heads]."""
+    n, d = kr.shape
+    return scale * (qr * kr).reshape(n, heads, d // heads).sum(axis=2)
+
+
+def attention_fwd(idx: Index, q, k, v, heads: int, scale: float):
+    """Segmented softmax attention over the joined tuples of an index whose
+    three body atoms are (Q, K, V): for every group g and head h, the score
+    of tuple tau is s = scale <q_h[r_Q(tau)], k_h[r_K(tau)]>, the attention
+    weight is the softmax of s over the tuples of g (the maximum subtracted
+    before the exponential), and the output is sum_tau a_tau v_h[r_V(tau)]
+    (the Attention rule's sum(a*v)).  Returns (out [G, dv], lse [G, heads]),
+    lse the log of the sum of exponentials of the group's scores."""
+    q, k, v = (np.asarray(a, np.float64) for a in (q, k, v))
+    dv = v.shape[1]
+    out = np.zeros((idx.G, dv))
+    lse = np.zeros((idx.G, heads))
+    for g in range(idx.G):
+        s0, e0 = int(idx.offsets[g]), int(idx.offsets[g + 1])
+        S = _head_scores(q[idx.rows[0][s0:e0]], k[idx.rows[1][s0:e0]], heads, scale)
+        m = S.max(axis=0)
+        ex = np.exp(S - m)
+        l = ex.sum(axis=0)
+        a = ex / l
+        V = v[idx.rows[2][s0:e0]].reshape(e0 - s0, heads, dv // heads)
+        out[g] = (a[:, :, None] * V).sum(axis=0).reshape(dv)
+        lse[g] = m + np.log(l)
+    return out, lse
+
+
+def attention_bwd(idx: Index, q, k, v, heads: int, scale: float, dout):
+    """Gradients of sum(out * dout) through attention_fwd with respect to the
+    Q, K and V relations' embeddings (chain rule through the softmax: ds =
+    a (dp - sum_tau a dp), dp = <dout_h, v_h>)."""
+    q, k, v, dout = (np.asarray(a, np.float64) for a in (q, k, v, dout))
+    d, dv = k.shape[1], v.shape[1]
+    dq, dk, dvv = np.zeros_like(q), np.zeros_like(k), np.zeros_like(v)
+    for g in range(idx.G):
+        s0, e0 = int(idx.offsets[g]), int(idx.offsets[g + 1])
+        n = e0 - s0
+        rq, rk, rv = idx.rows[0][s0:e0], idx.rows[1][s0:e0], idx.rows[2][s0:e0]
+        S = _head_scores(q[rq], k[rk], heads, scale)
+        ex = np.exp(S - S.max(axis=0))
+        a = ex / ex.sum(axis=0)                                    # [n, heads]
+        V = v[rv].reshape(n, heads, dv // heads)
+        do = dout[g].reshape(heads, dv // heads)
+        dp = (V * do[None]).sum(axis=2)                            # [n, heads]
+        ds = a * (dp - (a * dp).sum(axis=0))
+        np.add.at(dvv, rv, (a[:, :, None] * do[None]).reshape(n, dv))
+        Qh = q[rq].reshape(n, heads, d // heads)
+        Kh = k[rk].reshape(n, heads, d // heads)
+        np.add.at(dq, rq, (scale * ds[:, :, None] * Kh).reshape(n, d))
+        np.add.at(dk, rk, (scale * ds[:, :, None] * Qh).reshape(n, d))
+    return dq, dk, dvv

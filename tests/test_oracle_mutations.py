@@ -289,3 +289,46 @@ def test_planted_union_mistake_is_caught(name, monkeypatch):
 
 def test_unmutated_union_oracle_passes_every_pin():
     assert not _union_caught()
+
+
+# -------------------------------------------------------- segmented softmax
+from tests import test_oracle_attention as attn_pins
+
+ATTN_PINS = [attn_pins.test_golden_forward, attn_pins.test_golden_backward, attn_pins.test_shift_invariance,
+             attn_pins.test_special_cases, attn_pins.test_matches_torch_softmax_and_autograd]
+
+ATTN_MUTANTS = {
+    "lse_without_max": [("        lse[g] = m + np.log(l)", "        lse[g] = np.log(l)")],
+    "softmax_over_heads": [("        l = ex.sum(axis=0)\n", "        l = ex.sum(axis=1, keepdims=True)\n")],
+    "scale_dropped": [("    return scale * (qr * kr)", "    return (qr * kr)")],
+    "ds_without_centering": [("ds = a * (dp - (a * dp).sum(axis=0))", "ds = a * dp")],
+    "dk_from_keys": [("np.add.at(dk, rk, (scale * ds[:, :, None] * Qh)", "np.add.at(dk, rk, (scale * ds[:, :, None] * Kh)")],
+    "value_head_misaligned": [("V = v[rv].reshape(n, heads, dv // heads)", "V = v[rv].reshape(n, dv // heads, heads).transpose(0, 2, 1)")],
+}
+
+
+def _attn_caught():
+    for pin in ATTN_PINS:
+        try:
+            pin()
+        except Exception:
+            return True
+    return False
+
+
+@pytest.mark.parametrize("name", sorted(ATTN_MUTANTS))
+def test_planted_attention_mistake_is_caught(name, monkeypatch):
+    src = inspect.getsource(orc)
+    for old, new in ATTN_MUTANTS[name]:
+        assert src.count(old) == 1, f"mutant {name} no longer matches the oracle's source"
+        src = src.replace(old, new)
+    mod = types.ModuleType("relnn_oracle_attn_mutant")
+    monkeypatch.setitem(sys.modules, "relnn_oracle_attn_mutant", mod)
+    exec(compile(src, "<relnn_oracle mutant>", "exec"), mod.__dict__)
+    monkeypatch.setattr(orc, "attention_fwd", mod.attention_fwd)
+    monkeypatch.setattr(orc, "attention_bwd", mod.attention_bwd)
+    assert _attn_caught(), f"no pin caught the planted attention mistake {name}"
+
+
+def test_unmutated_attention_oracle_passes_every_pin():
+    assert not _attn_caught()
