@@ -258,6 +258,45 @@ relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_layer_desc* L,
                              float* const* demb, float* dW, float* db,
                              void* ws, size_t ws_bytes, relnn_stream_t stream);
 
+/* ------------------------------------------------------------ attention */
+
+/* Segmented softmax attention: the paper's attention as rules (Section 1,
+ * Score(p,t; q*k) and Attention(p; sum(a*v)); Section 5.2, the HGT head with
+ * a softmax over each target's tuples).  The index's three body atoms are
+ * (Q, K, V); for every group g (head key) and head h:
+ *
+ *   s_tau   = scale * <q_h[r_Q(tau)], k_h[r_K(tau)]>     (q*k summed per head)
+ *   a_tau   = exp(s_tau - max s) / sum exp(s - max s)    over the tuples of g
+ *   out_g,h = sum_tau a_tau v_h[r_V(tau)]
+ *   lse_g,h = log sum_tau exp(s_tau)
+ *
+ * d and dv <= 128, multiples of 4, split into `heads` blocks of a power of
+ * two columns each. */
+typedef struct {
+  int32_t heads;
+  int32_t d;          /* width of the Q and K rows */
+  int32_t dv;         /* width of the V rows */
+  float scale;        /* 1 / sqrt(d / heads) in the HGT head */
+  int32_t dtype;      /* relnn_dtype of q, k, v; arithmetic and outputs FP32 */
+} relnn_attn_desc;
+
+relnn_status relnn_attn_workspace_size(const relnn_index* idx, const relnn_attn_desc* A, int bwd,
+                                       size_t* bytes);
+
+/* q: device [n_Q, d], k: [n_K, d], v: [n_V, dv] (dtype), rows of the
+ * index's atoms 0, 1, 2.  out: device [G, dv] FP32; lse: device [G, heads]
+ * FP32 or NULL (the backward needs it).  Async. */
+relnn_status relnn_attn_fwd(const relnn_index* idx, const relnn_attn_desc* A, const void* q, const void* k,
+                            const void* v, float* out, float* lse, void* ws, size_t ws_bytes,
+                            relnn_stream_t stream);
+
+/* Backward of sum(out * dout): dq, dk, dv device FP32 shaped as q, k, v,
+ * ACCUMULATED (+=), may alias (K and V from one relation).  Needs an index
+ * built with RELNN_IDX_BWD and the forward's out and lse. */
+relnn_status relnn_attn_bwd(const relnn_index* idx, const relnn_attn_desc* A, const void* q, const void* k,
+                            const void* v, const float* out, const float* lse, const float* dout, float* dq,
+                            float* dk, float* dv, void* ws, size_t ws_bytes, relnn_stream_t stream);
+
 /* ---------------------------------------------------------------- union */
 
 /* The k-ary projected union (Section 2.2) of the join results of k rules

@@ -43,6 +43,11 @@ class Pred(C.Structure):
 CMP = {"eq": 0, "ne": 1, "lt": 2, "le": 3, "gt": 4, "ge": 5}
 
 
+class AttnDesc(C.Structure):
+    _fields_ = [("heads", C.c_int32), ("d", C.c_int32), ("dv", C.c_int32), ("scale", C.c_float),
+                ("dtype", C.c_int32)]
+
+
 class JoinDesc(C.Structure):
     _fields_ = [("n_link", C.c_int64), ("n_cols", C.c_int32), ("cols", C.POINTER(C.c_void_p)),
                 ("n_chains", C.c_int32), ("chains", C.POINTER(Chain)),
@@ -98,6 +103,12 @@ _SIGS = {
     "relnn_layer_fwd_static": (C.c_int, [C.c_void_p, C.POINTER(LayerDesc), C.POINTER(C.c_void_p), C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "relnn_static_scratch_bytes": (C.c_int, [C.POINTER(C.c_size_t)]),
+    "relnn_attn_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(AttnDesc), C.c_int, C.POINTER(C.c_size_t)]),
+    "relnn_attn_fwd": (C.c_int, [C.c_void_p, C.POINTER(AttnDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "relnn_attn_bwd": (C.c_int, [C.c_void_p, C.POINTER(AttnDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_size_t, C.c_void_p]),
     "relnn_union_build": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "relnn_union_query": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "relnn_union_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

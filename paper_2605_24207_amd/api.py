@@ -135,6 +135,55 @@ class Index:
             pass
 
 
+def _attn_desc(d, dv, heads, scale, dtype):
+    a = L.AttnDesc()
+    a.heads, a.d, a.dv, a.scale, a.dtype = int(heads), int(d), int(dv), float(scale), _DTYPES[dtype][0]
+    return a
+
+
+def _attn_inputs(index: "Index", q, k, v):
+    if index.k != 3:
+        raise ValueError("attention needs an index with three atoms (Q, K, V)")
+    dt = q.dtype
+    for name, t in (("q", q), ("k", k), ("v", v)):
+        if t.dtype != dt or t.dtype not in (torch.float32, torch.bfloat16) or not t.is_cuda \
+                or not t.is_contiguous() or t.dim() != 2:
+            raise TypeError(f"{name} must be a contiguous 2-d float32 or bfloat16 CUDA tensor like q")
+    if k.shape[1] != q.shape[1]:
+        raise ValueError("q and k must have the same width")
+    return "bf16" if dt == torch.bfloat16 else "f32"
+
+
+def attn_fwd(index: "Index", q, k, v, heads: int, scale: float, stream=None):
+    """relnn_attn_fwd: (out [G, dv], lse [G, heads])."""
+    dtype = _attn_inputs(index, q, k, v)
+    a = _attn_desc(q.shape[1], v.shape[1], heads, scale, dtype)
+    n = C.c_size_t()
+    check(lib().relnn_attn_workspace_size(index.handle, C.byref(a), 0, C.byref(n)))
+    ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=index.device)
+    out = torch.empty(index.G, v.shape[1], dtype=torch.float32, device=index.device)
+    lse = torch.empty(index.G, heads, dtype=torch.float32, device=index.device)
+    check(lib().relnn_attn_fwd(index.handle, C.byref(a), _vp(q), _vp(k), _vp(v), _vp(out), _vp(lse), _vp(ws),
+                               ws.numel(), _stream(stream)))
+    return out, lse
+
+
+def attn_bwd(index: "Index", q, k, v, heads: int, scale: float, out, lse, dout, dq, dk, dv, stream=None):
+    """relnn_attn_bwd: adds the gradients into dq, dk, dv (FP32, may alias)."""
+    dtype = _attn_inputs(index, q, k, v)
+    for name, t, ref in (("dq", dq, q), ("dk", dk, k), ("dv", dv, v)):
+        if t.dtype != torch.float32 or tuple(t.shape) != tuple(ref.shape) or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float32 tensor shaped like its input")
+    if dout.dtype != torch.float32 or tuple(dout.shape) != (index.G, v.shape[1]) or not dout.is_contiguous():
+        raise TypeError("dout must be a contiguous float32 [G, dv] tensor")
+    a = _attn_desc(q.shape[1], v.shape[1], heads, scale, dtype)
+    n = C.c_size_t()
+    check(lib().relnn_attn_workspace_size(index.handle, C.byref(a), 1, C.byref(n)))
+    ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=index.device)
+    check(lib().relnn_attn_bwd(index.handle, C.byref(a), _vp(q), _vp(k), _vp(v), _vp(out), _vp(lse), _vp(dout),
+                               _vp(dq), _vp(dk), _vp(dv), _vp(ws), ws.numel(), _stream(stream)))
+
+
 class Union:
     """relnn_union_build: the k-ary projected union of the head keys of k
     join indices (device-resident, library-owned; the indices must outlive

@@ -28,27 +28,6 @@ constexpr int kGsTM = 64;          // unit boundaries on multiples of 64 positio
 constexpr int kGsWaves = 4;        // waves per block
 constexpr int kGsBatch = 8;        // positions loaded together
 
-struct GsArgs {
-  const void* emb[kMaxAtoms];      // [n_j][d_j], FP32 or BF16
-  const int32_t* rows[kMaxAtoms];  // [n] row of atom j at each list position
-  int d[kMaxAtoms];
-  int koff[kMaxAtoms];
-  int k;
-  int K;                           // sum of d_j, a multiple of 4
-  bool bf16;
-  int64_t n;                       // list positions
-  Seg sg;                          // segments of the sorted list
-  float* out;                      // [nseg][ldo]
-  int ldo;                         // row stride of out and carry (>= K)
-  float* carry;                    // [nunits][2][ldo]
-  int64_t ntiles, nunits;
-  // routing of a gathered gradient row (one atom, dA of width h; rows[0] is
-  // the group of the tuple at each position, rows[1] its canonical position)
-  const uint32_t* own;             // [E][own_w] bits: keep column c only where the tuple owns it (MAX)
-  int own_w;
-  const uint8_t* mask;             // [E][h]: act_pre' of the tuple
-};
-
 __device__ __forceinline__ void kahan_add1(float& s, float& c, float x) {
   const float y = x - c;
   const float t = s + y;
@@ -164,6 +143,12 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
             row = A.j == j ? rj : row;
           }
           v[i] = gs_load<VW, kBF16>(a, A, row, on ? col : 0);
+          if (a.wgt) {                                  // one weight per tuple and column block
+            const int32_t tau = __builtin_amdgcn_readlane(R[1], q);
+            const float wv = a.wgt[(int64_t)tau * a.wh + (on ? col : 0) / a.whd];
+#pragma unroll
+            for (int x = 0; x < VW; ++x) v[i][x] *= wv;
+          }
           if (a.own || a.mask) {                        // route the gradient row of this tuple
             const int32_t tau = __builtin_amdgcn_readlane(R[1], q);
             if (a.own) {                                // VW columns of one 32-column word
@@ -205,6 +190,8 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
   }
 }
 
+}  // namespace
+
 int64_t gs_units(int64_t n) {
   const int64_t nt = cdiv(std::max<int64_t>(n, 1), kGsTM);
   return std::max<int64_t>(1, std::min<int64_t>(nt, 8192));
@@ -236,7 +223,6 @@ void seg_gather_sum(GsArgs a, int64_t nseg_units_cap, hipStream_t s) {
   launch_fixup(a.sg, kGsTM, a.ldo, a.ntiles, a.nunits, sk, a.carry, nullptr, s);
 }
 
-}  // namespace
 
 // Workspace of the aggregated backward, after `base` bytes.
 LinBwdPlan plan_lin_bwd(const relnn_index* idx, const relnn_layer_desc* L, size_t base, bool xs_dw) {

@@ -95,6 +95,38 @@ void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P,
                  float* carry, int32_t* carry_arg, int64_t G, float* V, hipStream_t s);
 int64_t push_units(int64_t E);
 
+// Segmented gather-sum over a sorted list (bwd_linear.hip): out[s] = sum
+// over the positions e of segment s of the joined row at e (the atoms' rows
+// concatenated), optionally routed (MAX ownership bits, act_pre mask) and
+// weighted (one weight per tuple and block of whd columns); atomic-free,
+// Kahan within a wave's range, carries combined in order.
+struct GsArgs {
+  const void* emb[kMaxAtoms];      // [n_j][d_j], FP32 or BF16
+  const int32_t* rows[kMaxAtoms];  // [n] row of atom j at each list position
+  int d[kMaxAtoms];
+  int koff[kMaxAtoms];
+  int k;
+  int K;                           // sum of d_j, a multiple of 4
+  bool bf16;
+  int64_t n;                       // list positions
+  Seg sg;                          // segments of the sorted list
+  float* out;                      // [nseg][ldo]
+  int ldo;                         // row stride of out and carry (>= K)
+  float* carry;                    // [nunits][2][ldo]
+  int64_t ntiles, nunits;
+  // routing of a gathered gradient row (one atom, dA of width h; rows[0] is
+  // the group of the tuple at each position, rows[1] its canonical position)
+  const uint32_t* own;             // [E][own_w] bits: keep column c only where the tuple owns it (MAX)
+  int own_w;
+  const uint8_t* mask;             // [E][h]: act_pre' of the tuple
+  // weights: column c of the row at position e times wgt[tau wh + c / whd],
+  // tau = rows[1][e] (whd a multiple of the columns a lane holds)
+  const float* wgt;
+  int wh, whd;
+};
+int64_t gs_units(int64_t n);
+void seg_gather_sum(GsArgs a, int64_t nseg_units_cap, hipStream_t s);
+
 // Backward through sums over groups and joined rows (bwd_linear.hip).
 // lin_bwd_dx: dz_j of every atom, for any layer (routed by argmax for MAX,
 // masked by act_pre'); lin_bwd_dw: dW and db when the transform is affine
