@@ -76,14 +76,26 @@ def join(rule):
     return out
 
 
-def layer(rule, embs=None, W=None, b=None):
-    """dict head key -> (pre-activation aggregate as a list, output list)."""
+def layer(rule, embs=None, W=None, b=None, tf="linear"):
+    """dict head key -> (pre-activation aggregate as a list, output list).
+    tf = "product": the transform is the elementwise product of the atoms'
+    embedding rows."""
     embs = [a.emb for a in rule.atoms] if embs is None else embs
     W = rule.W if W is None else W
     b = rule.b if b is None else b
     K, h = len(W), len(W[0])
     groups = {}
     for ell, rows, cols in join(rule):
+        if tf == "product":
+            hp = len(embs[0][rows[0]])
+            y = []
+            for c in range(hp):
+                acc = 1.0
+                for e, r in zip(embs, rows):
+                    acc *= float(e[r][c])
+                y.append(max(acc, 0.0) if rule.act_pre == "relu" else acc)
+            groups.setdefault(cols[rule.group_col], []).append(y)
+            continue
         x = []
         for e, r in zip(embs, rows):
             x.extend(float(v) for v in e[r])

@@ -198,7 +198,7 @@ def build_index(rule) -> Index:
 # ---------------------------------------------------------------------------
 def bf16_round(x: np.ndarray) -> np.ndarray:
     """float32 -> bfloat16 (round to nearest, ties to even), returned as the
-    float32 value it represents.  NaN is not expected in these inputs."""
+    float32 value it represents; infinities and the quiet NaN are kept."""
     b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
     lsb = (b >> 16) & 1
     b = (b + 0x7FFF + lsb) & 0xFFFF0000
@@ -240,20 +240,34 @@ def _groups(idx: Index, groups):
     return np.arange(idx.G) if groups is None else np.asarray(groups, np.int64)
 
 
+def product(idx: Index, embs, sel, act_pre: str) -> np.ndarray:
+    """The product transform: act_pre(z_1[r_1] * ... * z_k[r_k]), elementwise
+    (the Score rule's q*k and the Attention rule's a*v of Section 1, the
+    gated mean z_e*z_w of Section 5.4); all atoms have the output width."""
+    y = np.asarray(embs[0])[idx.rows[0][sel]].astype(np.float64)
+    for e, r in zip(embs[1:], idx.rows[1:]):
+        y = y * np.asarray(e)[r[sel]].astype(np.float64)
+    return _act(act_pre, y)
+
+
 def layer_fwd(idx: Index, embs, W, b, agg="sum", act_pre="none", act_post="none",
-              groups=None):
+              groups=None, tf="linear"):
     """Evaluate the layer for all groups (or the listed group numbers).
 
     Returns (out, pre, argmax): out = act_post(pre); pre = alpha over the
-    group's tuples of act_pre(x W + b); argmax [G', h] is the canonical
-    tuple position of the first maximiser (MAX only, else None)."""
+    group's tuples of act_pre(x W + b) (tf = "product": of the product
+    transform, W and b unused); argmax [G', h] is the canonical tuple
+    position of the first maximiser (MAX only, else None)."""
     gsel = _groups(idx, groups)
-    h = W.shape[1]
+    h = np.asarray(embs[0]).shape[1] if tf == "product" else W.shape[1]
     pre = np.zeros((len(gsel), h), np.float64)
     amax = np.full((len(gsel), h), -1, np.int64) if agg == "max" else None
     for q, g in enumerate(gsel):
         s, e = int(idx.offsets[g]), int(idx.offsets[g + 1])
-        y = transform(gather_concat(idx, embs, slice(s, e)), W, b, act_pre)
+        if tf == "product":
+            y = product(idx, embs, slice(s, e), act_pre)
+        else:
+            y = transform(gather_concat(idx, embs, slice(s, e)), W, b, act_pre)
         if agg == "sum":
             pre[q] = y.sum(axis=0)
         elif agg == "mean":

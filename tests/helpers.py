@@ -79,6 +79,37 @@ def oracle_fwd(rule, dtype="f32", groups=None, idx=None):
     return idx, out, pre, am
 
 
+def elem_scale(rule, idx, dtype="f32", chunk=8192):
+    """Per group and column, the condition scale of the aggregate: the
+    aggregate over the group's tuples (SUM: sum, MEAN: mean, MAX: max) of
+    |x| |W| + |b|, the sum of the magnitudes of the terms of each tuple's
+    value.  A rounding error of relative size u in every product and sum
+    moves an output element by at most about u times this, cancellation
+    included, so element-wise bounds are stated against it."""
+    embs, W, b = oracle_inputs(rule, dtype)
+    aW = np.abs(np.asarray(W, np.float64))
+    ab = np.abs(np.asarray(b, np.float64))
+    t = np.empty((idx.E, aW.shape[1]))
+    for s in range(0, idx.E, chunk):
+        e = min(idx.E, s + chunk)
+        t[s:e] = np.abs(orc.gather_concat(idx, embs, slice(s, e))) @ aW + ab
+    if idx.E == 0:
+        return np.zeros((0, aW.shape[1]))
+    starts = np.asarray(idx.offsets[:-1], np.int64)
+    if rule.agg == "max":
+        return np.maximum.reduceat(t, starts, axis=0)
+    agg = np.add.reduceat(t, starts, axis=0)
+    if rule.agg == "mean":
+        agg /= np.diff(idx.offsets)[:, None]
+    return agg
+
+
+def elem_err(z, ref, scale):
+    """Largest |z - ref| / scale over the elements (scale from elem_scale)."""
+    z = np.asarray(z, np.float64)
+    return float((np.abs(z - np.asarray(ref, np.float64)) / np.maximum(scale, 1e-30)).max(initial=0.0))
+
+
 def rel_rows(z, ref, scale_ref=None):
     z = np.asarray(z, np.float64)
     ref = np.asarray(ref, np.float64)

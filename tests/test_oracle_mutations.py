@@ -332,3 +332,38 @@ def test_planted_attention_mistake_is_caught(name, monkeypatch):
 
 def test_unmutated_attention_oracle_passes_every_pin():
     assert not _attn_caught()
+
+
+# --------------------------------------------------------- product transform
+from tests import test_oracle_product as prod_pins
+
+PROD_PINS = [lambda: prod_pins.test_product_matches_nested_loop("sum", "none"),
+             lambda: prod_pins.test_product_matches_nested_loop("max", "relu"),
+             prod_pins.test_product_closed_forms]
+
+PROD_MUTANTS = {
+    "product_as_sum": [("        y = y * np.asarray(e)[r[sel]].astype(np.float64)",
+                        "        y = y + np.asarray(e)[r[sel]].astype(np.float64)")],
+    "product_drops_atoms": [("for e, r in zip(embs[1:], idx.rows[1:]):", "for e, r in zip(embs[1:1], idx.rows[1:1]):")],
+    "product_act_pre_ignored": [("    return _act(act_pre, y)\n", "    return y\n")],
+}
+
+
+@pytest.mark.parametrize("name", sorted(PROD_MUTANTS))
+def test_planted_product_mistake_is_caught(name, monkeypatch):
+    src = inspect.getsource(orc)
+    for old, new in PROD_MUTANTS[name]:
+        assert src.count(old) == 1, f"mutant {name} no longer matches the oracle's source"
+        src = src.replace(old, new)
+    mod = types.ModuleType("relnn_oracle_prod_mutant")
+    monkeypatch.setitem(sys.modules, "relnn_oracle_prod_mutant", mod)
+    exec(compile(src, "<relnn_oracle mutant>", "exec"), mod.__dict__)
+    monkeypatch.setattr(orc, "product", mod.product)
+    caught = False
+    for pin in PROD_PINS:
+        try:
+            pin()
+        except Exception:
+            caught = True
+            break
+    assert caught, f"no pin caught the planted product mistake {name}"
