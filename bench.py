@@ -140,23 +140,29 @@ def step_bytes(ix, Ks, ks, h, esz):
     return b
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused FP32 forward from the committed
-    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
-    the kernel source has changed since the counters were taken."""
+def measured_value(summary: str, sources, key: str):
+    """A machine-readable figure of a committed profile summary, or None when
+    a kernel source it was taken on has changed since (sha256 prefix of the
+    sources' concatenated bytes)."""
     import hashlib
     import re
 
-    summ = os.path.join(ROOT, "profiles", "fused_fwd_er_counters.md")
-    src = os.path.join(ROOT, "paper_2605_24207_amd", "csrc", "layer_ws.hip")
     try:
-        text = open(summ).read()
-        have = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        text = open(os.path.join(ROOT, "profiles", summary)).read()
+        h = hashlib.sha256()
+        for src in sources:
+            h.update(open(os.path.join(ROOT, "paper_2605_24207_amd", "csrc", src), "rb").read())
         want = re.search(r"source_sha256_prefix:\s*([0-9a-f]+)", text).group(1)
-        val = float(re.search(r"traffic_bytes_per_launch_fused_f32:\s*([0-9.e+]+)", text).group(1))
+        val = float(re.search(key + r":\s*([0-9.e+]+)", text).group(1))
     except (OSError, AttributeError, ValueError):
         return None
-    return val if have == want else None
+    return val if h.hexdigest()[:16] == want else None
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused FP32 forward from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return measured_value("fused_fwd_er_counters.md", ["layer_ws.hip"], "traffic_bytes_per_launch_fused_f32")
 
 
 def gbs(nbytes_per_step, steps, kt):
@@ -272,6 +278,8 @@ def cobuy_leg(D, steps: int, warmup: int):
     def step():
         layer_fwd(ix, L, [U, U], W, b, want_pre=False, want_argmax=False, ws=ws, out=out)
 
+    D["cobuy_out"] = (out, ix.export()["group_keys"])
+
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -332,20 +340,26 @@ def serve_leg(D, dtype: str, rates, seconds: float):
 
         th = threading.Thread(target=submitter)
         th.start()
-        done, lat, tuples, first, last = set(), [], 0, None, None
-        while len(done) < len(reqs):
-            for q, t in enumerate(tickets):
-                if t is None or q in done:
-                    continue
-                r = srv.poll(t, len(reqs[q].seeds))
+        n_done, lat, tuples, first, last = 0, [], 0, None, None
+        seen = 0                                # tickets [0, seen) have been handed to the poller
+        outstanding = []
+        while n_done < len(reqs):
+            while seen < len(reqs) and tickets[seen] is not None:
+                outstanding.append(seen)
+                seen += 1
+            still = []
+            for q in outstanding:
+                r = srv.poll(tickets[q], len(reqs[q].seeds))
                 if r is None:
+                    still.append(q)
                     continue
                 st = r[2]
-                done.add(q)
+                n_done += 1
                 lat.append((st["t_done_ns"] - st["t_arrive_ns"]) * 1e-6)
                 tuples += st["tuples"]
                 first = st["t_arrive_ns"] if first is None else min(first, st["t_arrive_ns"])
                 last = st["t_done_ns"] if last is None else max(last, st["t_done_ns"])
+            outstanding = still
             time.sleep(0.0002)
         th.join()
         lat = np.array(lat)
@@ -370,18 +384,13 @@ def copy_calibration(gib: float):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
 
 
-def cpu_baseline(D, budget_tuples: int):
-    """The FP64 oracle, as it stands, on a seeded sample of output groups of
-    both rules (all tuples of the sampled groups)."""
-    import relgen
-    from oracle import relnn_oracle as orc
-
-    g = D["g"]
+def sample_groups(g, budget_tuples: int):
+    """A seeded sample of output groups of both layer-1 rules (all tuples of
+    the sampled groups), about budget_tuples / 2 tuples per rule."""
     rng = np.random.default_rng(42)
-    total_t, total_s, desc = 0, 0.0, []
-    for name, gcol in (("item", 1), ("user", 0)):
-        keys = g.buys_i if gcol == 1 else g.buys_u
-        cnt = np.bincount(keys, minlength=(g.item if gcol == 1 else g.user).shape[0])
+    out = {}
+    for name, keys, n in (("item", g.buys_i, g.item.shape[0]), ("user", g.buys_u, g.user.shape[0])):
+        cnt = np.bincount(keys, minlength=n)
         cand = rng.permutation(np.nonzero(cnt)[0])
         take, acc = [], 0
         for k in cand:
@@ -391,25 +400,260 @@ def cpu_baseline(D, budget_tuples: int):
             acc += cnt[k]
             if acc >= 0.9 * (budget_tuples // 2):
                 break
-        sel = np.isin(keys, np.array(take))
+        out[name] = np.sort(np.array(take, np.int64))
+    return out
+
+
+def gpu_rows(net, D, keys):
+    """Layer-1 outputs of the sampled groups (FP32 on the host)."""
+    import torch
+
+    res = {}
+    for name, q, gk in (("item", 0, D["keys"][0]), ("user", 1, D["keys"][1])):
+        pos = torch.searchsorted(gk.long(), torch.from_numpy(keys[name]).to(gk.device))
+        res[name] = net.out[q].index_select(0, pos).float().cpu().numpy()
+    return res
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(g, keys):
+    """The FP64 oracle, as it stands, on the sampled output groups of both
+    layer-1 rules: once on one thread (BLAS limited to one) and once on all
+    the host's cores.  Returns the line's field and the oracle's outputs
+    (pre-activation aggregates and outputs per rule) for the error report."""
+    import relgen
+    from oracle import relnn_oracle as orc
+    from threadpoolctl import threadpool_limits
+
+    rules = {}
+    for name in ("item", "user"):
+        bk = g.buys_i if name == "item" else g.buys_u
+        sel = np.isin(bk, keys[name])
         sub = relgen.ERGraph(g.user, g.item, g.cat, g.buys_u[sel], g.buys_i[sel], g.belongs_cat,
                              g.W_item, g.W_user, g.b_item, g.b_user)
-        rule = relgen.er_item_rule(sub) if gcol == 1 else relgen.er_user_rule(sub)
+        rules[name] = relgen.er_item_rule(sub) if name == "item" else relgen.er_user_rule(sub)
+
+    def run_all():
         t0 = time.perf_counter()
-        idx = orc.build_index(rule)
-        orc.layer_fwd(idx, [a.emb for a in rule.atoms], rule.W, rule.b, rule.agg, rule.act_pre,
-                      rule.act_post)
-        total_s += time.perf_counter() - t0
-        total_t += idx.E
-        desc.append(f"{len(take)} {name} groups ({idx.E} tuples)")
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        cores = 1
-    return {"value": total_t / total_s, "unit": "tuples/s", "cores": int(cores), "kind": "oracle",
-            "sample": "layer-1 forward of both rules over a seeded sample of output groups: "
-                      + ", ".join(desc) + f"; {total_s:.1f}s of FP64 numpy"}
+        outs, tuples = {}, 0
+        for name, rule in rules.items():
+            idx = orc.build_index(rule)
+            outs[name] = orc.layer_fwd(idx, [a.emb for a in rule.atoms], rule.W, rule.b, rule.agg, rule.act_pre,
+                                       rule.act_post)[:2]
+            tuples += idx.E
+        return tuples, time.perf_counter() - t0, outs
+
+    with threadpool_limits(limits=1):
+        t1, s1, _ = run_all()
+    tn, sn, outs = run_all()
+    model, cores = cpu_info()
+    field = {"value": tn / sn, "unit": "tuples/s", "cores": cores, "kind": "oracle",
+             "single_thread_value": t1 / s1, "cpu_model": model,
+             "sample": f"layer-1 forward of both ER rules over a seeded sample of output groups "
+                       f"({len(keys['item'])} Item groups, {len(keys['user'])} User groups, {tn} tuples): "
+                       f"{sn:.1f}s on all {cores} cores, {s1:.1f}s on one thread, FP64 numpy"}
+    return field, outs
+
+
+def row_errors(gpu, outs):
+    """max and p99 over the sampled rows of |z - z_ref| / |pre_ref| (rows of
+    both rules together)."""
+    errs = []
+    for name in ("item", "user"):
+        o_out, o_pre = outs[name]
+        den = np.maximum(np.linalg.norm(o_pre, axis=1), 1e-30)
+        errs.append(np.linalg.norm(gpu[name].astype(np.float64) - o_out, axis=1) / den)
+    e = np.concatenate(errs)
+    return {"max": float(e.max()), "p99": float(np.percentile(e, 99)), "rows": int(e.size),
+            "vs": "FP64 oracle on the FP32 master values, sampled output groups"}
+
+
+def cfg1_leg(reps: int):
+    """Workload 1: Node [1000, 32], Edge 5000 (s, t uniform), W [64, 32]
+    ~ N(0, 0.1), SUM then ReLU, FP32; fused and plain.  Launch-latency bound
+    (20 MFLOP, L2-resident): tuples/s over `reps` back-to-back layer calls,
+    and the error of the whole output against the FP64 oracle."""
+    import torch
+
+    import relgen
+    from oracle import relnn_oracle as orc
+    from paper_2605_24207_amd import Index, Layer, layer_fwd, workspace
+
+    rule = relgen.node_edge()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    ix = Index([t(c) for c in rule.cols], [(1000, 0, None), (1000, 1, None)], 1)
+    z, W, b = t(rule.atoms[0].emb), t(rule.W), t(rule.b)
+    res = {"workload": "Node 1000 x 32, Edge 5000, W [64, 32], SUM, ReLU, FP32", "tuples": ix.E, "groups": ix.G}
+    idx = orc.build_index(rule)
+    o_out, o_pre, _ = orc.layer_fwd(idx, [rule.atoms[0].emb] * 2, rule.W, rule.b, "sum", "none", "relu")
+    for name, plain in (("fused", False), ("plain", True)):
+        L = Layer([32, 32], 32, "f32", "sum", "none", "relu", plain=plain)
+        ws = workspace(ix, L)
+        out = torch.empty(ix.G, 32, device="cuda")
+        for _ in range(20):
+            layer_fwd(ix, L, [z, z], W, b, want_pre=False, ws=ws, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            layer_fwd(ix, L, [z, z], W, b, want_pre=False, ws=ws, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        err = np.linalg.norm(out.cpu().numpy() - o_out, axis=1) / np.maximum(np.linalg.norm(o_pre, axis=1), 1e-30)
+        res[name] = {"value": ix.E / dt, "unit": "tuples/s", "us_per_layer": dt * 1e6, "max_row_err": float(err.max())}
+    return res
+
+
+def time_calls(fn, reps: int, warmup: int = 2):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def next_legs(D, reps: int):
+    """The rows built beyond the plain layer, each at a size of the ER
+    workload's scale, with joined tuples/s and the bytes each path must move:
+      attention  HGT-like head: 2M targets, 4M sources, 20M (target, source)
+                 tuples with Zipf(1.1) targets, d = dv = 128, 8 heads, FP32
+                 and BF16; forward and backward;
+      union      Item(i) as the union of two bodies (the Item rule over the
+                 first 10M Buys rows, the User rule's body grouped by item over
+                 the other 10M), MEAN applied once, FP32;
+      product    Item(i; mean(z_u * z_i * z_c)) over Buys (20M), FP32;
+      triangle   the DHN triangle rule on 20k graphs of 40 nodes (index build
+                 by sort-and-probe joins, then the layer), FP32."""
+    import torch
+
+    import relgen
+    from paper_2605_24207_amd import (Index, Layer, Union, api, attn_bwd, attn_fwd, layer_fwd, union_fwd,
+                                      workspace)
+
+    res = {}
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    # attention
+    rng = np.random.default_rng(7)
+    n_t, n_s, E, d = 2_000_000, 4_000_000, 20_000_000, 128
+    tgt = relgen.zipf_ids(rng, E, n_t, 1.1).astype(np.int32)
+    src = rng.integers(0, n_s, E).astype(np.int32)
+    ix = Index([t(tgt), t(src)], [(n_t, 0, None), (n_s, 1, None), (n_s, 1, None)], 0, bwd=True)
+    Qf = torch.randn(n_t, d, device="cuda")
+    Kf = torch.randn(n_s, d, device="cuda")
+    Vf = torch.randn(n_s, d, device="cuda")
+    att = {"workload": "2M targets, 4M sources, 20M tuples (targets Zipf 1.1), d = dv = 128, 8 heads",
+           "tuples": ix.E, "groups": ix.G}
+    for dt in ("f32", "bf16"):
+        cv = (lambda x: x.to(torch.bfloat16)) if dt == "bf16" else (lambda x: x)
+        q, k, v = cv(Qf), cv(Kf), cv(Vf)
+        esz = 2 if dt == "bf16" else 4
+        ms = time_calls(lambda: attn_fwd(ix, q, k, v, 8, 0.25), reps) * 1e3
+        out, lse = attn_fwd(ix, q, k, v, 8, 0.25)
+        dout = torch.randn_like(out)
+        dq, dk, dv = (torch.zeros(x.shape, device="cuda") for x in (q, k, v))
+        msb = time_calls(lambda: attn_bwd(ix, q, k, v, 8, 0.25, out, lse, dout, dq, dk, dv), max(1, reps // 2)) * 1e3
+        byt = ix.E * (3 * d * esz + 16) + ix.G * d * 4                  # q, k, v rows + indices per tuple; out
+        att[dt] = {"fwd_ms": ms, "fwd_tuples_per_s": ix.E / (ms * 1e-3), "fwd_hbm_gbs_algorithmic": byt / (ms * 1e-3) / 1e9,
+                   "bwd_ms": msb, "fwd_bwd_tuples_per_s": ix.E / ((ms + msb) * 1e-3)}
+        log(f"attention {dt}: fwd {ms:.2f} ms, bwd {msb:.2f} ms")
+    res["attention"] = att
+    del ix, Qf, Kf, Vf, q, k, v, out, lse, dout, dq, dk, dv
+    torch.cuda.empty_cache()
+    # union of two bodies of Item(i)
+    g = D["g"]
+    half = len(g.buys_u) // 2
+    nu, ni, nc = g.user.shape[0], g.item.shape[0], g.cat.shape[0]
+    b1 = Index([D["bu"][:half].contiguous(), D["bi"][:half].contiguous()], [(nu, 0, None), (ni, 1, None),
+                                                                            (nc, 2, None)], 1,
+               chains=[(1, D["bc"], None)])
+    b2 = Index([D["bu"][half:].contiguous(), D["bi"][half:].contiguous()], [(nu, 0, None), (ni, 1, None)], 1)
+    U = Union([b1, b2])
+    L1 = Layer([128, 128, 128], 128, "f32", "mean")
+    L2 = Layer([128, 128], 128, "f32", "mean")
+    fn = lambda: union_fwd(U, [L1, L2], "mean", "relu", [[D["U"], D["I"], D["C"]], [D["U"], D["I"]]],
+                           [D["W_item"][0], D["W_user"][0]], [D["b_item"][0], D["b_user"][0]], want_pre=False)
+    ms = time_calls(fn, reps) * 1e3
+    res["union"] = {"workload": "Item(i) over two bodies: Item rule on Buys rows 0..10M (K = 384), User body "
+                                "grouped by item on rows 10M..20M (K = 256); MEAN once; FP32",
+                    "ms": ms, "tuples_per_s": (b1.E + b2.E) / (ms * 1e-3), "groups": U.G}
+    log(f"union: {ms:.2f} ms")
+    del U, b1, b2
+    # product transform
+    ixp = D["ix_item1"]
+    Lp = Layer([128, 128, 128], 128, "f32", "mean", "relu", "none", transform="product")
+    wsp = workspace(ixp, Lp)
+    outp = torch.empty(ixp.G, 128, device="cuda")
+    ms = time_calls(lambda: layer_fwd(ixp, Lp, [D["U"], D["I"], D["C"]], None, want_pre=False, ws=wsp, out=outp),
+                    reps) * 1e3
+    byt = ixp.E * (3 * 128 * 4 + 16) + ixp.G * 128 * 4
+    res["product"] = {"workload": "Item(i; mean(relu(z_u * z_i * z_c))) over Buys 20M, FP32", "ms": ms,
+                      "tuples_per_s": ixp.E / (ms * 1e-3), "hbm_gbs_algorithmic": byt / (ms * 1e-3) / 1e9}
+    log(f"product: {ms:.2f} ms")
+    # triangle rule
+    rule = relgen.triangle_rule(n_graphs=20_000, n_nodes=40, avg_degree=6, d=64, h=64)
+    tc = lambda cols: [t(c) for c in cols]
+    mk = lambda: Index(tc(rule.cols), [(a.n_rows, a.col, None) for a in rule.atoms], rule.group_col,
+                       steps=[(tc(st.cols), st.on, st.key) for st in rule.steps])
+    t0 = time.perf_counter()
+    ixt = mk()
+    torch.cuda.synchronize()
+    build = time.perf_counter() - t0
+    Lt = Layer([64, 64, 64], 64, "f32", "sum", "none", "relu")
+    z = t(rule.atoms[0].emb)
+    Wt, bt = t(rule.W), t(rule.b)
+    wst = workspace(ixt, Lt)
+    outt = torch.empty(ixt.G, 64, device="cuda")
+    ms = time_calls(lambda: layer_fwd(ixt, Lt, [z, z, z], Wt, bt, want_pre=False, ws=wst, out=outt), reps) * 1e3
+    res["triangle"] = {"workload": "C3(n; sum(Lin(h_n (+) h_v (+) h_w))) on 20k graphs x 40 nodes, 4.8M directed "
+                                   "edges, d = h = 64, FP32", "matches": ixt.E, "index_build_s": build,
+                       "layer_ms": ms, "tuples_per_s": ixt.E / (ms * 1e-3)}
+    log(f"triangle: {ixt.E} matches, build {build:.2f} s, layer {ms:.2f} ms")
+    return res
+
+
+def cobuy_error(g, gpu_out, gpu_keys, frac=0.01):
+    """gpu_out / gpu_keys: the co-buy leg's output [G, 256] and group keys
+    (device tensors)."""
+    import torch
+
+    """Error of the precision form (co-buy MAX, BF16) against the FP64 oracle
+    on a seeded sample of its output groups: the oracle's two-hop paths are
+    built for every item the sampled users bought (a path list depends only
+    on its item's rows), and the sampled groups evaluated."""
+    import relgen
+    from oracle import relnn_oracle as orc
+
+    rule = relgen.cobuy_rule(g, d=256, h=256, cap=50, agg="max")
+    users = np.unique(g.buys_u)
+    rng = np.random.default_rng(29)
+    samp = np.sort(rng.choice(users, max(1, int(frac * len(users))), replace=False))
+    items = np.unique(g.buys_i[np.isin(g.buys_u, samp)])
+    sel = np.isin(g.buys_i, items)
+    sub = relgen.Rule(cols=[c[sel] for c in rule.cols], atoms=rule.atoms, group_col=rule.group_col, W=rule.W,
+                      b=rule.b, agg="max", two_hop_mid=rule.two_hop_mid, two_hop_cap=rule.two_hop_cap)
+    idx = orc.build_index(sub)
+    groups = np.nonzero(np.isin(idx.group_keys, samp))[0]
+    _, pre, _ = orc.layer_fwd(idx, [a.emb for a in rule.atoms], rule.W, rule.b, "max", groups=groups)
+    pos = torch.searchsorted(gpu_keys.long(), torch.from_numpy(idx.group_keys[groups]).to(gpu_keys.device))
+    z = gpu_out.index_select(0, pos).cpu().numpy().astype(np.float64)
+    e = np.linalg.norm(z - pre, axis=1) / np.maximum(np.linalg.norm(pre, axis=1), 1e-30)
+    return {"max": float(e.max()), "p99": float(np.percentile(e, 99)), "rows": int(len(groups)),
+            "vs": "FP64 oracle on the FP32 master values, 1% of the output groups"}
 
 
 def main():
@@ -418,14 +662,14 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
-    ap.add_argument("--cpu-budget", type=int, default=9_000_000, help="oracle sample size in tuples")
+    ap.add_argument("--cpu-budget", type=int, default=4_000_000, help="oracle sample size in tuples")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="f32,plain,bf16,push_f32,push_bf16,cobuy_bf16,serve,fwdbwd,fwdbwd_bf16,"
-                                      "fwdbwd_push",
+                                      "fwdbwd_push,cfg1,next",
                     help="comma list of f32,plain,bf16,push_f32,push_bf16,cobuy_bf16,serve,fwdbwd,fwdbwd_bf16,"
-                         "fwdbwd_push")
-    ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per serving rate")
-    ap.add_argument("--serve-rates", default="200,500,1000,2000", help="Poisson arrival rates (req/s)")
+                         "fwdbwd_push,cfg1,next")
+    ap.add_argument("--serve-seconds", type=float, default=15.0, help="arrival window per serving rate")
+    ap.add_argument("--serve-rates", default="200,1000,2000", help="Poisson arrival rates (req/s)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain copy of this many GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -441,6 +685,8 @@ def main():
 
     legs = set(args.legs.split(","))
     D = build_workload(args.scale)
+    keys = sample_groups(D["g"], args.cpu_budget)
+    gpu_sample = {}
     res = {}
     for leg in ("f32", "plain", "bf16", "push_f32", "push_bf16"):
         if leg not in legs:
@@ -453,6 +699,7 @@ def main():
         dt, kt = time_net(net, steps, args.warmup, kern)
         res[leg] = {"dt": dt, "steps": steps, "kt": kt, "tuples": net.tuples, "flops": net.flops,
                     "bytes": net.bytes}
+        gpu_sample[leg] = gpu_rows(net, D, keys)
         log(f"{leg}: {dt / steps * 1e3:.2f} ms/step, {net.tuples * steps / dt / 1e9:.3f} G tuples/s; "
             + ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms x{v[1]}" for k, v in kt.items()))
         del net
@@ -498,6 +745,12 @@ def main():
         line["plain_f32"]["gemm_tflops"] = (r["flops"] * r["steps"] / (r["kt"]["fwd_gemm"][0] * 1e-3) / 1e12
                                             if r["kt"]["fwd_gemm"][0] > 0 else None)
         line["plain_f32"]["hbm_peak_gbs"] = PEAK_HBM_GBS
+        # DRAM bytes by rocprof counters (copy-calibrated FETCH_SIZE + WRITE_SIZE per launch)
+        cnt = {k: measured_value("plain_er_counters.md", ["layer_fwd.hip", "plain.hip"], f"{k}_hbm_bytes_per_launch")
+               for k in ("gather", "reduce")}
+        line["plain_f32"]["hbm_gbs_counters"] = {
+            k: (cnt[k] / (r["kt"]["fwd_" + k][0] / r["kt"]["fwd_" + k][1] * 1e-3) / 1e9 if cnt[k] else None)
+            for k in ("gather", "reduce")}
     if "bf16" in res:
         r = res["bf16"]
         bk_ms, bk_n = r["kt"]["fwd_fused"]
@@ -510,6 +763,17 @@ def main():
         line["cobuy_bf16"] = cb
         log(f"cobuy bf16: {cb['ms_per_step']:.2f} ms/step, {cb['value'] / 1e9:.3f} G tuples/s, "
             f"{cb['kernel_ms_per_launch']:.3f} ms/launch")
+        if not args.no_cpu_baseline:
+            t0 = time.perf_counter()
+            cb["error"] = cobuy_error(D["g"], *D.pop("cobuy_out"))
+            log(f"cobuy error against the oracle in {time.perf_counter() - t0:.1f}s: {cb['error']}")
+        D.pop("cobuy_out", None)
+        torch.cuda.empty_cache()
+    if "cfg1" in legs:
+        line["workload1_f32"] = cfg1_leg(2000)
+        log(f"workload 1: {line['workload1_f32']}")
+    if "next" in legs:
+        line["next_rows"] = next_legs(D, args.steps)
         torch.cuda.empty_cache()
     if "serve" in legs:
         rates = [float(x) for x in args.serve_rates.split(",")]
@@ -532,8 +796,14 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        line["cpu_baseline"] = cpu_baseline({"g": g_host}, args.cpu_budget)
+        line["cpu_baseline"], outs = cpu_baseline(g_host, keys)
         log(f"cpu baseline in {time.perf_counter() - t0:.1f}s")
+        # accuracy of the fused legs on the same sampled groups (layer 1)
+        line["accuracy"] = {leg: row_errors(gpu_sample[leg], outs) for leg in ("f32", "bf16", "plain",
+                                                                                 "push_f32", "push_bf16")
+                            if leg in gpu_sample}
+        if "cobuy_bf16" in line and "error" in line["cobuy_bf16"]:
+            line["accuracy"]["cobuy_bf16"] = line["cobuy_bf16"]["error"]
     print(json.dumps(line), flush=True)
 
 

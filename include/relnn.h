@@ -200,8 +200,8 @@ relnn_status relnn_index_free(relnn_index* idx);
                               even) so it can feed a bf16 layer; `pre` stays
                               FP32 */
 #define RELNN_PUSHDOWN 8u  /* forward with the transform pushed below the join
-                              (the "once per node instead of once per edge"
-                              rewrite named as future work in Section 6):
+                              (Section 6's future-work rewrite: the transform
+                              evaluated per node rather than per edge):
                               for act_pre = NONE, Linear(z_1 (+) ... (+) z_k)
                               = sum_j z_j W_j + b, so P_j = Z_j W_j is formed
                               once per atom row and each tuple sums P rows;
@@ -211,6 +211,15 @@ relnn_status relnn_index_free(relnn_index* idx);
                               RELNN_E_INVALID), d_j a multiple of 4 (FP32) or
                               32 (BF16) and h <= 128 with h % 4 == 0 (else
                               RELNN_E_UNSUPPORTED); not with RELNN_PLAIN */
+
+#define RELNN_TF_PRODUCT 16u /* transform tau = act_pre(z_1 * ... * z_k), the
+                              elementwise product of the atoms' embeddings
+                              (Section 1's Score rule q*k, Attention's a*v,
+                              Section 5.4's gated mean z_e*z_w); every d_j
+                              must equal h; W and b are not read (may be
+                              NULL); forward only (relnn_layer_bwd:
+                              RELNN_E_UNSUPPORTED); not with RELNN_PLAIN or
+                              RELNN_PUSHDOWN */
 
 typedef struct {
   int32_t k;               /* body atoms, equal to the index's */
@@ -222,7 +231,8 @@ typedef struct {
   int32_t act_pre;         /* relnn_act inside tau, per joined tuple */
   int32_t act_post;        /* relnn_act after the aggregate */
   uint32_t flags;          /* RELNN_FUSED | RELNN_PLAIN | RELNN_PUSHDOWN,
-                              RELNN_DW_ACCUM, RELNN_OUT_BF16 */
+                              RELNN_TF_PRODUCT, RELNN_DW_ACCUM,
+                              RELNN_OUT_BF16 */
 } relnn_layer_desc;
 
 /* Workspace bytes relnn_layer_fwd (bwd = 0) or relnn_layer_bwd (bwd = 1)
@@ -445,6 +455,15 @@ relnn_status relnn_serve_submit(relnn_server* srv, const int32_t* seeds, int32_t
  * ticket.  RELNN_E_INVALID for an unknown ticket. */
 relnn_status relnn_serve_poll(relnn_server* srv, uint64_t ticket, float* out, uint8_t* present,
                               relnn_req_stats* stats);
+
+/* Cancels a request: a request still queued is removed and never runs; one
+ * already taken into the running step finishes there and its result is
+ * dropped; a finished one not yet polled is forgotten.  Either way the
+ * ticket is unknown afterwards (poll and cancel: RELNN_E_INVALID).
+ * was_admitted (may be NULL) receives 1 if the request had been taken into
+ * a step (its work was spent), else 0.  RELNN_E_INVALID for an unknown
+ * ticket. */
+relnn_status relnn_serve_cancel(relnn_server* srv, uint64_t ticket, int32_t* was_admitted);
 
 /* Stops the scheduler after the step in flight and frees everything the
  * server owns.  Requests not yet polled are dropped. */

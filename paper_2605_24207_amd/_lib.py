@@ -15,7 +15,7 @@ F32, BF16 = 0, 1
 SUM, MEAN, MAX = 0, 1, 2
 ACT_NONE, ACT_RELU = 0, 1
 IDX_BWD = 1
-FUSED, PLAIN, DW_ACCUM, OUT_BF16, PUSHDOWN = 0, 1, 2, 4, 8
+FUSED, PLAIN, DW_ACCUM, OUT_BF16, PUSHDOWN, TF_PRODUCT = 0, 1, 2, 4, 8, 16
 MAX_ATOMS = 4
 
 p_i32 = C.POINTER(C.c_int32)
@@ -125,6 +125,7 @@ _SIGS = {
     "relnn_serve_create": (C.c_int, [C.POINTER(ServeDesc), C.POINTER(C.c_void_p)]),
     "relnn_serve_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_uint64, C.POINTER(C.c_uint64)]),
     "relnn_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.POINTER(ReqStats)]),
+    "relnn_serve_cancel": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]),
     "relnn_serve_destroy": (C.c_int, [C.c_void_p]),
     "relnn_timing_enable": (C.c_int, [C.c_int]),
     "relnn_timing_reset": (C.c_int, []),

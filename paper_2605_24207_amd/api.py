@@ -265,11 +265,16 @@ def _lib_alive():
 
 
 class Layer:
-    """relnn_layer_desc: widths, output width, dtype, aggregate, activations."""
+    """relnn_layer_desc: widths, output width, dtype, aggregate, activations.
+    transform: "linear" (Concat + Linear) or "product" (the elementwise
+    product of the atoms' embeddings, no weights)."""
 
     def __init__(self, dims: Sequence[int], h: int, dtype: str = "f32", agg: str = "sum",
                  act_pre: str = "none", act_post: str = "none", plain: bool = False,
-                 out_dtype: str = "f32", pushdown: bool = False):
+                 out_dtype: str = "f32", pushdown: bool = False, transform: str = "linear"):
+        if transform not in ("linear", "product"):
+            raise ValueError("transform is 'linear' or 'product'")
+        self.transform = transform
         self.out_dtype = out_dtype
         self.pushdown = pushdown
         self.dims = [int(x) for x in dims]
@@ -302,7 +307,8 @@ class Layer:
         d.act_post = _ACTS[self.act_post]
         d.flags = ((L.PLAIN if self.plain else L.FUSED) | (L.DW_ACCUM if dw_accum else 0)
                    | (L.OUT_BF16 if self.out_dtype == "bf16" and not bwd else 0)
-                   | (L.PUSHDOWN if self.pushdown else 0))
+                   | (L.PUSHDOWN if self.pushdown else 0)
+                   | (L.TF_PRODUCT if self.transform == "product" else 0))
         return d
 
 
@@ -332,7 +338,9 @@ def layer_fwd(index: Index, layer: Layer, embs: Sequence[torch.Tensor], W: torch
               ws: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None, stream=None):
     """relnn_layer_fwd.  Returns (out [G,h], pre [G,h] or None, argmax [G,h] or None)."""
     _check_embs(layer, embs)
-    if W.dtype != layer.torch_dtype or W.shape != (layer.K, layer.h) or not W.is_contiguous():
+    if layer.transform == "product":
+        W = b = None                                   # no weights
+    elif W.dtype != layer.torch_dtype or W.shape != (layer.K, layer.h) or not W.is_contiguous():
         raise TypeError(f"W must be a contiguous {layer.torch_dtype} [{layer.K}, {layer.h}] tensor")
     if b is not None and (b.dtype != torch.float32 or b.numel() != layer.h):
         raise TypeError("b must be float32 [h]")
@@ -532,6 +540,13 @@ class Server:
         check(r)
         stats = {k: getattr(st, k) for k, _ in L.ReqStats._fields_}
         return out, pres.astype(bool), stats
+
+    def cancel(self, ticket: int) -> bool:
+        """Cancel a request; True if it was taken into a step already (its
+        result is dropped), False if it was still queued (it never runs)."""
+        adm = C.c_int32()
+        check(lib().relnn_serve_cancel(self._handle, C.c_uint64(ticket), C.byref(adm)))
+        return bool(adm.value)
 
     def wait(self, ticket: int, n: int, timeout_s: float = 120.0, poll_s: float = 0.0002):
         import time

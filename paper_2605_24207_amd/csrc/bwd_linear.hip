@@ -28,10 +28,12 @@ constexpr int kGsTM = 64;          // unit boundaries on multiples of 64 positio
 constexpr int kGsWaves = 4;        // waves per block
 constexpr int kGsBatch = 8;        // positions loaded together
 
+// Compensated add; the compensation is dropped once the sum is not finite
+// (an infinite sum stays infinite instead of turning NaN).
 __device__ __forceinline__ void kahan_add1(float& s, float& c, float x) {
   const float y = x - c;
   const float t = s + y;
-  c = (t - s) - y;
+  c = __builtin_isfinite(t) ? (t - s) - y : 0.0f;
   s = t;
 }
 
@@ -149,22 +151,12 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
 #pragma unroll
             for (int x = 0; x < VW; ++x) v[i][x] *= wv;
           }
-          if (a.own || a.mask) {                        // route the gradient row of this tuple
-            const int32_t tau = __builtin_amdgcn_readlane(R[1], q);
-            if (a.own) {                                // VW columns of one 32-column word
-              const int cc = on ? col : 0;
-              const uint32_t bits = a.own[(int64_t)tau * a.own_w + (cc >> 5)] >> (cc & 31);
+          if (a.own) {                                  // route the gradient row of this tuple:
+            const int32_t tau = __builtin_amdgcn_readlane(R[1], q);   // VW columns of one 32-column word
+            const int cc = on ? col : 0;
+            const uint32_t bits = a.own[(int64_t)tau * a.own_w + (cc >> 5)] >> (cc & 31);
 #pragma unroll
-              for (int x = 0; x < VW; ++x) v[i][x] = ((bits >> x) & 1u) ? v[i][x] : 0.0f;
-            }
-            if (a.mask) {
-              const uint8_t* mp = a.mask + (int64_t)tau * a.d[0] + (on ? col : 0);
-              const uint32_t m = VW == 4 ? *reinterpret_cast<const uint32_t*>(mp) : *reinterpret_cast<const uint16_t*>(mp);
-              v[i][0] = (m & 0xffu) ? v[i][0] : 0.0f;
-              v[i][1] = (m & 0xff00u) ? v[i][1] : 0.0f;
-              v[i][2] = (m & 0xff0000u) ? v[i][2] : 0.0f;
-              v[i][3] = (m & 0xff000000u) ? v[i][3] : 0.0f;
-            }
+            for (int x = 0; x < VW; ++x) v[i][x] = ((bits >> x) & 1u) ? v[i][x] : 0.0f;
           }
         }
 #pragma unroll
@@ -305,13 +297,13 @@ void gk_dw(const relnn_index* idx, int j, const void* emb, bool bf16, int d, int
 }
 
 void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdPlan& P, const void* W,
-                const float* dA, const uint32_t* own, int own_w, const uint8_t* mask, float* const* demb, char* w,
+                const float* dA, const uint32_t* route, int route_w, bool per_tuple, float* const* demb, char* w,
                 hipStream_t s) {
   const int h = L->h;
   const int64_t E = idx->E;
   const bool bf16 = L->dtype == RELNN_BF16;
   const size_t esz = bf16 ? 2 : 4;
-  const bool routed = own != nullptr || mask != nullptr;
+  const bool routed = route != nullptr;
   // dz_j = DS_j W_j^T, added into the rows of atom j.  W_j = rows koff.. of
   // W ([d][h]), so the product's B[k][n] = W[koff + n][k] (k < h, n < d).
   for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
@@ -320,7 +312,7 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
     if (nseg == 0) continue;
     RELNN_REQUIRE(d % 4 == 0, RELNN_E_UNSUPPORTED, "backward needs d %% 4 == 0");
     const void* Wj = static_cast<const char*>(W) + (size_t)koff * h * esz;
-    if (idx->atom_gk[j] && mask == nullptr) {
+    if (idx->atom_gk[j] && !per_tuple) {
       // one row per group: DS_j[row of g] = w_g dA_g, w_g = |g| (SUM, MEAN)
       // or 1 (MAX: each column goes to exactly one tuple of the group)
       KTimer tm("bwd_dx", s);
@@ -349,9 +341,8 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
     a.out = ds;
     a.ldo = h;
     a.carry = reinterpret_cast<float*>(w + P.ws_carry);
-    a.own = own;
-    a.own_w = own_w;
-    a.mask = mask;
+    a.own = route;
+    a.own_w = route_w;
     seg_gather_sum(a, P.units, s);
     RowsEpi epi;
     epi.orow = idx->t_segrow[j];

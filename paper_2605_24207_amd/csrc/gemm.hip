@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
   const int64_t ch = blockIdx.x;
   const int64_t tb = a.ntiles * ch / a.nchunk, te = a.ntiles * (ch + 1) / a.nchunk;
   const bool do_db = a.do_db && blockIdx.y == 0;
-  const bool route = a.b.own != nullptr || a.b.mask != nullptr;
+  const bool route = a.b.own != nullptr;
   const bool wave_on = i0 + 16 * w < a.Ka;
 
   int unit_mat[PER], unit_mg[PER], unit_cg[PER];
@@ -396,16 +396,8 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
           const int64_t m = min<int64_t>(t * MT + 4 * unit_mg[p] + r, a.M - 1);
           S.x[p][r] = *reinterpret_cast<const f32x4*>(a.b.B + rn[p][r] * a.b.ldb + col);
           if (do_db && a.wcnt) S.cnt[p][r] = a.wcnt[m + 1] - a.wcnt[m];
-          if (route) {                              // the four columns col .. col + 3 of row m
-            uint32_t k = 15u;
-            if (a.b.own) k &= a.b.own[m * a.b.own_w + (col >> 5)] >> (col & 31);
-            if (a.b.mask) {
-              const uint32_t mb = *reinterpret_cast<const uint32_t*>(a.b.mask + m * a.b.mask_ld + col);
-              k &= (uint32_t)((mb & 0xffu) != 0) | ((uint32_t)((mb & 0xff00u) != 0) << 1) |
-                   ((uint32_t)((mb & 0xff0000u) != 0) << 2) | ((uint32_t)((mb & 0xff000000u) != 0) << 3);
-            }
-            S.keep[p][r] = k;
-          }
+          if (route)                                // the four columns col .. col + 3 of row m
+            S.keep[p][r] = 15u & (a.b.own[m * a.b.own_w + (col >> 5)] >> (col & 31));
         }
       }
     }
@@ -565,7 +557,7 @@ __global__ void k_tn_sum(const float* part, const float* dbpart, int64_t nchunk,
     for (int64_t k = 0; k < nchunk; ++k) {
       const float y = src[k * stride] - c;
       const float t = s + y;
-      c = (t - s) - y;
+      c = __builtin_isfinite(t) ? (t - s) - y : 0.0f;    // no NaN compensation of an infinite sum
       s = t;
     }
     float* o = is_d ? D + i : db + (i - nd);
@@ -646,8 +638,8 @@ void gemm_tn(bool mfma_bf16, const void* Asrc, bool a_bf16, int64_t lda, const i
              const TnB& B, int64_t M, int Ka, int N, const int32_t* wcnt, float* D, float* db, bool accumulate,
              float* ws, hipStream_t s) {
   if (Ka <= 0 || N <= 0) return;
-  RELNN_REQUIRE(Ka % 4 == 0 && N % 4 == 0 && lda % 4 == 0 && B.ldb % 4 == 0 && (!B.mask || B.mask_ld % 4 == 0),
-                RELNN_E_UNSUPPORTED, "product widths %d x %d not supported", Ka, N);
+  RELNN_REQUIRE(Ka % 4 == 0 && N % 4 == 0 && lda % 4 == 0 && B.ldb % 4 == 0, RELNN_E_UNSUPPORTED,
+                "product widths %d x %d not supported", Ka, N);
   if (M <= 0) {
     k_zero_or_keep<<<grid_1d((int64_t)Ka * N), 256, 0, s>>>(D, (int64_t)Ka * N, accumulate ? 1 : 0);
     RELNN_LAUNCHED();

@@ -32,23 +32,21 @@ void gemm_rows(bool mfma_bf16, const void* A, bool a_bf16, int64_t lda, int64_t 
 
 // The B side of gemm_tn: row m is B[brow[m]] (brow null: B[m]), [.][ldb]
 // FP32, with column n kept only where bit n % 32 of own[m own_w + n / 32] is
-// set (own non-null) and mask[m mask_ld + n] != 0 (mask non-null), zero
-// elsewhere: the routed gradient rows of the backward.
+// set (own non-null), zero elsewhere: the routed gradient rows of the
+// backward.
 struct TnB {
   const float* B = nullptr;
   int64_t ldb = 0;
   const int32_t* brow = nullptr;
   const uint32_t* own = nullptr;
   int own_w = 0;
-  const uint8_t* mask = nullptr;
-  int64_t mask_ld = 0;
 };
 
 // D[i][n] (+)= sum_{m < M} A(m)[i] B(m)[n] for i < Ka, n < N, and, when db
 // is given, db[n] (+)= sum_m w_m B(m)[n] with w_m = wcnt[m+1] - wcnt[m]
 // (wcnt null: 1).  A(m) is row arow[aidx[m]] (aidx null: arow[m]; arow
 // null: m) of Asrc [.][lda], FP32 or bf16.  Ka % 4 == 0, N % 4 == 0, lda,
-// ldb and mask_ld multiples of 4.  The sum over m is split over contiguous
+// ldb multiples of 4.  The sum over m is split over contiguous
 // chunks whose partials (ws: gemm_tn_ws_floats(M, Ka, N) floats) are added
 // in chunk order, so results are deterministic.
 int64_t gemm_tn_ws_floats(int64_t M, int Ka, int N);

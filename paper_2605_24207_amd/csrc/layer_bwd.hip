@@ -32,7 +32,7 @@ namespace {
 // and the sums over joined rows then read 4 bytes per 32 columns of a tuple
 // instead of its argmax row.
 __global__ void k_own_bits(const int32_t* argmax, const int32_t* tuple_group, int64_t E, int h, int nw,
-                           uint32_t* own) {
+                           const uint32_t* mask, uint32_t* own) {
   const bool vec = (h & 31) == 0 && (((uintptr_t)argmax) & 15) == 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E * nw;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -52,7 +52,7 @@ __global__ void k_own_bits(const int32_t* argmax, const int32_t* tuple_group, in
       const int nb = min(32, h - 32 * w);
       for (int b = 0; b < nb; ++b) bits |= (uint32_t)(am[b] == tt) << b;
     }
-    own[i] = bits;
+    own[i] = mask ? bits & mask[i] : bits;           // act_pre: also where x W + b > 0
   }
 }
 
@@ -98,8 +98,8 @@ BwdPlan plan_bwd(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   const int64_t E = idx->E;
   p.xs_dw = L->act_pre == RELNN_ACT_NONE && L->agg != RELNN_MAX;
   size_t off = 0;
-  p.ws_mask = off;
-  if (L->act_pre != RELNN_ACT_NONE) off += round_up(std::max<int64_t>(E, 1) * L->h, 256);
+  p.ws_mask = off;                                       // act_pre: mask bits [E][ceil(h / 32)]
+  if (L->act_pre != RELNN_ACT_NONE) off += round_up(std::max<int64_t>(E, 1) * cdiv(L->h, 32) * 4, 256);
   p.ws_fwsw = off;
   if (L->act_pre != RELNN_ACT_NONE)                     // W swizzled for the mask kernel
     off += round_up((int64_t)F.Kp * L->h * (L->dtype == RELNN_BF16 ? 2 : 4), 256);
@@ -144,6 +144,7 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
     FwdPlan F = checked_plan(idx, L);
     RELNN_REQUIRE(idx->has_bwd, RELNN_E_INVALID, "the index was built without RELNN_IDX_BWD");
     RELNN_REQUIRE(!(L->flags & RELNN_OUT_BF16), RELNN_E_INVALID, "RELNN_OUT_BF16 is a forward-only flag");
+    RELNN_REQUIRE(!(L->flags & RELNN_TF_PRODUCT), RELNN_E_UNSUPPORTED, "no backward for the product transform");
     const BwdPlan P = plan_bwd(idx, L, F);
     RELNN_REQUIRE(emb != nullptr && W != nullptr && dW != nullptr && demb != nullptr, RELNN_E_INVALID,
                   "emb, W, dW and demb are required");
@@ -182,8 +183,9 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
     float* dA = reinterpret_cast<float*>(w + P.ws_dA);
     k_route_prep<<<grid_for(idx->G * h), 256, 0, s>>>(dout, pre, idx->offsets, idx->G, h, L->agg, L->act_post, dA);
     RELNN_LAUNCHED();
-    uint8_t* mask = nullptr;
-    if (L->act_pre != RELNN_ACT_NONE) {      // recompute act_pre'(x W + b) per tuple
+    const int nw = (int)cdiv(h, 32);
+    uint32_t* mask = nullptr;
+    if (L->act_pre != RELNN_ACT_NONE) {      // recompute act_pre'(x W + b) per tuple, one bit per column
       FwdArgs a{};
       a.at = at;
       a.rows = idx->rows;
@@ -196,18 +198,17 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
       a.off_y = (int)F.off_y;
       a.Wsw = w + P.ws_fwsw;
       a.b = b;
-      a.mask = reinterpret_cast<uint8_t*>(w + P.ws_mask);
+      a.mask = reinterpret_cast<uint32_t*>(w + P.ws_mask);
       swizzle_w(W, L->dtype, F.K, F.Kp, h, w + P.ws_fwsw, s);
       launch_mask(F, a, L->dtype, s);
       mask = a.mask;
     }
-    // MAX routing: one bit per tuple and column, set where the tuple is its
-    // group's maximiser
-    uint32_t* own = nullptr;
-    const int nw = (int)cdiv(h, 32);
+    // routing of dY: one bit per tuple and column, set where the tuple is
+    // its group's maximiser (MAX) and where x W + b > 0 (act_pre)
+    uint32_t* route = mask;
     if (L->agg == RELNN_MAX) {
-      own = reinterpret_cast<uint32_t*>(w + P.ws_own);
-      k_own_bits<<<grid_for(E * nw), 256, 0, s>>>(argmax, idx->tuple_group, E, h, nw, own);
+      route = reinterpret_cast<uint32_t*>(w + P.ws_own);
+      k_own_bits<<<grid_for(E * nw), 256, 0, s>>>(argmax, idx->tuple_group, E, h, nw, mask, route);
       RELNN_LAUNCHED();
     }
 
@@ -221,10 +222,8 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
       B.B = dA;
       B.ldb = h;
       B.brow = idx->tuple_group;
-      B.own = own;
+      B.own = route;
       B.own_w = nw;
-      B.mask = mask;
-      B.mask_ld = h;
       const bool bf16 = L->dtype == RELNN_BF16;
       float* part = reinterpret_cast<float*>(w + P.ws_part);
       for (int j = 0, koff = 0; j < L->k; koff += L->d[j], ++j) {
@@ -238,6 +237,6 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
     }
 
     // dz_j for every atom, in body order (through the per-row sums of dY)
-    lin_bwd_dx(idx, L, P.lin, W, dA, own, nw, mask, demb, w, s);
+    lin_bwd_dx(idx, L, P.lin, W, dA, route, nw, mask != nullptr, demb, w, s);
   });
 }

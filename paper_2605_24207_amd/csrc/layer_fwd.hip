@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int64_t ntiles, int6
           for (int64_t i = i0; i < i1; ++i) inner += carry[at(i) + c];
           const float y = inner - comp;
           const float tt = v + y;
-          comp = (tt - v) - y;
+          comp = __builtin_isfinite(tt) ? (tt - v) - y : 0.0f;   // an infinite sum stays infinite
           v = tt;
         }
       }
@@ -207,8 +207,13 @@ __global__ void __launch_bounds__(kThreads) k_layer_fwd(FwdArgs a) {
     f32x4 acc[kMaxQ];
     mfma_tile<T>(Xs, XS, a.Kp, nblk, ncb, static_cast<const T*>(a.Wsw), acc);
     if constexpr (MODE == MODE_MASK) {
+      // one bit per tuple and column: lanes 16 g .. 16 g + 15 hold the 16
+      // columns of column block cb for row 4 g + i of the row block, so one
+      // ballot gives four 16-bit halves of the rows' bit words
       const int lane = __lane_id();
       const int w = threadIdx.x / 64;
+      const int nhalf = 2 * (int)((a.h + 31) / 32);
+      uint16_t* bits = reinterpret_cast<uint16_t*>(a.mask);
 #pragma unroll
       for (int qi = 0; qi < kMaxQ; ++qi) {
         const int q = w + 4 * qi;
@@ -218,8 +223,10 @@ __global__ void __launch_bounds__(kThreads) k_layer_fwd(FwdArgs a) {
           const float bv = a.b ? a.b[col] : 0.0f;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
+            const uint64_t bal = __ballot((acc[qi][i] + bv) > 0.0f);
             const int row = rb * 16 + (lane >> 4) * 4 + i;
-            if (row < nv) a.mask[(e0 + row) * a.h + col] = (acc[qi][i] + bv) > 0.0f ? 1 : 0;
+            if ((lane & 15) == 0 && row < nv)
+              bits[(e0 + row) * nhalf + cb] = (uint16_t)(bal >> (lane & 48));
           }
         }
       }
@@ -342,9 +349,12 @@ FwdPlan plan_fwd(const relnn_index* idx, const relnn_layer_desc* L) {
   // covers the shape, the tile kernel otherwise)
   const WsPlan wp = plan_ws(L->dtype, K, h, E);
   const bool plain = (L->flags & RELNN_PLAIN) != 0;
-  P.carry_units = std::max<int64_t>(1, plain ? seg_reduce_units(E) : wp.KP ? wp.nunits : P.ntiles);
-  // the weight as the kernel that runs reads it (the plain path reads W as given)
-  const size_t wsw = plain ? 0 : wp.KP ? wp.wsw_bytes : (size_t)P.Kp * h * esz;
+  const bool prod = (L->flags & RELNN_TF_PRODUCT) != 0;
+  P.carry_units = std::max<int64_t>(1, prod ? push_units(E) : plain ? seg_reduce_units(E) : wp.KP ? wp.nunits
+                                                                                               : P.ntiles);
+  // the weight as the kernel that runs reads it (the plain path reads W as
+  // given, the product transform has none)
+  const size_t wsw = (plain || prod) ? 0 : wp.KP ? wp.wsw_bytes : (size_t)P.Kp * h * esz;
   size_t off = 0;
   P.ws_wsw = off;
   off += round_up(wsw, 256);
@@ -385,7 +395,14 @@ void check_layer_args(const relnn_index* idx, const relnn_layer_desc* L) {
   RELNN_REQUIRE((L->act_pre == RELNN_ACT_NONE || L->act_pre == RELNN_ACT_RELU) &&
                     (L->act_post == RELNN_ACT_NONE || L->act_post == RELNN_ACT_RELU),
                 RELNN_E_INVALID, "unknown activation");
-  RELNN_REQUIRE((L->flags & ~(RELNN_PLAIN | RELNN_DW_ACCUM | RELNN_OUT_BF16 | RELNN_PUSHDOWN)) == 0, RELNN_E_INVALID, "unknown layer flags");
+  RELNN_REQUIRE((L->flags & ~(RELNN_PLAIN | RELNN_DW_ACCUM | RELNN_OUT_BF16 | RELNN_PUSHDOWN | RELNN_TF_PRODUCT)) == 0,
+                RELNN_E_INVALID, "unknown layer flags");
+  if (L->flags & RELNN_TF_PRODUCT) {
+    RELNN_REQUIRE(!(L->flags & (RELNN_PLAIN | RELNN_PUSHDOWN)), RELNN_E_INVALID,
+                  "RELNN_TF_PRODUCT excludes RELNN_PLAIN and RELNN_PUSHDOWN");
+    for (int j = 0; j < L->k; ++j)
+      RELNN_REQUIRE(L->d[j] == L->h, RELNN_E_INVALID, "the product transform needs d[%d] == h", j);
+  }
   RELNN_REQUIRE(L->h > 0, RELNN_E_INVALID, "h must be positive");
   const int epc = L->dtype == RELNN_BF16 ? 8 : 4;
   for (int j = 0; j < L->k; ++j) {
@@ -399,7 +416,8 @@ void check_layer_args(const relnn_index* idx, const relnn_layer_desc* L) {
 FwdPlan checked_plan(const relnn_index* idx, const relnn_layer_desc* L) {
   check_layer_args(idx, L);
   FwdPlan P = plan_fwd(idx, L);
-  RELNN_REQUIRE(P.TM > 0, RELNN_E_UNSUPPORTED, "K = %d, h = %d does not fit the LDS tile", P.K, L->h);
+  RELNN_REQUIRE(P.TM > 0 || (L->flags & RELNN_TF_PRODUCT), RELNN_E_UNSUPPORTED,
+                "K = %d, h = %d does not fit the LDS tile", P.K, L->h);
   return P;
 }
 
@@ -494,7 +512,8 @@ void layer_fwd_run(const relnn_index* idx, const relnn_layer_desc* L, const void
       RELNN_REQUIRE(emb[j] != nullptr || idx->n_rows[j] == 0, RELNN_E_INVALID, "emb[%d] is NULL", j);
       RELNN_REQUIRE(((uintptr_t)emb[j] & 15) == 0, RELNN_E_UNSUPPORTED, "emb[%d] is not 16-byte aligned", j);
     }
-    RELNN_REQUIRE(W != nullptr, RELNN_E_INVALID, "W is NULL");
+    const bool prod = (L->flags & RELNN_TF_PRODUCT) != 0;
+    RELNN_REQUIRE(W != nullptr || prod, RELNN_E_INVALID, "W is NULL");
     RELNN_REQUIRE(out != nullptr || idx->G == 0, RELNN_E_INVALID, "out is NULL");
     RELNN_REQUIRE(ws != nullptr && ws_bytes >= need, RELNN_E_INVALID,
                   "workspace of %zu bytes given, %zu needed", ws_bytes, need);
@@ -522,6 +541,10 @@ void layer_fwd_run(const relnn_index* idx, const relnn_layer_desc* L, const void
     a.carry_arg = L->agg == RELNN_MAX ? reinterpret_cast<int32_t*>(w + P.ws_carry_arg) : nullptr;
     a.X = w + P.ws_x;
     a.Y = reinterpret_cast<float*>(w + P.ws_y);
+    if (prod) {                         // tau = z_1 * ... * z_k, elementwise
+      launch_product(a, L->dtype == RELNN_BF16, P.carry_units, a.carry, a.carry_arg, s);
+      return;
+    }
     if (push) {
       // node products P_j = Z_j W_j, once per atom row
       const int esz = L->dtype == RELNN_BF16 ? 2 : 4;

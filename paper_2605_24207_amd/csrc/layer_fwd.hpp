@@ -30,7 +30,7 @@ struct FwdArgs {
   const void* W;             // plain: W as given, row-major [K][h]
   const void* X;             // plain: [E][Kp]
   float* Y;                  // plain: [E][h]
-  uint8_t* mask;             // act_pre mask: [E][h], 1 where x W + b > 0
+  uint32_t* mask;            // act_pre mask: [E][ceil(h / 32)] words, bit c % 32 of word c / 32 set where x W + b > 0
 };
 
 struct FwdPlan {
@@ -68,7 +68,7 @@ void plain_gemm(int dtype, const void* X, int64_t n, int K, int ldx, const void*
 int64_t seg_reduce_units(int64_t E);
 void launch_seg_reduce(const float* Y, int64_t E, int h, const Seg& sg, const float* b, int act_pre,
                        const Sink& sink, float* carry, int32_t* carry_arg, int64_t carry_units, hipStream_t s);
-// Recomputes y = x W + b per tuple and writes mask = (y > 0) (tile kernel).
+// Recomputes y = x W + b per tuple and writes the bits (y > 0) (tile kernel).
 void launch_mask(const FwdPlan& P, const FwdArgs& a, int dtype, hipStream_t s);
 void launch_fixup(const Seg& sg, int TM, int h, int64_t ntiles, int64_t nunits, const Sink& sink,
                   const float* carry, const int32_t* carry_arg, hipStream_t s);
@@ -94,6 +94,10 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
 void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P, const int32_t* const* rows,
                  float* carry, int32_t* carry_arg, int64_t G, float* V, hipStream_t s);
 int64_t push_units(int64_t E);
+// Product transform (RELNN_TF_PRODUCT): the same gather over the atoms'
+// embeddings, multiplied elementwise per tuple (act_pre applied), then
+// aggregated through the sink.
+void launch_product(const FwdArgs& f, bool bf16, int64_t nunits, float* carry, int32_t* carry_arg, hipStream_t s);
 
 // Segmented gather-sum over a sorted list (bwd_linear.hip): out[s] = sum
 // over the positions e of segment s of the joined row at e (the atoms' rows
@@ -115,10 +119,11 @@ struct GsArgs {
   float* carry;                    // [nunits][2][ldo]
   int64_t ntiles, nunits;
   // routing of a gathered gradient row (one atom, dA of width h; rows[0] is
-  // the group of the tuple at each position, rows[1] its canonical position)
-  const uint32_t* own;             // [E][own_w] bits: keep column c only where the tuple owns it (MAX)
+  // the group of the tuple at each position, rows[1] its canonical position):
+  // keep column c only where bit c % 32 of word c / 32 of the tuple is set
+  // (MAX: the tuple is its group's maximiser; act_pre: x W + b > 0)
+  const uint32_t* own;             // [E][own_w] or null
   int own_w;
-  const uint8_t* mask;             // [E][h]: act_pre' of the tuple
   // weights: column c of the row at position e times wgt[tau wh + c / whd],
   // tau = rows[1][e] (whd a multiple of the columns a lane holds)
   const float* wgt;
@@ -139,10 +144,12 @@ struct LinBwdPlan {
 LinBwdPlan plan_lin_bwd(const relnn_index* idx, const relnn_layer_desc* L, size_t base, bool xs_dw);
 void lin_bwd_dw(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdPlan& P, const void* const* emb,
                 const float* dA, float* dW, float* db, bool accum, char* ws, hipStream_t s);
-// own: MAX routing bits [E][own_w] (bit c % 32 of word c / 32: the tuple is
-// its group's maximiser in column c), or null
+// route: routing bits [E][route_w] (bit c % 32 of word c / 32: the tuple's
+// gradient reaches column c: it is its group's maximiser (MAX) and x W + b >
+// 0 there (act_pre)), or null; per_tuple: act_pre, so a group-keyed atom
+// cannot take its rows from the group sums
 void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdPlan& P, const void* W,
-                const float* dA, const uint32_t* own, int own_w, const uint8_t* mask, float* const* demb, char* ws,
+                const float* dA, const uint32_t* route, int route_w, bool per_tuple, float* const* demb, char* ws,
                 hipStream_t s);
 size_t bwd_workspace(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P);
 // dW rows [d][h] of atom j when its FK is the group column, for MAX without

@@ -57,10 +57,13 @@ struct WsArgs {
   int32_t* carry_arg;
 };
 
+// Compensated add.  Once the sum is infinite or NaN the compensation
+// (t - s) - y would be NaN and turn an infinite sum into NaN, so it is
+// dropped: the sum then carries the non-finite value as plain addition does.
 __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
   const float y = x - c;
   const float t = s + y;
-  c = (t - s) - y;
+  c = __builtin_isfinite(t) ? (t - s) - y : 0.0f;
   s = t;
 }
 
@@ -121,7 +124,7 @@ __device__ __forceinline__ AtomSel atom_sel(const Atoms& at, int el) {
   return r;
 }
 
-template <class T, int KP, int NB>
+template <class T, int KP, int NB, int XS = 0>
 struct DmaGeo {
   static constexpr int EPC = 16 / (int)sizeof(T);          // elements per 16-byte chunk
   static constexpr int CPR = KP / EPC;                     // chunks per row
@@ -129,7 +132,7 @@ struct DmaGeo {
   static constexpr int NIW = NI / kDmaWaves;               // ... per DMA wave
   static constexpr int SWM = (CPR < 16 ? CPR : 16) - 1;    // chunk swizzle mask
   static constexpr int TILE = kTM * KP * (int)sizeof(T);   // bytes per LDS tile
-  static constexpr int NIR = 2 * NB - 1;                   // index slots (tiles t .. t+2NB-2)
+  static constexpr int NIR = 2 * NB - 1 + XS;              // index slots (tiles t .. t+2NB-2, XS more)
   static constexpr int IRB = kDmaWaves * 256;              // bytes per index slot
   // vector-memory operations a DMA wave issues after the loads of tile t+1
   // up to the end of iteration t: NB-2 iterations of (1 + NIW)
@@ -273,6 +276,89 @@ __device__ __forceinline__ void dma_barrier() {
 }
 __device__ __forceinline__ void compute_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Non-finite tuple values in the run sums.  The products that form the
+// sums of a tile's runs multiply every value of the tile by 0 or 1, and
+// 0 x Inf is NaN, so one infinite value would reach every run of its tile.
+// A wave that holds such a value (a wave-uniform test, rare) takes the
+// non-finite values out of those products (finite_or_zero) and sums codes
+// for them instead (codes: +Inf 1, -Inf 2^12, NaN 2^24; a run of at most
+// 32 rows sums them exactly in FP32), from which nf_kind reads the run's
+// non-finite part: NaN for a NaN or both infinities, else the infinity
+// present, else 0.  Adding it to the finite part gives what plain addition
+// gives, so a non-finite value stays in its own group.  The run sums are
+// always formed as usual and only redone when the wave holds a non-finite
+// value, so the usual path carries none of this work; the code sums are
+// packed into two bits per column before the finite part is redone.
+__device__ __forceinline__ bool wave_has_nonfinite(const f32x4& a, const f32x4& b) {
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) bad |= !__builtin_isfinite(a[i]) | !__builtin_isfinite(b[i]);
+  return __ballot(bad) != 0;
+}
+__device__ __forceinline__ float finite_or_zero(float y) { return __builtin_isfinite(y) ? y : 0.0f; }
+// kind of one value (0: finite, 1: +Inf, 2: -Inf, 3: NaN) and its code
+__device__ __forceinline__ uint32_t nf_val_kind(float y) {
+  const uint32_t u = __float_as_uint(y);
+  const uint32_t k = (u & 0x7FFFFFu) ? 3u : (u >> 31) ? 2u : 1u;
+  return (u & 0x7F800000u) == 0x7F800000u ? k : 0u;
+}
+__device__ __forceinline__ float nf_kind_code(uint32_t k) {
+  k &= 3u;
+  return k == 0u ? 0.0f : k == 1u ? 1.0f : k == 2u ? 4096.0f : 16777216.0f;
+}
+// 0: finite, 1: +Inf, 2: -Inf, 3: NaN
+__device__ __forceinline__ uint32_t nf_kind(float code_sum) {
+  if (code_sum == 0.0f) return 0u;
+  if (code_sum >= 16777216.0f) return 3u;
+  const float neg = floorf(code_sum * (1.0f / 4096.0f));
+  const float pos = code_sum - 4096.0f * neg;
+  return neg > 0.0f ? (pos > 0.0f ? 3u : 2u) : 1u;
+}
+__device__ __forceinline__ uint32_t nf_pack(const f32x4& n) {
+  return nf_kind(n[0]) | (nf_kind(n[1]) << 2) | (nf_kind(n[2]) << 4) | (nf_kind(n[3]) << 6);
+}
+__device__ __forceinline__ float nf_value(uint32_t packed, int i) {
+  const uint32_t k = (packed >> (2 * i)) & 3u;
+  return k == 0u ? 0.0f : k == 1u ? INFINITY : k == 2u ? -INFINITY : __builtin_nanf("");
+}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// The same on eight bf16 values, on their bits (exponent all ones: not
+// finite; codes 1.0 = 0x3F80, 2^12 = 0x4580, 2^24 = 0x4B80).
+__device__ __forceinline__ uint32_t nf_half_code(uint32_t hb) {
+  const uint32_t code = (hb & 0x7Fu) ? 0x4B80u : (hb & 0x8000u) ? 0x4580u : 0x3F80u;
+  return (hb & 0x7F80u) == 0x7F80u ? code : 0u;
+}
+__device__ __forceinline__ bf16x8 finite_or_zero8(const bf16x8& v) {
+  u32x4 u = __builtin_bit_cast(u32x4, v);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t x = u[i];
+    const uint32_t bad = ((x & 0x7F80u) == 0x7F80u ? 0xFFFFu : 0u) |
+                         ((x & 0x7F800000u) == 0x7F800000u ? 0xFFFF0000u : 0u);
+    u[i] = x & ~bad;
+  }
+  return __builtin_bit_cast(bf16x8, u);
+}
+__device__ __forceinline__ bf16x8 nf_code8(const bf16x8& v) {
+  u32x4 u = __builtin_bit_cast(u32x4, v);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) u[i] = nf_half_code(u[i] & 0xFFFFu) | (nf_half_code(u[i] >> 16) << 16);
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+// A copy the compiler cannot see through: the slow path's work on values
+// that do not change across the run passes would otherwise be hoisted out
+// of the pass loop, and so out of its branch, into every tile.
+__device__ __forceinline__ f32x4 opaque(f32x4 v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ bf16x8 opaque(bf16x8 v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // y if bit i of m is set, else +0 (a bit mask, not a multiply: exact for
 // every y, infinities included)
 __device__ __forceinline__ float keep_bit(float y, uint32_t m, int i) {
@@ -304,56 +390,55 @@ struct DmaMfma<__bf16> {                 // bf16 16x16x32, one 16-byte A read pe
 // accumulator values (rows 4 (l/16) + i and 16 + 4 (l/16) + i, column
 // l % 16) and its B operand whether each of those rows lies in the run of
 // column l % 16, as in the FP32 kernel.
-template <int KP, int NB>
-__device__ __forceinline__ void fwd_wide_bf16(const WsArgs& a, char* smem, int64_t tb, int64_t te, int64_t range_hi,
-                                              int cw, int lane, int64_t bidx) {
-  using G = DmaGeo<__bf16, KP, NB>;
-  constexpr int NKS = KP / 32;
-  constexpr int TM = kTM;
-  const int h = a.h;
-  char* irs = smem + NB * G::TILE;
-  auto wrap = [](int v, int n) { return v >= n ? v - n : v; };
-  const int colA = 32 * cw + (lane & 15);
-  const float bcA = a.b ? a.b[colA] : 0.0f, bcB = a.b ? a.b[colA + 16] : 0.0f;
+//
+// WideMma holds a wave's slice of W in registers and multiplies one LDS
+// tile; WideRed reduces the products of one tile into the wave's 32
+// columns and carries the group left open at the tile's end.  The fused
+// form runs both in the same wave.  The split form (wide_split_*) gives
+// each compute wave a reducer wave on the same SIMD: the compute wave
+// passes its accumulators through LDS and goes on to the next tile's
+// products while the reducer's vector instructions (split, run sums,
+// finish) run beside them.
+template <int KP, int NB, int XS>
+struct WideMma {
+  using G = DmaGeo<__bf16, KP, NB, XS>;
+  static constexpr int NKS = KP / 32;
+  static constexpr int PD = NKS < 4 ? NKS : 4;               // operand reads ahead of the products
   bf16x8 wA[NKS], wB[NKS];
-#pragma unroll
-  for (int ks = 0; ks < NKS; ++ks) {
-    wA[ks] = reinterpret_cast<const bf16x8*>(a.Wsw)[((2 * cw) * NKS + ks) * 64 + lane];
-    wB[ks] = reinterpret_cast<const bf16x8*>(a.Wsw)[((2 * cw + 1) * NKS + ks) * 64 + lane];
-  }
-  __builtin_amdgcn_s_waitcnt(0);
-  const int q4 = 4 * (lane >> 4);
-  const int r0 = lane & 15, r1 = 16 + (lane & 15);
-  const int cq = lane >> 4;
-  auto chunk_base = [&](int sw, int j) { return 4 * (j ^ (sw >> 2)) + ((cq ^ sw) & 3); };
   int b0[4], b1[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    b0[j] = G::EPC * chunk_base(r0 & G::SWM, j);
-    b1[j] = G::EPC * chunk_base(r1 & G::SWM, j);
-  }
-  // group open at the end of the previous tile, in the lanes of column off
-  f32x4 oSA = {0.f, 0.f, 0.f, 0.f}, oCA = oSA, oSB = oSA, oCB = oSA;
-  int oN = 0;
-  bool oCut = false;
-  int off = 0;
-  const int n16 = lane & 15;
-  const int col4 = 32 * cw + q4;
+  int r0, r1;
+  float bcA, bcB;
 
-  compute_barrier();                                         // (index slots staged)
-  compute_barrier();                                         // tile tb is in LDS
-  int rr = 0, ri = 0;
-  for (int64_t t = tb; t < te; ++t) {
-    const int32_t* gsl = reinterpret_cast<const int32_t*>(irs + ri * G::IRB);
-    const int gl = (n16 - off) & 15;
-    const int hdr = gsl[kSlotHdr];
-    const int rs0 = gsl[kSlotRunStart + gl];
-    const int rn0 = gsl[kSlotRunStart + gl + 1];
-    const int gid0 = gsl[kSlotRunGroup + gl];
-    const __bf16* x0 = reinterpret_cast<const __bf16*>(smem + rr * G::TILE) + r0 * KP;
-    const __bf16* x1 = reinterpret_cast<const __bf16*>(smem + rr * G::TILE) + r1 * KP;
-    f32x4 a0A = {bcA, bcA, bcA, bcA}, a1A = a0A, a0B = {bcB, bcB, bcB, bcB}, a1B = a0B;
-    constexpr int PD = NKS < 4 ? NKS : 4;
+  __device__ __forceinline__ WideMma(const WsArgs& a, int cw, int lane) {
+    const int colA = 32 * cw + (lane & 15);
+    bcA = a.b ? a.b[colA] : 0.0f;
+    bcB = a.b ? a.b[colA + 16] : 0.0f;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      wA[ks] = reinterpret_cast<const bf16x8*>(a.Wsw)[((2 * cw) * NKS + ks) * 64 + lane];
+      wB[ks] = reinterpret_cast<const bf16x8*>(a.Wsw)[((2 * cw + 1) * NKS + ks) * 64 + lane];
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    r0 = lane & 15;
+    r1 = 16 + (lane & 15);
+    const int cq = lane >> 4;
+    auto chunk_base = [&](int sw, int j) { return 4 * (j ^ (sw >> 2)) + ((cq ^ sw) & 3); };
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      b0[j] = G::EPC * chunk_base(r0 & G::SWM, j);
+      b1[j] = G::EPC * chunk_base(r1 & G::SWM, j);
+    }
+  }
+
+  // x W + b of the tile at X: a0 / a1 rows 4 (l/16) + i and 16 + 4 (l/16) + i
+  // of column block A (columns 32 cw + l % 16) and B (16 further)
+  __device__ __forceinline__ void tile(const char* X, f32x4& a0A, f32x4& a1A, f32x4& a0B, f32x4& a1B) const {
+    const __bf16* x0 = reinterpret_cast<const __bf16*>(X) + r0 * KP;
+    const __bf16* x1 = reinterpret_cast<const __bf16*>(X) + r1 * KP;
+    a0A = f32x4{bcA, bcA, bcA, bcA};
+    a1A = a0A;
+    a0B = f32x4{bcB, bcB, bcB, bcB};
+    a1B = a0B;
     auto rd = [&](const __bf16* x, const int (&b)[4], int k) {
       return *reinterpret_cast<const bf16x8*>(x + 32 * (k & ~3) + b[k & 3]);
     };
@@ -376,6 +461,47 @@ __device__ __forceinline__ void fwd_wide_bf16(const WsArgs& a, char* smem, int64
       a1B = __builtin_amdgcn_mfma_f32_16x16x32_bf16(u1, wB[ks], a1B, 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
+  }
+};
+
+struct WideRed {
+  // group open at the end of the previous tile, in the lanes of column off
+  f32x4 oSA, oCA, oSB, oCB;
+  int oN, off;
+  bool oCut;
+  int n16, q4, col4;
+
+  __device__ __forceinline__ WideRed(int cw, int lane) {
+    oSA = f32x4{0.f, 0.f, 0.f, 0.f};
+    oCA = oSA;
+    oSB = oSA;
+    oCB = oSA;
+    oN = 0;
+    off = 0;
+    oCut = false;
+    n16 = lane & 15;
+    q4 = 4 * (lane >> 4);
+    col4 = 32 * cw + q4;
+  }
+
+  // the run-table words of this lane's first-pass run (read early, so the
+  // LDS latency hides behind other work)
+  struct Run {
+    int hdr, rs0, rn0, gid0;
+  };
+  __device__ __forceinline__ Run run(const int32_t* gsl) const {
+    const int gl = (n16 - off) & 15;
+    return Run{gsl[kSlotHdr], gsl[kSlotRunStart + gl], gsl[kSlotRunStart + gl + 1], gsl[kSlotRunGroup + gl]};
+  }
+
+  // reduce tile t (index slot gsl) of the unit whose tiles are tb .. with
+  // tuple values y = act_pre(acc) of this lane's 8 rows in each block
+  __device__ __forceinline__ void tile(const WsArgs& a, const int32_t* gsl, const Run& R, int64_t t, int64_t tb,
+                                       int64_t range_hi, int64_t bidx, f32x4 a0A, f32x4 a1A, f32x4 a0B,
+                                       f32x4 a1B) {
+    constexpr int TM = kTM;
+    const int h = a.h;
+    const int gl = (n16 - off) & 15;
     if (a.act_pre == RELNN_ACT_RELU) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -396,17 +522,18 @@ __device__ __forceinline__ void fwd_wide_bf16(const WsArgs& a, char* smem, int64
         lo[i] = (__bf16)(y - (float)hb);
       }
     };
+    const bool nonfin = wave_has_nonfinite(a0A, a1A) || wave_has_nonfinite(a0B, a1B);
     bf16x8 hA, lA, hB, lB;
     split(a0A, a1A, hA, lA);
     split(a0B, a1B, hB, lB);
 
-    const int hd = __builtin_amdgcn_readfirstlane(hdr);
+    const int hd = __builtin_amdgcn_readfirstlane(R.hdr);
     const int nr = hd & 63, nv = hd >> 16;
     const bool prev_same = (hd >> 8) & 1, next_same = (hd >> 9) & 1;
     const int64_t e0 = t * TM;
     const bool keep_open = next_same && e0 + nv < range_hi;
     for (int pass = 0; 16 * pass < nr; ++pass) {
-      int g = gl, rs = rs0, rn = rn0, gid = gid0;
+      int g = gl, rs = R.rs0, rn = R.rn0, gid = R.gid0;
       if (pass) {                                            // runs 16 .. 31 (rare)
         g = 16 + gl;
         rs = gsl[kSlotRunStart + g];
@@ -425,6 +552,21 @@ __device__ __forceinline__ void fwd_wide_bf16(const WsArgs& a, char* smem, int64
       DB = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hB, sel, DB, 0, 0, 0);
       DA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lA, sel, DA, 0, 0, 0);
       DB = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lB, sel, DB, 0, 0, 0);
+      if (nonfin) {                // redone; a non-finite y has a non-finite hi term
+        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+        const bf16x8 xhA = opaque(hA), xlA = opaque(lA), xhB = opaque(hB), xlB = opaque(lB);
+        const uint32_t nfA = nf_pack(__builtin_amdgcn_mfma_f32_16x16x32_bf16(nf_code8(xhA), sel, z, 0, 0, 0));
+        const uint32_t nfB = nf_pack(__builtin_amdgcn_mfma_f32_16x16x32_bf16(nf_code8(xhB), sel, z, 0, 0, 0));
+        DA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(finite_or_zero8(xhA), sel, z, 0, 0, 0);
+        DA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(finite_or_zero8(xlA), sel, DA, 0, 0, 0);
+        DB = __builtin_amdgcn_mfma_f32_16x16x32_bf16(finite_or_zero8(xhB), sel, z, 0, 0, 0);
+        DB = __builtin_amdgcn_mfma_f32_16x16x32_bf16(finite_or_zero8(xlB), sel, DB, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          DA[i] += nf_value(nfA, i);
+          DB[i] += nf_value(nfB, i);
+        }
+      }
       const int cnt = re - rs;
       const bool first = g == 0 && prev_same;
       const bool last = g == nr - 1 && next_same;
@@ -479,18 +621,99 @@ __device__ __forceinline__ void fwd_wide_bf16(const WsArgs& a, char* smem, int64
       }
     }
     off = (off + nr - 1) & 15;
+  }
+};
+
+template <int KP, int NB>
+__device__ __forceinline__ void fwd_wide_bf16(const WsArgs& a, char* smem, int64_t tb, int64_t te, int64_t range_hi,
+                                              int cw, int lane, int64_t bidx) {
+  using G = DmaGeo<__bf16, KP, NB, 0>;
+  char* irs = smem + NB * G::TILE;
+  auto wrap = [](int v, int n) { return v >= n ? v - n : v; };
+  const WideMma<KP, NB, 0> M(a, cw, lane);
+  WideRed R(cw, lane);
+  compute_barrier();                                         // (index slots staged)
+  compute_barrier();                                         // tile tb is in LDS
+  int rr = 0, ri = 0;
+  for (int64_t t = tb; t < te; ++t) {
+    const int32_t* gsl = reinterpret_cast<const int32_t*>(irs + ri * G::IRB);
+    const WideRed::Run run = R.run(gsl);
+    f32x4 a0A, a1A, a0B, a1B;
+    M.tile(smem + rr * G::TILE, a0A, a1A, a0B, a1B);
+    R.tile(a, gsl, run, t, tb, range_hi, bidx, a0A, a1A, a0B, a1B);
     rr = wrap(rr + 1, NB);
     ri = wrap(ri + 1, G::NIR);
     compute_barrier();
   }
 }
 
+// Split form.  Iteration t (tb <= t <= te) has two barriers, Y_t and X_t:
+//   compute wave: writes the accumulators of tile t-1 to its LDS buffer,
+//                 Y_t, multiplies tile t (kept in registers), X_t;
+//   reducer wave: Y_t, reads those accumulators and reduces tile t-1, X_t;
+//   DMA waves:    issue their loads of iteration t, Y_t, wait for tile t+1, X_t.
+// So tile t-1's buffer is written before Y_t and read between Y_t and X_t,
+// and rewritten only after X_t.  The reducer reads the index slot of tile
+// t-1 while the DMA waves fill the slot of tile t+2NB-2: one more slot than
+// the fused form keeps them apart.
+constexpr int kAccBuf = 4096;                                // bytes of accumulators per compute wave
+
+template <int KP, int NB>
+__device__ __forceinline__ void wide_split_compute(const WsArgs& a, char* smem, int64_t tb, int64_t te, int cw,
+                                                   int cwl, int lane) {
+  using G = DmaGeo<__bf16, KP, NB, 1>;
+  auto wrap = [](int v, int n) { return v >= n ? v - n : v; };
+  const WideMma<KP, NB, 1> M(a, cw, lane);
+  f32x4* acc = reinterpret_cast<f32x4*>(smem + NB * G::TILE + G::NIR * G::IRB + cwl * kAccBuf) + lane;
+  compute_barrier();                                         // (index slots staged)
+  compute_barrier();                                         // tile tb is in LDS
+  f32x4 a0A = {0.f, 0.f, 0.f, 0.f}, a1A = a0A, a0B = a0A, a1B = a0A;
+  int rr = 0;
+  for (int64_t t = tb; t <= te; ++t) {
+    if (t > tb) {                                            // 64-lane rows of 1 KB: no bank conflicts
+      acc[0] = a0A;
+      acc[64] = a1A;
+      acc[128] = a0B;
+      acc[192] = a1B;
+    }
+    compute_barrier();                                       // Y_t
+    if (t < te) M.tile(smem + rr * G::TILE, a0A, a1A, a0B, a1B);
+    compute_barrier();                                       // X_t
+    rr = wrap(rr + 1, NB);
+  }
+}
+
+template <int KP, int NB>
+__device__ __forceinline__ void wide_split_reduce(const WsArgs& a, char* smem, int64_t tb, int64_t te,
+                                                  int64_t range_hi, int cw, int cwl, int lane, int64_t bidx) {
+  using G = DmaGeo<__bf16, KP, NB, 1>;
+  auto wrap = [](int v, int n) { return v >= n ? v - n : v; };
+  char* irs = smem + NB * G::TILE;
+  const f32x4* acc = reinterpret_cast<const f32x4*>(irs + G::NIR * G::IRB + cwl * kAccBuf) + lane;
+  WideRed R(cw, lane);
+  compute_barrier();                                         // (index slots staged)
+  compute_barrier();                                         // tile tb is in LDS
+  int ri = 0;
+  for (int64_t t = tb; t <= te; ++t) {
+    compute_barrier();                                       // Y_t
+    if (t > tb) {
+      const int32_t* gsl = reinterpret_cast<const int32_t*>(irs + ri * G::IRB);
+      const WideRed::Run run = R.run(gsl);
+      R.tile(a, gsl, run, t - 1, tb, range_hi, bidx, acc[0], acc[64], acc[128], acc[192]);
+      ri = wrap(ri + 1, G::NIR);
+    }
+    compute_barrier();                                       // X_t
+  }
+}
+
 // kWide: BF16 SUM / MEAN with h % 32 == 0 (32-column compute waves).
-template <class T, int KP, int NB, bool kMax, bool kWide, bool kArg>
-__global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves) * 64) k_fwd_dma(WsArgs a) {
+template <class T, int KP, int NB, bool kMax, bool kWide, bool kArg, bool kRed>
+__global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) * (kRed ? 2 : 1) + kDmaWaves) * 64)
+    k_fwd_dma(WsArgs a) {
   static_assert(!kWide || (std::is_same<T, __bf16>::value && !kMax), "wide waves: BF16 SUM / MEAN");
   static_assert(!kArg || kMax, "maximiser positions: MAX only");
-  using G = DmaGeo<T, KP, NB>;
+  static_assert(!kRed || kWide, "reducer waves: the wide BF16 waves");
+  using G = DmaGeo<T, KP, NB, kRed ? 1 : 0>;
   using WT = typename DmaMfma<T>::W;
   constexpr int NKS = DmaMfma<T>::template nks<KP>();
   constexpr int TM = kTM;
@@ -528,6 +751,13 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
   // (it % NIR); both kept as wrapping 32-bit counters
   auto wrap = [](int v, int n) { return v >= n ? v - n : v; };
 
+  if constexpr (kRed) {
+    if (wave >= ncw + kDmaWaves) {                           // reducer of compute wave r
+      const int r = wave - ncw - kDmaWaves;
+      wide_split_reduce<KP, NB>(a, smem, tb, te, range_hi, chunk * ncw + r, r, lane, bidx);
+      return;
+    }
+  }
   if (wave >= ncw) {
     // ------------------------------------------------------------ DMA waves
     // At iteration t a wave issues the index slot of tile t+2NB-2, then its
@@ -554,10 +784,15 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
       P.index(a, min(t + 2 * NB - 2, tl), irs + si * G::IRB, dw);
       P.tile(irs + sr * G::IRB, smem + rr * G::TILE, dw);
       if (!kMax && dw == 0) P.run_table(a, min(t + NB - 1, tl), irs + sr * G::IRB);
+      if constexpr (kRed) compute_barrier();                  // Y_t (the split form's second barrier)
       dma_barrier<G::WAIT>();                                 // tile t+1 has landed
       si = wrap(si + 1, G::NIR);
       sr = wrap(sr + 1, G::NIR);
       rr = wrap(rr + 1, NB);
+    }
+    if constexpr (kRed) {                                     // the reducers' last tile
+      compute_barrier();                                      // Y_te
+      compute_barrier();                                      // X_te
     }
     // loads past the range may still be landing: the LDS must not be
     // released to another block before they have
@@ -566,7 +801,10 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
   }
 
   // -------------------------------------------------------------- compute waves
-  if constexpr (kWide) {
+  if constexpr (kRed) {
+    wide_split_compute<KP, NB>(a, smem, tb, te, chunk * ncw + wave, wave, lane);
+    return;
+  } else if constexpr (kWide) {
     fwd_wide_bf16<KP, NB>(a, smem, tb, te, range_hi, chunk * ncw + wave, lane, bidx);
     return;
   }
@@ -936,6 +1174,7 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
     const int64_t e0 = t * TM;
 
     if constexpr (!kMax) {
+      const bool nonfin = wave_has_nonfinite(acc0, acc1);
       // ---- SUM / MEAN: per-run sums on the matrix cores.  With S the 0/1
       // matrix [row][run] of the tile, D[c][n] = sum_row y[row][c] S[row][n]
       // is one f32 16x16x4 product per accumulator register: its A operand
@@ -965,6 +1204,26 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
 #pragma unroll
         for (int i = 0; i < 4; ++i)
           D = __builtin_amdgcn_mfma_f32_16x16x4f32(acc1[i], keep_bit(1.0f, m1, i), D, 0, 0, 0);
+        if (nonfin) {            // redone: the finite part, then the run's non-finite part added
+          const f32x4 y0 = opaque(acc0), y1 = opaque(acc1);
+          f32x4 N = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            N = __builtin_amdgcn_mfma_f32_16x16x4f32(nf_kind_code(nf_val_kind(y0[i])), keep_bit(1.0f, m0, i), N, 0,
+                                                     0, 0);
+            N = __builtin_amdgcn_mfma_f32_16x16x4f32(nf_kind_code(nf_val_kind(y1[i])), keep_bit(1.0f, m1, i), N, 0,
+                                                     0, 0);
+          }
+          const uint32_t nfp = nf_pack(N);
+          D = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            D = __builtin_amdgcn_mfma_f32_16x16x4f32(finite_or_zero(y0[i]), keep_bit(1.0f, m0, i), D, 0, 0, 0);
+            D = __builtin_amdgcn_mfma_f32_16x16x4f32(finite_or_zero(y1[i]), keep_bit(1.0f, m1, i), D, 0, 0, 0);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) D[i] += nf_value(nfp, i);
+        }
         const int cnt = re - rs;
         const bool first = g == 0 && prev_same;              // continues the group open before the tile
         const bool last = g == nr - 1 && next_same;          // runs on past the tile
@@ -1038,9 +1297,14 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
 // (runs past the end), which k_fixup combines in range order.
 struct PushArgs {
   int n;                                  // atoms gathered per tuple
-  const float* P[RELNN_MAX_ATOMS];        // [n_rows_j][h]
+  const void* P[RELNN_MAX_ATOMS];         // [n_rows_j][h]: FP32 node products, or the embeddings (product)
   const int32_t* rows[RELNN_MAX_ATOMS];   // [E] joined row per tuple
+  int act_pre;                            // product transform: activation per tuple
 };
+
+// Gather-combine modes: the sum of FP32 node products (pushdown), or the
+// product of the atoms' embeddings, FP32 or bf16 (product transform).
+enum { PS_SUM = 0, PS_PROD_F32 = 1, PS_PROD_BF16 = 2 };
 
 // Second pass of the pushdown: V holds each group's aggregate of the varying
 // atoms (MEAN already divided by the count); the group constant is added
@@ -1087,6 +1351,7 @@ constexpr int kPsTM = 64;       // range boundaries on multiples of 64 positions
 constexpr int kPsWaves = 4;     // waves per block
 constexpr int kPsBatch = 8;     // tuples whose rows are loaded together
 
+template <int kMode>
 __global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs pa) {
   const int lane = threadIdx.x % 64;
   const int64_t u = (int64_t)blockIdx.x * kPsWaves + threadIdx.x / 64;
@@ -1152,15 +1417,31 @@ __global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs p
 #pragma unroll
         for (int i = 0; i < kPsBatch; ++i) {
           const int q = min(bt + i, n - 1);                 // clamped: every load is valid
-          v[i] = make_float2(0.0f, 0.0f);
+          v[i] = kMode == PS_SUM ? make_float2(0.0f, 0.0f) : make_float2(1.0f, 1.0f);
 #pragma unroll
           for (int j = 0; j < RELNN_MAX_ATOMS; ++j) {
             if (j < pa.n) {
               const int32_t row = __builtin_amdgcn_readlane(R[j], q);
-              const float2 p = *reinterpret_cast<const float2*>(pa.P[j] + (int64_t)row * h + cc);
-              v[i].x += p.x;
-              v[i].y += p.y;
+              float2 p;
+              if constexpr (kMode == PS_PROD_BF16) {
+                const uint32_t u = *reinterpret_cast<const uint32_t*>(static_cast<const __bf16*>(pa.P[j]) +
+                                                                      (int64_t)row * h + cc);
+                p = make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
+              } else {
+                p = *reinterpret_cast<const float2*>(static_cast<const float*>(pa.P[j]) + (int64_t)row * h + cc);
+              }
+              if constexpr (kMode == PS_SUM) {
+                v[i].x += p.x;
+                v[i].y += p.y;
+              } else {
+                v[i].x *= p.x;
+                v[i].y *= p.y;
+              }
             }
+          }
+          if (kMode != PS_SUM && pa.act_pre == RELNN_ACT_RELU) {
+            v[i].x = fmaxf(v[i].x, 0.0f);
+            v[i].y = fmaxf(v[i].y, 0.0f);
           }
         }
 #pragma unroll
@@ -1202,22 +1483,35 @@ void allow_lds(KernelT k, size_t bytes) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
-// LDS ring depth NB: as many tiles as fit with their 2 NB - 1 index slots,
-// at most 6 (tiles t+1 .. t+4 in flight while t is multiplied).
-template <class T, int KP>
+// LDS ring depth NB: as many tiles as fit with their 2 NB - 1 + XS index
+// slots and `extra` bytes, at most 6 (tiles t+1 .. t+4 in flight while t
+// is multiplied).
+template <class T, int KP, int XS = 0, int extra = 0>
 constexpr int ring_depth() {
   constexpr int TILE = DmaGeo<T, KP, 2>::TILE;
   constexpr int IRB = DmaGeo<T, KP, 2>::IRB;
-  constexpr int fit = (160 * 1024 + IRB) / (TILE + 2 * IRB);
+  constexpr int fit = (160 * 1024 - extra + IRB - XS * IRB) / (TILE + 2 * IRB);
   return fit < 6 ? fit : 6;
 }
 
-template <class T, int KP, int NB, bool kMax, bool kWide, bool kArg>
+// The split form (reducer waves beside the compute waves) for BF16 SUM /
+// MEAN tiles up to 384 wide: its three waves per SIMD leave 168 registers a
+// wave, which the W slice of a 512-wide tile (128 registers) does not fit
+// with its operands; that width keeps the fused form.
+template <class T, int KP>
+constexpr bool use_split() {
+  return std::is_same<T, __bf16>::value && KP <= 384;
+}
+constexpr int kSplitExtra = (kHMax / 32) * kAccBuf;
+
+template <class T, int KP, int NB, bool kMax, bool kWide, bool kArg, bool kRed>
 void launch_dma(const WsArgs& a, size_t lds, hipStream_t s) {
-  allow_lds(k_fwd_dma<T, KP, NB, kMax, kWide, kArg>, lds);
+  allow_lds(k_fwd_dma<T, KP, NB, kMax, kWide, kArg, kRed>, lds);
   KTimer tm("fwd_fused", s);
   const int64_t grid = a.nch == 1 ? a.nunits : round_up(a.nunits, 8) * a.nch;
-  k_fwd_dma<T, KP, NB, kMax, kWide, kArg><<<(unsigned)grid, (a.hc / (kWide ? 32 : 16) + kDmaWaves) * 64, lds, s>>>(a);
+  const int ncw = a.hc / (kWide ? 32 : 16);
+  k_fwd_dma<T, KP, NB, kMax, kWide, kArg, kRed><<<(unsigned)grid, (ncw * (kRed ? 2 : 1) + kDmaWaves) * 64, lds, s>>>(
+      a);
   RELNN_LAUNCHED();
 }
 
@@ -1228,15 +1522,25 @@ void run_dma(const WsArgs& a, hipStream_t s) {
   static_assert(NB >= 2, "two LDS tiles at least");
   const size_t lds = (size_t)NB * G::TILE + (size_t)G::NIR * G::IRB;
   RELNN_REQUIRE(lds <= 160 * 1024, RELNN_E_HIP, "internal: LDS ring of %zu bytes", lds);
-  if (a.sink.agg == RELNN_MAX)
+  if (a.sink.agg == RELNN_MAX) {
     if (a.sink.argmax)
-      launch_dma<T, KP, NB, true, false, true>(a, lds, s);
+      launch_dma<T, KP, NB, true, false, true, false>(a, lds, s);
     else                           // values only (the carry positions are written as 0)
-      launch_dma<T, KP, NB, true, false, false>(a, lds, s);
-  else if (std::is_same<T, __bf16>::value && a.hc % 32 == 0)
-    launch_dma<T, KP, NB, false, std::is_same<T, __bf16>::value, false>(a, lds, s);
-  else
-    launch_dma<T, KP, NB, false, false, false>(a, lds, s);
+      launch_dma<T, KP, NB, true, false, false, false>(a, lds, s);
+  } else if (std::is_same<T, __bf16>::value && a.hc % 32 == 0) {
+    if constexpr (use_split<T, KP>()) {
+      constexpr int NBS = ring_depth<T, KP, 1, kSplitExtra>();
+      using GS = DmaGeo<T, KP, NBS, 1>;
+      static_assert(NBS >= 3, "three LDS tiles at least");
+      const size_t ldss = (size_t)NBS * GS::TILE + (size_t)GS::NIR * GS::IRB + kSplitExtra;
+      RELNN_REQUIRE(ldss <= 160 * 1024, RELNN_E_HIP, "internal: LDS ring of %zu bytes", ldss);
+      launch_dma<T, KP, NBS, false, true, false, true>(a, ldss, s);
+    } else {
+      launch_dma<T, KP, NB, false, std::is_same<T, __bf16>::value, false, false>(a, lds, s);
+    }
+  } else {
+    launch_dma<T, KP, NB, false, false, false, false>(a, lds, s);
+  }
 }
 
 int num_cus() {
@@ -1295,7 +1599,7 @@ void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P,
     pa.rows[j] = rows[j];
   }
   KTimer tm("fwd_push", s);                // gather-sum, fix-up and finish
-  k_push_sum<<<(unsigned)cdiv(a.nunits, kPsWaves), kPsWaves * 64, 0, s>>>(a, pa);
+  k_push_sum<PS_SUM><<<(unsigned)cdiv(a.nunits, kPsWaves), kPsWaves * 64, 0, s>>>(a, pa);
   RELNN_LAUNCHED();
   launch_fixup(f.sg, kPsTM, f.h, a.ntiles, a.nunits, raw, carry, carry_arg, s);
   Sink fin = f.sink;
@@ -1307,6 +1611,35 @@ void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P,
         V, G, f.h, fin);
     RELNN_LAUNCHED();
   }
+}
+
+void launch_product(const FwdArgs& f, bool bf16, int64_t nunits, float* carry, int32_t* carry_arg, hipStream_t s) {
+  RELNN_REQUIRE(f.h % 4 == 0, RELNN_E_UNSUPPORTED, "the product transform needs h %% 4 == 0");
+  WsArgs a{};
+  a.at = f.at;
+  a.E = f.E;
+  a.h = f.h;
+  a.ntiles = cdiv(f.E, kPsTM);
+  a.nunits = std::max<int64_t>(1, std::min<int64_t>(a.ntiles, nunits));
+  a.act_pre = f.act_pre;
+  a.sg = f.sg;
+  a.sink = f.sink;
+  a.carry = carry;
+  a.carry_arg = carry_arg;
+  PushArgs pa{};
+  pa.n = f.at.k;
+  pa.act_pre = f.act_pre;
+  for (int j = 0; j < f.at.k; ++j) {
+    pa.P[j] = f.at.emb[j];
+    pa.rows[j] = f.at.rows[j];
+  }
+  KTimer tm("fwd_product", s);
+  if (bf16)
+    k_push_sum<PS_PROD_BF16><<<(unsigned)cdiv(a.nunits, kPsWaves), kPsWaves * 64, 0, s>>>(a, pa);
+  else
+    k_push_sum<PS_PROD_F32><<<(unsigned)cdiv(a.nunits, kPsWaves), kPsWaves * 64, 0, s>>>(a, pa);
+  RELNN_LAUNCHED();
+  launch_fixup(f.sg, kPsTM, f.h, a.ntiles, a.nunits, f.sink, carry, carry_arg, s);
 }
 
 // ranges of the pushdown gather-sum (and carry pairs): up to 8192 waves
@@ -1385,10 +1718,10 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
 
 // Explicit instantiations of the fused kernel: with implicit ones alone the
 // host pass left the launch stubs of some instances undefined.
-#define RELNN_DMA_INST(T, KP)                                                             \
-  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), false, false, false>(WsArgs); \
-  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false, true>(WsArgs);   \
-  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false, false>(WsArgs);
+#define RELNN_DMA_INST(T, KP)                                                                    \
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), false, false, false, false>(WsArgs); \
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false, true, false>(WsArgs);   \
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false, false, false>(WsArgs);
 RELNN_DMA_INST(float, 64)
 RELNN_DMA_INST(float, 128)
 RELNN_DMA_INST(float, 256)
@@ -1398,11 +1731,14 @@ RELNN_DMA_INST(__bf16, 128)
 RELNN_DMA_INST(__bf16, 256)
 RELNN_DMA_INST(__bf16, 384)
 RELNN_DMA_INST(__bf16, 512)
-template __global__ void k_fwd_dma<__bf16, 64, ring_depth<__bf16, 64>(), false, true, false>(WsArgs);
-template __global__ void k_fwd_dma<__bf16, 128, ring_depth<__bf16, 128>(), false, true, false>(WsArgs);
-template __global__ void k_fwd_dma<__bf16, 256, ring_depth<__bf16, 256>(), false, true, false>(WsArgs);
-template __global__ void k_fwd_dma<__bf16, 384, ring_depth<__bf16, 384>(), false, true, false>(WsArgs);
-template __global__ void k_fwd_dma<__bf16, 512, ring_depth<__bf16, 512>(), false, true, false>(WsArgs);
+#define RELNN_SPLIT_INST(KP) \
+  template __global__ void k_fwd_dma<__bf16, KP, ring_depth<__bf16, KP, 1, kSplitExtra>(), false, true, false, true>(WsArgs);
+RELNN_SPLIT_INST(64)
+RELNN_SPLIT_INST(128)
+RELNN_SPLIT_INST(256)
+RELNN_SPLIT_INST(384)
+#undef RELNN_SPLIT_INST
+template __global__ void k_fwd_dma<__bf16, 512, ring_depth<__bf16, 512>(), false, true, false, false>(WsArgs);
 #undef RELNN_DMA_INST
 
 }  // namespace relnn

@@ -27,10 +27,12 @@ constexpr int kRedWaves = 4;          // waves per block
 constexpr int kRedBatch = 16;         // rows loaded together per wave
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
+// Compensated add; the compensation is dropped once the sum is not finite
+// (an infinite sum stays infinite instead of turning NaN).
 __device__ __forceinline__ void kahan(float& s, float& c, float x) {
   const float y = x - c;
   const float t = s + y;
-  c = (t - s) - y;
+  c = __builtin_isfinite(t) ? (t - s) - y : 0.0f;
   s = t;
 }
 

@@ -10,6 +10,7 @@
 // the canonical order of those joins, so the layer kernels consume them
 // directly as an index.  A host scheduler thread admits requests, fills
 // the pinned input buffers, launches the graph and hands results back.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -173,6 +174,8 @@ struct Request {
   relnn_req_stats st{};
   std::vector<float> out;
   std::vector<uint8_t> present;
+  bool admitted = false;             // taken into a step
+  bool cancelled = false;            // admitted, then cancelled: dropped when its step ends
   bool done = false;
 };
 
@@ -319,6 +322,11 @@ void relnn_server::run_step(std::vector<Request*>& batch) {
   std::lock_guard<std::mutex> lk(mu);
   for (Request* r : batch) {
     const int64_t m = (int64_t)r->seeds.size();
+    if (r->cancelled) {              // its caller no longer wants it
+      base += m;
+      reqs.erase(r->ticket);
+      continue;
+    }
     r->out.assign(out_h + base * D.h, out_h + (base + m) * D.h);
     r->present.resize(m);
     for (int64_t q = 0; q < m; ++q) {
@@ -350,6 +358,7 @@ void relnn_server::loop() {
         Request* r = pending.front();
         if (seeds + (int64_t)r->seeds.size() > cap_seeds) break;   // waits for the next step
         seeds += (int64_t)r->seeds.size();
+        r->admitted = true;
         batch.push_back(r);
         pending.pop_front();
       }
@@ -556,7 +565,8 @@ extern "C" relnn_status relnn_serve_poll(relnn_server* S, uint64_t ticket, float
     {
       std::lock_guard<std::mutex> lk(S->mu);
       auto it = S->reqs.find(ticket);
-      RELNN_REQUIRE(it != S->reqs.end(), RELNN_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+      RELNN_REQUIRE(it != S->reqs.end() && !it->second->cancelled, RELNN_E_INVALID, "unknown ticket %llu",
+                    (unsigned long long)ticket);
       if (!it->second->done) {
         RELNN_REQUIRE(!S->stop, RELNN_E_HIP, "server stopped: %s", S->worker_error.c_str());
         st = RELNN_E_NOT_READY;
@@ -570,6 +580,27 @@ extern "C" relnn_status relnn_serve_poll(relnn_server* S, uint64_t ticket, float
     if (stats) *stats = r->st;
   });
   return g != RELNN_OK ? g : st;
+}
+
+extern "C" relnn_status relnn_serve_cancel(relnn_server* S, uint64_t ticket, int32_t* was_admitted) {
+  return guard([&] {
+    RELNN_REQUIRE(S != nullptr, RELNN_E_INVALID, "NULL server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    RELNN_REQUIRE(it != S->reqs.end() && !it->second->cancelled, RELNN_E_INVALID, "unknown ticket %llu",
+                  (unsigned long long)ticket);
+    Request* r = it->second.get();
+    if (was_admitted) *was_admitted = r->admitted ? 1 : 0;
+    if (!r->admitted) {              // still queued: it never runs
+      auto q = std::find(S->pending.begin(), S->pending.end(), r);
+      if (q != S->pending.end()) S->pending.erase(q);
+      S->reqs.erase(it);
+    } else if (r->done) {            // finished, not yet polled
+      S->reqs.erase(it);
+    } else {                         // in the running step: its result is dropped at the step's end
+      r->cancelled = true;
+    }
+  });
 }
 
 extern "C" relnn_status relnn_serve_destroy(relnn_server* S) {

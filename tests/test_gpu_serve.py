@@ -140,6 +140,42 @@ def test_serve_tiny_budget_queues_requests():
     srv.close()
 
 
+def test_serve_cancel():
+    """Cancelled requests: queued ones never run, one in the running step
+    is dropped at its end; every other request still comes back correct,
+    and a cancelled ticket is unknown to poll and to a second cancel."""
+    from paper_2605_24207_amd import RelnnError
+
+    g = small_graph(seed=15)
+    per_seed = 16 + 8 + 15 * 28 + 150 * 12 + 15 * 128 * 4 + 128 * 4 + 128 * 4 + 4 * 128
+    budget = 64 * per_seed + 256 * 2 * 128 * 4 + (1 << 20)
+    srv = make_server(g, "f32", max_seeds=64, max_slots=2, budget_bytes=budget)   # about one request per step
+    ref = oracle_for(g, "f32")
+    reqs = requests(g, 40, seed=6)
+    tickets = [srv.submit(s, rs) for s, rs in reqs]
+    admitted = {}
+    for q in range(1, len(tickets), 2):
+        admitted[q] = srv.cancel(tickets[q])
+    assert not all(admitted.values())                       # some were still queued
+    for q in admitted:
+        with pytest.raises(RelnnError, match="INVALID"):
+            srv.poll(tickets[q], len(reqs[q][0]))
+        with pytest.raises(RelnnError, match="INVALID"):
+            srv.cancel(tickets[q])
+    steps = []
+    for q in range(0, len(tickets), 2):
+        s, rs = reqs[q]
+        out, present, st = srv.wait(tickets[q], len(s))
+        steps.append(st["step"])
+        assert rows_close(out, ref(s, rs)[0], 1e-5)
+    # a queued request that was cancelled took no step: fewer steps than requests submitted
+    assert max(steps) + 1 < len(tickets)
+    s, rs = reqs[1]
+    out, _, _ = srv.wait(srv.submit(s, rs), len(s))         # the server goes on serving
+    assert rows_close(out, ref(s, rs)[0], 1e-5)
+    srv.close()
+
+
 def test_serve_errors():
     from paper_2605_24207_amd import RelnnError
 
