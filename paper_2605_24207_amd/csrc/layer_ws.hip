@@ -124,7 +124,7 @@ __device__ __forceinline__ AtomSel atom_sel(const Atoms& at, int el) {
   return r;
 }
 
-template <class T, int KP, int NB, int XS = 0>
+template <class T, int KP, int NB>
 struct DmaGeo {
   static constexpr int EPC = 16 / (int)sizeof(T);          // elements per 16-byte chunk
   static constexpr int CPR = KP / EPC;                     // chunks per row
@@ -132,7 +132,7 @@ struct DmaGeo {
   static constexpr int NIW = NI / kDmaWaves;               // ... per DMA wave
   static constexpr int SWM = (CPR < 16 ? CPR : 16) - 1;    // chunk swizzle mask
   static constexpr int TILE = kTM * KP * (int)sizeof(T);   // bytes per LDS tile
-  static constexpr int NIR = 2 * NB - 1 + XS;              // index slots (tiles t .. t+2NB-2, XS more)
+  static constexpr int NIR = 2 * NB - 1;                   // index slots (tiles t .. t+2NB-2)
   static constexpr int IRB = kDmaWaves * 256;              // bytes per index slot
   // vector-memory operations a DMA wave issues after the loads of tile t+1
   // up to the end of iteration t: NB-2 iterations of (1 + NIW)
@@ -289,11 +289,18 @@ __device__ __forceinline__ void compute_barrier() { asm volatile("s_waitcnt lgkm
 // always formed as usual and only redone when the wave holds a non-finite
 // value, so the usual path carries none of this work; the code sums are
 // packed into two bits per column before the finite part is redone.
+// The test is one sum of magnitudes per lane and one ballot: the sum is not
+// finite when a value is not (a sum that overflows only takes the slow
+// path, which gives the same result); a test per value, each compare
+// feeding a scalar OR, cost a tenth of the BF16 kernel's time.
+__device__ __forceinline__ float abs_sum(const f32x4& a) {
+  return (fabsf(a[0]) + fabsf(a[1])) + (fabsf(a[2]) + fabsf(a[3]));
+}
 __device__ __forceinline__ bool wave_has_nonfinite(const f32x4& a, const f32x4& b) {
-  bool bad = false;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) bad |= !__builtin_isfinite(a[i]) | !__builtin_isfinite(b[i]);
-  return __ballot(bad) != 0;
+  return __ballot(!__builtin_isfinite(abs_sum(a) + abs_sum(b))) != 0;
+}
+__device__ __forceinline__ bool wave_has_nonfinite(const f32x4& a, const f32x4& b, const f32x4& c, const f32x4& d) {
+  return __ballot(!__builtin_isfinite((abs_sum(a) + abs_sum(b)) + (abs_sum(c) + abs_sum(d)))) != 0;
 }
 __device__ __forceinline__ float finite_or_zero(float y) { return __builtin_isfinite(y) ? y : 0.0f; }
 // kind of one value (0: finite, 1: +Inf, 2: -Inf, 3: NaN) and its code
@@ -393,15 +400,14 @@ struct DmaMfma<__bf16> {                 // bf16 16x16x32, one 16-byte A read pe
 //
 // WideMma holds a wave's slice of W in registers and multiplies one LDS
 // tile; WideRed reduces the products of one tile into the wave's 32
-// columns and carries the group left open at the tile's end.  The fused
-// form runs both in the same wave.  The split form (wide_split_*) gives
-// each compute wave a reducer wave on the same SIMD: the compute wave
-// passes its accumulators through LDS and goes on to the next tile's
-// products while the reducer's vector instructions (split, run sums,
-// finish) run beside them.
-template <int KP, int NB, int XS>
+// columns and carries the group left open at the tile's end.  (Giving each
+// compute wave a reducer wave on its SIMD, with the accumulators passed
+// through LDS, was slower: 3.7 against 2.8 ms for the ER Item rule.  The
+// reducer's dependent chain alone took 3.4 ms, and the extra LDS buffer
+// cost a tile of the load ring.)
+template <int KP, int NB>
 struct WideMma {
-  using G = DmaGeo<__bf16, KP, NB, XS>;
+  using G = DmaGeo<__bf16, KP, NB>;
   static constexpr int NKS = KP / 32;
   static constexpr int PD = NKS < 4 ? NKS : 4;               // operand reads ahead of the products
   bf16x8 wA[NKS], wB[NKS];
@@ -522,7 +528,7 @@ struct WideRed {
         lo[i] = (__bf16)(y - (float)hb);
       }
     };
-    const bool nonfin = wave_has_nonfinite(a0A, a1A) || wave_has_nonfinite(a0B, a1B);
+    const bool nonfin = wave_has_nonfinite(a0A, a1A, a0B, a1B);
     bf16x8 hA, lA, hB, lB;
     split(a0A, a1A, hA, lA);
     split(a0B, a1B, hB, lB);
@@ -627,10 +633,10 @@ struct WideRed {
 template <int KP, int NB>
 __device__ __forceinline__ void fwd_wide_bf16(const WsArgs& a, char* smem, int64_t tb, int64_t te, int64_t range_hi,
                                               int cw, int lane, int64_t bidx) {
-  using G = DmaGeo<__bf16, KP, NB, 0>;
+  using G = DmaGeo<__bf16, KP, NB>;
   char* irs = smem + NB * G::TILE;
   auto wrap = [](int v, int n) { return v >= n ? v - n : v; };
-  const WideMma<KP, NB, 0> M(a, cw, lane);
+  const WideMma<KP, NB> M(a, cw, lane);
   WideRed R(cw, lane);
   compute_barrier();                                         // (index slots staged)
   compute_barrier();                                         // tile tb is in LDS
@@ -647,73 +653,13 @@ __device__ __forceinline__ void fwd_wide_bf16(const WsArgs& a, char* smem, int64
   }
 }
 
-// Split form.  Iteration t (tb <= t <= te) has two barriers, Y_t and X_t:
-//   compute wave: writes the accumulators of tile t-1 to its LDS buffer,
-//                 Y_t, multiplies tile t (kept in registers), X_t;
-//   reducer wave: Y_t, reads those accumulators and reduces tile t-1, X_t;
-//   DMA waves:    issue their loads of iteration t, Y_t, wait for tile t+1, X_t.
-// So tile t-1's buffer is written before Y_t and read between Y_t and X_t,
-// and rewritten only after X_t.  The reducer reads the index slot of tile
-// t-1 while the DMA waves fill the slot of tile t+2NB-2: one more slot than
-// the fused form keeps them apart.
-constexpr int kAccBuf = 4096;                                // bytes of accumulators per compute wave
-
-template <int KP, int NB>
-__device__ __forceinline__ void wide_split_compute(const WsArgs& a, char* smem, int64_t tb, int64_t te, int cw,
-                                                   int cwl, int lane) {
-  using G = DmaGeo<__bf16, KP, NB, 1>;
-  auto wrap = [](int v, int n) { return v >= n ? v - n : v; };
-  const WideMma<KP, NB, 1> M(a, cw, lane);
-  f32x4* acc = reinterpret_cast<f32x4*>(smem + NB * G::TILE + G::NIR * G::IRB + cwl * kAccBuf) + lane;
-  compute_barrier();                                         // (index slots staged)
-  compute_barrier();                                         // tile tb is in LDS
-  f32x4 a0A = {0.f, 0.f, 0.f, 0.f}, a1A = a0A, a0B = a0A, a1B = a0A;
-  int rr = 0;
-  for (int64_t t = tb; t <= te; ++t) {
-    if (t > tb) {                                            // 64-lane rows of 1 KB: no bank conflicts
-      acc[0] = a0A;
-      acc[64] = a1A;
-      acc[128] = a0B;
-      acc[192] = a1B;
-    }
-    compute_barrier();                                       // Y_t
-    if (t < te) M.tile(smem + rr * G::TILE, a0A, a1A, a0B, a1B);
-    compute_barrier();                                       // X_t
-    rr = wrap(rr + 1, NB);
-  }
-}
-
-template <int KP, int NB>
-__device__ __forceinline__ void wide_split_reduce(const WsArgs& a, char* smem, int64_t tb, int64_t te,
-                                                  int64_t range_hi, int cw, int cwl, int lane, int64_t bidx) {
-  using G = DmaGeo<__bf16, KP, NB, 1>;
-  auto wrap = [](int v, int n) { return v >= n ? v - n : v; };
-  char* irs = smem + NB * G::TILE;
-  const f32x4* acc = reinterpret_cast<const f32x4*>(irs + G::NIR * G::IRB + cwl * kAccBuf) + lane;
-  WideRed R(cw, lane);
-  compute_barrier();                                         // (index slots staged)
-  compute_barrier();                                         // tile tb is in LDS
-  int ri = 0;
-  for (int64_t t = tb; t <= te; ++t) {
-    compute_barrier();                                       // Y_t
-    if (t > tb) {
-      const int32_t* gsl = reinterpret_cast<const int32_t*>(irs + ri * G::IRB);
-      const WideRed::Run run = R.run(gsl);
-      R.tile(a, gsl, run, t - 1, tb, range_hi, bidx, acc[0], acc[64], acc[128], acc[192]);
-      ri = wrap(ri + 1, G::NIR);
-    }
-    compute_barrier();                                       // X_t
-  }
-}
 
 // kWide: BF16 SUM / MEAN with h % 32 == 0 (32-column compute waves).
-template <class T, int KP, int NB, bool kMax, bool kWide, bool kArg, bool kRed>
-__global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) * (kRed ? 2 : 1) + kDmaWaves) * 64)
-    k_fwd_dma(WsArgs a) {
+template <class T, int KP, int NB, bool kMax, bool kWide, bool kArg>
+__global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves) * 64) k_fwd_dma(WsArgs a) {
   static_assert(!kWide || (std::is_same<T, __bf16>::value && !kMax), "wide waves: BF16 SUM / MEAN");
   static_assert(!kArg || kMax, "maximiser positions: MAX only");
-  static_assert(!kRed || kWide, "reducer waves: the wide BF16 waves");
-  using G = DmaGeo<T, KP, NB, kRed ? 1 : 0>;
+  using G = DmaGeo<T, KP, NB>;
   using WT = typename DmaMfma<T>::W;
   constexpr int NKS = DmaMfma<T>::template nks<KP>();
   constexpr int TM = kTM;
@@ -751,13 +697,6 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) * (kRed ? 2
   // (it % NIR); both kept as wrapping 32-bit counters
   auto wrap = [](int v, int n) { return v >= n ? v - n : v; };
 
-  if constexpr (kRed) {
-    if (wave >= ncw + kDmaWaves) {                           // reducer of compute wave r
-      const int r = wave - ncw - kDmaWaves;
-      wide_split_reduce<KP, NB>(a, smem, tb, te, range_hi, chunk * ncw + r, r, lane, bidx);
-      return;
-    }
-  }
   if (wave >= ncw) {
     // ------------------------------------------------------------ DMA waves
     // At iteration t a wave issues the index slot of tile t+2NB-2, then its
@@ -784,15 +723,10 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) * (kRed ? 2
       P.index(a, min(t + 2 * NB - 2, tl), irs + si * G::IRB, dw);
       P.tile(irs + sr * G::IRB, smem + rr * G::TILE, dw);
       if (!kMax && dw == 0) P.run_table(a, min(t + NB - 1, tl), irs + sr * G::IRB);
-      if constexpr (kRed) compute_barrier();                  // Y_t (the split form's second barrier)
       dma_barrier<G::WAIT>();                                 // tile t+1 has landed
       si = wrap(si + 1, G::NIR);
       sr = wrap(sr + 1, G::NIR);
       rr = wrap(rr + 1, NB);
-    }
-    if constexpr (kRed) {                                     // the reducers' last tile
-      compute_barrier();                                      // Y_te
-      compute_barrier();                                      // X_te
     }
     // loads past the range may still be landing: the LDS must not be
     // released to another block before they have
@@ -801,10 +735,7 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) * (kRed ? 2
   }
 
   // -------------------------------------------------------------- compute waves
-  if constexpr (kRed) {
-    wide_split_compute<KP, NB>(a, smem, tb, te, chunk * ncw + wave, wave, lane);
-    return;
-  } else if constexpr (kWide) {
+  if constexpr (kWide) {
     fwd_wide_bf16<KP, NB>(a, smem, tb, te, range_hi, chunk * ncw + wave, lane, bidx);
     return;
   }
@@ -1483,35 +1414,22 @@ void allow_lds(KernelT k, size_t bytes) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
-// LDS ring depth NB: as many tiles as fit with their 2 NB - 1 + XS index
-// slots and `extra` bytes, at most 6 (tiles t+1 .. t+4 in flight while t
-// is multiplied).
-template <class T, int KP, int XS = 0, int extra = 0>
+// LDS ring depth NB: as many tiles as fit with their 2 NB - 1 index slots,
+// at most 6 (tiles t+1 .. t+4 in flight while t is multiplied).
+template <class T, int KP>
 constexpr int ring_depth() {
   constexpr int TILE = DmaGeo<T, KP, 2>::TILE;
   constexpr int IRB = DmaGeo<T, KP, 2>::IRB;
-  constexpr int fit = (160 * 1024 - extra + IRB - XS * IRB) / (TILE + 2 * IRB);
+  constexpr int fit = (160 * 1024 + IRB) / (TILE + 2 * IRB);
   return fit < 6 ? fit : 6;
 }
 
-// The split form (reducer waves beside the compute waves) for BF16 SUM /
-// MEAN tiles up to 384 wide: its three waves per SIMD leave 168 registers a
-// wave, which the W slice of a 512-wide tile (128 registers) does not fit
-// with its operands; that width keeps the fused form.
-template <class T, int KP>
-constexpr bool use_split() {
-  return std::is_same<T, __bf16>::value && KP <= 384;
-}
-constexpr int kSplitExtra = (kHMax / 32) * kAccBuf;
-
-template <class T, int KP, int NB, bool kMax, bool kWide, bool kArg, bool kRed>
+template <class T, int KP, int NB, bool kMax, bool kWide, bool kArg>
 void launch_dma(const WsArgs& a, size_t lds, hipStream_t s) {
-  allow_lds(k_fwd_dma<T, KP, NB, kMax, kWide, kArg, kRed>, lds);
+  allow_lds(k_fwd_dma<T, KP, NB, kMax, kWide, kArg>, lds);
   KTimer tm("fwd_fused", s);
   const int64_t grid = a.nch == 1 ? a.nunits : round_up(a.nunits, 8) * a.nch;
-  const int ncw = a.hc / (kWide ? 32 : 16);
-  k_fwd_dma<T, KP, NB, kMax, kWide, kArg, kRed><<<(unsigned)grid, (ncw * (kRed ? 2 : 1) + kDmaWaves) * 64, lds, s>>>(
-      a);
+  k_fwd_dma<T, KP, NB, kMax, kWide, kArg><<<(unsigned)grid, (a.hc / (kWide ? 32 : 16) + kDmaWaves) * 64, lds, s>>>(a);
   RELNN_LAUNCHED();
 }
 
@@ -1524,22 +1442,13 @@ void run_dma(const WsArgs& a, hipStream_t s) {
   RELNN_REQUIRE(lds <= 160 * 1024, RELNN_E_HIP, "internal: LDS ring of %zu bytes", lds);
   if (a.sink.agg == RELNN_MAX) {
     if (a.sink.argmax)
-      launch_dma<T, KP, NB, true, false, true, false>(a, lds, s);
+      launch_dma<T, KP, NB, true, false, true>(a, lds, s);
     else                           // values only (the carry positions are written as 0)
-      launch_dma<T, KP, NB, true, false, false, false>(a, lds, s);
+      launch_dma<T, KP, NB, true, false, false>(a, lds, s);
   } else if (std::is_same<T, __bf16>::value && a.hc % 32 == 0) {
-    if constexpr (use_split<T, KP>()) {
-      constexpr int NBS = ring_depth<T, KP, 1, kSplitExtra>();
-      using GS = DmaGeo<T, KP, NBS, 1>;
-      static_assert(NBS >= 3, "three LDS tiles at least");
-      const size_t ldss = (size_t)NBS * GS::TILE + (size_t)GS::NIR * GS::IRB + kSplitExtra;
-      RELNN_REQUIRE(ldss <= 160 * 1024, RELNN_E_HIP, "internal: LDS ring of %zu bytes", ldss);
-      launch_dma<T, KP, NBS, false, true, false, true>(a, ldss, s);
-    } else {
-      launch_dma<T, KP, NB, false, std::is_same<T, __bf16>::value, false, false>(a, lds, s);
-    }
+    launch_dma<T, KP, NB, false, std::is_same<T, __bf16>::value, false>(a, lds, s);
   } else {
-    launch_dma<T, KP, NB, false, false, false, false>(a, lds, s);
+    launch_dma<T, KP, NB, false, false, false>(a, lds, s);
   }
 }
 
@@ -1719,9 +1628,9 @@ void launch_ws(const WsPlan& p, int dtype, const FwdArgs& f, const void* Wsw, fl
 // Explicit instantiations of the fused kernel: with implicit ones alone the
 // host pass left the launch stubs of some instances undefined.
 #define RELNN_DMA_INST(T, KP)                                                                    \
-  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), false, false, false, false>(WsArgs); \
-  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false, true, false>(WsArgs);   \
-  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false, false, false>(WsArgs);
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), false, false, false>(WsArgs); \
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false, true>(WsArgs);   \
+  template __global__ void k_fwd_dma<T, KP, ring_depth<T, KP>(), true, false, false>(WsArgs);
 RELNN_DMA_INST(float, 64)
 RELNN_DMA_INST(float, 128)
 RELNN_DMA_INST(float, 256)
@@ -1731,14 +1640,11 @@ RELNN_DMA_INST(__bf16, 128)
 RELNN_DMA_INST(__bf16, 256)
 RELNN_DMA_INST(__bf16, 384)
 RELNN_DMA_INST(__bf16, 512)
-#define RELNN_SPLIT_INST(KP) \
-  template __global__ void k_fwd_dma<__bf16, KP, ring_depth<__bf16, KP, 1, kSplitExtra>(), false, true, false, true>(WsArgs);
-RELNN_SPLIT_INST(64)
-RELNN_SPLIT_INST(128)
-RELNN_SPLIT_INST(256)
-RELNN_SPLIT_INST(384)
-#undef RELNN_SPLIT_INST
-template __global__ void k_fwd_dma<__bf16, 512, ring_depth<__bf16, 512>(), false, true, false, false>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 64, ring_depth<__bf16, 64>(), false, true, false>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 128, ring_depth<__bf16, 128>(), false, true, false>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 256, ring_depth<__bf16, 256>(), false, true, false>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 384, ring_depth<__bf16, 384>(), false, true, false>(WsArgs);
+template __global__ void k_fwd_dma<__bf16, 512, ring_depth<__bf16, 512>(), false, true, false>(WsArgs);
 #undef RELNN_DMA_INST
 
 }  // namespace relnn
