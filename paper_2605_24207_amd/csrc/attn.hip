@@ -223,20 +223,10 @@ __global__ void __launch_bounds__(256) k_attn_tuple(AttnArgs a, const int32_t* t
   }
 }
 
-// x[ord[i]] = y[i]
+// out[i] = y[ord[i]]
 __global__ void k_gather_rows_idx(const int32_t* ord, const int32_t* y, int64_t n, int32_t* out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     out[i] = y[ord[i]];
-}
-
-// dst[row[s]][:] += src[s][:] (rows distinct)
-__global__ void k_add_rows(const float* src, const int32_t* row, int64_t nseg, int w, float* dst) {
-  const int64_t total = nseg * w;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = i / w;
-    const int c = (int)(i - s * w);
-    dst[(int64_t)row[s] * w + c] += src[i];
-  }
 }
 
 unsigned grid_n(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 1 << 16)); }
@@ -279,7 +269,7 @@ AttnArgs make_args(const relnn_index* idx, const relnn_attn_desc* A, const void*
 }
 
 struct AttnPlan {
-  size_t carry = 0, lse = 0, D = 0, A = 0, DS = 0, yrow = 0, seg = 0, gcarry = 0, total = 0;
+  size_t carry = 0, lse = 0, D = 0, A = 0, DS = 0, yrow = 0, gcarry = 0, total = 0;
 };
 
 AttnPlan plan_attn(const relnn_index* idx, const relnn_attn_desc* A, bool bwd) {
@@ -293,15 +283,12 @@ AttnPlan plan_attn(const relnn_index* idx, const relnn_attn_desc* A, bool bwd) {
   const int64_t E = std::max<int64_t>(idx->E, 1), G = std::max<int64_t>(idx->G, 1);
   p.carry = take((size_t)attn_units(idx->E) * 2 * (A->dv + 2 * A->heads) * 4);
   if (bwd) {
-    int64_t nseg = 1;
-    for (int j = 0; j < 3; ++j) nseg = std::max<int64_t>(nseg, idx->t_nseg[j]);
     const int w = std::max(A->d, A->dv);
     p.lse = take((size_t)G * A->heads * 4);
     p.D = take((size_t)G * A->heads * 4);
     p.A = take((size_t)E * A->heads * 4);
     p.DS = take((size_t)E * A->heads * 4);
     p.yrow = take((size_t)E * 4);
-    p.seg = take((size_t)nseg * w * 4);
     p.gcarry = take((size_t)gs_units(E) * 2 * w * 4);
   }
   p.total = off;
@@ -405,7 +392,6 @@ extern "C" relnn_status relnn_attn_bwd(const relnn_index* idx, const relnn_attn_
         {2, dout, false, idx->tuple_group, A->dv, Aw, A->dv / A->heads, dv},
     };
     int32_t* yrow_t = reinterpret_cast<int32_t*>(w + P.yrow);
-    float* seg = reinterpret_cast<float*>(w + P.seg);
     for (const Part& pt : parts) {
       const int j = pt.j;
       const int64_t nseg = idx->t_nseg[j];
@@ -422,15 +408,15 @@ extern "C" relnn_status relnn_attn_bwd(const relnn_index* idx, const relnn_attn_
       g.bf16 = pt.y_bf16;
       g.n = E;
       g.sg = Seg{idx->t_seg[j], idx->t_segoff[j], E, nullptr};
-      g.out = seg;
+      g.out = pt.dst;                          // each segment's sum added into its row of dX_j
+      g.out_row = idx->t_segrow[j];
+      g.accumulate = true;
       g.ldo = pt.width;
       g.carry = reinterpret_cast<float*>(w + P.gcarry);
       g.wgt = pt.wgt;
       g.wh = A->heads;
       g.whd = pt.whd;
       seg_gather_sum(g, gs_units(E), s);
-      k_add_rows<<<grid_n(nseg * pt.width), 256, 0, s>>>(seg, idx->t_segrow[j], nseg, pt.width, pt.dst);
-      RELNN_LAUNCHED();
     }
   });
 }

@@ -112,9 +112,19 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
       const bool cut_lo = first && lo_cont;
       const bool cut_hi = last_seg && r1 < a.n && a.sg.seg_of[r1] == g;
       if (on) {
-        const f32x4 v = s - c;
-        float* dst = (cut_lo || cut_hi) ? a.carry + (u * 2 + (cut_lo ? 0 : 1)) * a.ldo + col
-                                        : a.out + (int64_t)g * a.ldo + col;
+        f32x4 v = s - c;
+        const bool cut = cut_lo || cut_hi;
+        float* dst = cut ? a.carry + (u * 2 + (cut_lo ? 0 : 1)) * a.ldo + col
+                         : a.out + (int64_t)(a.out_row ? a.out_row[g] : g) * a.ldo + col;
+        if (a.accumulate && !cut) {               // a segment's row is written by its wave alone
+          if constexpr (VW == 4)
+            v += *reinterpret_cast<const f32x4*>(dst);
+          else {
+            const float2 o = *reinterpret_cast<const float2*>(dst);
+            v[0] += o.x;
+            v[1] += o.y;
+          }
+        }
         if constexpr (VW == 4)
           *reinterpret_cast<f32x4*>(dst) = v;
         else
@@ -212,6 +222,8 @@ void seg_gather_sum(GsArgs a, int64_t nseg_units_cap, hipStream_t s) {
   sk.agg = RELNN_SUM;
   sk.act_post = RELNN_ACT_NONE;
   sk.out = a.out;
+  sk.out_row = a.out_row;
+  sk.accumulate = a.accumulate;
   launch_fixup(a.sg, kGsTM, a.ldo, a.ntiles, a.nunits, sk, a.carry, nullptr, s);
 }
 

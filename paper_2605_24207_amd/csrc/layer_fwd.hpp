@@ -114,8 +114,10 @@ struct GsArgs {
   bool bf16;
   int64_t n;                       // list positions
   Seg sg;                          // segments of the sorted list
-  float* out;                      // [nseg][ldo]
+  float* out;                      // [nseg][ldo], or rows out_row[seg] of it
   int ldo;                         // row stride of out and carry (>= K)
+  const int32_t* out_row;          // optional remap: segment -> row of out
+  bool accumulate;                 // out row += sum (rows distinct) instead of ==
   float* carry;                    // [nunits][2][ldo]
   int64_t ntiles, nunits;
   // routing of a gathered gradient row (one atom, dA of width h; rows[0] is

@@ -945,15 +945,24 @@ __global__ void __launch_bounds__(((kWide ? kHMax / 32 : kHMax / 16) + kDmaWaves
     };
     const bool has_pre = a.sink.pre != nullptr, has_arg = a.sink.argmax != nullptr;
     const bool obf = a.sink.out_bf16;
-    uint32_t plain = ends & ~(next_same ? last_bit : 0u) & ~(cut0 ? first_end : 0u);
-    while (plain) {                                      // finished inside the tile
-      const int r = __builtin_ctz(plain);
-      plain &= plain - 1u;
+    // Runs finished inside the tile.  Each lane row of the column writes the
+    // run ends among its own rows, one per pass, so a store instruction
+    // carries up to four ends (all 64 lanes) instead of one (16 lanes):
+    // one end per instruction spent more than half of the BF16 kernel's
+    // time in the stores.
+    const uint32_t plain = ends & ~(next_same ? last_bit : 0u) & ~(cut0 ? first_end : 0u);
+    uint32_t mine = plain & ((0xFu << (4 * qr)) | (0xF0000u << (4 * qr)));   // rows of this lane row
+    while (__ballot(mine != 0u)) {                       // wave-uniform: every lane runs each pass
+      const bool has = mine != 0u;
+      const int r = has ? __builtin_ctz(mine) : 0;
+      mine &= mine - 1u;
       float v;
       int32_t ag;
       row_val(r, v, ag);
-      const int32_t gid = __builtin_amdgcn_readlane(gcur, r);
-      if (qr == ((r >> 2) & 3)) {
+      // lane r holds the group of row r; read with every lane active (a
+      // permute from an inactive lane does not return its value)
+      const int32_t gid = __shfl(gcur, r);
+      if (has) {
         const int64_t o = (int64_t)gid * h + col;
         if (has_pre) a.sink.pre[o] = v;
         if (kArg && has_arg) a.sink.argmax[o] = ag;
