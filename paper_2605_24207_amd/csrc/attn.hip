@@ -193,7 +193,12 @@ __global__ void k_attn_delta(const float* dout, const float* out, int64_t G, int
 }
 
 // Per tuple and head: A = exp(s - lse) and DS = scale A (dp - D), dp =
-// <dout_g,h, v_h>.  One wave per tuple (lanes over columns, as the forward).
+// <dout_g,h, v_h>.  Lanes over columns, as the forward; a wave takes 64
+// consecutive tuples, reads their row numbers as one vector each, and
+// loads the rows of kTupB tuples before using any of them, so that the
+// random K and V rows of several tuples are in flight at once (one tuple
+// at a time left the kernel waiting on one row fetch after another).
+constexpr int kTupB = 4;
 template <bool kBF16>
 __global__ void __launch_bounds__(256) k_attn_tuple(AttnArgs a, const int32_t* tuple_group, const float* dout,
                                                     const float* lse, const float* D, float* A, float* DS) {
@@ -202,23 +207,39 @@ __global__ void __launch_bounds__(256) k_attn_tuple(AttnArgs a, const int32_t* t
   const bool on_q = cq < a.d, on_v = cv < a.dv;
   const int cqc = on_q ? cq : 0, cvc = on_v ? cv : 0;
   const int hq_lanes = a.hd / 2, hv_lanes = a.hdv / 2;
-  for (int64_t t = (int64_t)blockIdx.x * 4 + threadIdx.x / 64; t < a.E; t += (int64_t)gridDim.x * 4) {
-    const int64_t g = tuple_group[t];
-    const float2 qv = ld2<kBF16>(a.q, a.rq[t], a.d, cqc);
-    const float2 kv = ld2<kBF16>(a.k, a.rk[t], a.d, cqc);
-    const float2 vv = ld2<kBF16>(a.v, a.rv[t], a.dv, cvc);
-    const float2 dv = *reinterpret_cast<const float2*>(dout + g * a.dv + cvc);
-    float p = on_q ? qv.x * kv.x + qv.y * kv.y : 0.0f;
-    for (int off = 1; off < hq_lanes; off <<= 1) p += __shfl_xor(p, off);
-    float dp = on_v ? dv.x * vv.x + dv.y * vv.y : 0.0f;
-    for (int off = 1; off < hv_lanes; off <<= 1) dp += __shfl_xor(dp, off);
-    // lane h * hv_lanes writes head h; its score sits on lane h * hq_lanes
-    const int h = on_v ? cv / a.hdv : 0;
-    const float s = a.scale * __shfl(p, h * hq_lanes);
-    if (on_v && cv % a.hdv == 0) {
-      const float w = expf(s - lse[g * a.heads + h]);
-      A[t * a.heads + h] = w;
-      DS[t * a.heads + h] = a.scale * w * (dp - D[g * a.heads + h]);
+  const int h = on_v ? cv / a.hdv : 0;                 // the head this lane's columns belong to
+  const int64_t stride = (int64_t)gridDim.x * 4 * 64;
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + threadIdx.x / 64) * 64; base < a.E; base += stride) {
+    const int n = (int)min<int64_t>(64, a.E - base);
+    const int64_t e = base + min(lane, n - 1);
+    const int32_t Rq = a.rq[e], Rk = a.rk[e], Rv = a.rv[e], Rg = tuple_group[e];
+    for (int bt = 0; bt < n; bt += kTupB) {
+      float2 qv[kTupB], kv[kTupB], vv[kTupB], dv[kTupB];
+#pragma unroll
+      for (int i = 0; i < kTupB; ++i) {               // clamped: every load is valid
+        const int q = min(bt + i, n - 1);
+        qv[i] = ld2<kBF16>(a.q, __builtin_amdgcn_readlane(Rq, q), a.d, cqc);
+        kv[i] = ld2<kBF16>(a.k, __builtin_amdgcn_readlane(Rk, q), a.d, cqc);
+        vv[i] = ld2<kBF16>(a.v, __builtin_amdgcn_readlane(Rv, q), a.dv, cvc);
+        dv[i] = *reinterpret_cast<const float2*>(dout + (int64_t)__builtin_amdgcn_readlane(Rg, q) * a.dv + cvc);
+      }
+#pragma unroll
+      for (int i = 0; i < kTupB; ++i) {
+        if (bt + i >= n) break;
+        const int64_t t = base + bt + i;
+        const int64_t g = __builtin_amdgcn_readlane(Rg, bt + i);
+        float p = on_q ? qv[i].x * kv[i].x + qv[i].y * kv[i].y : 0.0f;
+        for (int off = 1; off < hq_lanes; off <<= 1) p += __shfl_xor(p, off);
+        float dp = on_v ? dv[i].x * vv[i].x + dv[i].y * vv[i].y : 0.0f;
+        for (int off = 1; off < hv_lanes; off <<= 1) dp += __shfl_xor(dp, off);
+        // lane h * hv_lanes writes head h; its score sits on lane h * hq_lanes
+        const float sc = a.scale * __shfl(p, h * hq_lanes);
+        if (on_v && cv % a.hdv == 0) {
+          const float w = expf(sc - lse[g * a.heads + h]);
+          A[t * a.heads + h] = w;
+          DS[t * a.heads + h] = a.scale * w * (dp - D[g * a.heads + h]);
+        }
+      }
     }
   }
 }
@@ -369,7 +390,7 @@ extern "C" relnn_status relnn_attn_bwd(const relnn_index* idx, const relnn_attn_
     KTimer tm("attn_bwd", s);
     k_attn_delta<<<grid_n(G * A->heads), 256, 0, s>>>(dout, out, G, A->dv, A->heads, D);
     RELNN_LAUNCHED();
-    const unsigned gt = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(E, 4), 1 << 16));
+    const unsigned gt = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(E, 4 * 64), 1 << 16));
     if (a.bf16)
       k_attn_tuple<true><<<gt, 256, 0, s>>>(a, idx->tuple_group, dout, lse, D, Aw, DS);
     else
