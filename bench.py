@@ -568,8 +568,18 @@ def next_legs(D, reps: int):
         dq, dk, dv = (torch.zeros(x.shape, device="cuda") for x in (q, k, v))
         msb = time_calls(lambda: attn_bwd(ix, q, k, v, 8, 0.25, out, lse, dout, dq, dk, dv), max(1, reps // 2)) * 1e3
         byt = ix.E * (3 * d * esz + 16) + ix.G * d * 4                  # q, k, v rows + indices per tuple; out
+        # backward: the weights pass reads q, k, v and dout rows and writes two
+        # weights per head; the three gather-sums read a row, a weight and two
+        # indices per tuple, and add each segment's row once
+        byt_b = (ix.E * (3 * d * esz + d * 4 + 2 * 8 * 4 + 16) + ix.E * (2 * d * esz + d * 4 + 3 * (4 + 8))
+                 + 2 * (ix.G * d * 4 + n_s * d * 4 * 2))
         att[dt] = {"fwd_ms": ms, "fwd_tuples_per_s": ix.E / (ms * 1e-3), "fwd_hbm_gbs_algorithmic": byt / (ms * 1e-3) / 1e9,
-                   "bwd_ms": msb, "fwd_bwd_tuples_per_s": ix.E / ((ms + msb) * 1e-3)}
+                   "bwd_ms": msb, "fwd_bwd_tuples_per_s": ix.E / ((ms + msb) * 1e-3),
+                   "roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
+                                "fwd_achieved": byt / (ms * 1e-3) / 1e9, "fwd_frac": byt / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                "bwd_achieved": byt_b / (msb * 1e-3) / 1e9,
+                                "bwd_frac": byt_b / (msb * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                "fwd_bytes": byt, "bwd_bytes": byt_b}}
         log(f"attention {dt}: fwd {ms:.2f} ms, bwd {msb:.2f} ms")
     res["attention"] = att
     del ix, Qf, Kf, Vf, q, k, v, out, lse, dout, dq, dk, dv
@@ -588,9 +598,13 @@ def next_legs(D, reps: int):
     fn = lambda: union_fwd(U, [L1, L2], "mean", "relu", [[D["U"], D["I"], D["C"]], [D["U"], D["I"]]],
                            [D["W_item"][0], D["W_user"][0]], [D["b_item"][0], D["b_user"][0]], want_pre=False)
     ms = time_calls(fn, reps) * 1e3
+    ufl = b1.E * (2 * 384 * 128 + 2 * 128) + b2.E * (2 * 256 * 128 + 2 * 128)
     res["union"] = {"workload": "Item(i) over two bodies: Item rule on Buys rows 0..10M (K = 384), User body "
                                 "grouped by item on rows 10M..20M (K = 256); MEAN once; FP32",
-                    "ms": ms, "tuples_per_s": (b1.E + b2.E) / (ms * 1e-3), "groups": U.G}
+                    "ms": ms, "tuples_per_s": (b1.E + b2.E) / (ms * 1e-3), "groups": U.G,
+                    "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_TFLOPS["f32"],
+                                 "achieved": ufl / (ms * 1e-3) / 1e12,
+                                 "frac": ufl / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["f32"], "flop": ufl}}
     log(f"union: {ms:.2f} ms")
     del U, b1, b2
     # product transform
@@ -602,7 +616,10 @@ def next_legs(D, reps: int):
                     reps) * 1e3
     byt = ixp.E * (3 * 128 * 4 + 16) + ixp.G * 128 * 4
     res["product"] = {"workload": "Item(i; mean(relu(z_u * z_i * z_c))) over Buys 20M, FP32", "ms": ms,
-                      "tuples_per_s": ixp.E / (ms * 1e-3), "hbm_gbs_algorithmic": byt / (ms * 1e-3) / 1e9}
+                      "tuples_per_s": ixp.E / (ms * 1e-3), "hbm_gbs_algorithmic": byt / (ms * 1e-3) / 1e9,
+                      "roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
+                                   "achieved": byt / (ms * 1e-3) / 1e9,
+                                   "frac": byt / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "bytes": byt}}
     log(f"product: {ms:.2f} ms")
     # triangle rule
     rule = relgen.triangle_rule(n_graphs=20_000, n_nodes=40, avg_degree=6, d=64, h=64)
@@ -619,9 +636,13 @@ def next_legs(D, reps: int):
     wst = workspace(ixt, Lt)
     outt = torch.empty(ixt.G, 64, device="cuda")
     ms = time_calls(lambda: layer_fwd(ixt, Lt, [z, z, z], Wt, bt, want_pre=False, ws=wst, out=outt), reps) * 1e3
+    tfl = ixt.E * (2 * 192 * 64 + 2 * 64)
     res["triangle"] = {"workload": "C3(n; sum(Lin(h_n (+) h_v (+) h_w))) on 20k graphs x 40 nodes, 4.8M directed "
                                    "edges, d = h = 64, FP32", "matches": ixt.E, "index_build_s": build,
-                       "layer_ms": ms, "tuples_per_s": ixt.E / (ms * 1e-3)}
+                       "layer_ms": ms, "tuples_per_s": ixt.E / (ms * 1e-3),
+                       "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_TFLOPS["f32"],
+                                    "achieved": tfl / (ms * 1e-3) / 1e12,
+                                    "frac": tfl / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["f32"], "flop": tfl}}
     log(f"triangle: {ixt.E} matches, build {build:.2f} s, layer {ms:.2f} ms")
     return res
 
