@@ -244,6 +244,110 @@ __global__ void __launch_bounds__(256) k_attn_tuple(AttnArgs a, const int32_t* t
   }
 }
 
+// When Q's key is the group column (one Q row per group, distinct across
+// groups, as in the HGT head), the weights pass also forms dQ: dQ_g = sum
+// over the group's tuples of DS_tau,h k_tau (the columns of head h), in
+// canonical order with Kahan compensation, added into the group's Q row
+// once; groups cut by range edges leave partials for the fix-up.  This
+// saves the gather-sum over Q's rows, which read every K row a second
+// time.  One wave per contiguous tuple range, as the forward.
+// compensated add; the compensation is dropped once the sum is not finite
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+  const float y = x - c;
+  const float t = s + y;
+  c = __builtin_isfinite(t) ? (t - s) - y : 0.0f;
+  s = t;
+}
+
+template <bool kBF16>
+__global__ void __launch_bounds__(kAtWaves * 64) k_attn_tuple_q(AttnArgs a, const float* dout, const float* lse,
+                                                               const float* D, float* A, float* DS,
+                                                               const int32_t* qrow, float* dq, float* carry) {
+  const int lane = threadIdx.x % 64;
+  const int64_t u = (int64_t)blockIdx.x * kAtWaves + threadIdx.x / 64;
+  if (u >= a.nunits) return;
+  const int64_t r0 = ((a.ntiles * u) / a.nunits) * kAtTM;
+  const int64_t r1 = min<int64_t>(((a.ntiles * (u + 1)) / a.nunits) * kAtTM, a.E);
+  if (r0 >= r1) return;
+  const int cq = 2 * lane, cv = 2 * lane;
+  const bool on_q = cq < a.d, on_v = cv < a.dv;
+  const int cqc = on_q ? cq : 0, cvc = on_v ? cv : 0;
+  const int hq_lanes = a.hd / 2, hv_lanes = a.hdv / 2;
+  const int h = on_v ? cv / a.hdv : 0;                    // head of this lane's value columns
+  const int hq = cqc / a.hd;                              // head of this lane's q / k columns
+  const bool head_lead = on_v && cv % a.hdv == 0;
+
+  float s0 = 0.f, s1 = 0.f, c0 = 0.f, c1 = 0.f;           // dQ of the open group, this lane's columns
+  int32_t g = a.sg.seg_of[r0];
+  const bool lo_cont = r0 > 0 && a.sg.seg_of[r0 - 1] == g;
+  bool first = true;
+  auto flush = [&](bool last_seg) {
+    const bool cut_lo = first && lo_cont;
+    const bool cut_hi = last_seg && r1 < a.E && a.sg.seg_of[r1] == g;
+    if (on_q) {
+      const float v0 = s0 - c0, v1 = s1 - c1;
+      if (cut_lo || cut_hi) {
+        *reinterpret_cast<float2*>(carry + (u * 2 + (cut_lo ? 0 : 1)) * a.d + cq) = make_float2(v0, v1);
+      } else {                                            // the group's row is written by this wave alone
+        float2* dst = reinterpret_cast<float2*>(dq + (int64_t)qrow[g] * a.d + cq);
+        const float2 o = *dst;
+        *dst = make_float2(o.x + v0, o.y + v1);
+      }
+    }
+    first = false;
+    s0 = s1 = c0 = c1 = 0.f;
+  };
+  for (int64_t base = r0; base < r1; base += 64) {
+    const int n = (int)min<int64_t>(64, r1 - base);
+    const int64_t e = base + min(lane, n - 1);
+    const int32_t gl = a.sg.seg_of[e];
+    const int32_t Rq = a.rq[e], Rk = a.rk[e], Rv = a.rv[e];
+    for (int bt = 0; bt < n; bt += kTupB) {
+      float2 qv[kTupB], kv[kTupB], vv[kTupB], dv[kTupB];
+#pragma unroll
+      for (int i = 0; i < kTupB; ++i) {                  // clamped: every load is valid
+        const int q = min(bt + i, n - 1);
+        qv[i] = ld2<kBF16>(a.q, __builtin_amdgcn_readlane(Rq, q), a.d, cqc);
+        kv[i] = ld2<kBF16>(a.k, __builtin_amdgcn_readlane(Rk, q), a.d, cqc);
+        vv[i] = ld2<kBF16>(a.v, __builtin_amdgcn_readlane(Rv, q), a.dv, cvc);
+        dv[i] = *reinterpret_cast<const float2*>(dout + (int64_t)__builtin_amdgcn_readlane(gl, q) * a.dv + cvc);
+      }
+#pragma unroll
+      for (int i = 0; i < kTupB; ++i) {
+        const int q = bt + i;
+        if (q >= n) break;
+        const int32_t gq = __builtin_amdgcn_readlane(gl, q);
+        if (gq != g) {                                    // a group ends
+          flush(false);
+          g = gq;
+        }
+        const int64_t t = base + q;
+        float p = on_q ? qv[i].x * kv[i].x + qv[i].y * kv[i].y : 0.0f;
+        for (int off = 1; off < hq_lanes; off <<= 1) p += __shfl_xor(p, off);
+        float dp = on_v ? dv[i].x * vv[i].x + dv[i].y * vv[i].y : 0.0f;
+        for (int off = 1; off < hv_lanes; off <<= 1) dp += __shfl_xor(dp, off);
+        const float sc = a.scale * __shfl(p, h * hq_lanes);
+        const float w = expf(sc - lse[(int64_t)g * a.heads + h]);
+        const float ds = a.scale * w * (dp - D[(int64_t)g * a.heads + h]);
+        if (head_lead) {
+          A[t * a.heads + h] = w;
+          DS[t * a.heads + h] = ds;
+        }
+        const float dsq = __shfl(ds, hq * hv_lanes);     // DS of the head of this lane's k columns
+        kahan_add(s0, c0, dsq * kv[i].x);
+        kahan_add(s1, c1, dsq * kv[i].y);
+      }
+    }
+  }
+  flush(true);
+}
+
+// qrow[g] = row of atom 0 joined to the first tuple of group g
+__global__ void k_group_rows(const int32_t* offsets, const int32_t* rq, int64_t G, int32_t* qrow) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x)
+    qrow[g] = rq[offsets[g]];
+}
+
 // out[i] = y[ord[i]]
 __global__ void k_gather_rows_idx(const int32_t* ord, const int32_t* y, int64_t n, int32_t* out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -290,7 +394,7 @@ AttnArgs make_args(const relnn_index* idx, const relnn_attn_desc* A, const void*
 }
 
 struct AttnPlan {
-  size_t carry = 0, lse = 0, D = 0, A = 0, DS = 0, yrow = 0, gcarry = 0, total = 0;
+  size_t carry = 0, lse = 0, D = 0, A = 0, DS = 0, yrow = 0, gcarry = 0, qrow = 0, qcarry = 0, total = 0;
 };
 
 AttnPlan plan_attn(const relnn_index* idx, const relnn_attn_desc* A, bool bwd) {
@@ -311,6 +415,8 @@ AttnPlan plan_attn(const relnn_index* idx, const relnn_attn_desc* A, bool bwd) {
     p.DS = take((size_t)E * A->heads * 4);
     p.yrow = take((size_t)E * 4);
     p.gcarry = take((size_t)gs_units(E) * 2 * w * 4);
+    p.qrow = take((size_t)G * 4);
+    p.qcarry = take((size_t)attn_units(idx->E) * 2 * A->d * 4);
   }
   p.total = off;
   return p;
@@ -390,12 +496,36 @@ extern "C" relnn_status relnn_attn_bwd(const relnn_index* idx, const relnn_attn_
     KTimer tm("attn_bwd", s);
     k_attn_delta<<<grid_n(G * A->heads), 256, 0, s>>>(dout, out, G, A->dv, A->heads, D);
     RELNN_LAUNCHED();
-    const unsigned gt = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(E, 4 * 64), 1 << 16));
-    if (a.bf16)
-      k_attn_tuple<true><<<gt, 256, 0, s>>>(a, idx->tuple_group, dout, lse, D, Aw, DS);
-    else
-      k_attn_tuple<false><<<gt, 256, 0, s>>>(a, idx->tuple_group, dout, lse, D, Aw, DS);
-    RELNN_LAUNCHED();
+    // Q keyed by the group column: dQ is formed by the weights pass
+    const bool q_fused = idx->atom_gk[0];
+    if (q_fused) {
+      int32_t* qrow = reinterpret_cast<int32_t*>(w + P.qrow);
+      float* qcarry = reinterpret_cast<float*>(w + P.qcarry);
+      k_group_rows<<<grid_n(G), 256, 0, s>>>(idx->offsets, a.rq, G, qrow);
+      RELNN_LAUNCHED();
+      a.ntiles = cdiv(E, kAtTM);
+      a.nunits = attn_units(E);
+      const unsigned gu = (unsigned)cdiv(a.nunits, kAtWaves);
+      if (a.bf16)
+        k_attn_tuple_q<true><<<gu, kAtWaves * 64, 0, s>>>(a, dout, lse, D, Aw, DS, qrow, dq, qcarry);
+      else
+        k_attn_tuple_q<false><<<gu, kAtWaves * 64, 0, s>>>(a, dout, lse, D, Aw, DS, qrow, dq, qcarry);
+      RELNN_LAUNCHED();
+      Sink sk{};
+      sk.agg = RELNN_SUM;
+      sk.act_post = RELNN_ACT_NONE;
+      sk.out = dq;
+      sk.out_row = qrow;
+      sk.accumulate = true;
+      launch_fixup(a.sg, kAtTM, A->d, a.ntiles, a.nunits, sk, qcarry, nullptr, s);
+    } else {
+      const unsigned gt = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(E, 4 * 64), 1 << 16));
+      if (a.bf16)
+        k_attn_tuple<true><<<gt, 256, 0, s>>>(a, idx->tuple_group, dout, lse, D, Aw, DS);
+      else
+        k_attn_tuple<false><<<gt, 256, 0, s>>>(a, idx->tuple_group, dout, lse, D, Aw, DS);
+      RELNN_LAUNCHED();
+    }
     // dX_j[r] += sum over the tuples joined to row r of atom j of the
     // weighted rows: dQ <- scale ds K rows, dK <- scale ds Q rows, dV <- a dout rows
     struct Part {
@@ -415,6 +545,7 @@ extern "C" relnn_status relnn_attn_bwd(const relnn_index* idx, const relnn_attn_
     int32_t* yrow_t = reinterpret_cast<int32_t*>(w + P.yrow);
     for (const Part& pt : parts) {
       const int j = pt.j;
+      if (j == 0 && q_fused) continue;
       const int64_t nseg = idx->t_nseg[j];
       if (nseg == 0) continue;
       k_gather_rows_idx<<<grid_n(E), 256, 0, s>>>(idx->t_pos[j], pt.yrow, E, yrow_t);

@@ -143,6 +143,26 @@ def test_attention_keys_and_values_from_one_relation():
     check(rule, Q, K, V, 4, 0.3, "f32", same_kv=True)
 
 
+def test_attention_query_not_keyed_by_the_group():
+    """Q joined on its own column (not the group key): a Q row meets several
+    groups, so dQ goes through the gather-sum over Q's rows instead of the
+    weights pass."""
+    rng = np.random.default_rng(12)
+    n_t, n_s, n_q, m, d = 2000, 3000, 500, 80_000, 32
+    t = rng.integers(0, n_t, m).astype(np.int32)
+    s = rng.integers(0, n_s, m).astype(np.int32)
+    x = rng.integers(0, n_q, m).astype(np.int32)
+    Q = rng.standard_normal((n_q, d)).astype(np.float32)
+    K = rng.standard_normal((n_s, d)).astype(np.float32)
+    V = rng.standard_normal((n_s, d)).astype(np.float32)
+    import relgen
+
+    rule = relgen.Rule(cols=[t, s, x], atoms=[relgen.Atom(2, Q), relgen.Atom(1, K), relgen.Atom(1, V)],
+                       group_col=0, W=np.zeros((1, 1), np.float32), b=np.zeros(1, np.float32))
+    for dtype in ("f32", "bf16"):
+        check(rule, Q, K, V, 4, 0.35, dtype)
+
+
 def test_attention_deterministic():
     rule, Q, K, V = workload(5, m=200_000, hot=100_000)
     a = run(rule, Q, K, V, 2, 0.5, "f32")
