@@ -54,7 +54,7 @@ typedef enum {
   RELNN_E_HIP = 5,          /* a HIP runtime call failed */
   RELNN_E_BUSY = 6,         /* server: no slot or budget free right now */
   RELNN_E_NOT_READY = 7,    /* server: request not finished yet */
-  RELNN_E_UNSUPPORTED = 8   /* valid, but a shape this build does not run */
+  RELNN_E_UNSUPPORTED = 8   /* valid, but a shape the library does not run */
 } relnn_status;
 
 typedef enum { RELNN_F32 = 0, RELNN_BF16 = 1 } relnn_dtype;
