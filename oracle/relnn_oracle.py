@@ -323,6 +323,49 @@ def layer_bwd(idx: Index, embs, W, b, pre, argmax, dout, agg="sum",
     return demb, dW, db
 
 
+def product_bwd(idx: Index, embs, pre, argmax, dout, agg="sum", act_pre="none", act_post="none",
+                pre_mask=None):
+    """Gradients of sum(out * dout) through the product transform of
+    ``layer_fwd(tf="product")`` with respect to every atom's embedding (the
+    transform has no weights).  With y = act_pre(z_1 * ... * z_k) per tuple
+    and dY the gradient reaching y (routed as in ``layer_bwd``), the
+    gradient of atom j's row is dY * act_pre'(z_1 * ... * z_k) times the
+    product of the other atoms' rows, summed over the tuples that join it.
+    ``pre_mask`` ([E, h] booleans) gives act_pre' taken in another
+    precision.  Returns demb (one entry per atom, shaped as embs[j])."""
+    dA = np.asarray(dout, np.float64) * _act_grad(act_post, np.asarray(pre, np.float64))
+    g = idx.tuple_group
+    cnt = np.diff(idx.offsets).astype(np.float64)
+    if agg == "sum":
+        dY = dA[g]
+    elif agg == "mean":
+        dY = dA[g] / cnt[g][:, None]
+    elif agg == "max":
+        pos = np.arange(idx.E)[:, None]
+        dY = np.where(np.asarray(argmax)[g] == pos, dA[g], 0.0)
+    else:
+        raise ValueError(agg)
+    Z = [np.asarray(e, np.float64)[r] for e, r in zip(embs, idx.rows)]
+    if act_pre != "none":
+        if pre_mask is not None:
+            dY = dY * np.asarray(pre_mask, np.float64)
+        else:
+            full = Z[0].copy()
+            for z in Z[1:]:
+                full = full * z
+            dY = dY * _act_grad(act_pre, full)
+    demb = []
+    for j, (e, r) in enumerate(zip(embs, idx.rows)):
+        others = np.ones_like(dY)
+        for i, z in enumerate(Z):
+            if i != j:
+                others = others * z
+        acc = np.zeros(np.asarray(e).shape, np.float64)
+        np.add.at(acc, r, dY * others)
+        demb.append(acc)
+    return demb
+
+
 # ---------------------------------------------------------------------------
 # k-ary projected union (Section 2.2) and union rules (Section 3.1)
 # ---------------------------------------------------------------------------

@@ -367,3 +367,41 @@ def test_planted_product_mistake_is_caught(name, monkeypatch):
             caught = True
             break
     assert caught, f"no pin caught the planted product mistake {name}"
+
+
+PROD_BWD_PINS = [lambda: prod_pins.test_product_backward_finite_differences("sum", "none"),
+                 lambda: prod_pins.test_product_backward_finite_differences("mean", "relu"),
+                 lambda: prod_pins.test_product_backward_finite_differences("max", "relu"),
+                 prod_pins.test_product_backward_closed_form]
+
+PROD_BWD_MUTANTS = {
+    "product_bwd_includes_own_row": [("            if i != j:\n", "            if True:\n")],
+    "product_bwd_mask_ignored": [("            dY = dY * _act_grad(act_pre, full)\n", "            dY = dY\n")],
+    "product_bwd_mean_undivided": [("        dY = dA[g] / cnt[g][:, None]\n", "        dY = dA[g]\n")],
+    "product_bwd_max_unrouted": [("        dY = np.where(np.asarray(argmax)[g] == pos, dA[g], 0.0)\n",
+                                  "        dY = dA[g]\n")],
+}
+
+
+@pytest.mark.parametrize("name", sorted(PROD_BWD_MUTANTS))
+def test_planted_product_backward_mistake_is_caught(name, monkeypatch):
+    src = inspect.getsource(orc.product_bwd)
+    for old, new in PROD_BWD_MUTANTS[name]:
+        assert src.count(old) == 1, f"mutant {name} no longer matches the oracle's source"
+        src = src.replace(old, new)
+    ns = dict(orc.__dict__)
+    exec(compile(src, "<product_bwd mutant>", "exec"), ns)
+    monkeypatch.setattr(orc, "product_bwd", ns["product_bwd"])
+    caught = False
+    for pin in PROD_BWD_PINS:
+        try:
+            pin()
+        except Exception:
+            caught = True
+            break
+    assert caught, f"no pin caught the planted product-backward mistake {name}"
+
+
+def test_unmutated_product_backward_passes_every_pin():
+    for pin in PROD_BWD_PINS:
+        pin()
