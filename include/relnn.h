@@ -217,9 +217,9 @@ relnn_status relnn_index_free(relnn_index* idx);
                               (Section 1's Score rule q*k, Attention's a*v,
                               Section 5.4's gated mean z_e*z_w); every d_j
                               must equal h; W and b are not read (may be
-                              NULL); forward only (relnn_layer_bwd:
-                              RELNN_E_UNSUPPORTED); not with RELNN_PLAIN or
-                              RELNN_PUSHDOWN */
+                              NULL); relnn_layer_bwd gives the embedding
+                              gradients only (W, b, dW, db not used; h even);
+                              not with RELNN_PLAIN or RELNN_PUSHDOWN */
 
 typedef struct {
   int32_t k;               /* body atoms, equal to the index's */

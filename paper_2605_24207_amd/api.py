@@ -395,19 +395,23 @@ def static_scratch_bytes() -> int:
 
 def layer_bwd(index: Index, layer: Layer, embs: Sequence[torch.Tensor], W: torch.Tensor,
               b: Optional[torch.Tensor], pre: Optional[torch.Tensor], argmax: Optional[torch.Tensor],
-              dout: torch.Tensor, demb: Sequence[torch.Tensor], dW: torch.Tensor,
+              dout: torch.Tensor, demb: Sequence[torch.Tensor], dW: Optional[torch.Tensor],
               db: Optional[torch.Tensor] = None, dw_accum: bool = False,
               ws: Optional[torch.Tensor] = None, stream=None):
-    """relnn_layer_bwd.  demb entries are accumulated (+=) and may alias."""
+    """relnn_layer_bwd.  demb entries are accumulated (+=) and may alias.
+    The product transform has no weights: W, b, dW and db are ignored."""
     _check_embs(layer, embs)
     G, h = index.G, layer.h
+    if layer.transform == "product":
+        W = b = dW = db = None
 
     def f32(t, shape, what):
         if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
             raise TypeError(f"{what} must be a contiguous float32 CUDA tensor of shape {shape}")
 
     f32(dout, (G, h), "dout")
-    f32(dW, (layer.K, h), "dW")
+    if dW is not None:
+        f32(dW, (layer.K, h), "dW")
     if db is not None:
         f32(db, (h,), "db")
     if pre is not None:
@@ -460,6 +464,9 @@ class RelLayerFn(torch.autograd.Function):
         demb = [bufs[e.data_ptr()] for e in embs]
         # the ABI takes an FP32 gradient (a bf16 output receives a bf16 one)
         dout = dout.to(torch.float32).contiguous()
+        if layer.transform == "product":                 # no weights
+            layer_bwd(index, layer, embs, None, None, pre, am, dout, demb, None)
+            return (None, None, None, None) + tuple(grads)
         dW = torch.empty(layer.K, layer.h, dtype=torch.float32, device=dev)
         db = torch.empty(layer.h, dtype=torch.float32, device=dev) if b is not None else None
         layer_bwd(index, layer, embs, W, b, pre, am, dout, demb, dW, db)

@@ -85,7 +85,7 @@ unsigned grid_for(int64_t n) {
 struct BwdPlan {
   FwdPlan F;
   int K = 0;
-  size_t ws_mask = 0, ws_fwsw = 0, ws_dA = 0, ws_own = 0, ws_part = 0, total = 0;
+  size_t ws_mask = 0, ws_fwsw = 0, ws_dA = 0, ws_own = 0, ws_part = 0, ws_prod = 0, total = 0;
   int kv = 0;                // per-tuple dW: atoms 0 .. kv-1 (MAX: the others are keyed by the group column)
   bool xs_dw = false;        // dW through the per-group sums (SUM / MEAN, affine)
   LinBwdPlan lin;
@@ -96,6 +96,17 @@ BwdPlan plan_bwd(const relnn_index* idx, const relnn_layer_desc* L, const FwdPla
   p.F = F;
   p.K = F.K;
   const int64_t E = idx->E;
+  if (L->flags & RELNN_TF_PRODUCT) {                     // dA, maximiser bits, the per-atom passes
+    size_t off = 0;
+    p.ws_dA = off;
+    off += round_up(std::max<int64_t>(idx->G, 1) * L->h * 4, 256);
+    p.ws_own = off;
+    if (L->agg == RELNN_MAX) off += round_up(std::max<int64_t>(E, 1) * cdiv(L->h, 32) * 4, 256);
+    p.ws_prod = off;
+    off += prod_bwd_ws_bytes(idx, L);
+    p.total = off;
+    return p;
+  }
   p.xs_dw = L->act_pre == RELNN_ACT_NONE && L->agg != RELNN_MAX;
   size_t off = 0;
   p.ws_mask = off;                                       // act_pre: mask bits [E][ceil(h / 32)]
@@ -144,10 +155,10 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
     FwdPlan F = checked_plan(idx, L);
     RELNN_REQUIRE(idx->has_bwd, RELNN_E_INVALID, "the index was built without RELNN_IDX_BWD");
     RELNN_REQUIRE(!(L->flags & RELNN_OUT_BF16), RELNN_E_INVALID, "RELNN_OUT_BF16 is a forward-only flag");
-    RELNN_REQUIRE(!(L->flags & RELNN_TF_PRODUCT), RELNN_E_UNSUPPORTED, "no backward for the product transform");
+    const bool prod = (L->flags & RELNN_TF_PRODUCT) != 0;
     const BwdPlan P = plan_bwd(idx, L, F);
-    RELNN_REQUIRE(emb != nullptr && W != nullptr && dW != nullptr && demb != nullptr, RELNN_E_INVALID,
-                  "emb, W, dW and demb are required");
+    RELNN_REQUIRE(emb != nullptr && demb != nullptr && (prod || (W != nullptr && dW != nullptr)), RELNN_E_INVALID,
+                  "emb, W, dW and demb are required (W and dW not for the product transform)");
     RELNN_REQUIRE(dout != nullptr || idx->G == 0, RELNN_E_INVALID, "dout is NULL");
     RELNN_REQUIRE(L->act_post == RELNN_ACT_NONE || pre != nullptr || idx->G == 0, RELNN_E_INVALID,
                   "pre is required when act_post is not NONE");
@@ -157,7 +168,7 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
       RELNN_REQUIRE(emb[j] != nullptr || idx->n_rows[j] == 0, RELNN_E_INVALID, "emb[%d] is NULL", j);
       RELNN_REQUIRE(demb[j] != nullptr || idx->n_rows[j] == 0, RELNN_E_INVALID, "demb[%d] is NULL", j);
       RELNN_REQUIRE(((uintptr_t)emb[j] & 15) == 0, RELNN_E_UNSUPPORTED, "emb[%d] is not 16-byte aligned", j);
-      RELNN_REQUIRE(L->d[j] % 16 == 0, RELNN_E_UNSUPPORTED, "backward needs d[%d] %% 16 == 0", j);
+      RELNN_REQUIRE(prod || L->d[j] % 16 == 0, RELNN_E_UNSUPPORTED, "backward needs d[%d] %% 16 == 0", j);
     }
     RELNN_REQUIRE(ws != nullptr && ws_bytes >= P.total, RELNN_E_INVALID,
                   "workspace of %zu bytes given, %zu needed", ws_bytes, P.total);
@@ -168,6 +179,21 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
     const int h = L->h;
     const int64_t E = idx->E;
     const bool accum = (L->flags & RELNN_DW_ACCUM) != 0;
+    if (prod) {                                  // no weights: the embedding gradients only
+      if (E == 0) return;
+      float* dA = reinterpret_cast<float*>(w + P.ws_dA);
+      k_route_prep<<<grid_for(idx->G * h), 256, 0, s>>>(dout, pre, idx->offsets, idx->G, h, L->agg, L->act_post, dA);
+      RELNN_LAUNCHED();
+      const int nw = (int)cdiv(h, 32);
+      uint32_t* own = nullptr;
+      if (L->agg == RELNN_MAX) {
+        own = reinterpret_cast<uint32_t*>(w + P.ws_own);
+        k_own_bits<<<grid_for(E * nw), 256, 0, s>>>(argmax, idx->tuple_group, E, h, nw, nullptr, own);
+        RELNN_LAUNCHED();
+      }
+      prod_bwd(idx, L, emb, dA, own, nw, demb, w + P.ws_prod, s);
+      return;
+    }
     if (E == 0) {
       if (!accum) {
         k_fill_f32<<<grid_for((int64_t)P.K * h), 256, 0, s>>>(dW, (int64_t)P.K * h, 0.0f);

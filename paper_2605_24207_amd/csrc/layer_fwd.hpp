@@ -154,6 +154,12 @@ void lin_bwd_dx(const relnn_index* idx, const relnn_layer_desc* L, const LinBwdP
                 const float* dA, const uint32_t* route, int route_w, bool per_tuple, float* const* demb, char* ws,
                 hipStream_t s);
 size_t bwd_workspace(const relnn_index* idx, const relnn_layer_desc* L, const FwdPlan& P);
+// Backward of the product transform (prod_bwd.hip): dz_j of every atom from
+// the routed gradient dA [G][h] (MEAN divided) and, for MAX, the maximiser
+// bits; act_pre' is taken from the full product inside the pass.
+size_t prod_bwd_ws_bytes(const relnn_index* idx, const relnn_layer_desc* L);
+void prod_bwd(const relnn_index* idx, const relnn_layer_desc* L, const void* const* emb, const float* dA,
+              const uint32_t* own, int own_w, float* const* demb, char* ws, hipStream_t s);
 // dW rows [d][h] of atom j when its FK is the group column, for MAX without
 // act_pre: sum_g x_j(g)^T dA_g over the groups (part: gk_dw_ws_floats(G, d,
 // h) FP32 workspace).

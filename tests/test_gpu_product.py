@@ -2,13 +2,13 @@
 ABI): tau = z_1 * ... * z_k elementwise, aggregated with SUM, MEAN or MAX
 (with maximiser positions), FP32 within 1e-5 and BF16 within 2e-2 of the
 FP64 oracle; two and three atoms; ReLU per tuple; a group spanning many
-waves' ranges; the backward is refused."""
+waves' ranges; the backward (embedding gradients) against the oracle's."""
 import numpy as np
 import pytest
 
 import relgen
 from oracle import relnn_oracle as orc
-from tests.helpers import distinct_embs, gpu_index, rel_rows, to_dev
+from tests.helpers import distinct_embs, gpu_index, oracle_inputs, rel_rows, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -64,15 +64,123 @@ def test_product_three_atoms_relu_and_hot_group():
     assert np.diff(gi.export()["offsets"].cpu().numpy()).max() > 10_000
 
 
-def test_product_backward_is_refused():
+def run_bwd(rule, dtype, dout_seed=3):
+    """Forward, then relnn_layer_bwd with no weights; one gradient buffer per
+    distinct relation (a self-join adds both roles into it)."""
     import torch
 
-    from paper_2605_24207_amd import RelnnError, layer_bwd
+    from paper_2605_24207_amd import layer_bwd
 
-    rule = relgen.node_edge(seed=41, d=32, h=32)
-    gi, lay, out, pre, am = run(rule, "f32")
-    z = distinct_embs(rule)[0]
-    with pytest.raises(RelnnError, match="UNSUPPORTED"):
-        layer_bwd(gi, lay, [z, z], to_dev(np.zeros((64, 32), np.float32)), None, torch.from_numpy(pre).cuda(), None,
-                  torch.zeros(gi.G, 32, device="cuda"), [torch.zeros_like(z)] * 2,
-                  torch.zeros(64, 32, device="cuda"))
+    gi, lay, out, pre, am = run(rule, dtype)
+    embs = distinct_embs(rule, dtype)
+    dout = np.random.default_rng(dout_seed).standard_normal((gi.G, rule.h)).astype(np.float32)
+    uniq, demb = {}, []
+    for e in embs:
+        if e.data_ptr() not in uniq:
+            uniq[e.data_ptr()] = torch.zeros(e.shape, dtype=torch.float32, device="cuda")
+        demb.append(uniq[e.data_ptr()])
+    layer_bwd(gi, lay, embs, None, None, torch.from_numpy(pre).cuda(),
+              None if am is None else torch.from_numpy(am).cuda(), to_dev(dout), demb, None)
+    torch.cuda.synchronize()
+    return dout.astype(np.float64), [d.cpu().numpy() for d in demb], pre, am
+
+
+def oracle_grad(rule, dtype, dout, pre, am):
+    """Oracle gradient per atom (summed over atoms sharing a relation) and
+    the matching magnitude scale: the same gradient with |z| and |dout| and
+    the per-tuple ReLU mask of the signed product, i.e. the sum of the
+    magnitudes of the terms of each row.  The forward's decisions (pre for
+    ReLU after the aggregate, the MAX maximisers) are the kernel's."""
+    idx = orc.build_index(rule)
+    embs = oracle_inputs(rule, dtype)[0]
+    demb = orc.product_bwd(idx, embs, pre, am, dout, rule.agg, rule.act_pre, rule.act_post)
+    mask = orc.product(idx, embs, slice(None), "none") > 0 if rule.act_pre == "relu" else None
+    mag = orc.product_bwd(idx, [np.abs(e) for e in embs], pre, am, np.abs(dout), rule.agg, rule.act_pre,
+                          rule.act_post, pre_mask=mask)
+    tot, tmag = {}, {}
+    for a, g, m in zip(rule.atoms, demb, mag):
+        tot[id(a.emb)] = tot.get(id(a.emb), 0) + g
+        tmag[id(a.emb)] = tmag.get(id(a.emb), 0) + m
+    return [tot[id(a.emb)] for a in rule.atoms], [tmag[id(a.emb)] for a in rule.atoms]
+
+
+def check_bwd(rule, dtype):
+    dout, demb, pre, am = run_bwd(rule, dtype)
+    # the kernel's arithmetic is FP32 on the layer's stored values: against
+    # the oracle on those values (bf16-rounded for a BF16 layer) it is held
+    # to the FP32 bound ...
+    ref, mag = oracle_grad(rule, dtype, dout, pre, am)
+    for g, r, m in zip(demb, ref, mag):
+        assert rel_rows(g, r, scale_ref=m).max() <= TOL["f32"]
+    # ... and against the FP32 master values to the layer's own bound
+    if dtype == "bf16":
+        ref, mag = oracle_grad(rule, "f32", dout, pre, am)
+        for g, r, m in zip(demb, ref, mag):
+            assert rel_rows(g, r, scale_ref=m).max() <= TOL["bf16"]
+    # rows that no tuple joins get no gradient
+    idx = orc.build_index(rule)
+    for a, g, r in zip(rule.atoms, demb, idx.rows):
+        joined = np.zeros(len(g), bool)
+        for b, rr in zip(rule.atoms, idx.rows):
+            if b.emb is a.emb:
+                joined[rr] = True
+        assert not np.any(g[~joined])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("agg", ["sum", "mean", "max"])
+@pytest.mark.parametrize("acts", [("none", "relu"), ("relu", "none")])
+def test_product_backward_self_join(agg, dtype, acts):
+    """Node(t; agg(act_pre(z_s * z_t))) over an edge relation: both atoms
+    read one relation, so its gradient sums both roles."""
+    rule = relgen.node_edge(seed=42, n_nodes=3000, n_edges=80_000, d=64, h=64, agg=agg, act_pre=acts[0],
+                            act_post=acts[1])
+    check_bwd(rule, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_product_backward_three_atoms_hot_group(dtype):
+    """Item(i; mean(relu(z_u * z_i * z_c))) over Buys with a hot item: the
+    item's gradient row sums tens of thousands of tuples across many waves'
+    ranges (carries and the fix-up)."""
+    g = relgen.er_graph(seed=9, n_user=20_000, n_item=5000, n_cat=40, n_buys=300_000, n_layers=1)
+    rule = relgen.er_item_rule(g)
+    rule.agg, rule.act_pre = "mean", "relu"
+    rule.W = np.zeros((3 * 128, 128), np.float32)
+    check_bwd(rule, dtype)
+
+
+@pytest.mark.parametrize("h", [16, 48, 144])
+def test_product_backward_ragged_width(h):
+    """Widths that leave lanes idle in the last 128-column pass (rows stay
+    multiples of 16, as every layer requires)."""
+    rule = relgen.node_edge(seed=43, n_nodes=500, n_edges=6000, d=h, h=h, agg="max", act_post="none")
+    check_bwd(rule, "f32")
+
+
+@pytest.mark.parametrize("case", ["empty", "one_tuple", "one_group"])
+def test_product_backward_degenerate(case):
+    """No tuple (the gradients stay zero), one tuple, and one group holding
+    every tuple."""
+    n_edges = {"empty": 0, "one_tuple": 1, "one_group": 20_000}[case]
+    rule = relgen.node_edge(seed=44, n_nodes=300, n_edges=n_edges, d=32, h=32, agg="mean")
+    if case == "one_group":
+        rule.cols[1][:] = 5
+    check_bwd(rule, "f32")
+
+
+def test_product_autograd_matches_explicit_call():
+    """RelLayerFn over a product layer returns no weight gradients and the
+    embedding gradient of an explicit relnn_layer_bwd call."""
+    import torch
+
+    from paper_2605_24207_amd import RelLayerFn
+
+    rule = relgen.node_edge(seed=45, n_nodes=800, n_edges=9000, d=32, h=32, agg="sum", act_post="relu")
+    gi, lay, _, _, _ = run(rule, "f32")
+    z = to_dev(rule.atoms[0].emb).requires_grad_(True)
+    out = RelLayerFn.apply(gi, lay, None, None, z, z)
+    dout = np.random.default_rng(3).standard_normal((gi.G, rule.h)).astype(np.float32)
+    out.backward(to_dev(dout))
+    ref, mag = oracle_grad(rule, "f32", dout.astype(np.float64), out.detach().cpu().numpy(), None)
+    assert rel_rows(z.grad.cpu().numpy(), ref[0], scale_ref=mag[0]).max() <= TOL["f32"]
