@@ -414,6 +414,70 @@ def union_fwd(branches, agg="sum", act_post="none", W_post=None, b_post=None):
     return np.array(keys, np.int64), _act(act_post, v), pre, arg
 
 
+def union_bwd(branches, pre, arg, dout, agg="sum", act_post="none", W_post=None, b_post=None, pre_masks=None):
+    """Gradients of sum(out * dout) through ``union_fwd`` (chain rule, from
+    the output back to every branch's weights and embeddings).
+
+    With v = pre the aggregate of key t, u = v W_post + b_post (u = v
+    without W_post) and out = act_post(u): dU = dout * act_post'(u),
+    dW_post = v^T dU, db_post = sum_t dU[t], dV = dU W_post^T.  A tuple of
+    branch i at canonical position p with key t then receives dV[t] (SUM),
+    dV[t] / |B_t| (MEAN, |B_t| the members of t over all branches), or, for
+    MAX, column c of dV[t] when arg[t, c] == (i, p) and 0 otherwise.  From
+    there the gradient runs through branch i's transform as in
+    ``layer_bwd``.  ``pre_masks`` (one [E_i, h] boolean array per branch,
+    or None) gives act_pre' taken in another precision.  Returns (grads,
+    dW_post, db_post): grads[i] = (demb_i, dW_i, db_i), demb_i one entry
+    per atom (atoms or branches sharing a relation get separate entries,
+    which the caller adds); dW_post and db_post are None without W_post."""
+    keys = np.array(sorted(set().union(*[set(int(k) for k in b[0].group_keys) for b in branches])), np.int64)
+    v = np.asarray(pre, np.float64)
+    dout = np.asarray(dout, np.float64)
+    if W_post is None:
+        dV = dout * _act_grad(act_post, v)
+        dW_post = db_post = None
+    else:
+        Wp = np.asarray(W_post, np.float64)
+        u = v @ Wp + (0.0 if b_post is None else np.asarray(b_post, np.float64))
+        dU = dout * _act_grad(act_post, u)
+        dW_post = v.T @ dU
+        db_post = dU.sum(axis=0)
+        dV = dU @ Wp.T
+    members = np.zeros(len(keys))
+    for idx, *_ in branches:
+        members[np.searchsorted(keys, idx.group_keys)] += np.diff(idx.offsets)
+    grads = []
+    for bi, (idx, embs, W, b, act_pre) in enumerate(branches):
+        t = np.searchsorted(keys, idx.gkey)              # union row of each tuple
+        if agg == "sum":
+            dY = dV[t]
+        elif agg == "mean":
+            dY = dV[t] / members[t][:, None]
+        elif agg == "max":
+            a = np.asarray(arg)[t]
+            mine = (a[..., 0] == bi) & (a[..., 1] == np.arange(idx.E)[:, None])
+            dY = np.where(mine, dV[t], 0.0)
+        else:
+            raise ValueError(agg)
+        W64 = np.asarray(W, np.float64)
+        x = gather_concat(idx, embs)
+        if act_pre != "none":
+            if pre_masks is not None and pre_masks[bi] is not None:
+                dY = dY * np.asarray(pre_masks[bi], np.float64)
+            else:
+                dY = dY * _act_grad(act_pre, x @ W64 + (0.0 if b is None else np.asarray(b, np.float64)))
+        dX = dY @ W64.T
+        demb, off = [], 0
+        for e, r in zip(embs, idx.rows):
+            d = np.asarray(e).shape[1]
+            acc = np.zeros(np.asarray(e).shape, np.float64)
+            np.add.at(acc, r, dX[:, off:off + d])
+            demb.append(acc)
+            off += d
+        grads.append((demb, x.T @ dY, dY.sum(axis=0)))
+    return grads, dW_post, db_post
+
+
 # ---------------------------------------------------------------------------
 # product transforms and segmented softmax (Section 1's attention example,
 # Section 5.2's HGT head)

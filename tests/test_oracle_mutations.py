@@ -261,7 +261,8 @@ UNION_MUTANTS = {
                        "pre[q] = np.mean([v.mean(axis=0) for v in ys], axis=0)")],
     "keys_intersected": [("keys = sorted(set().union(*", "keys = sorted(set.intersection(*")],
     "max_last_branch_first": [("y = np.concatenate(ys, axis=0)", "y = np.concatenate(ys[::-1], axis=0)")],
-    "post_bias_dropped": [("0.0 if b_post is None else np.asarray(b_post, np.float64))", "0.0)")],
+    "post_bias_dropped": [("pre @ np.asarray(W_post, np.float64) + (\n        0.0 if b_post is None else np.asarray(b_post, np.float64))",
+                           "pre @ np.asarray(W_post, np.float64) + (\n        0.0)")],
 }
 
 
@@ -404,4 +405,54 @@ def test_planted_product_backward_mistake_is_caught(name, monkeypatch):
 
 def test_unmutated_product_backward_passes_every_pin():
     for pin in PROD_BWD_PINS:
+        pin()
+
+
+# ---------------------------------------------------------------------------
+# union backward
+# ---------------------------------------------------------------------------
+from tests import test_oracle_union as union_pins  # noqa: E402
+
+UNION_BWD_PINS = [lambda agg=agg, post=post: union_pins.test_union_backward_finite_differences(agg, post)
+                  for agg in ("sum", "mean", "max") for post in (False, True)]
+UNION_BWD_PINS += [lambda agg=agg: union_pins.test_union_backward_of_one_is_the_layer_backward(agg)
+                   for agg in ("sum", "mean", "max")]
+UNION_BWD_PINS += [union_pins.test_self_union_backward, union_pins.test_union_backward_mean_counts_every_relation]
+
+UNION_BWD_MUTANTS = {
+    "union_bwd_mean_per_branch_count": [("            dY = dV[t] / members[t][:, None]\n",
+                                         "            dY = dV[t] / np.diff(idx.offsets)[idx.tuple_group][:, None]\n")],
+    "union_bwd_max_ignores_the_branch": [("            mine = (a[..., 0] == bi) & (a[..., 1] == np.arange(idx.E)[:, None])\n",
+                                          "            mine = a[..., 1] == np.arange(idx.E)[:, None]\n")],
+    "union_bwd_post_mask_without_bias": [("        u = v @ Wp + (0.0 if b_post is None else np.asarray(b_post, np.float64))\n",
+                                          "        u = v @ Wp\n")],
+    "union_bwd_db_post_from_dout": [("        db_post = dU.sum(axis=0)\n", "        db_post = dout.sum(axis=0)\n")],
+    "union_bwd_act_pre_ignored": [(
+        "                dY = dY * _act_grad(act_pre, x @ W64 + (0.0 if b is None else np.asarray(b, np.float64)))\n",
+        "                dY = dY\n")],
+    "union_bwd_post_mask_ignored": [("        dV = dout * _act_grad(act_post, v)\n", "        dV = dout\n")],
+}
+
+
+@pytest.mark.parametrize("name", sorted(UNION_BWD_MUTANTS))
+def test_planted_union_backward_mistake_is_caught(name, monkeypatch):
+    src = inspect.getsource(orc.union_bwd)
+    for old, new in UNION_BWD_MUTANTS[name]:
+        assert src.count(old) == 1, f"mutant {name} no longer matches the oracle's source"
+        src = src.replace(old, new)
+    ns = dict(orc.__dict__)
+    exec(compile(src, "<union_bwd mutant>", "exec"), ns)
+    monkeypatch.setattr(orc, "union_bwd", ns["union_bwd"])
+    caught = False
+    for pin in UNION_BWD_PINS:
+        try:
+            pin()
+        except Exception:
+            caught = True
+            break
+    assert caught, f"no pin caught the planted union-backward mistake {name}"
+
+
+def test_unmutated_union_backward_passes_every_pin():
+    for pin in UNION_BWD_PINS:
         pin()

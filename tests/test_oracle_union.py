@@ -119,3 +119,113 @@ def test_union_rule_transform_after_the_union():
     Wp, bp = rng.standard_normal((3, 2)), rng.standard_normal(2)
     keys, out, pre, _ = orc.union_fwd([branch(r) for r in rules], "mean", "none", Wp, bp)
     np.testing.assert_allclose(out, pre @ Wp + bp, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# backward
+# ---------------------------------------------------------------------------
+def _union_loss(rules, arrays, agg, act_post, Wp, bp, dout):
+    """sum(out * dout) of the union of ``rules`` whose parameters are taken
+    from ``arrays`` = [zA_0, zB_0, W_0, b_0, zA_1, ...]."""
+    bs = []
+    for i, r in enumerate(rules):
+        zA, zB, W, b = arrays[4 * i: 4 * i + 4]
+        bs.append((orc.build_index(r), [zA, zB], W, b, r.act_pre))
+    _, out, _, _ = orc.union_fwd(bs, agg, act_post, Wp, bp)
+    return float((out * dout).sum())
+
+
+@pytest.mark.parametrize("agg", ["sum", "mean", "max"])
+@pytest.mark.parametrize("post", [False, True])
+def test_union_backward_finite_differences(agg, post):
+    """Every gradient of the union (both branches' embeddings, W and b, and
+    the union rule's W_post and b_post) against FP64 central differences of
+    sum(out * dout), with ReLU inside the second branch and after the
+    union."""
+    rules = [branch_rule(20, n_link=14, n_keys=5), branch_rule(21, n_link=11, n_keys=7, act_pre="relu")]
+    rng = np.random.default_rng(3)
+    arrays = []
+    for r in rules:
+        arrays += [r.atoms[0].emb.astype(np.float64), r.atoms[1].emb.astype(np.float64),
+                   r.W.astype(np.float64), r.b.astype(np.float64)]
+    Wp = rng.standard_normal((3, 4)) if post else None
+    bp = rng.standard_normal(4) if post else None
+    bs = [(orc.build_index(r), arrays[4 * i: 4 * i + 2], arrays[4 * i + 2], arrays[4 * i + 3], r.act_pre)
+          for i, r in enumerate(rules)]
+    keys, out, pre, arg = orc.union_fwd(bs, agg, "relu", Wp, bp)
+    dout = rng.standard_normal(out.shape)
+    grads, dWp, dbp = orc.union_bwd(bs, pre, arg, dout, agg, "relu", Wp, bp)
+    flat = []
+    for demb, dW, db in grads:
+        flat += [demb[0], demb[1], dW, db]
+    params = arrays + ([Wp, bp] if post else [])
+    flat += [dWp, dbp] if post else []
+    for a_i, (arr, gr) in enumerate(zip(params, flat)):
+        fd = np.zeros_like(arr)
+        for pos in np.ndindex(*arr.shape):
+            def f(delta):
+                ps = [p.copy() for p in params]
+                ps[a_i][pos] += delta
+                return _union_loss(rules, ps[:8], agg, "relu", ps[8] if post else None, ps[9] if post else None,
+                                   dout)
+            fd[pos] = (f(1e-6) - f(-1e-6)) / 2e-6
+        np.testing.assert_allclose(gr, fd, rtol=1e-5, atol=1e-6, err_msg=f"parameter {a_i}")
+
+
+@pytest.mark.parametrize("agg", ["sum", "mean", "max"])
+def test_union_backward_of_one_is_the_layer_backward(agg):
+    """k = 1: the union is the projection of one join rule, so its backward
+    is that layer's."""
+    rule = branch_rule(3, n_link=30, agg=agg, act_pre="relu")
+    idx = orc.build_index(rule)
+    embs = [a.emb for a in rule.atoms]
+    o_out, o_pre, o_am = orc.layer_fwd(idx, embs, rule.W, rule.b, agg, "relu", "relu")
+    keys, out, pre, arg = orc.union_fwd([branch(rule)], agg, "relu")
+    dout = np.random.default_rng(4).standard_normal(out.shape)
+    grads, dWp, dbp = orc.union_bwd([branch(rule)], pre, arg, dout, agg, "relu")
+    demb, dW, db = orc.layer_bwd(idx, embs, rule.W, rule.b, o_pre, o_am, dout, agg, "relu", "relu")
+    assert dWp is None and dbp is None
+    np.testing.assert_allclose(grads[0][1], dW, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(grads[0][2], db, rtol=1e-12, atol=1e-12)
+    for a, b in zip(grads[0][0], demb):
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12)
+
+
+def test_self_union_backward():
+    """R united with itself: each copy's tuples get the single rule's
+    gradient (SUM), half of it (MEAN: every multiset doubles), or all of it
+    in the first copy and none in the second (MAX: the first maximiser)."""
+    rule = branch_rule(4, n_link=25, act_pre="relu")
+    b = branch(rule)
+    rng = np.random.default_rng(5)
+    for agg, parts in (("sum", (1.0, 1.0)), ("mean", (0.5, 0.5)), ("max", (1.0, 0.0))):
+        _, out1, pre1, arg1 = orc.union_fwd([b], agg, "relu")
+        _, out2, pre2, arg2 = orc.union_fwd([b, b], agg, "relu")
+        dout = rng.standard_normal(out1.shape)
+        g1, _, _ = orc.union_bwd([b], pre1, arg1, dout, agg, "relu")
+        g2, _, _ = orc.union_bwd([b, b], pre2, arg2, dout, agg, "relu")
+        for copy, f in enumerate(parts):
+            np.testing.assert_allclose(g2[copy][1], f * g1[0][1], rtol=1e-12, atol=1e-12)
+            np.testing.assert_allclose(g2[copy][2], f * g1[0][2], rtol=1e-12, atol=1e-12)
+            for a, c in zip(g2[copy][0], g1[0][0]):
+                np.testing.assert_allclose(a, f * c, rtol=1e-12, atol=1e-12)
+
+
+def test_union_backward_mean_counts_every_relation():
+    """The hand-counted MEAN across two relations (one tuple with y = 1 in
+    R1, three in R2; W = identity on one column): out = 10 / 4, so every
+    one of the four embeddings has gradient dout / 4 and W gets
+    dout * (1 + 2 + 3 + 4) / 4 split by branch (1 / 4 and 9 / 4)."""
+    def rel(values):
+        z = np.array([[v] for v in values], np.float32)
+        return relgen.Rule(cols=[np.arange(len(values), dtype=np.int32), np.zeros(len(values), np.int32)],
+                           atoms=[relgen.Atom(0, z)], group_col=1, W=np.ones((1, 1), np.float32),
+                           b=np.zeros(1, np.float32))
+    bs = [branch(rel([1.0])), branch(rel([2.0, 3.0, 4.0]))]
+    keys, out, pre, arg = orc.union_fwd(bs, "mean")
+    grads, _, _ = orc.union_bwd(bs, pre, arg, np.array([[2.0]]), "mean")
+    np.testing.assert_allclose(grads[0][0][0], [[0.5]], rtol=0)
+    np.testing.assert_allclose(grads[1][0][0], [[0.5], [0.5], [0.5]], rtol=0)
+    np.testing.assert_allclose(grads[0][1], [[0.5]], rtol=0)
+    np.testing.assert_allclose(grads[1][1], [[4.5]], rtol=0)
+    np.testing.assert_allclose(grads[0][2] + grads[1][2], [2.0], rtol=0)
