@@ -341,18 +341,52 @@ relnn_status relnn_union_workspace_size(const relnn_union* u, const relnn_layer_
                                         size_t* bytes);
 
 /* Forward.  L: host [k] layer descriptors of the branches (widths, dtype,
- * act_pre; all the same h; their agg, act_post and flags are not used).
- * agg: the union's aggregate (SUM, MEAN, MAX; MAX gives values only).  emb:
- * host [k] of the branch's host [k_i] device embedding pointers; W: host
- * [k] device [K_i, h]; b: host [k] of device [h] or NULL (or b NULL).
- * W_post: device [h, h_out] FP32 row-major or NULL (then h_out = h);
- * b_post: device [h_out] or NULL.  out: device [G, h_out] FP32 =
+ * act_pre; all the same h; their agg and act_post are not used; flags may
+ * hold RELNN_FUSED and RELNN_DW_ACCUM, the latter used by the backward
+ * only).  agg: the union's aggregate (SUM, MEAN, MAX).  emb: host [k] of
+ * the branch's host [k_i] device embedding pointers; W: host [k] device
+ * [K_i, h]; b: host [k] of device [h] or NULL (or b NULL).  W_post: device
+ * [h, h_out] FP32 row-major or NULL (then h_out = h); b_post: device
+ * [h_out] or NULL.  out: device [G, h_out] FP32 =
  * act_post(tau_post(aggregate)); pre: device [G, h] FP32 aggregate or NULL.
- * Row u is the union's key u. */
+ * argmax: MAX only, device [G, h] int32 or NULL: the first maximiser of
+ * each column in (branch, position) order, as a position in the
+ * concatenation of the branches' canonical tuple orders (branch i's
+ * positions start at E_0 + ... + E_{i-1}); -1 where no value is larger
+ * than -Inf.  Row u is the union's key u. */
 relnn_status relnn_union_fwd(const relnn_union* u, const relnn_layer_desc* const* L, int32_t agg,
                              int32_t act_post, const void* const* const* emb, const void* const* W,
                              const float* const* b, const float* W_post, const float* b_post, int32_t h_out,
-                             float* out, float* pre, void* ws, size_t ws_bytes, relnn_stream_t stream);
+                             float* out, float* pre, int32_t* argmax, void* ws, size_t ws_bytes,
+                             relnn_stream_t stream);
+
+/* Workspace bytes of relnn_union_bwd for these branch layers and h_out. */
+relnn_status relnn_union_bwd_workspace_size(const relnn_union* u, const relnn_layer_desc* const* L, int32_t agg,
+                                            int32_t h_out, size_t* bytes);
+
+/* Backward of sum(out * dout) through relnn_union_fwd (chain rule,
+ * Sections 2.2-2.3 and 3.1): with u = v W_post + b_post, dU = dout *
+ * act_post'(u), dW_post = v^T dU, db_post = sum over keys of dU, dV = dU
+ * W_post^T (without W_post, dV = dout * act_post'(v)).  Each tuple of
+ * branch i with key t then receives dV[t] (SUM), dV[t] / members(t)
+ * (MEAN), or the columns of dV[t] it maximises (MAX, from argmax), and
+ * branch i's layer backward takes it to the branch's weights and
+ * embeddings.  Arguments as in the forward, plus: pre, the forward's
+ * aggregate (required with W_post or act_post); argmax, the forward's
+ * (required for MAX); dout device [G, h_out] FP32; demb: host [k] of host
+ * [k_i] device FP32 gradients shaped as emb, ACCUMULATED (+=), may alias;
+ * dW: host [k] of device [K_i, h] FP32, written (added with RELNN_DW_ACCUM
+ * in L[i]->flags, so branches sharing one W can share one dW); db: host
+ * [k] of device [h] or NULL (or db NULL), same rule; dW_post device [h,
+ * h_out] FP32, written (required with W_post); db_post device [h_out] or
+ * NULL.  Every branch index needs RELNN_IDX_BWD.  With W_post, h and h_out
+ * must be multiples of 4, at most 1024 (RELNN_E_UNSUPPORTED). */
+relnn_status relnn_union_bwd(const relnn_union* u, const relnn_layer_desc* const* L, int32_t agg,
+                             int32_t act_post, const void* const* const* emb, const void* const* W,
+                             const float* const* b, const float* W_post, const float* b_post, int32_t h_out,
+                             const float* pre, const int32_t* argmax, const float* dout,
+                             float* const* const* demb, float* const* dW, float* const* db, float* dW_post,
+                             float* db_post, void* ws, size_t ws_bytes, relnn_stream_t stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the

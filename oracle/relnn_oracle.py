@@ -414,7 +414,8 @@ def union_fwd(branches, agg="sum", act_post="none", W_post=None, b_post=None):
     return np.array(keys, np.int64), _act(act_post, v), pre, arg
 
 
-def union_bwd(branches, pre, arg, dout, agg="sum", act_post="none", W_post=None, b_post=None, pre_masks=None):
+def union_bwd(branches, pre, arg, dout, agg="sum", act_post="none", W_post=None, b_post=None, pre_masks=None,
+              post_mask=None):
     """Gradients of sum(out * dout) through ``union_fwd`` (chain rule, from
     the output back to every branch's weights and embeddings).
 
@@ -426,7 +427,8 @@ def union_bwd(branches, pre, arg, dout, agg="sum", act_post="none", W_post=None,
     MAX, column c of dV[t] when arg[t, c] == (i, p) and 0 otherwise.  From
     there the gradient runs through branch i's transform as in
     ``layer_bwd``.  ``pre_masks`` (one [E_i, h] boolean array per branch,
-    or None) gives act_pre' taken in another precision.  Returns (grads,
+    or None) gives act_pre' taken in another precision, ``post_mask``
+    ([G, h_out] booleans) act_post'(u) likewise.  Returns (grads,
     dW_post, db_post): grads[i] = (demb_i, dW_i, db_i), demb_i one entry
     per atom (atoms or branches sharing a relation get separate entries,
     which the caller adds); dW_post and db_post are None without W_post."""
@@ -439,7 +441,8 @@ def union_bwd(branches, pre, arg, dout, agg="sum", act_post="none", W_post=None,
     else:
         Wp = np.asarray(W_post, np.float64)
         u = v @ Wp + (0.0 if b_post is None else np.asarray(b_post, np.float64))
-        dU = dout * _act_grad(act_post, u)
+        dU = dout * (_act_grad(act_post, u) if post_mask is None or act_post == "none"
+                     else np.asarray(post_mask, np.float64))
         dW_post = v.T @ dU
         db_post = dU.sum(axis=0)
         dV = dU @ Wp.T

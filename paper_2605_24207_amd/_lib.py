@@ -118,7 +118,14 @@ _SIGS = {
     "relnn_union_fwd": (C.c_int, [C.c_void_p, C.POINTER(C.POINTER(LayerDesc)), C.c_int32, C.c_int32,
                                   C.POINTER(C.POINTER(C.c_void_p)), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                   C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
-                                  C.c_size_t, C.c_void_p]),
+                                  C.c_void_p, C.c_size_t, C.c_void_p]),
+    "relnn_union_bwd_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(C.POINTER(LayerDesc)), C.c_int32, C.c_int32,
+                                                 C.POINTER(C.c_size_t)]),
+    "relnn_union_bwd": (C.c_int, [C.c_void_p, C.POINTER(C.POINTER(LayerDesc)), C.c_int32, C.c_int32,
+                                  C.POINTER(C.POINTER(C.c_void_p)), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.POINTER(C.POINTER(C.c_void_p)), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "relnn_layer_bwd": (C.c_int, [C.c_void_p, C.POINTER(LayerDesc), C.POINTER(C.c_void_p), C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p),
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),

@@ -225,11 +225,7 @@ class Union:
             pass
 
 
-def union_fwd(union: Union, layers: Sequence["Layer"], agg: str, act_post: str, embs, Ws, bs=None,
-              W_post: Optional[torch.Tensor] = None, b_post: Optional[torch.Tensor] = None, want_pre: bool = True,
-              stream=None):
-    """relnn_union_fwd.  embs[i]: the branch's embedding tensors; Ws[i],
-    bs[i]: its transform.  Returns (out [G, h_out], pre [G, h] or None)."""
+def _union_args(union: Union, layers, embs, Ws, bs, W_post):
     k = union.k
     if not (len(layers) == len(embs) == len(Ws) == k):
         raise ValueError("one layer, embedding list and W per branch")
@@ -248,16 +244,139 @@ def union_fwd(union: Union, layers: Sequence["Layer"], agg: str, act_post: str, 
     if W_post is not None and (W_post.dtype != torch.float32 or tuple(W_post.shape) != (h, h_out)
                                or not W_post.is_contiguous()):
         raise TypeError(f"W_post must be a contiguous float32 [{h}, h_out] tensor")
+    # the ctypes arrays must outlive the call: keep them with the pointers
+    return (descs, emb_arrs), dptr, emb_pp, W_arr, b_arr, h, h_out
+
+
+def union_fwd(union: Union, layers: Sequence["Layer"], agg: str, act_post: str, embs, Ws, bs=None,
+              W_post: Optional[torch.Tensor] = None, b_post: Optional[torch.Tensor] = None, want_pre: bool = True,
+              want_argmax: bool = True, stream=None):
+    """relnn_union_fwd.  embs[i]: the branch's embedding tensors; Ws[i],
+    bs[i]: its transform.  Returns (out [G, h_out], pre [G, h] or None,
+    argmax [G, h] int32 for MAX (positions in the concatenation of the
+    branches' tuple orders) or None)."""
+    keep, dptr, emb_pp, W_arr, b_arr, h, h_out = _union_args(union, layers, embs, Ws, bs, W_post)
     dev = union.device
     out = torch.empty(union.G, h_out, dtype=torch.float32, device=dev)
     pre = torch.empty(union.G, h, dtype=torch.float32, device=dev) if want_pre else None
+    am = torch.empty(union.G, h, dtype=torch.int32, device=dev) if (want_argmax and agg == "max") else None
     n = C.c_size_t()
     check(lib().relnn_union_workspace_size(union.handle, dptr, _AGGS[agg], C.byref(n)))
     ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=dev)
     check(lib().relnn_union_fwd(union.handle, dptr, _AGGS[agg], _ACTS[act_post], emb_pp, W_arr, b_arr,
-                                _vp(W_post), _vp(b_post), h_out, _vp(out), _vp(pre), _vp(ws), ws.numel(),
+                                _vp(W_post), _vp(b_post), h_out, _vp(out), _vp(pre), _vp(am), _vp(ws), ws.numel(),
                                 _stream(stream)))
-    return out, pre
+    return out, pre, am
+
+
+def union_bwd(union: Union, layers: Sequence["Layer"], agg: str, act_post: str, embs, Ws, bs,
+              W_post: Optional[torch.Tensor], b_post: Optional[torch.Tensor], pre: Optional[torch.Tensor],
+              argmax: Optional[torch.Tensor], dout: torch.Tensor, demb, dWs, dbs=None,
+              dW_post: Optional[torch.Tensor] = None, db_post: Optional[torch.Tensor] = None, stream=None):
+    """relnn_union_bwd.  demb[i]: FP32 gradient tensors shaped as embs[i]
+    (accumulated, may alias); dWs[i], dbs[i]: FP32 gradients of Ws[i], bs[i]
+    (written, or added for a layer with dw_accum); dW_post, db_post: of the
+    union rule's transform (written)."""
+    keep, dptr, emb_pp, W_arr, b_arr, h, h_out = _union_args(union, layers, embs, Ws, bs, W_post)
+
+    def f32(t, shape, what):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise TypeError(f"{what} must be a contiguous float32 CUDA tensor of shape {shape}")
+
+    f32(dout, (union.G, h_out), "dout")
+    if pre is not None:
+        f32(pre, (union.G, h), "pre")
+    if argmax is not None and (argmax.dtype != torch.int32 or tuple(argmax.shape) != (union.G, h)
+                               or not argmax.is_contiguous()):
+        raise TypeError("argmax must be a contiguous int32 [G, h] tensor")
+    for l, e, d, dW in zip(layers, embs, demb, dWs):
+        if len(d) != len(e):
+            raise ValueError("one gradient per embedding")
+        for t, g in zip(e, d):
+            f32(g, tuple(t.shape), "demb")
+        f32(dW, (l.K, l.h), "dW")
+    if dbs is not None:
+        for db in dbs:
+            if db is not None:
+                f32(db, (h,), "db")
+    if W_post is not None:
+        if dW_post is None:
+            raise ValueError("dW_post is required with W_post")
+        f32(dW_post, (h, h_out), "dW_post")
+        if db_post is not None:
+            f32(db_post, (h_out,), "db_post")
+    k = union.k
+    demb_arrs = [(C.c_void_p * len(d))(*[g.data_ptr() for g in d]) for d in demb]
+    demb_pp = (C.POINTER(C.c_void_p) * k)(*[C.cast(a, C.POINTER(C.c_void_p)) for a in demb_arrs])
+    dW_arr = (C.c_void_p * k)(*[dW.data_ptr() for dW in dWs])
+    db_arr = None if dbs is None else (C.c_void_p * k)(*[None if db is None else db.data_ptr() for db in dbs])
+    n = C.c_size_t()
+    check(lib().relnn_union_bwd_workspace_size(union.handle, dptr, _AGGS[agg], h_out, C.byref(n)))
+    ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=union.device)
+    check(lib().relnn_union_bwd(union.handle, dptr, _AGGS[agg], _ACTS[act_post], emb_pp, W_arr, b_arr,
+                                _vp(W_post), _vp(b_post), h_out, _vp(pre), _vp(argmax), _vp(dout), demb_pp, dW_arr,
+                                db_arr, _vp(dW_post), _vp(db_post), _vp(ws), ws.numel(), _stream(stream)))
+
+
+class UnionFn(torch.autograd.Function):
+    """out = union rule over the branches, with the hand-written backward.
+
+    Usage: UnionFn.apply(union, layers, agg, act_post, W_post, b_post,
+    *params) with params = W_0, b_0, embs_0..., W_1, b_1, embs_1, ...
+    (b_i may be None; branch i has len(layers[i].dims) embeddings).  Gradients
+    flow to every W_i, b_i, embedding, W_post and b_post; tensors shared
+    by several atoms or branches get one buffer."""
+
+    @staticmethod
+    def forward(ctx, union: Union, layers, agg: str, act_post: str, W_post, b_post, *params):
+        Ws, bs, embs, i = [], [], [], 0
+        for l in layers:
+            Ws.append(params[i])
+            bs.append(params[i + 1])
+            embs.append(list(params[i + 2: i + 2 + len(l.dims)]))
+            i += 2 + len(l.dims)
+        out, pre, am = union_fwd(union, layers, agg, act_post, embs, Ws, bs, W_post, b_post)
+        ctx.union, ctx.layers, ctx.agg, ctx.act_post = union, layers, agg, act_post
+        ctx.has_b = [b is not None for b in bs]
+        ctx.save_for_backward(W_post, b_post, pre, am, *params)
+        return out
+
+    @staticmethod
+    def backward(ctx, dout):
+        W_post, b_post, pre, am, *params = ctx.saved_tensors
+        layers = ctx.layers
+        dev = dout.device
+        Ws, bs, embs, i = [], [], [], 0
+        for l in layers:
+            Ws.append(params[i])
+            bs.append(params[i + 1])
+            embs.append(list(params[i + 2: i + 2 + len(l.dims)]))
+            i += 2 + len(l.dims)
+        bufs = {}
+
+        def buf(t):
+            key = t.data_ptr()
+            first = key not in bufs
+            if first:
+                bufs[key] = torch.zeros(t.shape, dtype=torch.float32, device=dev)
+            return bufs[key], first
+
+        demb = [[buf(t)[0] for t in e] for e in embs]
+        dWs = [torch.empty(l.K, l.h, dtype=torch.float32, device=dev) for l in layers]
+        dbs = [torch.empty(l.h, dtype=torch.float32, device=dev) if hb else None
+               for l, hb in zip(layers, ctx.has_b)]
+        dW_post = None if W_post is None else torch.empty(W_post.shape, dtype=torch.float32, device=dev)
+        db_post = None if b_post is None else torch.empty(b_post.shape, dtype=torch.float32, device=dev)
+        union_bwd(ctx.union, layers, ctx.agg, ctx.act_post, embs, Ws, bs, W_post, b_post, pre, am,
+                  dout.to(torch.float32).contiguous(), demb, dWs, dbs, dW_post, db_post)
+        grads, seen = [], set()
+        for l, dW, db, e in zip(layers, dWs, dbs, embs):
+            grads += [dW, db]
+            for t in e:
+                key = t.data_ptr()
+                grads.append(bufs[key] if key not in seen else None)
+                seen.add(key)
+        return (None, None, None, None, dW_post, db_post) + tuple(grads)
 
 
 def _lib_alive():

@@ -142,16 +142,14 @@ size_t bwd_workspace(const relnn_index* idx, const relnn_layer_desc* L, const Fw
   return plan_bwd(idx, L, P).total;
 }
 
-}  // namespace relnn
+size_t layer_bwd_ws_bytes(const relnn_index* idx, const relnn_layer_desc* L) {
+  return plan_bwd(idx, L, checked_plan(idx, L)).total;
+}
 
-using namespace relnn;
-
-extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_layer_desc* L,
-                                        const void* const* emb, const void* W, const float* b,
-                                        const float* pre, const int32_t* argmax, const float* dout,
-                                        float* const* demb, float* dW, float* db, void* ws, size_t ws_bytes,
-                                        relnn_stream_t stream) {
-  return guard([&] {
+void layer_bwd_run(const relnn_index* idx, const relnn_layer_desc* L, const void* const* emb, const void* W,
+                   const float* b, const float* pre, const int32_t* argmax, const float* dout, float* const* demb,
+                   float* dW, float* db, void* ws, size_t ws_bytes, hipStream_t stream) {
+  {
     FwdPlan F = checked_plan(idx, L);
     RELNN_REQUIRE(idx->has_bwd, RELNN_E_INVALID, "the index was built without RELNN_IDX_BWD");
     RELNN_REQUIRE(!(L->flags & RELNN_OUT_BF16), RELNN_E_INVALID, "RELNN_OUT_BF16 is a forward-only flag");
@@ -264,5 +262,19 @@ extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_laye
 
     // dz_j for every atom, in body order (through the per-row sums of dY)
     lin_bwd_dx(idx, L, P.lin, W, dA, route, nw, mask != nullptr, demb, w, s);
+  }
+}
+
+}  // namespace relnn
+
+using namespace relnn;
+
+extern "C" relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_layer_desc* L,
+                                        const void* const* emb, const void* W, const float* b,
+                                        const float* pre, const int32_t* argmax, const float* dout,
+                                        float* const* demb, float* dW, float* db, void* ws, size_t ws_bytes,
+                                        relnn_stream_t stream) {
+  return guard([&] {
+    layer_bwd_run(idx, L, emb, W, b, pre, argmax, dout, demb, dW, db, ws, ws_bytes, (hipStream_t)stream);
   });
 }

@@ -52,6 +52,12 @@ void layer_fwd_run(const relnn_index* idx, const relnn_layer_desc* L, const void
                    const float* b, float* out, float* pre, int32_t* argmax, void* ws, size_t ws_bytes,
                    hipStream_t stream);
 size_t layer_fwd_ws_bytes(const relnn_index* idx, const relnn_layer_desc* L);
+// relnn_layer_bwd without the status mapping (throws Fail), and its
+// workspace bytes.
+void layer_bwd_run(const relnn_index* idx, const relnn_layer_desc* L, const void* const* emb, const void* W,
+                   const float* b, const float* pre, const int32_t* argmax, const float* dout, float* const* demb,
+                   float* dW, float* db, void* ws, size_t ws_bytes, hipStream_t stream);
+size_t layer_bwd_ws_bytes(const relnn_index* idx, const relnn_layer_desc* L);
 // Validates the index / layer pair, then plans (RELNN_E_* on failure).
 FwdPlan checked_plan(const relnn_index* idx, const relnn_layer_desc* L);
 Atoms make_atoms(const relnn_layer_desc* L, const void* const* emb, const relnn_index* idx);

@@ -12,7 +12,16 @@
 // divides the union's sums by the union's member counts: it is applied once
 // over the whole multiset, never as a mean of the branches' means.  The
 // union rule's transform (v W_post + b_post, then act_post) runs on the
-// union rows as one matrix-core product.
+// union rows as one matrix-core product.  MAX also records each column's
+// maximiser as a position in the concatenation of the branches' canonical
+// tuple orders: the first maximiser in (branch, position) order.
+//
+// The backward runs the chain rule the other way: through act_post and the
+// union rule's transform on the union rows (dW_post = v^T dU and dV = dU
+// W_post^T as matrix-core products), then, branch by branch, the union
+// row's gradient is routed to the branch's groups (MEAN divided by the
+// union's member count, MAX through the recorded maximisers) and the
+// branch's own layer backward carries it to its weights and embeddings.
 #include <memory>
 #include <vector>
 
@@ -29,6 +38,7 @@ struct relnn_union {
   relnn::DevBuf keys;                   // [G] ascending
   relnn::DevBuf cnt;                    // [G] members of each key over all branches
   relnn::DevBuf map[RELNN_MAX_UNION];   // [G_i] union row of each branch group
+  int64_t base[RELNN_MAX_UNION] = {};   // first position of branch i in the concatenated tuple order
 };
 
 using namespace relnn;
@@ -67,18 +77,55 @@ __global__ void k_fill(float* p, int64_t n, float v) {
 }
 
 // acc[map[q]][c] (+)= part[q][c] (SUM) or max (MAX: a later branch replaces
-// only a strictly smaller value, so ties stay with the earlier branch).
-__global__ void k_merge(const float* part, const int32_t* map, int64_t n, int h, int is_max, float* acc) {
+// only a strictly smaller value, so ties stay with the earlier branch; the
+// maximiser arg becomes base + the branch's own, when arg is given).
+__global__ void k_merge(const float* part, const int32_t* part_arg, const int32_t* map, int64_t n, int h, int is_max,
+                        int32_t base, float* acc, int32_t* arg) {
   const int64_t total = n * h;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t q = i / h;
     const int c = (int)(i - q * h);
-    float* o = acc + (int64_t)map[q] * h + c;
+    const int64_t o = (int64_t)map[q] * h + c;
     const float v = part[i];
-    if (is_max)
-      *o = v > *o ? v : *o;
-    else
-      *o += v;
+    if (is_max) {
+      if (v > acc[o]) {
+        acc[o] = v;
+        if (arg) arg[o] = base + part_arg[i];
+      }
+    } else {
+      acc[o] += v;
+    }
+  }
+}
+
+// d[i] = g[i] * act'(v[i]) (ReLU'(0) = 0; v unused for NONE)
+__global__ void k_act_grad(const float* g, const float* v, int64_t n, int act, float* d) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = (act == RELNN_ACT_RELU && !(v[i] > 0.0f)) ? 0.0f : g[i];
+}
+
+// The gradient reaching branch group q: row map[q] of dV (MEAN: divided by
+// the union row's member count); MAX: the branch's own maximiser position
+// where the union's maximiser lies in this branch, else -1 (no tuple) and a
+// zero gradient (the layer backward takes a group's whole gradient row for
+// an atom keyed by the group, which holds only where the group owns every
+// column).
+__global__ void k_union_route(const float* dV, const int32_t* cnt, const int32_t* map, int64_t n, int h, int mean,
+                              const int32_t* arg, int64_t base, int64_t E, float* dout, int32_t* am) {
+  const int64_t total = n * h;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = i / h;
+    const int c = (int)(i - q * h);
+    const int64_t o = (int64_t)map[q] * h + c;
+    float v = dV[o];
+    if (mean) v = v / (float)cnt[map[q]];
+    dout[i] = v;
+    if (arg) {
+      const int64_t a = (int64_t)arg[o] - base;
+      const bool mine = a >= 0 && a < E;
+      am[i] = mine ? (int32_t)a : -1;
+      if (!mine) dout[i] = 0.0f;
+    }
   }
 }
 
@@ -96,7 +143,7 @@ __global__ void k_union_finish(float* acc, const int32_t* cnt, int64_t G, int h,
 }
 
 struct UnionPlan {
-  size_t ws_acc = 0, ws_part[RELNN_MAX_UNION] = {}, ws_layer = 0, total = 0;
+  size_t ws_acc = 0, ws_part[RELNN_MAX_UNION] = {}, ws_arg[RELNN_MAX_UNION] = {}, ws_layer = 0, total = 0;
   size_t layer_bytes = 0;
 };
 
@@ -120,6 +167,7 @@ UnionPlan plan_union(const relnn_union* U, const relnn_layer_desc* const* L, int
   p.ws_acc = take((size_t)std::max<int64_t>(U->G, 1) * h * 4);
   for (int i = 0; i < U->k; ++i) {
     p.ws_part[i] = take((size_t)std::max<int64_t>(U->br[i]->G, 1) * h * 4);
+    if (agg == RELNN_MAX) p.ws_arg[i] = take((size_t)std::max<int64_t>(U->br[i]->G, 1) * h * 4);
     const relnn_layer_desc d = branch_desc(L[i], agg);
     p.layer_bytes = std::max(p.layer_bytes, layer_fwd_ws_bytes(U->br[i], &d));
   }
@@ -134,7 +182,8 @@ void check_union_args(const relnn_union* U, const relnn_layer_desc* const* L, in
   for (int i = 0; i < U->k; ++i) {
     RELNN_REQUIRE(L[i] != nullptr, RELNN_E_INVALID, "layer descriptor %d is NULL", i);
     RELNN_REQUIRE(L[i]->h == L[0]->h, RELNN_E_INVALID, "branch %d has width %d, branch 0 %d", i, L[i]->h, L[0]->h);
-    RELNN_REQUIRE((L[i]->flags & ~RELNN_FUSED) == 0, RELNN_E_UNSUPPORTED, "branch %d: layer flags are not used here", i);
+    RELNN_REQUIRE((L[i]->flags & ~(RELNN_FUSED | RELNN_DW_ACCUM)) == 0, RELNN_E_UNSUPPORTED,
+                  "branch %d: layer flags are not used here", i);
   }
 }
 
@@ -151,13 +200,16 @@ extern "C" relnn_status relnn_union_build(const relnn_index* const* branches, in
     std::unique_ptr<relnn_union> U(new relnn_union());
     RELNN_HIP(hipGetDevice(&U->device));
     U->k = k;
-    int64_t n = 0;
+    int64_t n = 0, e = 0;
     for (int i = 0; i < k; ++i) {
       RELNN_REQUIRE(branches[i] != nullptr, RELNN_E_INVALID, "branch %d is NULL", i);
       U->br[i] = branches[i];
+      U->base[i] = e;
       n += branches[i]->G;
+      e += branches[i]->E;
     }
     RELNN_REQUIRE(n < (int64_t)INT32_MAX, RELNN_E_RANGE, "too many groups");
+    RELNN_REQUIRE(e < (int64_t)INT32_MAX, RELNN_E_RANGE, "too many tuples over all branches");
     // all branch keys, sorted and deduplicated
     DevBuf all(std::max<int64_t>(n, 1) * sizeof(int32_t));
     int64_t o = 0;
@@ -234,8 +286,8 @@ extern "C" relnn_status relnn_union_workspace_size(const relnn_union* U, const r
 extern "C" relnn_status relnn_union_fwd(const relnn_union* U, const relnn_layer_desc* const* L, int32_t agg,
                                         int32_t act_post, const void* const* const* emb, const void* const* W,
                                         const float* const* b, const float* W_post, const float* b_post,
-                                        int32_t h_out, float* out, float* pre, void* ws, size_t ws_bytes,
-                                        relnn_stream_t stream) {
+                                        int32_t h_out, float* out, float* pre, int32_t* argmax, void* ws,
+                                        size_t ws_bytes, relnn_stream_t stream) {
   return guard([&] {
     check_union_args(U, L, agg);
     RELNN_REQUIRE(act_post == RELNN_ACT_NONE || act_post == RELNN_ACT_RELU, RELNN_E_INVALID, "unknown activation");
@@ -256,14 +308,21 @@ extern "C" relnn_status relnn_union_fwd(const relnn_union* U, const relnn_layer_
     const bool is_max = agg == RELNN_MAX;
     k_fill<<<grid_n(U->G * h), 256, 0, s>>>(acc, U->G * h, is_max ? -INFINITY : 0.0f);
     RELNN_LAUNCHED();
+    int32_t* arg = is_max ? argmax : nullptr;
+    if (arg) {
+      k_fill_i32<<<grid_n(U->G * h), 256, 0, s>>>(arg, U->G * h, -1);
+      RELNN_LAUNCHED();
+    }
     for (int i = 0; i < U->k; ++i) {                      // each branch, then its partials in branch order
       const relnn_index* bi = U->br[i];
       if (bi->G == 0) continue;
       const relnn_layer_desc d = branch_desc(L[i], agg);
       float* part = reinterpret_cast<float*>(w + P.ws_part[i]);
-      layer_fwd_run(bi, &d, emb[i], W[i], b ? b[i] : nullptr, part, nullptr, nullptr, w + P.ws_layer, P.layer_bytes,
-                    s);
-      k_merge<<<grid_n(bi->G * h), 256, 0, s>>>(part, U->map[i].as<int32_t>(), bi->G, h, is_max ? 1 : 0, acc);
+      int32_t* part_arg = arg ? reinterpret_cast<int32_t*>(w + P.ws_arg[i]) : nullptr;
+      layer_fwd_run(bi, &d, emb[i], W[i], b ? b[i] : nullptr, part, nullptr, part_arg, w + P.ws_layer,
+                    P.layer_bytes, s);
+      k_merge<<<grid_n(bi->G * h), 256, 0, s>>>(part, part_arg, U->map[i].as<int32_t>(), bi->G, h, is_max ? 1 : 0,
+                                                 (int32_t)U->base[i], acc, arg);
       RELNN_LAUNCHED();
     }
     k_union_finish<<<grid_n(U->G * h), 256, 0, s>>>(acc, U->cnt.as<int32_t>(), U->G, h, agg == RELNN_MEAN ? 1 : 0,
@@ -274,6 +333,137 @@ extern "C" relnn_status relnn_union_fwd(const relnn_union* U, const relnn_layer_
       epi.bias = b_post;
       epi.act = act_post;
       gemm_rows(false, acc, false, h, U->G, h, W_post, false, false, h_out, h_out, out, h_out, epi, s);
+    }
+  });
+}
+
+namespace {
+
+struct UnionBwdPlan {
+  size_t ws_dV = 0, ws_u = 0, ws_dU = 0, ws_tn = 0, ws_dout = 0, ws_am = 0, ws_layer = 0, total = 0;
+  size_t layer_bytes = 0;
+};
+
+relnn_layer_desc branch_bwd_desc(const relnn_layer_desc* L, int agg) {
+  relnn_layer_desc d = *L;
+  d.agg = agg == RELNN_MAX ? RELNN_MAX : RELNN_SUM;   // MEAN: the division is in the routed gradient
+  d.act_post = RELNN_ACT_NONE;
+  d.flags = L->flags & RELNN_DW_ACCUM;
+  return d;
+}
+
+UnionBwdPlan plan_union_bwd(const relnn_union* U, const relnn_layer_desc* const* L, int agg, int h_out) {
+  UnionBwdPlan p;
+  const int h = L[0]->h;
+  const int64_t G = std::max<int64_t>(U->G, 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += round_up(std::max<size_t>(bytes, 1), 256);
+    return o;
+  };
+  p.ws_dV = take((size_t)G * h * 4);
+  p.ws_u = take((size_t)G * h_out * 4);
+  p.ws_dU = take((size_t)G * h_out * 4);
+  p.ws_tn = take((size_t)gemm_tn_ws_floats(G, h, h_out) * 4);
+  int64_t gmax = 1;
+  for (int i = 0; i < U->k; ++i) {
+    gmax = std::max<int64_t>(gmax, U->br[i]->G);
+    const relnn_layer_desc d = branch_bwd_desc(L[i], agg);
+    p.layer_bytes = std::max(p.layer_bytes, layer_bwd_ws_bytes(U->br[i], &d));
+  }
+  p.ws_dout = take((size_t)gmax * h * 4);
+  if (agg == RELNN_MAX) p.ws_am = take((size_t)gmax * h * 4);
+  p.ws_layer = take(p.layer_bytes);
+  p.total = off;
+  return p;
+}
+
+}  // namespace
+
+extern "C" relnn_status relnn_union_bwd_workspace_size(const relnn_union* U, const relnn_layer_desc* const* L,
+                                                       int32_t agg, int32_t h_out, size_t* bytes) {
+  return guard([&] {
+    RELNN_REQUIRE(bytes != nullptr, RELNN_E_INVALID, "bytes is NULL");
+    check_union_args(U, L, agg);
+    RELNN_REQUIRE(h_out > 0, RELNN_E_INVALID, "h_out must be positive");
+    *bytes = plan_union_bwd(U, L, agg, h_out).total;
+  });
+}
+
+extern "C" relnn_status relnn_union_bwd(const relnn_union* U, const relnn_layer_desc* const* L, int32_t agg,
+                                        int32_t act_post, const void* const* const* emb, const void* const* W,
+                                        const float* const* b, const float* W_post, const float* b_post,
+                                        int32_t h_out, const float* pre, const int32_t* argmax, const float* dout,
+                                        float* const* const* demb, float* const* dW, float* const* db,
+                                        float* dW_post, float* db_post, void* ws, size_t ws_bytes,
+                                        relnn_stream_t stream) {
+  return guard([&] {
+    check_union_args(U, L, agg);
+    RELNN_REQUIRE(act_post == RELNN_ACT_NONE || act_post == RELNN_ACT_RELU, RELNN_E_INVALID, "unknown activation");
+    RELNN_REQUIRE(emb != nullptr && W != nullptr && demb != nullptr && dW != nullptr, RELNN_E_INVALID,
+                  "emb, W, demb and dW are required");
+    const int h = L[0]->h;
+    const bool post = W_post != nullptr;
+    RELNN_REQUIRE(post || h_out == h, RELNN_E_INVALID, "without W_post, h_out must equal h");
+    RELNN_REQUIRE(!post || dW_post != nullptr, RELNN_E_INVALID, "dW_post is required with W_post");
+    RELNN_REQUIRE(!post || (h % 4 == 0 && h_out % 4 == 0 && h <= 1024 && h_out <= 1024), RELNN_E_UNSUPPORTED,
+                  "the post transform's backward needs h and h_out multiples of 4, at most 1024");
+    const int64_t G = U->G;
+    RELNN_REQUIRE(dout != nullptr || G == 0, RELNN_E_INVALID, "dout is NULL");
+    RELNN_REQUIRE(pre != nullptr || G == 0 || (!post && act_post == RELNN_ACT_NONE), RELNN_E_INVALID,
+                  "pre is required with W_post or act_post");
+    RELNN_REQUIRE(agg != RELNN_MAX || argmax != nullptr || G == 0, RELNN_E_INVALID, "argmax is required for MAX");
+    const UnionBwdPlan P = plan_union_bwd(U, L, agg, h_out);
+    RELNN_REQUIRE(ws != nullptr && ws_bytes >= P.total, RELNN_E_INVALID, "workspace of %zu bytes given, %zu needed",
+                  ws_bytes, P.total);
+    RELNN_REQUIRE(((uintptr_t)ws & 255) == 0, RELNN_E_INVALID, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char* w = static_cast<char*>(ws);
+    float* dV = reinterpret_cast<float*>(w + P.ws_dV);
+    if (post && G == 0) {                                 // nothing flows: the post gradients are zero
+      k_fill<<<grid_n((int64_t)h * h_out), 256, 0, s>>>(dW_post, (int64_t)h * h_out, 0.0f);
+      RELNN_LAUNCHED();
+      if (db_post) {
+        k_fill<<<1, 256, 0, s>>>(db_post, h_out, 0.0f);
+        RELNN_LAUNCHED();
+      }
+    } else if (post) {
+      float* dU = reinterpret_cast<float*>(w + P.ws_dU);
+      if (act_post == RELNN_ACT_RELU) {                   // u = v W_post + b_post, as the forward formed it
+        float* u = reinterpret_cast<float*>(w + P.ws_u);
+        RowsEpi epi;
+        epi.bias = b_post;
+        gemm_rows(false, pre, false, h, G, h, W_post, false, false, h_out, h_out, u, h_out, epi, s);
+        k_act_grad<<<grid_n(G * h_out), 256, 0, s>>>(dout, u, G * h_out, act_post, dU);
+      } else {
+        k_act_grad<<<grid_n(G * h_out), 256, 0, s>>>(dout, nullptr, G * h_out, RELNN_ACT_NONE, dU);
+      }
+      RELNN_LAUNCHED();
+      TnB tb;
+      tb.B = dU;
+      tb.ldb = h_out;
+      gemm_tn(false, pre, false, h, nullptr, nullptr, tb, G, h, h_out, nullptr, dW_post, db_post, false,
+              reinterpret_cast<float*>(w + P.ws_tn), s);
+      gemm_rows(false, dU, false, h_out, G, h_out, W_post, false, true, h_out, h, dV, h, RowsEpi{}, s);
+    } else if (G > 0) {
+      k_act_grad<<<grid_n(G * h), 256, 0, s>>>(dout, pre, G * h, act_post, dV);
+      RELNN_LAUNCHED();
+    }
+    const bool is_max = agg == RELNN_MAX;
+    float* dout_i = reinterpret_cast<float*>(w + P.ws_dout);
+    int32_t* am_i = is_max ? reinterpret_cast<int32_t*>(w + P.ws_am) : nullptr;
+    for (int i = 0; i < U->k; ++i) {                      // each branch's share, then its layer backward
+      const relnn_index* bi = U->br[i];
+      if (bi->G > 0) {
+        k_union_route<<<grid_n(bi->G * h), 256, 0, s>>>(dV, U->cnt.as<int32_t>(), U->map[i].as<int32_t>(), bi->G, h,
+                                                         agg == RELNN_MEAN ? 1 : 0, is_max ? argmax : nullptr,
+                                                         U->base[i], bi->E, dout_i, am_i);
+        RELNN_LAUNCHED();
+      }
+      const relnn_layer_desc d = branch_bwd_desc(L[i], agg);
+      layer_bwd_run(bi, &d, emb[i], W[i], b ? b[i] : nullptr, nullptr, am_i, dout_i, demb[i], dW[i],
+                    db ? db[i] : nullptr, w + P.ws_layer, P.layer_bytes, s);
     }
   });
 }

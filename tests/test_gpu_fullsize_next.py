@@ -155,7 +155,7 @@ def test_union_full_size(er):
     r2.cols = [c[half:] for c in r2.cols]
     idx = [gpu_index(r) for r in (r1, r2)]
     U = Union(idx)
-    out, pre = union_fwd(U, [gpu_layer(r1), gpu_layer(r2)], "mean", "relu", [distinct_embs(r1), distinct_embs(r2)],
+    out, pre, _ = union_fwd(U, [gpu_layer(r1), gpu_layer(r2)], "mean", "relu", [distinct_embs(r1), distinct_embs(r2)],
                          [to_dev(r1.W), to_dev(r2.W)], [to_dev(r1.b), to_dev(r2.b)])
     torch.cuda.synchronize()
     keys_all = U.export()["keys"].cpu().numpy()

@@ -44,7 +44,7 @@ def run_union(rules, agg, dtype, act_post="relu", post=None):
     W_post = b_post = None
     if post is not None:
         W_post, b_post = to_dev(post[0]), to_dev(post[1])
-    out, pre = union_fwd(U, layers, agg, act_post, embs, Ws, bs, W_post, b_post)
+    out, pre, am = union_fwd(U, layers, agg, act_post, embs, Ws, bs, W_post, b_post)
     ex = U.export()
     return U, ex["keys"].cpu().numpy(), ex["counts"].cpu().numpy(), out.cpu().numpy(), pre.cpu().numpy()
 
