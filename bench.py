@@ -535,15 +535,16 @@ def next_legs(D, reps: int):
                  and BF16; forward and backward;
       union      Item(i) as the union of two bodies (the Item rule over the
                  first 10M Buys rows, the User rule's body grouped by item over
-                 the other 10M), MEAN applied once, FP32;
-      product    Item(i; mean(z_u * z_i * z_c)) over Buys (20M), FP32;
+                 the other 10M), MEAN applied once, FP32; forward and backward;
+      product    Item(i; mean(relu(z_u * z_i * z_c))) over Buys (20M), FP32;
+                 forward and backward;
       triangle   the DHN triangle rule on 20k graphs of 40 nodes (index build
                  by sort-and-probe joins, then the layer), FP32."""
     import torch
 
     import relgen
-    from paper_2605_24207_amd import (Index, Layer, Union, api, attn_bwd, attn_fwd, layer_fwd, union_fwd,
-                                      workspace)
+    from paper_2605_24207_amd import (Index, Layer, Union, api, attn_bwd, attn_fwd, layer_bwd, layer_fwd,
+                                      union_bwd, union_fwd, workspace)
 
     res = {}
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -590,8 +591,9 @@ def next_legs(D, reps: int):
     nu, ni, nc = g.user.shape[0], g.item.shape[0], g.cat.shape[0]
     b1 = Index([D["bu"][:half].contiguous(), D["bi"][:half].contiguous()], [(nu, 0, None), (ni, 1, None),
                                                                             (nc, 2, None)], 1,
-               chains=[(1, D["bc"], None)])
-    b2 = Index([D["bu"][half:].contiguous(), D["bi"][half:].contiguous()], [(nu, 0, None), (ni, 1, None)], 1)
+               chains=[(1, D["bc"], None)], bwd=True)
+    b2 = Index([D["bu"][half:].contiguous(), D["bi"][half:].contiguous()], [(nu, 0, None), (ni, 1, None)], 1,
+               bwd=True)
     U = Union([b1, b2])
     L1 = Layer([128, 128, 128], 128, "f32", "mean")
     L2 = Layer([128, 128], 128, "f32", "mean")
@@ -599,14 +601,38 @@ def next_legs(D, reps: int):
                            [D["W_item"][0], D["W_user"][0]], [D["b_item"][0], D["b_user"][0]], want_pre=False)
     ms = time_calls(fn, reps) * 1e3
     ufl = b1.E * (2 * 384 * 128 + 2 * 128) + b2.E * (2 * 256 * 128 + 2 * 128)
+    # backward of affine MEAN branches: per tuple the joined row is gathered
+    # again (FP32, for the per-group sums that dW needs) and, for every atom
+    # not keyed by the group, the routed gradient row and its row numbers are
+    # read in that atom's transpose order; every joined row's gradient is
+    # read and written once per branch.  The products themselves are per
+    # group and per joined row, not per tuple.
+    ub_bytes = (b1.E * (384 * 4 + 2 * (128 * 4 + 8) + 12) + b2.E * (256 * 4 + (128 * 4 + 8) + 8)
+                + 2 * (nu + ni) * 128 * 8 + nc * 128 * 8)
+    uembs = [[D["U"], D["I"], D["C"]], [D["U"], D["I"]]]
+    uW = [D["W_item"][0], D["W_user"][0]]
+    ub = [D["b_item"][0], D["b_user"][0]]
+    uout, upre, _ = union_fwd(U, [L1, L2], "mean", "relu", uembs, uW, ub)
+    udout = torch.randn_like(uout)
+    ug = {k: torch.zeros(D[k].shape, device="cuda") for k in ("U", "I", "C")}
+    udemb = [[ug["U"], ug["I"], ug["C"]], [ug["U"], ug["I"]]]
+    udW = [torch.empty(384, 128, device="cuda"), torch.empty(256, 128, device="cuda")]
+    udb = [torch.empty(128, device="cuda"), torch.empty(128, device="cuda")]
+    msb = time_calls(lambda: union_bwd(U, [L1, L2], "mean", "relu", uembs, uW, ub, None, None, upre, None, udout,
+                                       udemb, udW, udb), max(1, reps // 2)) * 1e3
     res["union"] = {"workload": "Item(i) over two bodies: Item rule on Buys rows 0..10M (K = 384), User body "
                                 "grouped by item on rows 10M..20M (K = 256); MEAN once; FP32",
                     "ms": ms, "tuples_per_s": (b1.E + b2.E) / (ms * 1e-3), "groups": U.G,
+                    "bwd_ms": msb, "fwd_bwd_tuples_per_s": (b1.E + b2.E) / ((ms + msb) * 1e-3),
                     "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_TFLOPS["f32"],
                                  "achieved": ufl / (ms * 1e-3) / 1e12,
-                                 "frac": ufl / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["f32"], "flop": ufl}}
-    log(f"union: {ms:.2f} ms")
-    del U, b1, b2
+                                 "frac": ufl / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["f32"], "flop": ufl},
+                    "bwd_roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
+                                     "achieved": ub_bytes / (msb * 1e-3) / 1e9,
+                                     "frac": ub_bytes / (msb * 1e-3) / 1e9 / PEAK_HBM_GBS, "bytes": ub_bytes}}
+    log(f"union: fwd {ms:.2f} ms, bwd {msb:.2f} ms")
+    del U, b1, b2, uout, upre, udout, ug, udemb, udW, udb
+    torch.cuda.empty_cache()
     # product transform
     ixp = D["ix_item1"]
     Lp = Layer([128, 128, 128], 128, "f32", "mean", "relu", "none", transform="product")
@@ -615,12 +641,33 @@ def next_legs(D, reps: int):
     ms = time_calls(lambda: layer_fwd(ixp, Lp, [D["U"], D["I"], D["C"]], None, want_pre=False, ws=wsp, out=outp),
                     reps) * 1e3
     byt = ixp.E * (3 * 128 * 4 + 16) + ixp.G * 128 * 4
+    # backward (on an index with the transpose orders): per atom one pass
+    # over the tuples reading the group's routed gradient row, the three
+    # rows (the atom's own for ReLU'), three row numbers, the group, the
+    # segment and the tuple's position; the other atoms' row numbers are
+    # first gathered into the atom's order (two reads and a write of 4
+    # bytes each); every joined row's gradient is read and written once
+    ixpb = Index([D["bu"], D["bi"]], [(nu, 0, None), (ni, 1, None), (nc, 2, None)], 1,
+                 chains=[(1, D["bc"], None)], bwd=True)
+    pembs = [D["U"], D["I"], D["C"]]
+    pout, _, _ = layer_fwd(ixpb, Lp, pembs, None)
+    pdout = torch.randn_like(pout)
+    pg = [torch.zeros(x.shape, device="cuda") for x in pembs]
+    msb = time_calls(lambda: layer_bwd(ixpb, Lp, pembs, None, None, None, None, pdout, pg, None),
+                     max(1, reps // 2)) * 1e3
+    byt_b = 3 * ixpb.E * (128 * 4 + 3 * 128 * 4 + 6 * 4) + 3 * 2 * ixpb.E * 12 + sum(
+        x.shape[0] * 128 * 8 for x in pembs)
     res["product"] = {"workload": "Item(i; mean(relu(z_u * z_i * z_c))) over Buys 20M, FP32", "ms": ms,
                       "tuples_per_s": ixp.E / (ms * 1e-3), "hbm_gbs_algorithmic": byt / (ms * 1e-3) / 1e9,
+                      "bwd_ms": msb, "fwd_bwd_tuples_per_s": ixp.E / ((ms + msb) * 1e-3),
                       "roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
                                    "achieved": byt / (ms * 1e-3) / 1e9,
-                                   "frac": byt / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "bytes": byt}}
-    log(f"product: {ms:.2f} ms")
+                                   "frac": byt / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "bytes": byt,
+                                   "bwd_achieved": byt_b / (msb * 1e-3) / 1e9,
+                                   "bwd_frac": byt_b / (msb * 1e-3) / 1e9 / PEAK_HBM_GBS, "bwd_bytes": byt_b}}
+    log(f"product: fwd {ms:.2f} ms, bwd {msb:.2f} ms")
+    del ixpb, pout, pdout, pg
+    torch.cuda.empty_cache()
     # triangle rule
     rule = relgen.triangle_rule(n_graphs=20_000, n_nodes=40, avg_degree=6, d=64, h=64)
     tc = lambda cols: [t(c) for c in cols]

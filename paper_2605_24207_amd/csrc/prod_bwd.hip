@@ -101,6 +101,14 @@ __global__ void __launch_bounds__(kPbWaves * 64) k_prod_bwd(ProdBwdArgs a) {
       int32_t R[RELNN_MAX_ATOMS];
 #pragma unroll
       for (int i = 0; i < RELNN_MAX_ATOMS; ++i) R[i] = i < a.k ? a.rows_t[i][e] : 0;
+      int32_t Rj = 0;                               // atom j's own row, read only for ReLU'
+      const void* ej = a.emb[0];
+#pragma unroll
+      for (int i = 0; i < RELNN_MAX_ATOMS; ++i)
+        if (i == a.j) {
+          Rj = R[i];
+          ej = a.emb[i];
+        }
       for (int bt = 0; bt < n; bt += kPbBatch) {
         float2 v[kPbBatch];
 #pragma unroll
@@ -117,17 +125,14 @@ __global__ void __launch_bounds__(kPbWaves * 64) k_prod_bwd(ProdBwdArgs a) {
           float2 others = make_float2(1.0f, 1.0f), mine = make_float2(1.0f, 1.0f);
 #pragma unroll
           for (int i = 0; i < RELNN_MAX_ATOMS; ++i) {
-            if (i < a.k) {
+            if (i < a.k && i != a.j) {
               const float2 z = row2<kBF16>(a.emb[i], __builtin_amdgcn_readlane(R[i], q), h, cc);
-              if (i == a.j) {
-                mine = z;
-              } else {
-                others.x *= z.x;
-                others.y *= z.y;
-              }
+              others.x *= z.x;
+              others.y *= z.y;
             }
           }
           if (a.act_pre == RELNN_ACT_RELU) {        // act_pre'(z_1 * ... * z_k), ReLU'(0) = 0
+            mine = row2<kBF16>(ej, __builtin_amdgcn_readlane(Rj, q), h, cc);
             d.x = others.x * mine.x > 0.0f ? d.x : 0.0f;
             d.y = others.y * mine.y > 0.0f ? d.y : 0.0f;
           }
