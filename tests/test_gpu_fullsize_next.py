@@ -7,8 +7,11 @@ configuration, on seeded samples of the output that the oracle evaluates.
   sampled targets; dK and dV of sampled sources, whose sums run over every
   group that joins them.
 * Union: Item(i) over two bodies on the halves of Buys 20M (the Item rule,
-  K = 384, and the User rule's body grouped by item, K = 256), MEAN once.
-* Product: Item(i; mean(relu(z_u * z_i * z_c))) over Buys 20M.
+  K = 384, and the User rule's body grouped by item, K = 256), MEAN once;
+  its backward on sampled User, Item and Category rows.
+* Product: Item(i; mean(relu(z_u * z_i * z_c))) over Buys 20M; its
+  backward on sampled User, Item (one of about 50k tuples) and Category
+  rows.
 * Triangle: the DHN triangle rule over 20k graphs of 40 nodes; the graphs are
   disjoint, so the oracle evaluates a sample of whole graphs.
 
@@ -223,3 +226,125 @@ def test_triangle_full_size():
     assert np.array_equal(gk[rows], idx.group_keys)
     assert rel_rows(pre.cpu().numpy()[rows], o_pre).max() <= TOL["f32"]
     assert rel_rows(out.cpu().numpy()[rows], o_out, scale_ref=o_pre).max() <= TOL["f32"]
+
+
+# ------------------------------------------------- backward of the next rows
+def sample_rows(g, rng):
+    """Sampled rows of each ER relation: users and categories at random,
+    items at random plus the one nearest 50k tuples."""
+    users = np.sort(rng.choice(g.user.shape[0], 60, replace=False))
+    big, cnt = near_size_key(g.buys_i, 50_000, rng)
+    items = np.unique(np.concatenate([rng.choice(np.nonzero(cnt)[0], 60, replace=False), [big]]))
+    cats = np.sort(rng.choice(g.cat.shape[0], 2, replace=False))
+    return users, items, cats
+
+
+def touching(rule, g, which, rows):
+    """The rule restricted to the tuples that join one of ``rows`` of the
+    given relation (0 user, 1 item, 2 category)."""
+    r_of = {0: rule.cols[0], 1: rule.cols[1], 2: g.belongs_cat[rule.cols[1]]}[which]
+    sub = copy.copy(rule)
+    sel = np.isin(r_of, rows)
+    sub.cols = [c[sel] for c in rule.cols]
+    return sub
+
+
+def test_product_backward_full_size(er):
+    """Item(i; mean(relu(z_u * z_i * z_c))) over Buys 20M: the gradients of
+    sampled User, Item and Category rows (the hot Item's row sums 50k
+    tuples; a Category's about 20k) against the oracle.  A sampled row's
+    gradient involves only the tuples that join it, each routed its group's
+    gradient over the group's full member count, so the oracle runs SUM over
+    those tuples with dout divided by the full counts (the definition of
+    MEAN's routing)."""
+    import torch
+
+    from paper_2605_24207_amd import Layer, layer_bwd, layer_fwd
+
+    g = er
+    rule = relgen.er_item_rule(g)
+    rule.agg, rule.act_pre, rule.act_post = "mean", "relu", "none"
+    gi = gpu_index(rule, bwd=True)
+    L = Layer([128, 128, 128], 128, "f32", "mean", "relu", "none", transform="product")
+    embs = distinct_embs(rule)
+    out, _, _ = layer_fwd(gi, L, embs, None)
+    dout = torch.from_numpy(np.random.default_rng(15).standard_normal((gi.G, 128)).astype(np.float32)).cuda()
+    demb = [torch.zeros(e.shape, device="cuda") for e in embs]
+    layer_bwd(gi, L, embs, None, None, None, None, dout, demb, None)
+    torch.cuda.synchronize()
+    ex = gi.export()
+    gk = ex["group_keys"].cpu().numpy()
+    cnt = np.diff(ex["offsets"].cpu().numpy()).astype(np.float64)
+    dout = dout.cpu().numpy().astype(np.float64)
+    o_embs = [a.emb for a in rule.atoms]
+    for which, rows in enumerate(sample_rows(g, np.random.default_rng(16))):
+        sub = touching(rule, g, which, rows)
+        idx = orc.build_index(sub)
+        q = np.searchsorted(gk, idx.group_keys)
+        assert np.array_equal(gk[q], idx.group_keys)
+        d = dout[q] / cnt[q][:, None]
+        zero = np.zeros_like(d)
+        ref = orc.product_bwd(idx, o_embs, zero, None, d, "sum", "relu", "none")[which][rows]
+        mask = orc.product(idx, o_embs, slice(None), "none") > 0
+        mag = orc.product_bwd(idx, [np.abs(e) for e in o_embs], zero, None, np.abs(d), "sum", "relu", "none",
+                              pre_mask=mask)[which][rows]
+        got = demb[which].cpu().numpy()[rows]
+        assert rel_rows(got, ref, scale_ref=mag).max() <= TOL["f32"], which
+
+
+def test_union_backward_full_size(er):
+    """The union of two bodies of Item(i) over the halves of Buys 20M, MEAN
+    once, ReLU after: the gradients of sampled User, Item and Category rows
+    (their tuples in both bodies) against the oracle's union backward.  The
+    union's ReLU is taken from the kernel's aggregate and the MEAN over the
+    union's full member counts, so the oracle runs SUM over the tuples that
+    join a sampled row with the gradient so divided."""
+    import torch
+
+    from paper_2605_24207_amd import Union, union_bwd, union_fwd
+
+    g = er
+    half = len(g.buys_u) // 2
+    r1 = relgen.er_item_rule(g)
+    r2 = relgen.er_user_rule(g)
+    r2.group_col = 1
+    r1.cols = [c[:half] for c in r1.cols]
+    r2.cols = [c[half:] for c in r2.cols]
+    U = Union([gpu_index(r, bwd=True) for r in (r1, r2)])
+    dev = {id(a): to_dev(a) for a in (g.user, g.item, g.cat)}
+    embs = [[dev[id(a.emb)] for a in r.atoms] for r in (r1, r2)]
+    grad = {k: torch.zeros(t.shape, device="cuda") for k, t in dev.items()}
+    demb = [[grad[id(a.emb)] for a in r.atoms] for r in (r1, r2)]
+    layers = [gpu_layer(r1), gpu_layer(r2)]
+    Ws, bs = [to_dev(r1.W), to_dev(r2.W)], [to_dev(r1.b), to_dev(r2.b)]
+    out, pre, _ = union_fwd(U, layers, "mean", "relu", embs, Ws, bs)
+    dout = torch.from_numpy(np.random.default_rng(17).standard_normal((U.G, 128)).astype(np.float32)).cuda()
+    dWs = [torch.empty(r.K, 128, device="cuda") for r in (r1, r2)]
+    union_bwd(U, layers, "mean", "relu", embs, Ws, bs, None, None, pre, None, dout, demb, dWs)
+    torch.cuda.synchronize()
+    ex = U.export()
+    keys_all = ex["keys"].cpu().numpy()
+    members = ex["counts"].cpu().numpy().astype(np.float64)
+    dV = dout.cpu().numpy().astype(np.float64) * (pre.cpu().numpy() > 0)
+    for which, rows in enumerate(sample_rows(g, np.random.default_rng(18))):
+        branches, abs_branches = [], []
+        for r in (r1, r2):
+            sub = touching(r, g, which, rows)
+            embs_o, W, b = oracle_inputs(sub, "f32")
+            branches.append((orc.build_index(sub), embs_o, W, b, sub.act_pre))
+            abs_branches.append((branches[-1][0], embs_o, np.abs(W.astype(np.float64)), b, sub.act_pre))
+        keys = np.array(sorted(set().union(*[set(br[0].group_keys.tolist()) for br in branches])), np.int64)
+        q = np.searchsorted(keys_all, keys)
+        assert np.array_equal(keys_all[q], keys)
+        d = dV[q] / members[q][:, None]
+        zero = np.zeros_like(d)
+        grads, _, _ = orc.union_bwd(branches, zero, None, d, "sum", "none")
+        mags, _, _ = orc.union_bwd(abs_branches, zero, None, np.abs(d), "sum", "none")
+        target = (g.user, g.item, g.cat)[which]
+        ref, mag = 0, 0
+        for r, (de, _, _), (dm, _, _) in zip((r1, r2), grads, mags):
+            for a, x, m in zip(r.atoms, de, dm):
+                if a.emb is target:
+                    ref, mag = ref + x[rows], mag + m[rows]
+        got = grad[id(target)].cpu().numpy()[rows]
+        assert rel_rows(got, ref, scale_ref=mag).max() <= TOL["f32"], which
