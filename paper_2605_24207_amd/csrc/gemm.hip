@@ -354,14 +354,17 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
     unit_mg[p] = idx / 32;
     unit_cg[p] = idx % 32;
   }
-  int64_t rn[PER][4];                              // source rows of the units (next tile to load)
+  int32_t rn0[PER][4], rn1[PER][4];                // source rows of the units, two tiles
+  // bf16 A into bf16 tiles moves the raw 16-bit values (no conversion)
+  constexpr bool kRawA = kA16 && kB16;
   struct Stage {                                   // one tile's loads, in registers
     f32x4 x[PER][4];                               // one f32x4 per unit row
+    uint2 raw[PER][4];                             // kRawA: the A unit rows as loaded
     int32_t cnt[PER][4];                           // db weights of the B unit rows
     uint32_t keep[PER][4];                         // routing of the B unit rows: one bit per column
   };
   Stage st0, st1;
-  auto fetch_idx = [&](int64_t t) {
+  auto fetch_idx = [&](int64_t t, int32_t (&rn)[PER][4]) {
 #pragma unroll
     for (int p = 0; p < PER; ++p)
 #pragma unroll
@@ -372,21 +375,25 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
         else if (unit_mat[p] == 1 && a.b.brow)
           rn[p][r] = a.b.brow[m];
         else
-          rn[p][r] = m;
+          rn[p][r] = (int32_t)m;
       }
   };
-  auto fetch_data = [&](int64_t t, Stage& S) {
+  auto fetch_data = [&](int64_t t, Stage& S, const int32_t (&rn)[PER][4]) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
       if (unit_mat[p] == 0) {
         const int col = min(i0 + 4 * unit_cg[p], a.Ka - 4);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          if constexpr (kA16) {
-            const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const __bf16*>(a.A) + rn[p][r] * a.lda + col);
+          if constexpr (kRawA) {
+            S.raw[p][r] =
+                *reinterpret_cast<const uint2*>(static_cast<const __bf16*>(a.A) + (int64_t)rn[p][r] * a.lda + col);
+          } else if constexpr (kA16) {
+            const uint2 v =
+                *reinterpret_cast<const uint2*>(static_cast<const __bf16*>(a.A) + (int64_t)rn[p][r] * a.lda + col);
             S.x[p][r] = bf4_f32(v.x, v.y);
           } else {
-            S.x[p][r] = *reinterpret_cast<const f32x4*>(static_cast<const float*>(a.A) + rn[p][r] * a.lda + col);
+            S.x[p][r] = *reinterpret_cast<const f32x4*>(static_cast<const float*>(a.A) + (int64_t)rn[p][r] * a.lda + col);
           }
         }
       } else {
@@ -394,7 +401,7 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t m = min<int64_t>(t * MT + 4 * unit_mg[p] + r, a.M - 1);
-          S.x[p][r] = *reinterpret_cast<const f32x4*>(a.b.B + rn[p][r] * a.b.ldb + col);
+          S.x[p][r] = *reinterpret_cast<const f32x4*>(a.b.B + (int64_t)rn[p][r] * a.b.ldb + col);
           if (do_db && a.wcnt) S.cnt[p][r] = a.wcnt[m + 1] - a.wcnt[m];
           if (route)                                // the four columns col .. col + 3 of row m
             S.keep[p][r] = 15u & (a.b.own[m * a.b.own_w + (col >> 5)] >> (col & 31));
@@ -409,6 +416,26 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
     for (int p = 0; p < PER; ++p) {
       const int mat = unit_mat[p], mg = unit_mg[p], cg = unit_cg[p];
       const bool col_on = mat == 0 ? i0 + 4 * cg + 4 <= a.Ka : n0 + 4 * cg + 4 <= a.N;
+      LT* dst = base + (mat * 128 + 4 * cg) * TS + 4 * mg;
+      if constexpr (kRawA) {
+        if (mat == 0) {                            // rows r of column cc: 16-bit half cc % 2 of word cc / 2
+          uint2 u[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const bool on = col_on && t * MT + 4 * mg + r < a.M;
+            u[r] = on ? S.raw[p][r] : make_uint2(0u, 0u);
+          }
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) {
+            const uint32_t w0 = cc < 2 ? u[0].x : u[0].y, w1 = cc < 2 ? u[1].x : u[1].y;
+            const uint32_t w2 = cc < 2 ? u[2].x : u[2].y, w3 = cc < 2 ? u[3].x : u[3].y;
+            const uint32_t sel = (cc & 1) ? 0x07060302u : 0x05040100u;
+            *reinterpret_cast<uint2*>(dst + cc * TS) =
+                make_uint2(__builtin_amdgcn_perm(w1, w0, sel), __builtin_amdgcn_perm(w3, w2, sel));
+          }
+          continue;
+        }
+      }
       f32x4 v[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -420,7 +447,6 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
         }
         if (mat == 1 && do_db) dbacc += (on ? (a.wcnt ? (float)S.cnt[p][r] : 1.0f) : 0.0f) * v[r];
       }
-      LT* dst = base + (mat * 128 + 4 * cg) * TS + 4 * mg;
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc) {
         if constexpr (kB16) {
@@ -470,49 +496,34 @@ __global__ void __launch_bounds__(kTnThreads) k_gemm_tn(TnArgs a) {
     }
   };
 
-  // FP32 tiles carry enough products per load to hide the loads one tile
-  // ahead; bf16 tiles (eight times fewer product cycles per byte) load two
-  // tiles ahead, alternating between two register stages so that the ring
-  // index is known at compile time.  Row numbers run one tile ahead of the
-  // values they address.  Tile t is multiplied from LDS buffer (t - tb) & 1
-  // while tile t + 1 is stashed into the other.  Prefetches past the
-  // chunk's last tile repeat it (valid, unused).
+  // Tile t is multiplied from LDS buffer (t - tb) & 1 while tile t + 1 is
+  // stashed into the other.  Values are loaded two tiles ahead into two
+  // register stages and row numbers three tiles ahead into two row buffers,
+  // all at indices known at compile time (the loop runs two tiles a pass).
+  // Each tile's row numbers are loaded before the previous tile's values,
+  // so waiting for them never waits for values still in flight.  Prefetches
+  // past the chunk's last tile repeat it (valid, unused).
   const int64_t tl = te - 1;
-  if constexpr (!kB16) {
-    fetch_idx(tb);
-    fetch_data(tb, st0);
-    fetch_idx(min(tb + 1, tl));
-    stash(0, tb, st0);
+  fetch_idx(tb, rn0);
+  fetch_idx(min(tb + 1, tl), rn1);
+  fetch_data(tb, st0, rn0);
+  fetch_idx(min(tb + 2, tl), rn0);
+  fetch_data(min(tb + 1, tl), st1, rn1);
+  fetch_idx(min(tb + 3, tl), rn1);
+  stash(0, tb, st0);
+  __syncthreads();
+  for (int64_t t = tb; t < te; t += 2) {
+    fetch_data(min(t + 2, tl), st0, rn0);
+    fetch_idx(min(t + 4, tl), rn0);
+    compute(0);
+    if (t + 1 < te) stash(1, t + 1, st1);
     __syncthreads();
-    for (int64_t t = tb; t < te; ++t) {
-      const int b = (int)((t - tb) & 1);
-      fetch_data(min(t + 1, tl), st0);
-      fetch_idx(min(t + 2, tl));
-      compute(b);
-      if (t + 1 < te) stash(b ^ 1, t + 1, st0);
-      __syncthreads();
-    }
-  } else {
-    fetch_idx(tb);
-    fetch_data(tb, st0);
-    fetch_idx(min(tb + 1, tl));
-    fetch_data(min(tb + 1, tl), st1);
-    fetch_idx(min(tb + 2, tl));
-    stash(0, tb, st0);
+    if (t + 1 >= te) break;
+    fetch_data(min(t + 3, tl), st1, rn1);
+    fetch_idx(min(t + 5, tl), rn1);
+    compute(1);
+    if (t + 2 < te) stash(0, t + 2, st0);
     __syncthreads();
-    for (int64_t t = tb; t < te; t += 2) {
-      fetch_data(min(t + 2, tl), st0);
-      fetch_idx(min(t + 3, tl));
-      compute(0);
-      if (t + 1 < te) stash(1, t + 1, st1);
-      __syncthreads();
-      if (t + 1 >= te) break;
-      fetch_data(min(t + 3, tl), st1);
-      fetch_idx(min(t + 4, tl));
-      compute(1);
-      if (t + 2 < te) stash(0, t + 2, st0);
-      __syncthreads();
-    }
   }
   if (wave_on) {
 #pragma unroll
@@ -640,6 +651,7 @@ void gemm_tn(bool mfma_bf16, const void* Asrc, bool a_bf16, int64_t lda, const i
   if (Ka <= 0 || N <= 0) return;
   RELNN_REQUIRE(Ka % 4 == 0 && N % 4 == 0 && lda % 4 == 0 && B.ldb % 4 == 0, RELNN_E_UNSUPPORTED,
                 "product widths %d x %d not supported", Ka, N);
+  RELNN_REQUIRE(M < (int64_t)INT32_MAX, RELNN_E_RANGE, "product over %lld rows", (long long)M);
   if (M <= 0) {
     k_zero_or_keep<<<grid_1d((int64_t)Ka * N), 256, 0, s>>>(D, (int64_t)Ka * N, accumulate ? 1 : 0);
     RELNN_LAUNCHED();
