@@ -268,6 +268,19 @@ relnn_status relnn_layer_bwd(const relnn_index* idx, const relnn_layer_desc* L,
                              float* const* demb, float* dW, float* db,
                              void* ws, size_t ws_bytes, relnn_stream_t stream);
 
+/* Dense layout of an output (Section 2.2: the output content is the set of
+ * head keys that occur, one compact row per group in key order).  dense
+ * row key = compact row g for the group g with that key; the rows of keys
+ * that do not occur are 0 and their present byte 0 (1 for the others).
+ * keys: device [G] ascending distinct, e.g. relnn_index_export's
+ * group_keys or relnn_union_export's keys; compact: device [G, h] FP32 (a
+ * layer's or union's out or pre); dense: device [n_out, h] FP32; present:
+ * device [n_out] uint8 or NULL.  Keys outside [0, n_out): RELNN_E_RANGE,
+ * nothing written.  Reads the first and last key to the host, so it
+ * synchronises `stream`. */
+relnn_status relnn_out_dense(const int32_t* keys, int64_t G, const float* compact, int32_t h, int64_t n_out,
+                             float* dense, uint8_t* present, relnn_stream_t stream);
+
 /* ------------------------------------------------------------ attention */
 
 /* Segmented softmax attention: the paper's attention as rules (Section 1,

@@ -109,6 +109,8 @@ _SIGS = {
     "relnn_attn_bwd": (C.c_int, [C.c_void_p, C.POINTER(AttnDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_size_t, C.c_void_p]),
+    "relnn_out_dense": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]),
     "relnn_union_build": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "relnn_union_query": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "relnn_union_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -379,6 +379,22 @@ class UnionFn(torch.autograd.Function):
         return (None, None, None, None, dW_post, db_post) + tuple(grads)
 
 
+def out_dense(keys: torch.Tensor, compact: torch.Tensor, n_out: int, want_present: bool = True, stream=None):
+    """relnn_out_dense: rows of ``compact`` ([G, h] FP32, one per key of the
+    ascending ``keys`` [G] int32) placed at row key of a dense [n_out, h]
+    tensor, zero elsewhere; returns (dense, present [n_out] uint8 or None)."""
+    if keys.dtype != torch.int32 or keys.dim() != 1 or not keys.is_contiguous():
+        raise TypeError("keys must be a contiguous int32 vector")
+    G = keys.numel()
+    if compact.dtype != torch.float32 or compact.dim() != 2 or compact.shape[0] != G or not compact.is_contiguous():
+        raise TypeError("compact must be a contiguous float32 [G, h] tensor")
+    h = compact.shape[1]
+    dense = torch.empty(n_out, h, dtype=torch.float32, device=compact.device)
+    present = torch.empty(n_out, dtype=torch.uint8, device=compact.device) if want_present else None
+    check(lib().relnn_out_dense(_vp(keys), G, _vp(compact), h, n_out, _vp(dense), _vp(present), _stream(stream)))
+    return dense, present
+
+
 def _lib_alive():
     return L._lib is not None
 

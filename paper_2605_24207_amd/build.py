@@ -18,7 +18,7 @@ ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "prims.hip", "index.hip", "layer_fwd.hip", "layer_ws.hip", "plain.hip", "layer_bwd.hip",
            "bwd_linear.hip", "gemm.hip", "serve.hip", "static_ws.hip", "union.hip", "attn.hip",
-           "prod_bwd.hip"]
+           "prod_bwd.hip", "out_dense.hip"]
 ROCM_LIB = "/opt/rocm/lib"
 
 FLAGS = [
