@@ -89,3 +89,19 @@ def test_static_variant_host_checks_without_gpu():
     ld.flags = _lib.PLAIN
     assert L.relnn_layer_fwd_static(None, ctypes.byref(ld), None, None, None, None, None, None, None) == \
         _lib.E_UNSUPPORTED
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librelnn.so not built")
+def test_union_backward_and_dense_host_checks_without_gpu():
+    from paper_2605_24207_amd import _lib
+
+    L = _lib.lib()
+    n = ctypes.c_size_t()
+    # union calls without a union
+    assert L.relnn_union_bwd_workspace_size(None, None, 0, 16, ctypes.byref(n)) == _lib.E_INVALID
+    assert L.relnn_union_bwd(None, None, 0, 0, None, None, None, None, None, 16, None, None, None, None, None, None,
+                             None, None, None, 0, None) == _lib.E_INVALID
+    # dense layout: a non-positive width, then keys missing for a non-empty output
+    assert L.relnn_out_dense(None, 0, None, 0, 10, None, None, None) == _lib.E_INVALID
+    assert L.relnn_out_dense(None, 5, None, 16, 10, None, None, None) == _lib.E_INVALID
+    assert b"required" in L.relnn_last_error()
