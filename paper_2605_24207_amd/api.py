@@ -225,11 +225,14 @@ class Union:
             pass
 
 
-def _union_args(union: Union, layers, embs, Ws, bs, W_post):
+def _union_args(union: Union, layers, embs, Ws, bs, W_post, dw_accum=None):
     k = union.k
     if not (len(layers) == len(embs) == len(Ws) == k):
         raise ValueError("one layer, embedding list and W per branch")
-    descs = [l.desc() for l in layers]
+    acc = [False] * k if dw_accum is None else [bool(x) for x in dw_accum]
+    if len(acc) != k:
+        raise ValueError("one dw_accum flag per branch")
+    descs = [l.desc(dw_accum=a) for l, a in zip(layers, acc)]
     dptr = (C.POINTER(L.LayerDesc) * k)(*[C.pointer(d) for d in descs])
     emb_arrs = [(C.c_void_p * len(e))(*[t.data_ptr() for t in e]) for e in embs]
     for l, e, W in zip(layers, embs, Ws):
@@ -272,12 +275,14 @@ def union_fwd(union: Union, layers: Sequence["Layer"], agg: str, act_post: str, 
 def union_bwd(union: Union, layers: Sequence["Layer"], agg: str, act_post: str, embs, Ws, bs,
               W_post: Optional[torch.Tensor], b_post: Optional[torch.Tensor], pre: Optional[torch.Tensor],
               argmax: Optional[torch.Tensor], dout: torch.Tensor, demb, dWs, dbs=None,
-              dW_post: Optional[torch.Tensor] = None, db_post: Optional[torch.Tensor] = None, stream=None):
+              dW_post: Optional[torch.Tensor] = None, db_post: Optional[torch.Tensor] = None, dw_accum=None,
+              stream=None):
     """relnn_union_bwd.  demb[i]: FP32 gradient tensors shaped as embs[i]
     (accumulated, may alias); dWs[i], dbs[i]: FP32 gradients of Ws[i], bs[i]
-    (written, or added for a layer with dw_accum); dW_post, db_post: of the
-    union rule's transform (written)."""
-    keep, dptr, emb_pp, W_arr, b_arr, h, h_out = _union_args(union, layers, embs, Ws, bs, W_post)
+    (written, or added where dw_accum[i] is true, so branches sharing one W
+    can share one buffer); dW_post, db_post: of the union rule's transform
+    (written)."""
+    keep, dptr, emb_pp, W_arr, b_arr, h, h_out = _union_args(union, layers, embs, Ws, bs, W_post, dw_accum)
 
     def f32(t, shape, what):
         if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:

@@ -150,6 +150,26 @@ def test_product_backward_three_atoms_hot_group(dtype):
     check_bwd(rule, dtype)
 
 
+def four_atom_rule(agg, act_pre, seed=46, n_link=40_000, h=32):
+    """T(a; agg(act_pre(z_a * z_b * z_c * z_d))) over a link relation with
+    four columns into four relations of different sizes (the most atoms a
+    rule may have)."""
+    rng = np.random.default_rng(seed)
+    sizes = [3000, 5000, 200, 40]
+    cols = [rng.integers(0, n, n_link).astype(np.int32) for n in sizes]
+    atoms = [relgen.Atom(j, rng.standard_normal((n, h)).astype(np.float32)) for j, n in enumerate(sizes)]
+    return relgen.Rule(cols=cols, atoms=atoms, group_col=0, W=np.zeros((4 * h, h), np.float32),
+                       b=np.zeros(h, np.float32), agg=agg, act_pre=act_pre)
+
+
+@pytest.mark.parametrize("agg", ["sum", "max"])
+@pytest.mark.parametrize("act_pre", ["none", "relu"])
+def test_product_four_atoms(agg, act_pre):
+    rule = four_atom_rule(agg, act_pre)
+    check(rule, "f32")
+    check_bwd(rule, "f32")
+
+
 @pytest.mark.parametrize("h", [16, 48, 144])
 def test_product_backward_ragged_width(h):
     """Widths that leave lanes idle in the last 128-column pass (rows stay

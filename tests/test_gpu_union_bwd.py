@@ -265,3 +265,38 @@ def test_union_backward_errors():
     dWs = [torch.zeros_like(W) for W in Ws]
     with pytest.raises(RelnnError, match="INVALID"):
         union_bwd(U, layers, "sum", "none", embs, Ws, None, None, None, pre, am, torch.zeros_like(out), demb, dWs)
+
+
+def test_union_backward_shared_weights_accumulate():
+    """Two bodies with one W and b: the second branch adds its weight
+    gradient into the first one's buffer (RELNN_DW_ACCUM), which then holds
+    the sum of both branches' shares."""
+    import torch
+
+    from paper_2605_24207_amd import Union, union_bwd, union_fwd
+
+    r1 = relgen.node_edge(seed=60, n_nodes=2000, n_edges=20_000, d=64, h=64, bias_std=0.2)
+    r2 = relgen.node_edge(seed=61, n_nodes=2000, n_edges=15_000, d=64, h=64, bias_std=0.2)
+    r2.W, r2.b = r1.W, r1.b
+    r2.atoms = [relgen.Atom(a.col, r1.atoms[0].emb) for a in r2.atoms]   # one relation for all atoms
+    U = Union([gpu_index(r, bwd=True) for r in (r1, r2)])
+    z = to_dev(r1.atoms[0].emb)
+    W, b = to_dev(r1.W), to_dev(r1.b)
+    layers = [gpu_layer(r1), gpu_layer(r2)]
+    out, pre, am = union_fwd(U, layers, "mean", "relu", [[z, z], [z, z]], [W, W], [b, b])
+    dout = torch.from_numpy(np.random.default_rng(6).standard_normal(out.shape).astype(np.float32)).cuda()
+    dz = torch.zeros_like(z)
+    dW = torch.full(W.shape, float("nan"), device="cuda")
+    db = torch.full(b.shape, float("nan"), device="cuda")
+    union_bwd(U, layers, "mean", "relu", [[z, z], [z, z]], [W, W], [b, b], None, None, pre, am, dout,
+              [[dz, dz], [dz, dz]], [dW, dW], [db, db], dw_accum=[False, True])
+    torch.cuda.synchronize()
+    branches = [(orc.build_index(r), [r1.atoms[0].emb] * 2, r1.W, r1.b, "none") for r in (r1, r2)]
+    grads, _, _ = orc.union_bwd(branches, pre.cpu().numpy(), None, dout.cpu().numpy().astype(np.float64),
+                                "mean", "relu")
+    ref_dW = grads[0][1] + grads[1][1]
+    ref_db = grads[0][2] + grads[1][2]
+    ref_dz = sum(g for de, _, _ in grads for g in de)
+    assert fro(dW.cpu().numpy(), ref_dW) <= TOL["f32"]
+    assert fro(db.cpu().numpy(), ref_db) <= TOL["f32"]
+    assert fro(dz.cpu().numpy(), ref_dz) <= TOL["f32"]
