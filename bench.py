@@ -641,12 +641,13 @@ def next_legs(D, reps: int):
     ms = time_calls(lambda: layer_fwd(ixp, Lp, [D["U"], D["I"], D["C"]], None, want_pre=False, ws=wsp, out=outp),
                     reps) * 1e3
     byt = ixp.E * (3 * 128 * 4 + 16) + ixp.G * 128 * 4
-    # backward (on an index with the transpose orders): per atom one pass
-    # over the tuples reading the group's routed gradient row, the three
-    # rows (the atom's own for ReLU'), three row numbers, the group, the
-    # segment and the tuple's position; the other atoms' row numbers are
-    # first gathered into the atom's order (two reads and a write of 4
-    # bytes each); every joined row's gradient is read and written once
+    # backward (on an index with the transpose orders).  Item and Category
+    # are constant inside a group, so their product Q_g is formed once per
+    # group: the User pass reads, per tuple, the group's R_g = dA_g * Q_g row,
+    # its sign bits and three row numbers; the per-group sum pass reads the
+    # User row and two numbers; the Category pass two numbers; per group the
+    # Item, Category, dA, R, S and V rows move once; every joined row's
+    # gradient is read and written once
     ixpb = Index([D["bu"], D["bi"]], [(nu, 0, None), (ni, 1, None), (nc, 2, None)], 1,
                  chains=[(1, D["bc"], None)], bwd=True)
     pembs = [D["U"], D["I"], D["C"]]
@@ -655,8 +656,8 @@ def next_legs(D, reps: int):
     pg = [torch.zeros(x.shape, device="cuda") for x in pembs]
     msb = time_calls(lambda: layer_bwd(ixpb, Lp, pembs, None, None, None, None, pdout, pg, None),
                      max(1, reps // 2)) * 1e3
-    byt_b = 3 * ixpb.E * (128 * 4 + 3 * 128 * 4 + 6 * 4) + 3 * 2 * ixpb.E * 12 + sum(
-        x.shape[0] * 128 * 8 for x in pembs)
+    byt_b = (ixpb.E * (128 * 4 + 32 + 12) + ixpb.E * (128 * 4 + 8) + ixpb.E * 8 + ixpb.G * (7 * 128 * 4 + 32)
+             + sum(x.shape[0] * 128 * 8 for x in pembs))
     res["product"] = {"workload": "Item(i; mean(relu(z_u * z_i * z_c))) over Buys 20M, FP32", "ms": ms,
                       "tuples_per_s": ixp.E / (ms * 1e-3), "hbm_gbs_algorithmic": byt / (ms * 1e-3) / 1e9,
                       "bwd_ms": msb, "fwd_bwd_tuples_per_s": ixp.E / ((ms + msb) * 1e-3),

@@ -170,6 +170,22 @@ def test_product_four_atoms(agg, act_pre):
     check_bwd(rule, "f32")
 
 
+@pytest.mark.parametrize("agg", ["mean", "max"])
+def test_product_backward_no_group_constant_atom(agg):
+    """Grouped by a link column that no atom reads: every atom varies inside
+    a group (one pass per atom over its transpose order)."""
+    rng = np.random.default_rng(47)
+    n_link, h = 30_000, 32
+    cols = [rng.integers(0, 4000, n_link).astype(np.int32), rng.integers(0, 700, n_link).astype(np.int32),
+            rng.integers(0, 2500, n_link).astype(np.int32)]
+    atoms = [relgen.Atom(0, rng.standard_normal((4000, h)).astype(np.float32)),
+             relgen.Atom(1, rng.standard_normal((700, h)).astype(np.float32))]
+    rule = relgen.Rule(cols=cols, atoms=atoms, group_col=2, W=np.zeros((2 * h, h), np.float32),
+                       b=np.zeros(h, np.float32), agg=agg, act_pre="relu")
+    check(rule, "f32")
+    check_bwd(rule, "f32")
+
+
 @pytest.mark.parametrize("h", [16, 48, 144])
 def test_product_backward_ragged_width(h):
     """Widths that leave lanes idle in the last 128-column pass (rows stay
