@@ -428,8 +428,10 @@ void launch_fwd_k(K kern, const AttnArgs& a, hipStream_t s) {
   RELNN_LAUNCHED();
 }
 
-void run_attn_fwd(const AttnArgs& a, hipStream_t s) {
+void run_attn_fwd(const AttnArgs& args, hipStream_t s) {
   KTimer tm("attn_fwd", s);
+  AttnArgs a = args;
+  a.nunits = one_round_units(a.bf16 ? k_attn_fwd<true> : k_attn_fwd<false>, kAtWaves * 64, a.nunits);
   if (a.bf16)
     launch_fwd_k(k_attn_fwd<true>, a, s);
   else
@@ -504,7 +506,8 @@ extern "C" relnn_status relnn_attn_bwd(const relnn_index* idx, const relnn_attn_
       k_group_rows<<<grid_n(G), 256, 0, s>>>(idx->offsets, a.rq, G, qrow);
       RELNN_LAUNCHED();
       a.ntiles = cdiv(E, kAtTM);
-      a.nunits = attn_units(E);
+      a.nunits = one_round_units(a.bf16 ? k_attn_tuple_q<true> : k_attn_tuple_q<false>, kAtWaves * 64,
+                                 attn_units(E));
       const unsigned gu = (unsigned)cdiv(a.nunits, kAtWaves);
       if (a.bf16)
         k_attn_tuple_q<true><<<gu, kAtWaves * 64, 0, s>>>(a, dout, lse, D, Aw, DS, qrow, dq, qcarry);

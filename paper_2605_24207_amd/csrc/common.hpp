@@ -96,6 +96,20 @@ class KTimer {
 };
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Waves of `kernel` (blocks of `threads` threads, no dynamic LDS) that the
+// GPU holds at once: its blocks per CU (the occupancy query, which accounts
+// for its registers) times the CUs.  Cached per kernel.  The range-split
+// kernels launch at most this many waves, so that all of them run in one
+// round instead of a full round followed by a partly empty one.
+int64_t resident_waves(const void* kernel, int threads);
+
+// min(cap, the waves of kernel held at once), at least 1
+template <class KernelT>
+int64_t one_round_units(KernelT kernel, int threads, int64_t cap) {
+  const int64_t r = resident_waves(reinterpret_cast<const void*>(kernel), threads);
+  return std::max<int64_t>(1, std::min<int64_t>(cap, r));
+}
 inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 
 // ------------------------------------------------------------------ device

@@ -30,6 +30,9 @@
 //
 // k_push_sum (pushdown) is a segmented gather-sum of node products, one wave
 // per range of tuples.
+#include <mutex>
+#include <vector>
+
 #include "layer_fwd.hpp"
 
 namespace relnn {
@@ -1471,6 +1474,7 @@ int num_cus() {
   return n;
 }
 
+
 // Tile width: K rounded up to 64, 128, 256 or 384, and 512 for BF16 (an
 // FP32 tile that wide leaves room for two LDS tiles only, no loads ahead).
 int pick_kp(int K, bool bf) {
@@ -1487,6 +1491,19 @@ int pick_hc(int h) {
 
 }  // namespace
 
+int64_t resident_waves(const void* kernel, int threads) {
+  static std::mutex mu;
+  static std::vector<std::pair<const void*, int64_t>> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  for (const auto& e : cache)
+    if (e.first == kernel) return e.second;
+  int blocks = 0;
+  RELNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, threads, 0));
+  const int64_t w = (int64_t)std::max(blocks, 1) * num_cus() * (threads / 64);
+  cache.emplace_back(kernel, w);
+  return w;
+}
+
 void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P, const int32_t* const* rows,
                  float* carry, int32_t* carry_arg, int64_t G, float* V, hipStream_t s) {
   RELNN_REQUIRE(f.h % 4 == 0 && f.h <= kHMax, RELNN_E_UNSUPPORTED, "pushdown needs h %% 4 == 0 and h <= %d", kHMax);
@@ -1495,7 +1512,7 @@ void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P,
   a.E = f.E;
   a.h = f.h;
   a.ntiles = cdiv(f.E, kPsTM);
-  a.nunits = std::max<int64_t>(1, std::min<int64_t>(a.ntiles, nunits));
+  a.nunits = one_round_units(k_push_sum<PS_SUM>, kPsWaves * 64, std::min<int64_t>(a.ntiles, nunits));
   a.b = nullptr;                      // the bias is part of the group constant
   a.act_pre = RELNN_ACT_NONE;
   a.sg = f.sg;
@@ -1538,7 +1555,8 @@ void launch_product(const FwdArgs& f, bool bf16, int64_t nunits, float* carry, i
   a.E = f.E;
   a.h = f.h;
   a.ntiles = cdiv(f.E, kPsTM);
-  a.nunits = std::max<int64_t>(1, std::min<int64_t>(a.ntiles, nunits));
+  a.nunits = one_round_units(bf16 ? k_push_sum<PS_PROD_BF16> : k_push_sum<PS_PROD_F32>, kPsWaves * 64,
+                             std::min<int64_t>(a.ntiles, nunits));
   a.act_pre = f.act_pre;
   a.sg = f.sg;
   a.sink = f.sink;

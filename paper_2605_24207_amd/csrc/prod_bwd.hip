@@ -349,7 +349,7 @@ void prod_bwd(const relnn_index* idx, const relnn_layer_desc* L, const void* con
   base.n = E;
   base.carry = carry;
   base.ntiles = cdiv(E, kPbTM);
-  base.nunits = pb_units(E);
+  base.nunits = one_round_units(bf16 ? k_prod_bwd<true> : k_prod_bwd<false>, kPbWaves * 64, pb_units(E));
   auto run = [&](ProdBwdArgs a, float* out, const int32_t* out_row) {
     a.out = out;
     a.out_row = out_row;
