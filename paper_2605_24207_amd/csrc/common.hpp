@@ -97,6 +97,13 @@ class KTimer {
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// A wave-uniform span of `bytes` bytes as a raw buffer resource (the gfx9
+// resource word 3 for raw 32-bit access): loads through it take the base
+// from scalar registers and a 32-bit lane offset, and read 0 past the end.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
 // Waves of `kernel` (blocks of `threads` threads, no dynamic LDS) that the
 // GPU holds at once: its blocks per CU (the occupancy query, which accounts
 // for its registers) times the CUs.  Cached per kernel.  The range-split

@@ -1294,7 +1294,10 @@ constexpr int kPsTM = 64;       // range boundaries on multiples of 64 positions
 constexpr int kPsWaves = 4;     // waves per block
 constexpr int kPsBatch = 8;     // tuples whose rows are loaded together
 
-template <int kMode>
+// kNA: the number of atoms gathered per tuple, fixed at compile time so
+// that the registers held for one batch's loads are those of kNA atoms
+// (8 waves per SIMD for one atom: more loads in flight per CU).
+template <int kMode, int kNA>
 __global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs pa) {
   const int lane = threadIdx.x % 64;
   const int64_t u = (int64_t)blockIdx.x * kPsWaves + threadIdx.x / 64;
@@ -1352,9 +1355,9 @@ __global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs p
       // row numbers of the 64 positions, one vector per atom (compile-time
       // atom indices: a run-time index into the argument would put it in
       // scratch memory)
-      int32_t R[RELNN_MAX_ATOMS];
+      int32_t R[kNA];
 #pragma unroll
-      for (int j = 0; j < RELNN_MAX_ATOMS; ++j) R[j] = j < pa.n ? pa.rows[j][e] : 0;
+      for (int j = 0; j < kNA; ++j) R[j] = pa.rows[j][e];
       for (int bt = 0; bt < n; bt += kPsBatch) {
         float2 v[kPsBatch];
 #pragma unroll
@@ -1362,16 +1365,21 @@ __global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs p
           const int q = min(bt + i, n - 1);                 // clamped: every load is valid
           v[i] = kMode == PS_SUM ? make_float2(0.0f, 0.0f) : make_float2(1.0f, 1.0f);
 #pragma unroll
-          for (int j = 0; j < RELNN_MAX_ATOMS; ++j) {
-            if (j < pa.n) {
+          for (int j = 0; j < kNA; ++j) {
+            {
               const int32_t row = __builtin_amdgcn_readlane(R[j], q);
+              // the row as a buffer resource (scalar registers) read at a
+              // 32-bit lane offset: a batch of loads holds no per-lane
+              // 64-bit addresses, which keeps 8 waves per SIMD
+              constexpr int esz = kMode == PS_PROD_BF16 ? 2 : 4;
+              const __amdgpu_buffer_rsrc_t rs = row_rsrc(static_cast<const char*>(pa.P[j]) + (int64_t)row * h * esz,
+                                                         (uint32_t)(h * esz));
               float2 p;
               if constexpr (kMode == PS_PROD_BF16) {
-                const uint32_t u = *reinterpret_cast<const uint32_t*>(static_cast<const __bf16*>(pa.P[j]) +
-                                                                      (int64_t)row * h + cc);
+                const uint32_t u = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, 2u * (uint32_t)cc, 0, 0);
                 p = make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
               } else {
-                p = *reinterpret_cast<const float2*>(static_cast<const float*>(pa.P[j]) + (int64_t)row * h + cc);
+                p = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, 4u * (uint32_t)cc, 0, 0));
               }
               if constexpr (kMode == PS_SUM) {
                 v[i].x += p.x;
@@ -1504,6 +1512,17 @@ int64_t resident_waves(const void* kernel, int threads) {
   return w;
 }
 
+template <int kMode>
+auto push_sum_kernel(int n) {
+  return n <= 1 ? k_push_sum<kMode, 1> : n == 2 ? k_push_sum<kMode, 2> : n == 3 ? k_push_sum<kMode, 3>
+                                                                                : k_push_sum<kMode, 4>;
+}
+
+template <int kMode>
+void launch_push_sum(int n, const WsArgs& a, const PushArgs& pa, hipStream_t s) {
+  push_sum_kernel<kMode>(n)<<<(unsigned)cdiv(a.nunits, kPsWaves), kPsWaves * 64, 0, s>>>(a, pa);
+}
+
 void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P, const int32_t* const* rows,
                  float* carry, int32_t* carry_arg, int64_t G, float* V, hipStream_t s) {
   RELNN_REQUIRE(f.h % 4 == 0 && f.h <= kHMax, RELNN_E_UNSUPPORTED, "pushdown needs h %% 4 == 0 and h <= %d", kHMax);
@@ -1512,7 +1531,7 @@ void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P,
   a.E = f.E;
   a.h = f.h;
   a.ntiles = cdiv(f.E, kPsTM);
-  a.nunits = one_round_units(k_push_sum<PS_SUM>, kPsWaves * 64, std::min<int64_t>(a.ntiles, nunits));
+  a.nunits = one_round_units(push_sum_kernel<PS_SUM>(n), kPsWaves * 64, std::min<int64_t>(a.ntiles, nunits));
   a.b = nullptr;                      // the bias is part of the group constant
   a.act_pre = RELNN_ACT_NONE;
   a.sg = f.sg;
@@ -1534,7 +1553,7 @@ void launch_push(const FwdArgs& f, int64_t nunits, int n, const float* const* P,
     pa.rows[j] = rows[j];
   }
   KTimer tm("fwd_push", s);                // gather-sum, fix-up and finish
-  k_push_sum<PS_SUM><<<(unsigned)cdiv(a.nunits, kPsWaves), kPsWaves * 64, 0, s>>>(a, pa);
+  launch_push_sum<PS_SUM>(n, a, pa, s);
   RELNN_LAUNCHED();
   launch_fixup(f.sg, kPsTM, f.h, a.ntiles, a.nunits, raw, carry, carry_arg, s);
   Sink fin = f.sink;
@@ -1555,8 +1574,8 @@ void launch_product(const FwdArgs& f, bool bf16, int64_t nunits, float* carry, i
   a.E = f.E;
   a.h = f.h;
   a.ntiles = cdiv(f.E, kPsTM);
-  a.nunits = one_round_units(bf16 ? k_push_sum<PS_PROD_BF16> : k_push_sum<PS_PROD_F32>, kPsWaves * 64,
-                             std::min<int64_t>(a.ntiles, nunits));
+  a.nunits = one_round_units(bf16 ? push_sum_kernel<PS_PROD_BF16>(f.at.k) : push_sum_kernel<PS_PROD_F32>(f.at.k),
+                             kPsWaves * 64, std::min<int64_t>(a.ntiles, nunits));
   a.act_pre = f.act_pre;
   a.sg = f.sg;
   a.sink = f.sink;
@@ -1571,9 +1590,9 @@ void launch_product(const FwdArgs& f, bool bf16, int64_t nunits, float* carry, i
   }
   KTimer tm("fwd_product", s);
   if (bf16)
-    k_push_sum<PS_PROD_BF16><<<(unsigned)cdiv(a.nunits, kPsWaves), kPsWaves * 64, 0, s>>>(a, pa);
+    launch_push_sum<PS_PROD_BF16>(f.at.k, a, pa, s);
   else
-    k_push_sum<PS_PROD_F32><<<(unsigned)cdiv(a.nunits, kPsWaves), kPsWaves * 64, 0, s>>>(a, pa);
+    launch_push_sum<PS_PROD_F32>(f.at.k, a, pa, s);
   RELNN_LAUNCHED();
   launch_fixup(f.sg, kPsTM, f.h, a.ntiles, a.nunits, f.sink, carry, carry_arg, s);
 }
