@@ -1294,9 +1294,10 @@ constexpr int kPsTM = 64;       // range boundaries on multiples of 64 positions
 constexpr int kPsWaves = 4;     // waves per block
 constexpr int kPsBatch = 8;     // tuples whose rows are loaded together
 
-// kNA: the number of atoms gathered per tuple, fixed at compile time so
-// that the registers held for one batch's loads are those of kNA atoms
-// (8 waves per SIMD for one atom: more loads in flight per CU).
+// kNA: the number of atoms gathered per tuple, fixed at compile time (no
+// run-time atom loop around a batch's loads); with the rows read through
+// buffer resources this took the ER pushdown gather-sum from 2.80 to 1.69
+// ms a launch.
 template <int kMode, int kNA>
 __global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs pa) {
   const int lane = threadIdx.x % 64;
@@ -1370,7 +1371,7 @@ __global__ void __launch_bounds__(kPsWaves * 64) k_push_sum(WsArgs a, PushArgs p
               const int32_t row = __builtin_amdgcn_readlane(R[j], q);
               // the row as a buffer resource (scalar registers) read at a
               // 32-bit lane offset: a batch of loads holds no per-lane
-              // 64-bit addresses, which keeps 8 waves per SIMD
+              // 64-bit addresses
               constexpr int esz = kMode == PS_PROD_BF16 ? 2 : 4;
               const __amdgpu_buffer_rsrc_t rs = row_rsrc(static_cast<const char*>(pa.P[j]) + (int64_t)row * h * esz,
                                                          (uint32_t)(h * esz));
