@@ -568,12 +568,19 @@ def next_legs(D, reps: int):
         dout = torch.randn_like(out)
         dq, dk, dv = (torch.zeros(x.shape, device="cuda") for x in (q, k, v))
         msb = time_calls(lambda: attn_bwd(ix, q, k, v, 8, 0.25, out, lse, dout, dq, dk, dv), max(1, reps // 2)) * 1e3
-        byt = ix.E * (3 * d * esz + 16) + ix.G * d * 4                  # q, k, v rows + indices per tuple; out
-        # backward: the weights pass reads q, k, v and dout rows and writes two
-        # weights per head; the three gather-sums read a row, a weight and two
-        # indices per tuple, and add each segment's row once
-        byt_b = (ix.E * (3 * d * esz + d * 4 + 2 * 8 * 4 + 16) + ix.E * (2 * d * esz + d * 4 + 3 * (4 + 8))
-                 + 2 * (ix.G * d * 4 + n_s * d * 4 * 2))
+        # Algorithmic bytes.  A row that is constant inside a group (here Q's,
+        # keyed by the target) counts once per group: the tuples come sorted
+        # by group, so it need not move more than once.  Forward: k and v
+        # rows and three row numbers per tuple; the q row, the output and the
+        # log-sum-exps per group.
+        byt = ix.E * (2 * d * esz + 12) + ix.G * (d * esz + d * 4 + 8 * 4)
+        # backward: the weights pass reads k and v rows and writes two
+        # weights per head per tuple, and per group the q and dout rows, D
+        # and lse, and writes dQ; the dK and dV gather-sums read a q or dout
+        # row, the head weights and three numbers per tuple, and add into
+        # each source row once
+        byt_b = (ix.E * (2 * d * esz + 2 * 8 * 4 + 12) + ix.G * (d * esz + 2 * d * 4 + 2 * 8 * 4)
+                 + ix.E * (d * esz + 8 * 4 + 12) + ix.E * (d * 4 + 8 * 4 + 12) + 2 * n_s * d * 4 * 2)
         att[dt] = {"fwd_ms": ms, "fwd_tuples_per_s": ix.E / (ms * 1e-3), "fwd_hbm_gbs_algorithmic": byt / (ms * 1e-3) / 1e9,
                    "bwd_ms": msb, "fwd_bwd_tuples_per_s": ix.E / ((ms + msb) * 1e-3),
                    "roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
@@ -640,7 +647,9 @@ def next_legs(D, reps: int):
     outp = torch.empty(ixp.G, 128, device="cuda")
     ms = time_calls(lambda: layer_fwd(ixp, Lp, [D["U"], D["I"], D["C"]], None, want_pre=False, ws=wsp, out=outp),
                     reps) * 1e3
-    byt = ixp.E * (3 * 128 * 4 + 16) + ixp.G * 128 * 4
+    # forward: the User row and four numbers per tuple; the Item and
+    # Category rows, constant inside a group, once per group, and the output
+    byt = ixp.E * (128 * 4 + 16) + ixp.G * (2 * 128 * 4 + 128 * 4)
     # backward (on an index with the transpose orders).  Item and Category
     # are constant inside a group, so their product Q_g is formed once per
     # group: the User pass reads, per tuple, the group's R_g = dA_g * Q_g row,
