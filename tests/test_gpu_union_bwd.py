@@ -164,15 +164,16 @@ def test_union_backward_two_bodies(agg, dtype):
     check([r1, r2], agg, dtype)
 
 
-@pytest.mark.parametrize("agg", ["max", "mean"])
-def test_union_backward_three_branches_post_transform(agg):
-    """Three bodies, then the union rule's transform 128 -> 96 and ReLU."""
+@pytest.mark.parametrize("agg,dtype", [("max", "f32"), ("mean", "f32"), ("mean", "bf16"), ("max", "bf16")])
+def test_union_backward_three_branches_post_transform(agg, dtype):
+    """Three bodies, then the union rule's transform 128 -> 96 and ReLU
+    (FP32 W_post over bf16 branch layers in the BF16 cases)."""
     r1, r2 = er_rules(seed=8, n_buys=40_000)
     r3 = relgen.node_edge(seed=17, n_nodes=3000, n_edges=20_000, d=128, h=128, bias_std=0.1)
     rng = np.random.default_rng(4)
     post = (rng.standard_normal((128, 96)).astype(np.float32) / np.sqrt(128),
             rng.standard_normal(96).astype(np.float32))
-    check([r1, r2, r3], agg, "f32", post=post)
+    check([r1, r2, r3], agg, dtype, post=post)
 
 
 def test_union_max_maximisers():
