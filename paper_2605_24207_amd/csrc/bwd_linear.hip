@@ -58,26 +58,45 @@ __device__ __forceinline__ GsAtom gs_atom(const GsArgs& a, int col) {
   return r;
 }
 
-// VW (4 or 2) consecutive elements of the joined row at list position e,
-// as FP32 (the unused lanes of an f32x4 are zero).
+// The words holding VW (4 or 2) consecutive elements of the joined row at
+// list position e (bf16: VW/2 words, FP32: VW words; the rest zero).  The
+// conversion to FP32 is kept apart (gs_cvt) so that it is done where the
+// value is added: a use right after the load would make the wave wait for
+// each row before it asks for the next.
 template <int VW, bool kBF16>
-__device__ __forceinline__ f32x4 gs_load(const GsArgs& a, const GsAtom& A, int32_t row, int col) {
+__device__ __forceinline__ uint4 gs_load_raw(const GsAtom& A, int32_t row, int col) {
   const int64_t o = (int64_t)row * A.d + (col - A.koff);
-  if constexpr (VW == 4) {
-    if constexpr (kBF16) {
-      const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const __bf16*>(A.emb) + o);
-      return f32x4{__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u), __uint_as_float(v.y << 16),
-                   __uint_as_float(v.y & 0xffff0000u)};
+  uint4 r{0u, 0u, 0u, 0u};
+  if constexpr (kBF16) {
+    const __bf16* p = static_cast<const __bf16*>(A.emb) + o;
+    if constexpr (VW == 4) {
+      const uint2 v = *reinterpret_cast<const uint2*>(p);
+      r.x = v.x;
+      r.y = v.y;
+    } else {
+      r.x = *reinterpret_cast<const uint32_t*>(p);
     }
-    return *reinterpret_cast<const f32x4*>(static_cast<const float*>(A.emb) + o);
   } else {
-    if constexpr (kBF16) {
-      const uint32_t v = *reinterpret_cast<const uint32_t*>(static_cast<const __bf16*>(A.emb) + o);
-      return f32x4{__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u), 0.f, 0.f};
+    const float* p = static_cast<const float*>(A.emb) + o;
+    if constexpr (VW == 4) {
+      r = *reinterpret_cast<const uint4*>(p);
+    } else {
+      const uint2 v = *reinterpret_cast<const uint2*>(p);
+      r.x = v.x;
+      r.y = v.y;
     }
-    const float2 v = *reinterpret_cast<const float2*>(static_cast<const float*>(A.emb) + o);
-    return f32x4{v.x, v.y, 0.f, 0.f};
   }
+  return r;
+}
+
+// The VW elements of gs_load_raw's words as FP32 (the unused lanes of the
+// f32x4 are zero).
+template <bool kBF16>
+__device__ __forceinline__ f32x4 gs_cvt(uint4 r) {
+  if constexpr (kBF16)
+    return f32x4{__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u), __uint_as_float(r.y << 16),
+                 __uint_as_float(r.y & 0xffff0000u)};
+  return f32x4{__uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), __uint_as_float(r.w)};
 }
 
 // out[s] = sum over the positions e of segment s of the joined row at e.
@@ -87,7 +106,9 @@ __device__ __forceinline__ f32x4 gs_load(const GsArgs& a, const GsAtom& A, int32
 // start) or 1 (runs past the end); k_fixup combines them in unit order.
 // VW columns per lane: 4, or 2 for rows of at most 128 elements (all 64
 // lanes busy; a wave instruction costs the same with 32 or 64 lanes on).
-template <int VW, bool kBF16>
+// kTw: the sum may scale rows by a per-tuple weight (wgt) or mask them by
+// per-tuple ownership bits (own).
+template <int VW, bool kBF16, bool kTw>
 __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
   const int lane = threadIdx.x % 64;
   const int64_t u = (int64_t)blockIdx.x * kGsWaves + threadIdx.x / 64;
@@ -144,7 +165,12 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
 #pragma unroll
       for (int j = 0; j < kMaxAtoms; ++j) R[j] = (a.rows[j] ? a.rows[j] : a.rows[0])[e];
       for (int bt = 0; bt < n; bt += kGsBatch) {
-        f32x4 v[kGsBatch];
+        // all loads of the batch first (rows, and the weight or ownership
+        // word of each tuple), then the conversions and the adds in order
+        uint4 raw[kGsBatch];
+        float wv[kGsBatch];
+        uint32_t ob[kGsBatch];
+        const int cc = on ? col : 0;
 #pragma unroll
         for (int i = 0; i < kGsBatch; ++i) {
           const int q = min(bt + i, n - 1);           // clamped: every load is valid
@@ -154,19 +180,11 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
             const int32_t rj = __builtin_amdgcn_readlane(R[j], q);
             row = A.j == j ? rj : row;
           }
-          v[i] = gs_load<VW, kBF16>(a, A, row, on ? col : 0);
-          if (a.wgt) {                                  // one weight per tuple and column block
+          raw[i] = gs_load_raw<VW, kBF16>(A, row, cc);
+          if constexpr (kTw) {
             const int32_t tau = __builtin_amdgcn_readlane(R[1], q);
-            const float wv = a.wgt[(int64_t)tau * a.wh + (on ? col : 0) / a.whd];
-#pragma unroll
-            for (int x = 0; x < VW; ++x) v[i][x] *= wv;
-          }
-          if (a.own) {                                  // route the gradient row of this tuple:
-            const int32_t tau = __builtin_amdgcn_readlane(R[1], q);   // VW columns of one 32-column word
-            const int cc = on ? col : 0;
-            const uint32_t bits = a.own[(int64_t)tau * a.own_w + (cc >> 5)] >> (cc & 31);
-#pragma unroll
-            for (int x = 0; x < VW; ++x) v[i][x] = ((bits >> x) & 1u) ? v[i][x] : 0.0f;
+            wv[i] = a.wgt ? a.wgt[(int64_t)tau * a.wh + cc / a.whd] : 1.0f;   // one weight per tuple and column block
+            ob[i] = a.own ? a.own[(int64_t)tau * a.own_w + (cc >> 5)] : ~0u;   // VW columns of one 32-column word
           }
         }
 #pragma unroll
@@ -178,10 +196,19 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
             flush(false);
             g = gq;
           }
+          f32x4 v = gs_cvt<kBF16>(raw[i]);
+          if (kTw && a.wgt) {
+#pragma unroll
+            for (int x = 0; x < VW; ++x) v[x] *= wv[i];
+          }
+          if (kTw && a.own) {                           // route the gradient row of this tuple
+#pragma unroll
+            for (int x = 0; x < VW; ++x) v[x] = ((ob[i] >> ((cc & 31) + x)) & 1u) ? v[x] : 0.0f;
+          }
 #pragma unroll
           for (int x = 0; x < VW; ++x) {
             float sx = s[x], cx = c[x];
-            kahan_add1(sx, cx, v[i][x]);
+            kahan_add1(sx, cx, v[x]);
             s[x] = sx;
             c[x] = cx;
           }
@@ -209,16 +236,20 @@ void seg_gather_sum(GsArgs a, int64_t nseg_units_cap, hipStream_t s) {
   RELNN_REQUIRE(a.nunits <= nseg_units_cap, RELNN_E_HIP, "internal: carry region too small");
   RELNN_REQUIRE(a.K % 4 == 0, RELNN_E_UNSUPPORTED, "row width %d is not a multiple of 4", a.K);
   const unsigned g = (unsigned)cdiv(a.nunits, kGsWaves);
+  // the per-tuple weight and ownership words cost registers in every
+  // variant that may read them; plain sums use one that does not
+  const bool tw = a.wgt || a.own;
+  auto go = [&](auto kern) { kern<<<g, kGsWaves * 64, 0, s>>>(a); };
   if (a.K <= 128) {
     if (a.bf16)
-      k_seg_gather_sum<2, true><<<g, kGsWaves * 64, 0, s>>>(a);
+      tw ? go(k_seg_gather_sum<2, true, true>) : go(k_seg_gather_sum<2, true, false>);
     else
-      k_seg_gather_sum<2, false><<<g, kGsWaves * 64, 0, s>>>(a);
+      tw ? go(k_seg_gather_sum<2, false, true>) : go(k_seg_gather_sum<2, false, false>);
   } else {
     if (a.bf16)
-      k_seg_gather_sum<4, true><<<g, kGsWaves * 64, 0, s>>>(a);
+      tw ? go(k_seg_gather_sum<4, true, true>) : go(k_seg_gather_sum<4, true, false>);
     else
-      k_seg_gather_sum<4, false><<<g, kGsWaves * 64, 0, s>>>(a);
+      tw ? go(k_seg_gather_sum<4, false, true>) : go(k_seg_gather_sum<4, false, false>);
   }
   RELNN_LAUNCHED();
   // the fix-up reads carry slots and writes out rows with stride ldo
