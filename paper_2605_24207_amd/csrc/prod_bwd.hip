@@ -44,6 +44,12 @@ struct ProdBwdArgs {
   const int32_t* rows_t[RELNN_MAX_ATOMS];    // row of atom i at each position (atoms read only)
   uint32_t mult;                             // atoms whose rows multiply the term
   uint32_t sgn;                              // atoms whose signs enter act_pre'
+  // the atoms a pass reads (mult, and sgn under ReLU), in atom order:
+  // table, rows in the pass's order, and whether each multiplies (bit k of
+  // lmult) or gives its sign (bit k of lsgn); filled at launch
+  const void* lemb[RELNN_MAX_ATOMS];
+  const int32_t* lrows[RELNN_MAX_ATOMS];
+  uint32_t lmult, lsgn;
   const uint32_t* qsign;                     // [G][2][own_w]: Q_g > 0, Q_g < 0 bits, or null (Q = 1)
   const int32_t* grp_t;                      // group of the tuple at each position
   const int32_t* tau_t;                      // its canonical position, or null (the position itself)
@@ -78,7 +84,25 @@ __device__ __forceinline__ float2 row2(const void* base, int32_t row, int h, int
   }
 }
 
+// The words of row2's two elements, loaded as they are (bf16: one word,
+// FP32: two); row2_cvt turns them into FP32 where they are used, so that a
+// batch's loads are all in flight before the first use waits for them.
 template <bool kBF16>
+__device__ __forceinline__ uint2 row2_raw(const void* base, int32_t row, int h, int col) {
+  if constexpr (kBF16)
+    return make_uint2(*reinterpret_cast<const uint32_t*>(static_cast<const __bf16*>(base) + (int64_t)row * h + col), 0u);
+  else
+    return *reinterpret_cast<const uint2*>(static_cast<const float*>(base) + (int64_t)row * h + col);
+}
+
+template <bool kBF16>
+__device__ __forceinline__ float2 row2_cvt(uint2 u) {
+  if constexpr (kBF16) return make_float2(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u));
+  return make_float2(__uint_as_float(u.x), __uint_as_float(u.y));
+}
+
+// kNL: the number of atoms whose rows the pass reads (lemb, lrows).
+template <bool kBF16, int kNL>
 __global__ void __launch_bounds__(kPbWaves * 64) k_prod_bwd(ProdBwdArgs a) {
   const int lane = threadIdx.x % 64;
   const int64_t u = (int64_t)blockIdx.x * kPbWaves + threadIdx.x / 64;
@@ -87,7 +111,7 @@ __global__ void __launch_bounds__(kPbWaves * 64) k_prod_bwd(ProdBwdArgs a) {
   const int64_t r1 = min<int64_t>(((a.ntiles * (u + 1)) / a.nunits) * kPbTM, a.n);
   if (r0 >= r1) return;
   const int h = a.h;
-  const uint32_t loads = a.mult | (a.relu ? a.sgn : 0u);
+  constexpr int kNA = kNL > 0 ? kNL : 1;
   for (int cb = 0; cb < h; cb += 128) {
     const int col = cb + 2 * lane;
     const bool on = col < h;
@@ -121,57 +145,45 @@ __global__ void __launch_bounds__(kPbWaves * 64) k_prod_bwd(ProdBwdArgs a) {
       const int32_t T = a.own ? (a.tau_t ? a.tau_t[e] : (int32_t)e) : 0;
       // the group of the position before the block (first_only)
       const int32_t gprev = (a.first_only && base > 0) ? a.grp_t[base - 1] : -1;
-      // rows of the 64 positions, one vector per atom (compile-time atom
-      // indices: a run-time index into the argument would go to scratch)
-      int32_t R[RELNN_MAX_ATOMS];
+      // rows of the 64 positions, one vector per read atom
+      int32_t R[kNA];
 #pragma unroll
-      for (int i = 0; i < RELNN_MAX_ATOMS; ++i) R[i] = ((loads >> i) & 1u) ? a.rows_t[i][e] : 0;
+      for (int i = 0; i < kNL; ++i) R[i] = a.lrows[i][e];
       for (int bt = 0; bt < n; bt += kPbBatch) {
-        float2 v[kPbBatch];
+        // the batch's group, position and row numbers first (one wait for
+        // the vectors they come from), then its loads (factor rows,
+        // maximiser and sign words, atom rows), then its arithmetic
+        int32_t sgrp[kPbBatch], sprev[kPbBatch], stau[kPbBatch], srow[kPbBatch][kNA];
 #pragma unroll
         for (int b = 0; b < kPbBatch; ++b) {
           const int q = min(bt + b, n - 1);         // clamped: every load is valid
-          const int32_t grp = __builtin_amdgcn_readlane(G, q);
-          if (a.first_only) {                       // a group's term once per segment: no loads for the rest
-            const int32_t gp = q > 0 ? __builtin_amdgcn_readlane(G, q - 1) : gprev;
-            if (gp == grp) {
-              v[b] = make_float2(0.0f, 0.0f);
-              continue;
-            }
-          }
-          float2 d = *reinterpret_cast<const float2*>(a.B + (int64_t)grp * h + cc);
-          if (a.own) {                              // MAX: the columns this tuple maximises
-            const int32_t tau = __builtin_amdgcn_readlane(T, q);
-            const uint32_t bits = a.own[(int64_t)tau * a.own_w + (cc >> 5)] >> (cc & 31);
-            d.x = (bits & 1u) ? d.x : 0.0f;
-            d.y = (bits & 2u) ? d.y : 0.0f;
-          }
-          float2 m = make_float2(1.0f, 1.0f), ps = make_float2(1.0f, 1.0f);
+          sgrp[b] = __builtin_amdgcn_readlane(G, q);
+          sprev[b] = q > 0 ? __builtin_amdgcn_readlane(G, q - 1) : gprev;
+          stau[b] = __builtin_amdgcn_readlane(T, q);
 #pragma unroll
-          for (int i = 0; i < RELNN_MAX_ATOMS; ++i) {
-            if ((loads >> i) & 1u) {
-              const float2 z = row2<kBF16>(a.emb[i], __builtin_amdgcn_readlane(R[i], q), h, cc);
-              if ((a.mult >> i) & 1u) {
-                m.x *= z.x;
-                m.y *= z.y;
-              }
-              if ((a.sgn >> i) & 1u) {
-                ps.x *= z.x;
-                ps.y *= z.y;
-              }
-            }
+          for (int i = 0; i < kNL; ++i) srow[b][i] = __builtin_amdgcn_readlane(R[i], q);
+        }
+        float2 dr[kPbBatch];
+        uint32_t ow[kPbBatch], qp[kPbBatch], qn[kPbBatch];
+        uint2 zr[kPbBatch][kNA];
+        uint32_t skip = 0u;                         // positions whose term is zero (first_only)
+#pragma unroll
+        for (int b = 0; b < kPbBatch; ++b) {
+          const int32_t grp = sgrp[b];
+          if (a.first_only && sprev[b] == grp) {    // a group's term once per segment: no loads for the rest
+            skip |= 1u << b;
+            continue;
           }
-          if (a.relu) {                             // act_pre'(product) = [product > 0], ReLU'(0) = 0
-            if (a.qsign) {                          // times the sign of the group's factor Q_g
-              const uint32_t* qs = a.qsign + (int64_t)grp * 2 * a.own_w + (cc >> 5);
-              const uint32_t pos = qs[0] >> (cc & 31), neg = qs[a.own_w] >> (cc & 31);
-              ps.x = (pos & 1u) ? ps.x : ((neg & 1u) ? -ps.x : 0.0f);
-              ps.y = (pos & 2u) ? ps.y : ((neg & 2u) ? -ps.y : 0.0f);
-            }
-            d.x = ps.x > 0.0f ? d.x : 0.0f;
-            d.y = ps.y > 0.0f ? d.y : 0.0f;
+          dr[b] = *reinterpret_cast<const float2*>(a.B + (int64_t)grp * h + cc);
+          if (a.own)                                // MAX: the columns this tuple maximises
+            ow[b] = a.own[(int64_t)stau[b] * a.own_w + (cc >> 5)];
+#pragma unroll
+          for (int i = 0; i < kNL; ++i) zr[b][i] = row2_raw<kBF16>(a.lemb[i], srow[b][i], h, cc);
+          if (a.relu && a.qsign) {                  // the signs of the group's factor Q_g
+            const uint32_t* qs = a.qsign + (int64_t)grp * 2 * a.own_w + (cc >> 5);
+            qp[b] = qs[0];
+            qn[b] = qs[a.own_w];
           }
-          v[b] = make_float2(d.x * m.x, d.y * m.y);
         }
 #pragma unroll
         for (int b = 0; b < kPbBatch; ++b) {
@@ -182,8 +194,40 @@ __global__ void __launch_bounds__(kPbWaves * 64) k_prod_bwd(ProdBwdArgs a) {
             flush(false);
             g = gq;
           }
-          kahan_add(s0, c0, v[b].x);
-          kahan_add(s1, c1, v[b].y);
+          float2 v = make_float2(0.0f, 0.0f);
+          if (!((skip >> b) & 1u)) {
+            float2 d = dr[b];
+            if (a.own) {
+              const uint32_t bits = ow[b] >> (cc & 31);
+              d.x = (bits & 1u) ? d.x : 0.0f;
+              d.y = (bits & 2u) ? d.y : 0.0f;
+            }
+            float2 m = make_float2(1.0f, 1.0f), ps = make_float2(1.0f, 1.0f);
+#pragma unroll
+            for (int i = 0; i < kNL; ++i) {
+              const float2 z = row2_cvt<kBF16>(zr[b][i]);
+              if ((a.lmult >> i) & 1u) {
+                m.x *= z.x;
+                m.y *= z.y;
+              }
+              if ((a.lsgn >> i) & 1u) {
+                ps.x *= z.x;
+                ps.y *= z.y;
+              }
+            }
+            if (a.relu) {                           // act_pre'(product) = [product > 0], ReLU'(0) = 0
+              if (a.qsign) {                        // times the sign of the group's factor Q_g
+                const uint32_t pos = qp[b] >> (cc & 31), neg = qn[b] >> (cc & 31);
+                ps.x = (pos & 1u) ? ps.x : ((neg & 1u) ? -ps.x : 0.0f);
+                ps.y = (pos & 2u) ? ps.y : ((neg & 2u) ? -ps.y : 0.0f);
+              }
+              d.x = ps.x > 0.0f ? d.x : 0.0f;
+              d.y = ps.y > 0.0f ? d.y : 0.0f;
+            }
+            v = make_float2(d.x * m.x, d.y * m.y);
+          }
+          kahan_add(s0, c0, v.x);
+          kahan_add(s1, c1, v.y);
         }
       }
     }
@@ -349,16 +393,41 @@ void prod_bwd(const relnn_index* idx, const relnn_layer_desc* L, const void* con
   base.n = E;
   base.carry = carry;
   base.ntiles = cdiv(E, kPbTM);
-  base.nunits = one_round_units(bf16 ? k_prod_bwd<true> : k_prod_bwd<false>, kPbWaves * 64, pb_units(E));
   auto run = [&](ProdBwdArgs a, float* out, const int32_t* out_row) {
     a.out = out;
     a.out_row = out_row;
+    // the atoms the pass reads, in atom order (their rows in rows_t)
+    const uint32_t loads = a.mult | (a.relu ? a.sgn : 0u);
+    int nl = 0;
+    a.lmult = a.lsgn = 0u;
+    for (int i = 0; i < RELNN_MAX_ATOMS; ++i) {
+      if (!((loads >> i) & 1u)) continue;
+      a.lemb[nl] = a.emb[i];
+      a.lrows[nl] = a.rows_t[i];
+      if ((a.mult >> i) & 1u) a.lmult |= 1u << nl;
+      if ((a.sgn >> i) & 1u) a.lsgn |= 1u << nl;
+      ++nl;
+    }
     {
       KTimer tm("bwd_dx", s);
+      auto go = [&](auto kern) {
+        a.nunits = one_round_units(kern, kPbWaves * 64, pb_units(E));
+        kern<<<(unsigned)cdiv(a.nunits, kPbWaves), kPbWaves * 64, 0, s>>>(a);
+      };
+      auto pick = [&](auto B) {
+        constexpr bool kB = decltype(B)::value;
+        switch (nl) {
+          case 0: go(k_prod_bwd<kB, 0>); break;
+          case 1: go(k_prod_bwd<kB, 1>); break;
+          case 2: go(k_prod_bwd<kB, 2>); break;
+          case 3: go(k_prod_bwd<kB, 3>); break;
+          default: go(k_prod_bwd<kB, 4>); break;
+        }
+      };
       if (bf16)
-        k_prod_bwd<true><<<(unsigned)cdiv(a.nunits, kPbWaves), kPbWaves * 64, 0, s>>>(a);
+        pick(std::true_type{});
       else
-        k_prod_bwd<false><<<(unsigned)cdiv(a.nunits, kPbWaves), kPbWaves * 64, 0, s>>>(a);
+        pick(std::false_type{});
       RELNN_LAUNCHED();
     }
     Sink sk{};
