@@ -214,20 +214,25 @@ __global__ void __launch_bounds__(256) k_attn_tuple(AttnArgs a, const int32_t* t
     const int64_t e = base + min(lane, n - 1);
     const int32_t Rq = a.rq[e], Rk = a.rk[e], Rv = a.rv[e], Rg = tuple_group[e];
     for (int bt = 0; bt < n; bt += kTupB) {
+      // every load of the batch first (the group's lse and D included),
+      // so that the arithmetic waits once for all of them
       float2 qv[kTupB], kv[kTupB], vv[kTupB], dv[kTupB];
+      float lw[kTupB], dw[kTupB];
 #pragma unroll
       for (int i = 0; i < kTupB; ++i) {               // clamped: every load is valid
         const int q = min(bt + i, n - 1);
+        const int64_t gi = __builtin_amdgcn_readlane(Rg, q);
         qv[i] = ld2<kBF16>(a.q, __builtin_amdgcn_readlane(Rq, q), a.d, cqc);
         kv[i] = ld2<kBF16>(a.k, __builtin_amdgcn_readlane(Rk, q), a.d, cqc);
         vv[i] = ld2<kBF16>(a.v, __builtin_amdgcn_readlane(Rv, q), a.dv, cvc);
-        dv[i] = *reinterpret_cast<const float2*>(dout + (int64_t)__builtin_amdgcn_readlane(Rg, q) * a.dv + cvc);
+        dv[i] = *reinterpret_cast<const float2*>(dout + gi * a.dv + cvc);
+        lw[i] = lse[gi * a.heads + h];
+        dw[i] = D[gi * a.heads + h];
       }
 #pragma unroll
       for (int i = 0; i < kTupB; ++i) {
         if (bt + i >= n) break;
         const int64_t t = base + bt + i;
-        const int64_t g = __builtin_amdgcn_readlane(Rg, bt + i);
         float p = on_q ? qv[i].x * kv[i].x + qv[i].y * kv[i].y : 0.0f;
         for (int off = 1; off < hq_lanes; off <<= 1) p += __shfl_xor(p, off);
         float dp = on_v ? dv[i].x * vv[i].x + dv[i].y * vv[i].y : 0.0f;
@@ -235,9 +240,9 @@ __global__ void __launch_bounds__(256) k_attn_tuple(AttnArgs a, const int32_t* t
         // lane h * hv_lanes writes head h; its score sits on lane h * hq_lanes
         const float sc = a.scale * __shfl(p, h * hq_lanes);
         if (on_v && cv % a.hdv == 0) {
-          const float w = expf(sc - lse[g * a.heads + h]);
+          const float w = expf(sc - lw[i]);
           A[t * a.heads + h] = w;
-          DS[t * a.heads + h] = a.scale * w * (dp - D[g * a.heads + h]);
+          DS[t * a.heads + h] = a.scale * w * (dp - dw[i]);
         }
       }
     }
@@ -281,6 +286,11 @@ __global__ void __launch_bounds__(kAtWaves * 64) k_attn_tuple_q(AttnArgs a, cons
   int32_t g = a.sg.seg_of[r0];
   const bool lo_cont = r0 > 0 && a.sg.seg_of[r0 - 1] == g;
   bool first = true;
+  // the open group's Q row and that row's dQ so far, fetched when the group
+  // opens (each row is written by one wave only), so that closing it waits
+  // for neither
+  int32_t grow = qrow[g];
+  float2 gold = on_q ? *reinterpret_cast<const float2*>(dq + (int64_t)grow * a.d + cq) : make_float2(0.f, 0.f);
   auto flush = [&](bool last_seg) {
     const bool cut_lo = first && lo_cont;
     const bool cut_hi = last_seg && r1 < a.E && a.sg.seg_of[r1] == g;
@@ -289,9 +299,7 @@ __global__ void __launch_bounds__(kAtWaves * 64) k_attn_tuple_q(AttnArgs a, cons
       if (cut_lo || cut_hi) {
         *reinterpret_cast<float2*>(carry + (u * 2 + (cut_lo ? 0 : 1)) * a.d + cq) = make_float2(v0, v1);
       } else {                                            // the group's row is written by this wave alone
-        float2* dst = reinterpret_cast<float2*>(dq + (int64_t)qrow[g] * a.d + cq);
-        const float2 o = *dst;
-        *dst = make_float2(o.x + v0, o.y + v1);
+        *reinterpret_cast<float2*>(dq + (int64_t)grow * a.d + cq) = make_float2(gold.x + v0, gold.y + v1);
       }
     }
     first = false;
@@ -302,15 +310,22 @@ __global__ void __launch_bounds__(kAtWaves * 64) k_attn_tuple_q(AttnArgs a, cons
     const int64_t e = base + min(lane, n - 1);
     const int32_t gl = a.sg.seg_of[e];
     const int32_t Rq = a.rq[e], Rk = a.rk[e], Rv = a.rv[e];
+    const int32_t QR = qrow[gl];                          // Q row of each position's group
     for (int bt = 0; bt < n; bt += kTupB) {
+      // every load of the batch first (the group's lse and D included),
+      // so that the arithmetic waits once for all of them
       float2 qv[kTupB], kv[kTupB], vv[kTupB], dv[kTupB];
+      float lw[kTupB], dw[kTupB];
 #pragma unroll
       for (int i = 0; i < kTupB; ++i) {                  // clamped: every load is valid
         const int q = min(bt + i, n - 1);
+        const int64_t gi = __builtin_amdgcn_readlane(gl, q);
         qv[i] = ld2<kBF16>(a.q, __builtin_amdgcn_readlane(Rq, q), a.d, cqc);
         kv[i] = ld2<kBF16>(a.k, __builtin_amdgcn_readlane(Rk, q), a.d, cqc);
         vv[i] = ld2<kBF16>(a.v, __builtin_amdgcn_readlane(Rv, q), a.dv, cvc);
-        dv[i] = *reinterpret_cast<const float2*>(dout + (int64_t)__builtin_amdgcn_readlane(gl, q) * a.dv + cvc);
+        dv[i] = *reinterpret_cast<const float2*>(dout + gi * a.dv + cvc);
+        lw[i] = lse[gi * a.heads + h];
+        dw[i] = D[gi * a.heads + h];
       }
 #pragma unroll
       for (int i = 0; i < kTupB; ++i) {
@@ -320,6 +335,8 @@ __global__ void __launch_bounds__(kAtWaves * 64) k_attn_tuple_q(AttnArgs a, cons
         if (gq != g) {                                    // a group ends
           flush(false);
           g = gq;
+          grow = __builtin_amdgcn_readlane(QR, q);
+          if (on_q) gold = *reinterpret_cast<const float2*>(dq + (int64_t)grow * a.d + cq);
         }
         const int64_t t = base + q;
         float p = on_q ? qv[i].x * kv[i].x + qv[i].y * kv[i].y : 0.0f;
@@ -327,8 +344,8 @@ __global__ void __launch_bounds__(kAtWaves * 64) k_attn_tuple_q(AttnArgs a, cons
         float dp = on_v ? dv[i].x * vv[i].x + dv[i].y * vv[i].y : 0.0f;
         for (int off = 1; off < hv_lanes; off <<= 1) dp += __shfl_xor(dp, off);
         const float sc = a.scale * __shfl(p, h * hq_lanes);
-        const float w = expf(sc - lse[(int64_t)g * a.heads + h]);
-        const float ds = a.scale * w * (dp - D[(int64_t)g * a.heads + h]);
+        const float w = expf(sc - lw[i]);
+        const float ds = a.scale * w * (dp - dw[i]);
         if (head_lead) {
           A[t * a.heads + h] = w;
           DS[t * a.heads + h] = ds;

@@ -106,9 +106,11 @@ __device__ __forceinline__ f32x4 gs_cvt(uint4 r) {
 // start) or 1 (runs past the end); k_fixup combines them in unit order.
 // VW columns per lane: 4, or 2 for rows of at most 128 elements (all 64
 // lanes busy; a wave instruction costs the same with 32 or 64 lanes on).
-// kTw: the sum may scale rows by a per-tuple weight (wgt) or mask them by
-// per-tuple ownership bits (own).
-template <int VW, bool kBF16, bool kTw>
+// kMode 0: plain sums written to out[s]; 1: rows may be scaled by a
+// per-tuple weight (wgt) or masked by per-tuple ownership bits (own); 2: as
+// 1, and the sums may go to remapped rows (out_row) and be added to what
+// they hold (accumulate).
+template <int VW, bool kBF16, int kMode>
 __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
   const int lane = threadIdx.x % 64;
   const int64_t u = (int64_t)blockIdx.x * kGsWaves + threadIdx.x / 64;
@@ -117,6 +119,8 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
   const int64_t r1 = min<int64_t>(((a.ntiles * (u + 1)) / a.nunits) * kGsTM, a.n);
   if (r0 >= r1) return;
   const int K = a.K;
+  constexpr bool kTw = kMode >= 1;
+  constexpr bool kRmw = kMode == 2;
 
   for (int cb = 0; cb < K; cb += 64 * VW) {
     const int col = cb + VW * lane;
@@ -129,21 +133,38 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
     // dependent offset reads at every segment end
     const bool lo_cont = r0 > 0 && a.sg.seg_of[r0 - 1] == g;
     bool first = true;
+    // the open segment's output row and (accumulate) that row's values so
+    // far, fetched when the segment opens, so that closing it waits for
+    // neither: a segment's row is written by its wave alone
+    auto old_vals = [&](int32_t orow) {
+      f32x4 o = {0.f, 0.f, 0.f, 0.f};
+      if (kRmw && a.accumulate && on) {
+        const float* p = a.out + (int64_t)orow * a.ldo + col;
+        if constexpr (VW == 4) {
+          o = *reinterpret_cast<const f32x4*>(p);
+        } else {
+          const float2 t = *reinterpret_cast<const float2*>(p);
+          o[0] = t.x;
+          o[1] = t.y;
+        }
+      }
+      return o;
+    };
+    int32_t grow = (kRmw && a.out_row) ? a.out_row[g] : g;
+    f32x4 gold = old_vals(grow);
     auto flush = [&](bool last_seg) {
       const bool cut_lo = first && lo_cont;
       const bool cut_hi = last_seg && r1 < a.n && a.sg.seg_of[r1] == g;
       if (on) {
         f32x4 v = s - c;
         const bool cut = cut_lo || cut_hi;
-        float* dst = cut ? a.carry + (u * 2 + (cut_lo ? 0 : 1)) * a.ldo + col
-                         : a.out + (int64_t)(a.out_row ? a.out_row[g] : g) * a.ldo + col;
-        if (a.accumulate && !cut) {               // a segment's row is written by its wave alone
-          if constexpr (VW == 4)
-            v += *reinterpret_cast<const f32x4*>(dst);
-          else {
-            const float2 o = *reinterpret_cast<const float2*>(dst);
-            v[0] += o.x;
-            v[1] += o.y;
+        float* dst = cut ? a.carry + (u * 2 + (cut_lo ? 0 : 1)) * a.ldo + col : a.out + (int64_t)grow * a.ldo + col;
+        if (kRmw && a.accumulate && !cut) {
+          if constexpr (VW == 4) {
+            v += gold;
+          } else {
+            v[0] += gold[0];
+            v[1] += gold[1];
           }
         }
         if constexpr (VW == 4)
@@ -159,6 +180,7 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
       const int n = (int)min<int64_t>(64, r1 - base);
       const int64_t e = base + min(lane, n - 1);
       const int32_t gl = a.sg.seg_of[e];
+      const int32_t orl = (kRmw && a.out_row) ? a.out_row[gl] : gl;   // output row of each position's segment
       // row numbers of the 64 positions, one vector per atom (absent ones
       // repeat atom 0)
       int32_t R[kMaxAtoms];
@@ -195,6 +217,8 @@ __global__ void __launch_bounds__(kGsWaves * 64) k_seg_gather_sum(GsArgs a) {
           if (__builtin_expect(gq != g, 0)) {         // a segment ends
             flush(false);
             g = gq;
+            grow = __builtin_amdgcn_readlane(orl, q);
+            gold = old_vals(grow);
           }
           f32x4 v = gs_cvt<kBF16>(raw[i]);
           if (kTw && a.wgt) {
@@ -236,20 +260,31 @@ void seg_gather_sum(GsArgs a, int64_t nseg_units_cap, hipStream_t s) {
   RELNN_REQUIRE(a.nunits <= nseg_units_cap, RELNN_E_HIP, "internal: carry region too small");
   RELNN_REQUIRE(a.K % 4 == 0, RELNN_E_UNSUPPORTED, "row width %d is not a multiple of 4", a.K);
   const unsigned g = (unsigned)cdiv(a.nunits, kGsWaves);
-  // the per-tuple weight and ownership words cost registers in every
-  // variant that may read them; plain sums use one that does not
-  const bool tw = a.wgt || a.own;
+  // the per-tuple words and the read-modify-write of output rows cost
+  // registers in every variant that may use them; plain sums use one that
+  // does not
+  const int mode = (a.out_row || a.accumulate) ? 2 : (a.wgt || a.own) ? 1 : 0;
   auto go = [&](auto kern) { kern<<<g, kGsWaves * 64, 0, s>>>(a); };
+  auto pick = [&](auto VWc, auto Bc) {
+    constexpr int kVW = decltype(VWc)::value;
+    constexpr bool kB = decltype(Bc)::value;
+    if (mode == 2)
+      go(k_seg_gather_sum<kVW, kB, 2>);
+    else if (mode == 1)
+      go(k_seg_gather_sum<kVW, kB, 1>);
+    else
+      go(k_seg_gather_sum<kVW, kB, 0>);
+  };
   if (a.K <= 128) {
     if (a.bf16)
-      tw ? go(k_seg_gather_sum<2, true, true>) : go(k_seg_gather_sum<2, true, false>);
+      pick(std::integral_constant<int, 2>{}, std::true_type{});
     else
-      tw ? go(k_seg_gather_sum<2, false, true>) : go(k_seg_gather_sum<2, false, false>);
+      pick(std::integral_constant<int, 2>{}, std::false_type{});
   } else {
     if (a.bf16)
-      tw ? go(k_seg_gather_sum<4, true, true>) : go(k_seg_gather_sum<4, true, false>);
+      pick(std::integral_constant<int, 4>{}, std::true_type{});
     else
-      tw ? go(k_seg_gather_sum<4, false, true>) : go(k_seg_gather_sum<4, false, false>);
+      pick(std::integral_constant<int, 4>{}, std::false_type{});
   }
   RELNN_LAUNCHED();
   // the fix-up reads carry slots and writes out rows with stride ldo

@@ -120,19 +120,20 @@ __global__ void __launch_bounds__(kPbWaves * 64) k_prod_bwd(ProdBwdArgs a) {
     int32_t g = a.sg.seg_of[r0];
     const bool lo_cont = r0 > 0 && a.sg.seg_of[r0 - 1] == g;
     bool first = true;
+    // the open segment's output row and that row's values so far, fetched
+    // when the segment opens (the row is written by this wave alone), so
+    // that closing it waits for neither
+    int32_t grow = a.out_row ? a.out_row[g] : g;
+    float2 gold = on ? *reinterpret_cast<const float2*>(a.out + (int64_t)grow * h + col) : make_float2(0.f, 0.f);
     auto flush = [&](bool last_seg) {
       const bool cut_lo = first && lo_cont;
       const bool cut_hi = last_seg && r1 < a.n && a.sg.seg_of[r1] == g;
       if (on) {
         const float v0 = s0 - c0, v1 = s1 - c1;
-        if (cut_lo || cut_hi) {
+        if (cut_lo || cut_hi)
           *reinterpret_cast<float2*>(a.carry + (u * 2 + (cut_lo ? 0 : 1)) * h + col) = make_float2(v0, v1);
-        } else {                                  // the row is written by this wave alone
-          const int64_t orow = a.out_row ? (int64_t)a.out_row[g] : (int64_t)g;
-          float2* dst = reinterpret_cast<float2*>(a.out + orow * h + col);
-          const float2 o = *dst;
-          *dst = make_float2(o.x + v0, o.y + v1);
-        }
+        else
+          *reinterpret_cast<float2*>(a.out + (int64_t)grow * h + col) = make_float2(gold.x + v0, gold.y + v1);
       }
       first = false;
       s0 = s1 = c0 = c1 = 0.f;
@@ -141,6 +142,7 @@ __global__ void __launch_bounds__(kPbWaves * 64) k_prod_bwd(ProdBwdArgs a) {
       const int n = (int)min<int64_t>(64, r1 - base);
       const int64_t e = base + min(lane, n - 1);
       const int32_t gl = a.sg.seg_of[e];
+      const int32_t orl = a.out_row ? a.out_row[gl] : gl;   // output row of each position's segment
       const int32_t G = a.grp_t[e];
       const int32_t T = a.own ? (a.tau_t ? a.tau_t[e] : (int32_t)e) : 0;
       // the group of the position before the block (first_only)
@@ -193,6 +195,8 @@ __global__ void __launch_bounds__(kPbWaves * 64) k_prod_bwd(ProdBwdArgs a) {
           if (gq != g) {                            // a segment ends
             flush(false);
             g = gq;
+            grow = __builtin_amdgcn_readlane(orl, q);
+            if (on) gold = *reinterpret_cast<const float2*>(a.out + (int64_t)grow * h + col);
           }
           float2 v = make_float2(0.0f, 0.0f);
           if (!((skip >> b) & 1u)) {
