@@ -37,7 +37,9 @@ namespace {
 
 constexpr int kPbTM = 64;        // range boundaries on multiples of 64 positions
 constexpr int kPbWaves = 4;      // waves per block
-constexpr int kPbBatch = 8;      // positions whose rows are loaded together
+constexpr int kPbBatch = 4;      // positions whose rows are loaded together (4: 8.3 ms a
+                                 // three-atom backward over 20M tuples; 2, 6, 8 and 12:
+                                 // 9.6, 8.8, 8.7 and 10.3 ms, fewer waves or fewer loads)
 
 struct ProdBwdArgs {
   const void* emb[RELNN_MAX_ATOMS];          // [n_i][h], FP32 or bf16
