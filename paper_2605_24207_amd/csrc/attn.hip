@@ -163,15 +163,28 @@ __global__ void k_attn_fixup(AttnArgs a) {
   for (int c = threadIdx.x; c < a.dv; c += blockDim.x) {
     const int h = c / a.hdv;
     float m = -INFINITY, l = 0.0f, acc = 0.0f;
-    for (int64_t i = 0; i < P; ++i) {
-      const float* st = at(i);
-      const float m2 = st[a.dv + h], l2 = st[a.dv + a.heads + h], acc2 = st[c];
-      const float mn = fmaxf(m, m2);
-      if (mn == -INFINITY) continue;                      // nothing seen yet on either side
-      const float fa = expf(m - mn), fb = expf(m2 - mn);
-      l = l * fa + l2 * fb;
-      acc = acc * fa + acc2 * fb;
-      m = mn;
+    // a hot group spans many ranges: the partials are loaded eight at a
+    // time, then merged in range order
+    constexpr int kFB = 8;
+    for (int64_t i0 = 0; i0 < P; i0 += kFB) {
+      float m2[kFB], l2[kFB], a2[kFB];
+#pragma unroll
+      for (int j = 0; j < kFB; ++j) {
+        const float* st = at(min<int64_t>(i0 + j, P - 1));   // clamped: every load is valid
+        m2[j] = st[a.dv + h];
+        l2[j] = st[a.dv + a.heads + h];
+        a2[j] = st[c];
+      }
+#pragma unroll
+      for (int j = 0; j < kFB; ++j) {
+        if (i0 + j >= P) break;
+        const float mn = fmaxf(m, m2[j]);
+        if (mn == -INFINITY) continue;                    // nothing seen yet on either side
+        const float fa = expf(m - mn), fb = expf(m2[j] - mn);
+        l = l * fa + l2[j] * fb;
+        acc = acc * fa + a2[j] * fb;
+        m = mn;
+      }
     }
     a.out[s * a.dv + c] = acc / l;
     if (a.lse && c % a.hdv == 0) a.lse[s * a.heads + h] = m + logf(l);

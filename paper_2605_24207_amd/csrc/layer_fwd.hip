@@ -129,21 +129,41 @@ __global__ void __launch_bounds__(kThreads) k_fixup(Seg sg, int64_t ntiles, int6
     int32_t am = -1;
     if (active) {
       const int64_t lo = (P * strand) / S, hi = (P * (strand + 1)) / S;
+      // a hot segment spans many units: the partials are loaded eight at a
+      // time (clamped to the strand's last), then combined in unit order
+      constexpr int kFB = 8;
       if (sink.agg == RELNN_MAX) {
         v = -INFINITY;
-        for (int64_t i = lo; i < hi; ++i) {
-          const float x = carry[at(i) + c];
-          const int32_t xa = carry_arg[at(i) + c];
-          if (x > v || am < 0) {
-            v = x;
-            am = xa;
+        for (int64_t i0 = lo; i0 < hi; i0 += kFB) {
+          float x[kFB];
+          int32_t xa[kFB];
+#pragma unroll
+          for (int j = 0; j < kFB; ++j) {
+            const int64_t i = min(i0 + j, hi - 1);
+            x[j] = carry[at(i) + c];
+            xa[j] = carry_arg[at(i) + c];
+          }
+#pragma unroll
+          for (int j = 0; j < kFB; ++j) {
+            if (i0 + j >= hi) break;
+            if (x[j] > v || am < 0) {
+              v = x[j];
+              am = xa[j];
+            }
           }
         }
       } else {
         for (int64_t i0 = lo; i0 < hi; i0 += 64) {
           float inner = 0.0f;
           const int64_t i1 = min(hi, i0 + 64);
-          for (int64_t i = i0; i < i1; ++i) inner += carry[at(i) + c];
+          for (int64_t ib = i0; ib < i1; ib += kFB) {
+            float x[kFB];
+#pragma unroll
+            for (int j = 0; j < kFB; ++j) x[j] = carry[at(min(ib + j, i1 - 1)) + c];
+#pragma unroll
+            for (int j = 0; j < kFB; ++j)
+              if (ib + j < i1) inner += x[j];
+          }
           const float y = inner - comp;
           const float tt = v + y;
           comp = __builtin_isfinite(tt) ? (tt - v) - y : 0.0f;   // an infinite sum stays infinite
